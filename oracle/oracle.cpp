@@ -1,0 +1,856 @@
+// CPU oracle of the pixel-track hot path.  TEST INFRASTRUCTURE ONLY.
+//
+// Plain, slow, double precision.  It exists so that tests, the smoke check and
+// the CPU baseline of the benchmark have something obviously correct to compare
+// the GPU library with.  It shares no code with the GPU library and is never
+// called by it.  Built with -ffp-contract=off so that every predicate below is
+// evaluated exactly as parenthesised.
+//
+// What it computes (Bocci et al., "Heterogeneous reconstruction of tracks and
+// primary vertices with the CMS pixel tracker"):
+//   * doublets between hits of chosen layer pairs, all inner x outer hits
+//     tested by brute force against the cuts of Table 1 (section 3.2);
+//   * cell links: doublets sharing a hit, compatible in R-Z alignment and in
+//     the distance of their circle from the beam spot (section 3.2);
+//   * n-tuplets: depth-first search from the root doublets over the cell
+//     graph, keeping maximal paths only (section 3.2);
+//   * duplicate removal: among n-tuplets sharing a hit doublet only those with
+//     the most hits survive (section 3.3, last paragraph);
+//   * the broken-line fit of each n-tuplet: a three-point pre-fit giving the
+//     momentum for multiple scattering, a line fit in S-Z and a circle fit in
+//     the transverse plane, combined into perigee parameters (section 3.4,
+//     after Blobel's broken lines);
+//   * the gradient of that fit with respect to hit coordinates by forward-mode
+//     dual numbers through the same templated code.
+//
+// Where the paper gives names but no formulas (cut definitions, material,
+// resolutions, the exact pre-fit) the readings are documented at each
+// function.  Parity pins for every function live in tests/test_oracle_*.py.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+constexpr int kMaxPairs = 32;
+constexpr int kMaxHits = 8;
+constexpr int kLayers = 10;
+
+enum { CUT_PHIW = 1, CUT_ZW = 2, CUT_ZIP = 4, CUT_PT = 8 };
+
+}  // namespace
+
+extern "C" {
+
+// Configuration as the Python side fills it (mirrors synth.config keys).
+struct oracle_config {
+  double bfield;
+  int32_t n_pairs;
+  int32_t pair_inner[kMaxPairs];
+  int32_t pair_outer[kMaxPairs];
+  double pair_dphi[kMaxPairs];
+  double pair_zlo[kMaxPairs];
+  double pair_zhi[kMaxPairs];
+  double pt_min;
+  double z0_max;
+  int32_t cut_mask;
+  double ca_theta_barrel;
+  double ca_theta_endcap;
+  double ca_rmax_bpix1;
+  double ca_rmax_other;
+  int32_t root_always_mask;
+  int32_t root_if_free_mask;
+  int32_t min_hits;
+  int32_t max_hits;
+  int32_t layer_barrel[kLayers];
+  double x_over_x0;
+  double highland_a;
+  double highland_b;
+  double sigma_rphi;
+  double sigma_z;
+  double sigma_r;
+  double p_cap;
+};
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Doublet cuts (section 3.2, Table 1).  For inner hit i and outer hit o:
+//   PhiW: the azimuth difference is below the pair's window dphi:
+//         D = Xi Xo + Yi Yo > 0  and  |Xi Yo - Yi Xo| <= tan(dphi) D
+//   ZW:   zlo <= Zi <= zhi (window on the inner hit's z)
+//   ZIP:  the straight R-Z line through both hits meets r = 0 within z0_max:
+//         Ro - Ri > 0 and |Zi Ro - Zo Ri| <= z0_max (Ro - Ri)
+//   PT:   the circle through the origin and both hits has curvature
+//         <= kappa_max = 0.299792458 B / (100 pt_min):
+//         (4 C) C <= (kappa_max^2 (Ri^2 Ro^2)) L^2 with C the cross product
+//         and L the distance between the hits
+// PhiHist (the 128-bin histogram of Table 1) is a search structure, not a
+// predicate; the brute force here needs none.
+struct DoubletCuts {
+  double tan_dphi[kMaxPairs];
+  double zlo[kMaxPairs], zhi[kMaxPairs];
+  double z0_max;
+  double kappa_max2;
+  int mask;
+};
+
+DoubletCuts doublet_cuts(const oracle_config& c) {
+  DoubletCuts k{};
+  for (int p = 0; p < c.n_pairs; ++p) {
+    k.tan_dphi[p] = std::tan(c.pair_dphi[p]);
+    k.zlo[p] = c.pair_zlo[p];
+    k.zhi[p] = c.pair_zhi[p];
+  }
+  k.z0_max = c.z0_max;
+  const double kappa_max = (0.299792458 * c.bfield) / (100.0 * c.pt_min);
+  k.kappa_max2 = kappa_max * kappa_max;
+  k.mask = c.cut_mask;
+  return k;
+}
+
+bool doublet_passes(const DoubletCuts& k, int p, double Xi, double Yi, double Zi,
+                    double Xo, double Yo, double Zo) {
+  const double R2i = Xi * Xi + Yi * Yi;
+  const double R2o = Xo * Xo + Yo * Yo;
+  const double Ri = std::sqrt(R2i);
+  const double Ro = std::sqrt(R2o);
+  const double D = Xi * Xo + Yi * Yo;
+  const double C = Xi * Yo - Yi * Xo;
+  if (k.mask & CUT_PHIW) {
+    if (!(D > 0.0 && std::fabs(C) <= k.tan_dphi[p] * D)) return false;
+  }
+  if (k.mask & CUT_ZW) {
+    if (!(k.zlo[p] <= Zi && Zi <= k.zhi[p])) return false;
+  }
+  if (k.mask & CUT_ZIP) {
+    const double dR = Ro - Ri;
+    if (!(dR > 0.0 && std::fabs(Zi * Ro - Zo * Ri) <= k.z0_max * dR)) return false;
+  }
+  if (k.mask & CUT_PT) {
+    const double dx = Xo - Xi;
+    const double dy = Yo - Yi;
+    const double L2 = dx * dx + dy * dy;
+    if (!((4.0 * C) * C <= (k.kappa_max2 * (R2i * R2o)) * L2)) return false;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Triplet compatibility (section 3.2): two doublets (h0,h1) and (h1,h2)
+//   R-Z alignment: the sine of the kink between the two R-Z segments is at
+//     most theta:  A = a_r b_z - a_z b_r,
+//     A A <= theta^2 ((a_r a_r + a_z a_z) (b_r b_r + b_z b_z));
+//     theta is the barrel value when h2 is on a barrel layer, else the
+//     end-cap value (barrel and end-caps get separate cuts, section 4.2).
+//   Beam spot: the circle through the three hits passes within r_max of the
+//     beam line (at the origin): | |centre| - radius | <= r_max, with the
+//     straight-line distance when the three hits are collinear; r_max is the
+//     BPix1 value when h0 is on BPix1, else the other value.
+struct LinkCuts {
+  double theta2_barrel, theta2_endcap;
+  double rmax_bpix1, rmax_other;
+  int barrel[kLayers];
+};
+
+LinkCuts link_cuts(const oracle_config& c) {
+  LinkCuts k{};
+  k.theta2_barrel = c.ca_theta_barrel * c.ca_theta_barrel;
+  k.theta2_endcap = c.ca_theta_endcap * c.ca_theta_endcap;
+  k.rmax_bpix1 = c.ca_rmax_bpix1;
+  k.rmax_other = c.ca_rmax_other;
+  for (int l = 0; l < kLayers; ++l) k.barrel[l] = c.layer_barrel[l];
+  return k;
+}
+
+bool link_passes(const LinkCuts& k, int layer0, int layer2,
+                 double X0, double Y0, double Z0,
+                 double X1, double Y1, double Z1,
+                 double X2, double Y2, double Z2) {
+  const double R0 = std::sqrt(X0 * X0 + Y0 * Y0);
+  const double R1 = std::sqrt(X1 * X1 + Y1 * Y1);
+  const double R2 = std::sqrt(X2 * X2 + Y2 * Y2);
+  const double ar = R1 - R0, az = Z1 - Z0;
+  const double br = R2 - R1, bz = Z2 - Z1;
+  const double A = ar * bz - az * br;
+  const double theta2 = k.barrel[layer2] ? k.theta2_barrel : k.theta2_endcap;
+  if (!(A * A <= theta2 * ((ar * ar + az * az) * (br * br + bz * bz)))) return false;
+
+  const double rmax = (layer0 == 0) ? k.rmax_bpix1 : k.rmax_other;
+  const double ux = X1 - X0, uy = Y1 - Y0;
+  const double vx = X2 - X0, vy = Y2 - Y0;
+  const double Dd = 2.0 * (ux * vy - uy * vx);
+  if (Dd == 0.0) {
+    const double cr = X0 * vy - Y0 * vx;
+    return cr * cr <= (rmax * rmax) * (vx * vx + vy * vy);
+  }
+  const double U2 = ux * ux + uy * uy;
+  const double V2 = vx * vx + vy * vy;
+  const double cx = (U2 * vy - V2 * uy) / Dd;
+  const double cy = (V2 * ux - U2 * vx) / Dd;
+  const double rho2 = cx * cx + cy * cy;
+  const double Cx = X0 + cx, Cy = Y0 + cy;
+  const double c2 = Cx * Cx + Cy * Cy;
+  return std::fabs(std::sqrt(c2) - std::sqrt(rho2)) <= rmax;
+}
+
+}  // namespace
+
+extern "C" {
+
+// All doublets of one event.  Hits are the arrays as given (indices 0..n-1).
+// For every pair p, every outer hit o on the pair's outer layer and every
+// inner hit i on its inner layer, in that order, the doublet (i, o, p) is
+// emitted when it passes the cuts.  Returns the number found; only the first
+// `cap` are written.
+int64_t oracle_doublets(const oracle_config* cfg, int32_t n, const double* x, const double* y,
+                        const double* z, const uint8_t* layer, int64_t cap, int32_t* inner,
+                        int32_t* outer, uint8_t* pair) {
+  const DoubletCuts k = doublet_cuts(*cfg);
+  std::vector<std::vector<int32_t>> by_layer(kLayers);
+  for (int32_t h = 0; h < n; ++h) by_layer[layer[h]].push_back(h);
+  int64_t count = 0;
+  for (int p = 0; p < cfg->n_pairs; ++p) {
+    const auto& outs = by_layer[cfg->pair_outer[p]];
+    const auto& ins = by_layer[cfg->pair_inner[p]];
+    for (int32_t o : outs) {
+      for (int32_t i : ins) {
+        if (doublet_passes(k, p, x[i], y[i], z[i], x[o], y[o], z[o])) {
+          if (count < cap) {
+            inner[count] = i;
+            outer[count] = o;
+            pair[count] = static_cast<uint8_t>(p);
+          }
+          ++count;
+        }
+      }
+    }
+  }
+  return count;
+}
+
+// Cell links of one event: for every cell c = (h1, h2) and every cell
+// c' = (h0, h1) ending on its inner hit, the link (c' -> c) when the triplet
+// passes the cuts.  Cells are given as (inner, outer) hit index arrays.
+// Returns the number of links; only the first `cap` are written.
+int64_t oracle_links(const oracle_config* cfg, int32_t n, const double* x, const double* y,
+                     const double* z, const uint8_t* layer, int32_t n_cells,
+                     const int32_t* cell_inner, const int32_t* cell_outer, int64_t cap,
+                     int32_t* link_in, int32_t* link_out) {
+  const LinkCuts k = link_cuts(*cfg);
+  std::vector<std::vector<int32_t>> ending_at(n);
+  for (int32_t c = 0; c < n_cells; ++c) ending_at[cell_outer[c]].push_back(c);
+  int64_t count = 0;
+  for (int32_t c = 0; c < n_cells; ++c) {
+    const int32_t h1 = cell_inner[c], h2 = cell_outer[c];
+    for (int32_t cp : ending_at[h1]) {
+      const int32_t h0 = cell_inner[cp];
+      if (link_passes(k, layer[h0], layer[h2], x[h0], y[h0], z[h0], x[h1], y[h1], z[h1], x[h2],
+                      y[h2], z[h2])) {
+        if (count < cap) {
+          link_in[count] = cp;
+          link_out[count] = c;
+        }
+        ++count;
+      }
+    }
+  }
+  return count;
+}
+
+// n-tuplets of one event (section 3.2, then the duplicate removal of section
+// 3.3).  Root doublets: inner hit on a layer in root_always_mask, or on a
+// layer in root_if_free_mask with no inner neighbour.  From every root a
+// depth-first search follows outer links; a path is emitted when it cannot be
+// extended (or has reached max_hits hits, which sets *truncated) and has at
+// least min_hits hits.  With dedup != 0, an n-tuplet is then dropped when one
+// of its cells belongs to an n-tuplet with more hits.
+//
+// Output: hits [cap][8] (-1 padded, inside -> out), cells [cap][7], nhits
+// [cap].  Returns the number of n-tuplets (after dedup when requested);
+// *n_raw receives the count before dedup.
+int64_t oracle_ntuplets(const oracle_config* cfg, int32_t n, const uint8_t* layer, int32_t n_cells,
+                        const int32_t* cell_inner, const int32_t* cell_outer, int32_t n_links,
+                        const int32_t* link_in, const int32_t* link_out, int32_t dedup,
+                        int64_t cap, int32_t* out_hits, int32_t* out_cells, uint8_t* out_n,
+                        int64_t* n_raw, int32_t* truncated) {
+  (void)n;
+  std::vector<std::vector<int32_t>> outer_links(n_cells);
+  std::vector<uint8_t> has_inner(n_cells, 0);
+  for (int32_t l = 0; l < n_links; ++l) {
+    outer_links[link_in[l]].push_back(link_out[l]);
+    has_inner[link_out[l]] = 1;
+  }
+  const int max_hits = std::min<int>(cfg->max_hits, kMaxHits);
+  std::vector<std::vector<int32_t>> paths;  // each: the cells of a path
+  *truncated = 0;
+  std::vector<int32_t> path;
+  // Recursive depth-first search, written with an explicit lambda.
+  struct Dfs {
+    const std::vector<std::vector<int32_t>>& links;
+    int max_hits, min_hits;
+    std::vector<std::vector<int32_t>>& paths;
+    int32_t* truncated;
+    void go(std::vector<int32_t>& path) {
+      const int32_t last = path.back();
+      const int nh = static_cast<int>(path.size()) + 1;
+      if (links[last].empty() || nh == max_hits) {
+        if (!links[last].empty()) *truncated = 1;
+        if (nh >= min_hits) paths.push_back(path);
+        return;
+      }
+      for (int32_t next : links[last]) {
+        path.push_back(next);
+        go(path);
+        path.pop_back();
+      }
+    }
+  } dfs{outer_links, max_hits, cfg->min_hits, paths, truncated};
+  for (int32_t c = 0; c < n_cells; ++c) {
+    const int L = layer[cell_inner[c]];
+    const bool root = ((cfg->root_always_mask >> L) & 1) ||
+                      (((cfg->root_if_free_mask >> L) & 1) && !has_inner[c]);
+    if (!root) continue;
+    path.assign(1, c);
+    dfs.go(path);
+  }
+  *n_raw = static_cast<int64_t>(paths.size());
+
+  std::vector<uint8_t> keep(paths.size(), 1);
+  if (dedup) {
+    std::vector<int> max_n(n_cells, 0);
+    for (const auto& p : paths)
+      for (int32_t c : p) max_n[c] = std::max<int>(max_n[c], static_cast<int>(p.size()) + 1);
+    for (size_t t = 0; t < paths.size(); ++t)
+      for (int32_t c : paths[t])
+        if (max_n[c] != static_cast<int>(paths[t].size()) + 1) keep[t] = 0;
+  }
+  int64_t count = 0;
+  for (size_t t = 0; t < paths.size(); ++t) {
+    if (!keep[t]) continue;
+    if (count < cap) {
+      const auto& p = paths[t];
+      for (int k = 0; k < kMaxHits; ++k) out_hits[count * kMaxHits + k] = -1;
+      for (int k = 0; k < kMaxHits - 1; ++k) out_cells[count * (kMaxHits - 1) + k] = -1;
+      out_hits[count * kMaxHits + 0] = cell_inner[p[0]];
+      for (size_t j = 0; j < p.size(); ++j) {
+        out_hits[count * kMaxHits + j + 1] = cell_outer[p[j]];
+        out_cells[count * (kMaxHits - 1) + j] = p[j];
+      }
+      out_n[count] = static_cast<uint8_t>(p.size() + 1);
+    }
+    ++count;
+  }
+  return count;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Broken-line fit (section 3.4), templated on the scalar so that the same code
+// runs in double and in forward-mode dual numbers.
+
+namespace {
+
+struct Dual {
+  double v;  // value
+  double d;  // derivative along the seeded direction
+};
+inline Dual mk(double v) { return {v, 0.0}; }
+inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
+inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+inline Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+inline Dual sqrt(Dual a) {
+  const double r = std::sqrt(a.v);
+  return {r, a.d / (2.0 * r)};
+}
+inline Dual asin(Dual a) { return {std::asin(a.v), a.d / std::sqrt(1.0 - a.v * a.v)}; }
+inline Dual atan(Dual a) { return {std::atan(a.v), a.d / (1.0 + a.v * a.v)}; }
+inline Dual atan2(Dual y, Dual x) {
+  const double r2 = x.v * x.v + y.v * y.v;
+  return {std::atan2(y.v, x.v), (x.v * y.d - y.v * x.d) / r2};
+}
+inline Dual log(Dual a) { return {std::log(a.v), a.d / a.v}; }
+inline Dual fabs(Dual a) { return a.v < 0 ? -a : a; }
+inline double val(Dual a) { return a.v; }
+inline double val(double a) { return a; }
+template <class T> inline T cst(double v) { return T(v); }
+template <> inline Dual cst<Dual>(double v) { return mk(v); }
+inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
+inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
+inline bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
+
+using std::asin;
+using std::atan;
+using std::atan2;
+using std::fabs;
+using std::log;
+using std::sqrt;
+
+struct FitSettings {
+  double K;             // 0.299792458 B / 100: p_T [GeV] = K / |kappa| [1/cm]
+  double x_over_x0, ha, hb;
+  double VT;            // transverse measurement variance
+  double VZ_barrel;     // sigma_z^2
+  double VR_disk;       // sigma_r^2
+  double p_cap;
+  int barrel[kLayers];
+};
+
+FitSettings fit_settings(const oracle_config& c) {
+  FitSettings f{};
+  f.K = 0.299792458 * c.bfield / 100.0;
+  f.x_over_x0 = c.x_over_x0;
+  f.ha = c.highland_a;
+  f.hb = c.highland_b;
+  f.VT = c.sigma_rphi * c.sigma_rphi;
+  f.VZ_barrel = c.sigma_z * c.sigma_z;
+  f.VR_disk = c.sigma_r * c.sigma_r;
+  f.p_cap = c.p_cap;
+  for (int l = 0; l < kLayers; ++l) f.barrel[l] = c.layer_barrel[l];
+  return f;
+}
+
+enum { FIT_OK = 0, FIT_BAD_ORDER = 1, FIT_SINGULAR = 4 };
+
+// Solve A x = b (dense, m x m, row-major) by Gaussian elimination with
+// partial pivoting.  Returns false when a pivot is exactly zero.
+template <class T>
+bool gauss_solve(int m, std::vector<T> A, std::vector<T> b, std::vector<T>& x) {
+  for (int col = 0; col < m; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < m; ++r)
+      if (std::fabs(val(A[r * m + col])) > std::fabs(val(A[piv * m + col]))) piv = r;
+    if (val(A[piv * m + col]) == 0.0) return false;
+    if (piv != col) {
+      for (int j = 0; j < m; ++j) std::swap(A[col * m + j], A[piv * m + j]);
+      std::swap(b[col], b[piv]);
+    }
+    for (int r = col + 1; r < m; ++r) {
+      const T f = A[r * m + col] / A[col * m + col];
+      for (int j = col; j < m; ++j) A[r * m + j] = A[r * m + j] - f * A[col * m + j];
+      b[r] = b[r] - f * b[col];
+    }
+  }
+  x.assign(m, cst<T>(0.0));
+  for (int r = m - 1; r >= 0; --r) {
+    T s = b[r];
+    for (int j = r + 1; j < m; ++j) s = s - A[r * m + j] * x[j];
+    x[r] = s / A[r * m + r];
+  }
+  return true;
+}
+
+template <class T>
+struct FitResult {
+  T kappa, phi0, cot, d0, z0, chi2;
+  int status;
+  // intermediate quantities, exported for the tests' independent checks
+  std::vector<T> s, um, delta, wT, wZ, VZ, ucirc, vline;
+  T kappa_pre, t_pre, p;
+  std::vector<T> A, b, N, q;
+};
+
+// The fit of one n-tuplet, hits P_k = (X_k, Y_k, Z_k), k = 0..n-1, inside out.
+//
+// 1. Pre-fit: the circle through P_0, P_b (b = n/2 rounded down) and P_{n-1};
+//    its curvature kappa_pre > 0 when the three points turn counter-clockwise.
+//    The momentum estimate p_T = K / |kappa_pre| feeds multiple scattering.
+// 2. Along that circle: s_k, the arc length from P_0 to the foot of P_k
+//    (chord form), and u_k, the signed offset of P_k to the left of the
+//    circle.  The s_k must increase.
+// 3. Slope t = (Z_{n-1} - Z_0) / s_{n-1}; p = min(p_T sqrt(1 + t^2), p_cap).
+// 4. Scattering at every inner hit k = 1..n-2 (Highland): with material
+//    X = x/X0 * path length (1/sin(theta) in the barrel, 1/|cos(theta)| on
+//    disks), theta0^2 = (a/p)^2 X (1 + b ln X)^2; projected kink variances
+//    theta0^2 (1+t^2) in the transverse plane and theta0^2 (1+t^2)^2 in S-Z.
+// 5. Measurement variances: sigma_rphi^2 transverse; sigma_z^2 on barrel
+//    layers and (sigma_r t)^2 on disks longitudinally.
+// 6. Circle fit: unknowns u_0..u_{n-1} and the curvature correction dk,
+//    minimising sum (um_k - u_k)^2 / VT + sum beta_k^2 / thetaT_k^2 with the
+//    kink beta_k = (u_{k+1}-u_k)/D_k - (u_k-u_{k-1})/D_{k-1} - dk (D_{k-1}+D_k)/2.
+// 7. Line fit: unknowns v_0..v_{n-1}, minimising sum (Z_k - v_k)^2 / VZ_k +
+//    sum gamma_k^2 / thetaZ_k^2, gamma_k the same second difference of v.
+// 8. Perigee: kappa = kappa_pre + dk; the fitted point Q = P_0 + u_0 n_0 and
+//    direction psi = psi_pre + atan(u'_0) at s = 0 give d0 and phi0 of the
+//    circle of curvature kappa through Q; cot(theta) = (v_1 - v_0)/D_0 and z0
+//    extrapolates v_0 back to the point of closest approach.
+//    chi2 = chi2_circle + chi2_line at the optimum (2n - 5 degrees of freedom).
+template <class T>
+FitResult<T> fit_track(const FitSettings& F, int n, const T* X, const T* Y, const T* Z,
+                       const int* lay) {
+  FitResult<T> R;
+  R.status = FIT_OK;
+  const T zero = cst<T>(0.0), one = cst<T>(1.0), two = cst<T>(2.0);
+  const int b = n / 2;
+
+  // 1. pre-fit circle
+  const T ux = X[b] - X[0], uy = Y[b] - Y[0];
+  const T vx = X[n - 1] - X[0], vy = Y[n - 1] - Y[0];
+  const T Dd = two * (ux * vy - uy * vx);
+  const T wx = X[n - 1] - X[b], wy = Y[n - 1] - Y[b];
+  const double sigma = (val(ux * wy - uy * wx) >= 0.0) ? 1.0 : -1.0;
+  const bool straight = val(Dd) == 0.0;
+  T cx = zero, cy = zero, rho = zero, kappa_pre = zero;
+  if (!straight) {
+    const T U2 = ux * ux + uy * uy, V2 = vx * vx + vy * vy;
+    const T ccx = (U2 * vy - V2 * uy) / Dd;
+    const T ccy = (V2 * ux - U2 * vx) / Dd;
+    cx = X[0] + ccx;
+    cy = Y[0] + ccy;
+    rho = sqrt(ccx * ccx + ccy * ccy);
+    kappa_pre = cst<T>(sigma) / rho;
+  }
+  R.kappa_pre = kappa_pre;
+
+  // direction of motion and left normal of the pre-fit at P_0
+  T tx, ty;
+  if (!straight) {
+    const T rx = X[0] - cx, ry = Y[0] - cy;
+    tx = cst<T>(sigma) * (-ry) / rho;
+    ty = cst<T>(sigma) * rx / rho;
+  } else {
+    const T lv = sqrt(vx * vx + vy * vy);
+    tx = vx / lv;
+    ty = vy / lv;
+  }
+  const T nx = -ty, ny = tx;
+
+  // 2. arc lengths and offsets
+  R.s.assign(n, zero);
+  R.um.assign(n, zero);
+  T f0x = X[0], f0y = Y[0];
+  if (!straight) {
+    const T dx0 = X[0] - cx, dy0 = Y[0] - cy;
+    const T l0 = sqrt(dx0 * dx0 + dy0 * dy0);
+    f0x = cx + rho * dx0 / l0;
+    f0y = cy + rho * dy0 / l0;
+  }
+  // P_0 is on the pre-fit circle: s_0 = 0 and u_0 = 0 by definition.
+  for (int k = 1; k < n; ++k) {
+    if (straight) {
+      const T rx = X[k] - X[0], ry = Y[k] - Y[0];
+      R.s[k] = rx * tx + ry * ty;
+      R.um[k] = rx * nx + ry * ny;
+      continue;
+    }
+    const T dx = X[k] - cx, dy = Y[k] - cy;
+    const T lk = sqrt(dx * dx + dy * dy);
+    const T fx = cx + rho * dx / lk, fy = cy + rho * dy / lk;
+    const T chx = fx - f0x, chy = fy - f0y;
+    const T d = sqrt(chx * chx + chy * chy);
+    T s = d;
+    if (val(d) > 0.0) {
+      const T half = fabs(kappa_pre) * d / two;
+      s = d * asin(half) / half;
+    }
+    const double ahead = val(chx * tx + chy * ty);
+    R.s[k] = (ahead >= 0.0) ? s : -s;
+    R.um[k] = -cst<T>(sigma) * (lk - rho);
+  }
+  R.delta.assign(n - 1, zero);
+  for (int k = 0; k + 1 < n; ++k) {
+    R.delta[k] = R.s[k + 1] - R.s[k];
+    if (!(val(R.delta[k]) > 0.0)) R.status = FIT_BAD_ORDER;
+  }
+  if (R.status != FIT_OK) return R;
+
+  // 3. slope and momentum
+  const T t = (Z[n - 1] - Z[0]) / R.s[n - 1];
+  const T sec2 = one + t * t;  // 1 + cot^2 = 1 / sin^2(theta)
+  T p = cst<T>(F.p_cap);
+  if (val(kappa_pre) != 0.0) {
+    const T pt = cst<T>(F.K) / fabs(kappa_pre);
+    const T pp = pt * sqrt(sec2);
+    if (val(pp) < F.p_cap) p = pp;
+  }
+  R.t_pre = t;
+  R.p = p;
+
+  // 4. scattering weights at the inner hits
+  R.wT.assign(n, zero);
+  R.wZ.assign(n, zero);
+  for (int k = 1; k + 1 < n; ++k) {
+    T path = sqrt(sec2);
+    if (!F.barrel[lay[k]]) path = path / fabs(t);
+    const T Xm = cst<T>(F.x_over_x0) * path;
+    const T lg = one + cst<T>(F.hb) * log(Xm);
+    const T th0 = (cst<T>(F.ha) / p);
+    const T theta02 = th0 * th0 * Xm * lg * lg;
+    R.wT[k] = one / (theta02 * sec2);
+    R.wZ[k] = one / (theta02 * sec2 * sec2);
+  }
+
+  // 5. longitudinal measurement variances
+  R.VZ.assign(n, zero);
+  for (int k = 0; k < n; ++k)
+    R.VZ[k] = F.barrel[lay[k]] ? cst<T>(F.VZ_barrel) : cst<T>(F.VR_disk) * t * t;
+
+  // 6. circle fit, dense normal equations of size n + 1
+  const int m = n + 1;
+  std::vector<T> A(m * m, zero), rhs(m, zero), xsol;
+  const T wmeas = one / cst<T>(F.VT);
+  for (int k = 0; k < n; ++k) {
+    A[k * m + k] = A[k * m + k] + wmeas;
+    rhs[k] = R.um[k] * wmeas;
+  }
+  auto kink_row = [&](int k, std::vector<T>& g, bool with_kappa) {
+    g.assign(m, zero);
+    g[k - 1] = one / R.delta[k - 1];
+    g[k] = -(one / R.delta[k - 1]) - one / R.delta[k];
+    g[k + 1] = one / R.delta[k];
+    if (with_kappa) g[n] = -(R.delta[k - 1] + R.delta[k]) / two;
+  };
+  std::vector<T> g;
+  for (int k = 1; k + 1 < n; ++k) {
+    kink_row(k, g, true);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) A[i * m + j] = A[i * m + j] + R.wT[k] * g[i] * g[j];
+  }
+  R.A = A;
+  R.b = rhs;
+  if (!gauss_solve(m, A, rhs, xsol)) {
+    R.status = FIT_SINGULAR;
+    return R;
+  }
+  R.ucirc = xsol;
+  T chi2T = zero;
+  for (int k = 0; k < n; ++k) {
+    const T r = R.um[k] - xsol[k];
+    chi2T = chi2T + r * r * wmeas;
+  }
+  for (int k = 1; k + 1 < n; ++k) {
+    kink_row(k, g, true);
+    T beta = zero;
+    for (int i = 0; i < m; ++i) beta = beta + g[i] * xsol[i];
+    chi2T = chi2T + beta * beta * R.wT[k];
+  }
+
+  // 7. line fit, n x n
+  std::vector<T> N(n * n, zero), q(n, zero), vsol;
+  for (int k = 0; k < n; ++k) {
+    N[k * n + k] = N[k * n + k] + one / R.VZ[k];
+    q[k] = Z[k] / R.VZ[k];
+  }
+  for (int k = 1; k + 1 < n; ++k) {
+    kink_row(k, g, false);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) N[i * n + j] = N[i * n + j] + R.wZ[k] * g[i] * g[j];
+  }
+  R.N = N;
+  R.q = q;
+  if (!gauss_solve(n, N, q, vsol)) {
+    R.status = FIT_SINGULAR;
+    return R;
+  }
+  R.vline = vsol;
+  T chi2Z = zero;
+  for (int k = 0; k < n; ++k) {
+    const T r = Z[k] - vsol[k];
+    chi2Z = chi2Z + r * r / R.VZ[k];
+  }
+  for (int k = 1; k + 1 < n; ++k) {
+    kink_row(k, g, false);
+    T gam = zero;
+    for (int i = 0; i < n; ++i) gam = gam + g[i] * vsol[i];
+    chi2Z = chi2Z + gam * gam * R.wZ[k];
+  }
+
+  // 8. perigee parameters
+  const T dk = xsol[n];
+  const T kappa = kappa_pre + dk;
+  const T Qx = X[0] + xsol[0] * nx;
+  const T Qy = Y[0] + xsol[0] * ny;
+  const T du0 = (xsol[1] - xsol[0]) / R.delta[0] - dk * R.delta[0] / two;
+  // direction psi = psi_pre + atan(du0): (tx, ty) rotated by atan(du0)
+  const T ca = one / sqrt(one + du0 * du0);
+  const T sa = du0 * ca;
+  const T cpsi = tx * ca - ty * sa;
+  const T spsi = ty * ca + tx * sa;
+  const T U = kappa * (Qx * Qx + Qy * Qy) + two * (-Qx * spsi + Qy * cpsi);
+  const T d0 = U / (one + sqrt(one + kappa * U));
+  // direction at the point of closest approach
+  const T hx = cpsi + kappa * Qy, hy = spsi - kappa * Qx;
+  const T phi0 = atan2(hy, hx);
+  const T hn = sqrt(hx * hx + hy * hy);
+  const T cph = hx / hn, sph = hy / hn;
+  const T at = Qx * cph + Qy * sph;
+  const T an = -Qx * sph + Qy * cph;
+  T ds = at;
+  if (val(kappa) != 0.0) ds = atan2(kappa * at, one + kappa * (d0 - an)) / kappa;
+  const T cot = (vsol[1] - vsol[0]) / R.delta[0];
+  const T z0 = vsol[0] - cot * ds;
+
+  R.kappa = kappa;
+  R.phi0 = phi0;
+  R.cot = cot;
+  R.d0 = d0;
+  R.z0 = z0;
+  R.chi2 = chi2T + chi2Z;
+  return R;
+}
+
+void gather(int n, const int32_t* hit, const double* x, const double* y, const double* z,
+            const uint8_t* layer, const int16_t* module, const double* offsets, double* X,
+            double* Y, double* Z, int* lay) {
+  for (int k = 0; k < n; ++k) {
+    const int32_t h = hit[k];
+    X[k] = x[h];
+    Y[k] = y[h];
+    Z[k] = z[h];
+    if (offsets) {
+      const int m = module[h];
+      X[k] += offsets[3 * m + 0];
+      Y[k] += offsets[3 * m + 1];
+      Z[k] += offsets[3 * m + 2];
+    }
+    lay[k] = layer[h];
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Fit every n-tuplet: tuplets [n_tracks][8] hit indices, nhits [n_tracks].
+// P_k = hit + offsets[module] when offsets is not NULL.  Outputs params
+// [n_tracks][5] = (kappa, phi0, cot(theta), d0, z0), chi2 [n_tracks], status
+// [n_tracks] (0 ok, 1 hits not ordered along the pre-fit, 4 singular).
+void oracle_fit(const oracle_config* cfg, int64_t n_tracks, const int32_t* tuplets,
+                const uint8_t* nhits, const double* x, const double* y, const double* z,
+                const uint8_t* layer, const int16_t* module, const double* offsets,
+                double* params, double* chi2, uint8_t* status) {
+  const FitSettings F = fit_settings(*cfg);
+  double X[kMaxHits], Y[kMaxHits], Z[kMaxHits];
+  int lay[kMaxHits];
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    const int n = nhits[t];
+    gather(n, tuplets + t * kMaxHits, x, y, z, layer, module, offsets, X, Y, Z, lay);
+    const FitResult<double> r = fit_track<double>(F, n, X, Y, Z, lay);
+    status[t] = static_cast<uint8_t>(r.status);
+    double* o = params + 5 * t;
+    if (r.status != FIT_OK) {
+      for (int i = 0; i < 5; ++i) o[i] = NAN;
+      chi2[t] = NAN;
+      continue;
+    }
+    o[0] = r.kappa;
+    o[1] = r.phi0;
+    o[2] = r.cot;
+    o[3] = r.d0;
+    o[4] = r.z0;
+    chi2[t] = r.chi2;
+  }
+}
+
+// Intermediate quantities of one track, for the tests' independent checks.
+// Arrays are sized for n = 8: s, um, delta, wT, wZ, VZ [8]; ucirc [9];
+// vline [8]; A [9*9]; b [9]; N [8*8]; q [8]; scal = (kappa_pre, t_pre, p).
+int32_t oracle_fit_debug(const oracle_config* cfg, int32_t n, const double* X, const double* Y,
+                         const double* Z, const int32_t* layer_k, double* s, double* um,
+                         double* delta, double* wT, double* wZ, double* VZ, double* ucirc,
+                         double* vline, double* A, double* b, double* N, double* q,
+                         double* scal, double* params) {
+  const FitSettings F = fit_settings(*cfg);
+  int lay[kMaxHits];
+  for (int k = 0; k < n; ++k) lay[k] = layer_k[k];
+  const FitResult<double> r = fit_track<double>(F, n, X, Y, Z, lay);
+  auto cp = [](const std::vector<double>& v, double* dst) {
+    std::copy(v.begin(), v.end(), dst);
+  };
+  cp(r.s, s);
+  cp(r.um, um);
+  cp(r.delta, delta);
+  if (r.status == FIT_OK) {
+    cp(r.wT, wT);
+    cp(r.wZ, wZ);
+    cp(r.VZ, VZ);
+    cp(r.ucirc, ucirc);
+    cp(r.vline, vline);
+    cp(r.A, A);
+    cp(r.b, b);
+    cp(r.N, N);
+    cp(r.q, q);
+    scal[0] = r.kappa_pre;
+    scal[1] = r.t_pre;
+    scal[2] = r.p;
+    params[0] = r.kappa;
+    params[1] = r.phi0;
+    params[2] = r.cot;
+    params[3] = r.d0;
+    params[4] = r.z0;
+    params[5] = r.chi2;
+  }
+  return r.status;
+}
+
+// Jacobian of (kappa, phi0, cot, d0, z0, chi2) with respect to the 3n hit
+// coordinates of one track (forward-mode dual numbers, one pass per input).
+// jac is [6][3n], column 3k+c = d/d(coordinate c of hit k).
+int32_t oracle_fit_jacobian(const oracle_config* cfg, int32_t n, const double* X, const double* Y,
+                            const double* Z, const int32_t* layer_k, double* jac) {
+  const FitSettings F = fit_settings(*cfg);
+  int lay[kMaxHits];
+  for (int k = 0; k < n; ++k) lay[k] = layer_k[k];
+  Dual DX[kMaxHits], DY[kMaxHits], DZ[kMaxHits];
+  int status = FIT_OK;
+  for (int col = 0; col < 3 * n; ++col) {
+    for (int k = 0; k < n; ++k) {
+      DX[k] = {X[k], (col == 3 * k + 0) ? 1.0 : 0.0};
+      DY[k] = {Y[k], (col == 3 * k + 1) ? 1.0 : 0.0};
+      DZ[k] = {Z[k], (col == 3 * k + 2) ? 1.0 : 0.0};
+    }
+    const FitResult<Dual> r = fit_track<Dual>(F, n, DX, DY, DZ, lay);
+    status = r.status;
+    if (status != FIT_OK) return status;
+    const Dual outs[6] = {r.kappa, r.phi0, r.cot, r.d0, r.z0, r.chi2};
+    for (int o = 0; o < 6; ++o) jac[o * 3 * n + col] = outs[o].d;
+  }
+  return status;
+}
+
+// Reference gradient of the fit (the adjoint's definition):
+//   grad_hits[h]    += sum over tracks containing h of J^T (g_params, g_chi2)
+//   grad_offsets[m] += the same, summed over the hits on module m
+// Both outputs are accumulated into.  Tracks whose fit fails contribute nothing.
+void oracle_fit_grad(const oracle_config* cfg, int64_t n_tracks, const int32_t* tuplets,
+                     const uint8_t* nhits, const double* x, const double* y, const double* z,
+                     const uint8_t* layer, const int16_t* module, const double* offsets,
+                     const double* g_params, const double* g_chi2, double* grad_hits,
+                     double* grad_offsets) {
+  double X[kMaxHits], Y[kMaxHits], Z[kMaxHits];
+  int lay[kMaxHits];
+  int32_t layk[kMaxHits];
+  double jac[6 * 3 * kMaxHits];
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    const int n = nhits[t];
+    const int32_t* hit = tuplets + t * kMaxHits;
+    gather(n, hit, x, y, z, layer, module, offsets, X, Y, Z, lay);
+    for (int k = 0; k < n; ++k) layk[k] = lay[k];
+    if (oracle_fit_jacobian(cfg, n, X, Y, Z, layk, jac) != FIT_OK) continue;
+    double g[6];
+    for (int o = 0; o < 5; ++o) g[o] = g_params[5 * t + o];
+    g[5] = g_chi2 ? g_chi2[t] : 0.0;
+    for (int col = 0; col < 3 * n; ++col) {
+      double acc = 0.0;
+      for (int o = 0; o < 6; ++o) acc += jac[o * 3 * n + col] * g[o];
+      const int k = col / 3, c = col % 3;
+      grad_hits[3 * hit[k] + c] += acc;
+      if (grad_offsets) grad_offsets[3 * module[hit[k]] + c] += acc;
+    }
+  }
+}
+
+int32_t oracle_abi_version(void) { return 1; }
+
+}  // extern "C"
