@@ -1,0 +1,330 @@
+#!/usr/bin/env python3
+"""Benchmark of the pixel-track hot path on one MI355X.
+
+Step: one pass of the whole path over a batch of 64 synthetic events at
+pileup 200 -- doublets, cell links, n-tuplets with duplicate removal, the
+broken-line fit (single precision with the double-precision refit of stiff
+tracks) and its adjoint -- launched as one hipGraph (pt_plan_run).  Inputs
+are resident in device memory before timing starts.
+
+Also reported: the same 64 events processed one event per call sequence
+(the per-event form), the fit forward + adjoint throughput on 10^6 tracks
+against the HBM roofline, per-kernel durations from HIP events, and the
+CPU oracle on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "events/s at PU200, batched vs per-event; fit fwd+bwd tracks/s vs HBM roofline"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def caps(n_hits, n_events):
+    cells = 128 * n_hits
+    return dict(n_hits=n_hits, n_events=n_events, cells_cap=cells, links_cap=cells // 4, tuplets_cap=n_hits)
+
+
+def chain_workload(args):
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from synth import config as C
+    from synth import events as E
+
+    cfg_d = C.default_config()
+    t0 = time.time()
+    h = E.config5(n_events=args.events)
+    off_np = E.module_offsets()
+    log(f"generated {h.n_events} events, {h.n_hits} hits in {time.time() - t0:.1f}s")
+    cfg = A.make_config(cfg_d, n_phi_bins=args.bins)
+    cp = caps(h.n_hits, h.n_events)
+    hits = api.Hits.from_host(h)
+    offsets = torch.from_numpy(off_np).cuda()
+    cells = api.Cells.empty(cp["cells_cap"], h.n_hits)
+    links = api.Links.empty(cp["links_cap"], cp["cells_cap"])
+    tup = api.Tuplets.empty(cp["tuplets_cap"])
+    tracks = api.Tracks.empty(cp["tuplets_cap"], A.PT_FIT_F32_F64SOLVE)
+    status = api.new_status()
+    gp_np, gc_np = E.cotangents(5, cp["tuplets_cap"])
+    g_params = torch.from_numpy(gp_np).cuda()
+    g_chi2 = torch.from_numpy(gc_np).cuda()
+    grad_hits = torch.zeros((h.n_hits, 3), dtype=torch.float32, device="cuda")
+    grad_off = torch.zeros((C.N_MODULES, 3), dtype=torch.float64, device="cuda")
+    plan = api.Plan(cfg, precision=A.PT_FIT_F32_F64SOLVE, with_adjoint=True, **cp)
+
+    def step():
+        plan.run(hits, cells, links, tup, tracks, status, offsets=offsets, g_params=g_params, g_chi2=g_chi2,
+                 grad_hits=grad_hits, grad_offsets=grad_off)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    flags = int(status[A.PT_ST_FLAGS].item()) & 0xFFFFFFFF
+    if flags & (A.PT_FLAG_CELLS_OVERFLOW | A.PT_FLAG_LINKS_OVERFLOW | A.PT_FLAG_TUPLETS_OVERFLOW):
+        raise RuntimeError(f"capacity overflow (flags {flags:#x}); raise the capacities")
+    n_cells = int(cells.count.item())
+    n_links = int(links.count.item())
+    n_raw = int(tup.count_raw.item())
+    n_trk = int(tup.count.item())
+    log(f"per batch: {n_cells} doublets, {n_links} links, {n_raw} n-tuplets, {n_trk} tracks")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / args.steps
+    log(f"batched (graph): {t_batched * 1e3:.3f} ms per step")
+    # the graph must keep producing the eager results
+    if int(cells.count.item()) != n_cells or int(tup.count.item()) != n_trk:
+        raise RuntimeError("graph replay changed the products")
+
+    # per-event form: the same calls event by event, no graph
+    ev_hits = []
+    for e in range(h.n_events):
+        a, b = int(h.event_offsets[e]), int(h.event_offsets[e + 1])
+        ev_hits.append(api.Hits(hits.x[a:b], hits.y[a:b], hits.z[a:b], hits.layer[a:b], hits.module[a:b],
+                                torch.tensor([0, b - a], dtype=torch.int32, device="cuda")))
+    max_ev = max(x.n_hits for x in ev_hits)
+    cpe = caps(max_ev, 1)
+    pipe = api.Pipeline(cfg_d, precision=A.PT_FIT_F32_F64SOLVE, n_phi_bins=args.bins, **cpe)
+    gh_e = torch.zeros((max_ev, 3), dtype=torch.float32, device="cuda")
+
+    def per_event_pass():
+        for eh in ev_hits:
+            pipe.reconstruct(eh, offsets=offsets)
+            pipe.backward(eh, g_params[: pipe.tuplets.cap], g_chi2[: pipe.tuplets.cap], gh_e[: eh.n_hits], grad_off,
+                          offsets=offsets)
+
+    per_event_pass()
+    torch.cuda.synchronize()
+    pe_steps = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(pe_steps):
+        per_event_pass()
+    torch.cuda.synchronize()
+    t_per_event = (time.perf_counter() - t0) / pe_steps
+    log(f"per-event: {t_per_event * 1e3:.3f} ms per pass")
+
+    # kernel durations (HIP events on the call stream), eager calls of the same step
+    api.timing_reset()
+    api.timing_enable(True)
+    pipe_b = api.Pipeline(cfg_d, precision=A.PT_FIT_F32_F64SOLVE, n_phi_bins=args.bins, **cp)
+    kt_steps = max(3, args.steps // 2)
+    for _ in range(kt_steps):
+        pipe_b.reconstruct(hits, offsets=offsets)
+        pipe_b.backward(hits, g_params, g_chi2, grad_hits, grad_off, offsets=offsets)
+    torch.cuda.synchronize()
+    api.timing_enable(False)
+    kern = {}
+    for name in ("doublets_count", "doublets_write", "links", "dfs", "fit_fwd", "fit_bwd"):
+        ms, n = api.timing_read(name)
+        if n:
+            kern[name] = ms / n
+    api.timing_reset()
+    # link candidates examined (for the link kernel's work accounting)
+    ci, co, _ = pipe_b.cells.valid()
+    n_cand = int(pipe_b.cells.inner_count[co.long()].sum().item())
+    counts = dict(hits=h.n_hits, doublets=n_cells, links=n_links, ntuplets=n_raw, tracks=n_trk,
+                  link_candidates=n_cand)
+    return dict(t_batched=t_batched, t_per_event=t_per_event, kernels_ms=kern, counts=counts, n_events=h.n_events,
+                hits_np=h, cfg_d=cfg_d)
+
+
+def fit_workload(args):
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from synth import config as C
+    from synth import events as E
+
+    t0 = time.time()
+    ts = E.config4(n_tracks=args.fit_tracks)
+    log(f"generated {len(ts.nhits)} tracks in {time.time() - t0:.1f}s")
+    cfg = A.make_config(C.default_config())
+    hits = api.Hits.from_host(ts.hits)
+    n = len(ts.nhits)
+    tup = api.Tuplets.from_rows(torch.from_numpy(ts.tuplets).cuda(), torch.from_numpy(ts.nhits).cuda())
+    tracks = api.Tracks.empty(n, A.PT_FIT_F32_F64SOLVE)
+    status = api.new_status()
+    ws = api.new_workspace(api.workspace_size(cfg, ts.hits.n_hits, 1, 0, 0, n))
+    off = torch.from_numpy(E.module_offsets()).cuda()
+    gp, gc = (torch.from_numpy(a).cuda() for a in E.cotangents(4, n))
+    gh = torch.zeros((ts.hits.n_hits, 3), dtype=torch.float32, device="cuda")
+    go = torch.zeros((C.N_MODULES, 3), dtype=torch.float64, device="cuda")
+
+    def step():
+        api.fit_broken_line(hits, cfg, tup, off, A.PT_FIT_F32_F64SOLVE, tracks, status, ws)
+        api.fit_broken_line_bwd(hits, cfg, tup, off, A.PT_FIT_F32_F64SOLVE, gp, gc, gh, go, status, ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    steps = max(args.steps, 5)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / steps
+    api.timing_reset()
+    api.timing_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    api.timing_enable(False)
+    fwd_ms, nf = api.timing_read("fit_fwd")
+    bwd_ms, nb = api.timing_read("fit_bwd")
+    api.timing_reset()
+    nh = ts.nhits.astype(np.int64)
+    n_f64 = int(status[A.PT_ST_FIT_F64].item())
+    return dict(t_step=t_step, fwd_ms=fwd_ms / max(nf, 1), bwd_ms=bwd_ms / max(nb, 1), n_tracks=n,
+                n_hits_total=int(nh.sum()), mean_n=float(nh.mean()), nhits=nh, f64_refits=n_f64 // (2 * (steps * 2 + args.warmup)) if False else None)
+
+
+def cpu_baseline(args, chain):
+    """The oracle as it stands, single-threaded, on whole events of the same batch."""
+    import oracle as O
+    from synth import events as E
+
+    h = chain["hits_np"]
+    cfg_d = chain["cfg_d"]
+    off = E.module_offsets()
+    budget = args.cpu_seconds
+    t0 = time.perf_counter()
+    done = 0
+    tracks = 0
+    while done < h.n_events:
+        ev = h.event(done)
+        r = O.reconstruct_event(cfg_d, ev.x, ev.y, ev.z, ev.layer)
+        p, c2, st = O.fit(cfg_d, r["hits"], r["n"], ev.x, ev.y, ev.z, ev.layer, ev.module, off)
+        gp, gc = E.cotangents(5, len(r["n"]))
+        O.fit_grad(cfg_d, r["hits"], r["n"], ev.x, ev.y, ev.z, ev.layer, ev.module, off, gp, gc)
+        done += 1
+        tracks += len(r["n"])
+        if time.perf_counter() - t0 > budget:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="events/s", cores=1, kind="oracle",
+                sample=f"{done} of the {h.n_events} pileup-200 events, whole path (doublets by brute force, links, "
+                       f"n-tuplets, dedup, fit, dual-number gradient of {tracks} tracks), {dt:.1f} s, 1 thread")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--events", type=int, default=64)
+    ap.add_argument("--fit-tracks", type=int, default=1_000_000)
+    ap.add_argument("--bins", type=int, default=0, help="azimuth bins per layer (0: tuned default)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); events shard across GPUs with no "
+              "communication, so run one process per GPU.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_2008_13461_amd import _abi as A
+
+    A.load()
+    chain = chain_workload(args)
+    fit = fit_workload(args)
+
+    n_ev = chain["n_events"]
+    value = n_ev / chain["t_batched"]
+    per_event = n_ev / chain["t_per_event"]
+    kern = chain["kernels_ms"]
+    cnt = chain["counts"]
+    dominant = max(kern, key=kern.get) if kern else None
+
+    # fit roofline: algorithmic bytes per track (float hits): forward 19n+26, adjoint 31n+25
+    nh = fit["nhits"]
+    fwd_bytes = float((19 * nh + 26).sum())
+    bwd_bytes = float((31 * nh + 25).sum())
+    fit_ms = fit["fwd_ms"] + fit["bwd_ms"]
+    fit_gbs = (fwd_bytes + bwd_bytes) / (fit_ms * 1e-3) / 1e9
+    fit_obj = {
+        "workload": f"{fit['n_tracks']} tracks (50% 4-hit, 30% 5-hit, 20% 6-hit), module offsets, f32 with f64 refit",
+        "tracks_per_s": fit["n_tracks"] / fit["t_step"],
+        "ms_fwd_bwd_step": fit["t_step"] * 1e3,
+        "kernel_ms": {"fit_fwd": fit["fwd_ms"], "fit_bwd": fit["bwd_ms"]},
+        "roofline": {"bound": "hbm", "achieved": fit_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": fit_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_track": (fwd_bytes + bwd_bytes) / fit["n_tracks"]},
+    }
+
+    # roofline of the dominant kernel of the step
+    roof = None
+    if dominant in ("fit_fwd", "fit_bwd"):
+        pass
+    if dominant == "links":
+        # R-Z test of every candidate (c', c): 15 double operations, the circle test for the few that pass
+        flops = 15.0 * cnt["link_candidates"]
+        achieved = flops / (kern["links"] * 1e-3) / 1e12
+        roof = {"kernel": "k_links", "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                "note": "fp64 operations of the R-Z test per candidate pair x candidates / kernel time"}
+    elif dominant in ("doublets_count", "doublets_write"):
+        byts = 32.0 * cnt["hits"] + (9.0 * cnt["doublets"] if dominant == "doublets_write" else 0.0)
+        achieved = byts / (kern[dominant] * 1e-3) / 1e9
+        roof = {"kernel": "k_doublets", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    elif dominant is not None:
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None, "traffic": None}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": chain["t_batched"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 predicates, f32 fit (f64 refit of stiff tracks)",
+        "data": "synthetic",
+        "config": {"workload": f"{n_ev} events at pileup 200 (200 vertices x Poisson(35) tracks, 15% noise), "
+                               "full path with fit adjoint, one hipGraph per step",
+                   "events": n_ev, "hits": cnt["hits"], "parallelism": "single GPU"},
+        "per_event_events_per_s": per_event,
+        "batched_over_per_event": value / per_event,
+        "tracks_per_s": cnt["tracks"] / chain["t_batched"],
+        "counts_per_batch": cnt,
+        "kernel_ms": kern,
+        "roofline": roof,
+        "fit": fit_obj,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, chain)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

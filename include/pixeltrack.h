@@ -1,0 +1,342 @@
+/*
+ * pixeltrack.h -- C interface of the MI355X pixel-track library.
+ *
+ * The library reconstructs pixel tracks from hits with the method of Bocci,
+ * Kortelainen, Innocente, Pantaleo and Rovere, "Heterogeneous reconstruction
+ * of tracks and primary vertices with the CMS pixel tracker": doublets
+ * between hits of chosen layer pairs, Cellular Automaton links between
+ * doublets, n-tuplets by depth-first search with duplicate removal
+ * (section 3.2, section 3.3) and the broken-line fit of each n-tuplet
+ * (section 3.4), plus the gradient of that fit with respect to hit positions
+ * and per-module alignment translations.
+ *
+ * Conventions shared by every call
+ *  - Memory: every array pointer is a DEVICE pointer owned by the caller;
+ *    struct arguments themselves (pt_hits, pt_config, ...) live in HOST
+ *    memory and are read before the call returns.  No call allocates or frees
+ *    memory.  Scratch space comes from the caller's pt_workspace.
+ *  - Streams: every call enqueues its kernels on `stream` (a hipStream_t,
+ *    NULL = the null stream) and returns without synchronising.  Outputs are
+ *    valid once the stream has reached the end of the call.  Calls are
+ *    re-entrant on distinct streams with distinct workspaces.  The plain
+ *    calls do not use hipMemsetAsync, so they may be captured in a graph.
+ *  - Errors: argument errors return PT_ERR_ARG synchronously and enqueue
+ *    nothing.  A failed kernel launch returns PT_ERR_DEVICE.  Conditions that
+ *    are only known on the device (capacity overflow, non-finite hits, layer
+ *    ids out of range, truncated searches, fit failures) set bits and
+ *    counters in the caller's pt_status block; outputs are then truncated
+ *    but valid.  The status block is only ever OR-ed / added into: clear it
+ *    when you want a fresh reading.
+ *  - Indices: hit indices are int32 positions in the hit arrays as passed.
+ *    Cell, link and n-tuplet indices are positions in their output arrays.
+ *  - Units: cm, GeV, tesla, radians.  kappa > 0 turns counter-clockwise seen
+ *    from +z (a negative particle in a field along +z).
+ *  - Order: doublets, links and n-tuplets come out in no particular order
+ *    (they are sets); the fit writes track i for kept n-tuplet i.
+ */
+#ifndef PIXELTRACK_H
+#define PIXELTRACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* pt_stream; /* same type as hipStream_t */
+
+typedef enum {
+  PT_OK = 0,
+  PT_ERR_ARG = 1,         /* invalid argument; nothing was enqueued */
+  PT_ERR_DEVICE = 2,      /* a HIP runtime call or kernel launch failed */
+  PT_ERR_UNSUPPORTED = 3, /* valid request that this build does not implement */
+  PT_ERR_WORKSPACE = 4    /* workspace smaller than pt_workspace_size() */
+} pt_err;
+
+enum { PT_F32 = 0, PT_F64 = 1 };
+
+/* Fit precision.
+ *  PT_FIT_F64           all arithmetic in double; params/chi2 are double.
+ *  PT_FIT_F32           single-precision fit; params/chi2 are float.  Sums and
+ *                       differences of absolute coordinates (hit + offset,
+ *                       positions relative to the first hit, their local frame
+ *                       coordinates) and the final perigee conversion are
+ *                       formed in double, where single precision would cancel.
+ *  PT_FIT_F32_F64SOLVE  as PT_FIT_F32, but the two broken-line band solves of a
+ *                       track are done in double when its conditioning
+ *                       estimate exceeds pt_config.f64_solve_threshold. */
+enum { PT_FIT_F64 = 0, PT_FIT_F32 = 1, PT_FIT_F32_F64SOLVE = 2 };
+
+/* Doublet cuts of Table 1 (bits of pt_config.cut_mask). */
+enum { PT_CUT_PHIW = 1, PT_CUT_ZW = 2, PT_CUT_ZIP = 4, PT_CUT_PT = 8 };
+
+#define PT_MAX_PAIRS 32
+#define PT_N_LAYERS 10
+#define PT_MAX_HITS 8 /* longest n-tuplet; rows of pt_ntuplets.hits */
+
+/* Status block: PT_STATUS_WORDS uint32 words of device memory. */
+#define PT_STATUS_WORDS 16
+enum {
+  PT_ST_FLAGS = 0,          /* OR of PT_FLAG_* */
+  PT_ST_BAD_HITS = 1,       /* hits skipped: non-finite coordinate or layer >= 10 */
+  PT_ST_TRUNCATED = 2,      /* searches that reached max_hits with links left */
+  PT_ST_FIT_BAD_ORDER = 3,  /* tracks whose hits are not ordered along the pre-fit */
+  PT_ST_FIT_F64 = 4,        /* tracks whose solve was routed to double */
+  PT_ST_FIT_FAILED = 5      /* tracks with a non-finite result */
+};
+enum {
+  PT_FLAG_CELLS_OVERFLOW = 1u << 0,
+  PT_FLAG_LINKS_OVERFLOW = 1u << 1,
+  PT_FLAG_TUPLETS_OVERFLOW = 1u << 2,
+  PT_FLAG_BAD_HITS = 1u << 3,
+  PT_FLAG_TRUNCATED = 1u << 4,
+  PT_FLAG_FIT_BAD_ORDER = 1u << 5,
+  PT_FLAG_FIT_FAILED = 1u << 6
+};
+/* Per-track fit status bits (pt_tracks.status). */
+enum { PT_FIT_OK = 0, PT_FIT_ST_BAD_ORDER = 1, PT_FIT_ST_F64_SOLVE = 2, PT_FIT_ST_FAILED = 4 };
+
+/* Reconstruction settings (host struct).  The library derives its cut
+ * constants from these fields on the host with these expressions, evaluated
+ * in double in this order:
+ *   tan_dphi[p] = tan(pair_dphi[p])                 (C library tan)
+ *   kappa_max   = (0.299792458 * bfield) / (100.0 * pt_min),  kappa_max2 = kappa_max * kappa_max
+ *   theta2_*    = ca_theta_* * ca_theta_*
+ * so that another implementation following the same expressions makes
+ * bit-identical decisions. */
+typedef struct {
+  double bfield;                      /* T, along +z */
+  int32_t n_pairs;                    /* 1..PT_MAX_PAIRS */
+  uint8_t pair_inner[PT_MAX_PAIRS];   /* layer of the inner hit of pair p */
+  uint8_t pair_outer[PT_MAX_PAIRS];   /* layer of the outer hit; inner != outer */
+  double pair_dphi[PT_MAX_PAIRS];     /* PhiW window (rad), in (0, pi/2) */
+  double pair_zlo[PT_MAX_PAIRS];      /* ZW window on the inner hit's z (cm) */
+  double pair_zhi[PT_MAX_PAIRS];
+  double pt_min;                      /* PT cut (GeV) > 0 */
+  double z0_max;                      /* ZIP cut (cm) */
+  uint32_t cut_mask;                  /* PT_CUT_* applied */
+  double ca_theta_barrel;             /* triplet R-Z kink sine, outer hit on barrel */
+  double ca_theta_endcap;             /* same, outer hit on a disk */
+  double ca_rmax_bpix1;               /* circle-to-beam distance (cm), inner hit on layer 0 */
+  double ca_rmax_other;               /* same, other inner layers */
+  uint32_t root_always_mask;          /* layers whose doublets always start a search */
+  uint32_t root_if_free_mask;         /* layers whose doublets start one without inner link */
+  int32_t min_hits;                   /* shortest n-tuplet emitted, >= 3 */
+  int32_t max_hits;                   /* longest, <= PT_MAX_HITS */
+  uint8_t layer_barrel[PT_N_LAYERS];  /* 1 = barrel layer, 0 = disk */
+  double x_over_x0;                   /* material per layer crossing (radiation lengths) */
+  double highland_a;                  /* 0.0136 GeV */
+  double highland_b;                  /* 0.038 */
+  double sigma_rphi;                  /* transverse hit resolution (cm) */
+  double sigma_z;                     /* barrel longitudinal resolution (cm) */
+  double sigma_r;                     /* disk radial resolution (cm) */
+  double p_cap;                       /* momentum cap of the scattering estimate (GeV) */
+  int32_t n_modules;                  /* rows of the module offset / gradient tables */
+  /* performance settings: never change a result */
+  int32_t n_phi_bins;                 /* azimuth bins per layer for the pair search; 0 = 128 */
+  int32_t block_doublets;             /* threads per block of the doublet kernel; 0 = 256 */
+  int32_t block_links;                /* threads per block of the link kernel; 0 = 256 */
+  double f64_solve_threshold;         /* see PT_FIT_F32_F64SOLVE; <= 0 means 1024 */
+} pt_config;
+
+/* Hits of n_events events.  Event e owns hits [event_offsets[e], event_offsets[e+1]). */
+typedef struct {
+  int32_t n_hits;                 /* length of every hit array, >= 0 */
+  int32_t n_events;               /* >= 0 */
+  const int32_t* event_offsets;   /* device [n_events + 1], nondecreasing, within [0, n_hits] */
+  int32_t dtype;                  /* PT_F32 or PT_F64: element type of x, y, z */
+  const void* x;                  /* device [n_hits] */
+  const void* y;
+  const void* z;
+  const uint8_t* layer;           /* device [n_hits], 0..9 (others are skipped and counted) */
+  const int16_t* module;          /* device [n_hits], 0..n_modules-1; used by the fit when
+                                     module offsets or their gradient are requested */
+} pt_hits;
+
+/* Caller-owned scratch memory (device), at least pt_workspace_size() bytes, 256-byte aligned. */
+typedef struct {
+  void* ptr;
+  size_t bytes;
+} pt_workspace;
+
+/* Doublets ("cells").  count[0] receives the number found, which may exceed
+ * cap; only min(count, cap) entries are written (PT_FLAG_CELLS_OVERFLOW set).
+ * The cells whose inner hit is h are [inner_first[h], inner_first[h] +
+ * inner_count[h]) (clipped to cap): pt_build_doublets writes them grouped by
+ * inner hit, and pt_link_cells relies on this index. */
+typedef struct {
+  int32_t cap;
+  int32_t* inner;       /* [cap] inner hit index */
+  int32_t* outer;       /* [cap] outer hit index */
+  uint8_t* pair;        /* [cap] layer-pair index */
+  int32_t* count;       /* [1] */
+  int32_t* inner_first; /* [n_hits] */
+  int32_t* inner_count; /* [n_hits] */
+} pt_cells;
+
+/* Cell links c_in -> c_out: c_out starts on the outer hit of c_in.  The links
+ * of one inner cell are contiguous: cell c's outer links are out_cell[j] for
+ * j in [out_start[c], out_start[c] + out_count[c]) (clipped to cap; out_start
+ * is only meaningful when out_count > 0).  has_inner[c] = 1 when some link
+ * ends on c.  The per-cell arrays hold the cells' capacity. */
+typedef struct {
+  int32_t cap;
+  int32_t* in_cell;   /* [cap] */
+  int32_t* out_cell;  /* [cap] */
+  int32_t* count;     /* [1] links found (may exceed cap) */
+  int32_t* out_start; /* [cells.cap] */
+  int32_t* out_count; /* [cells.cap] */
+  uint8_t* has_inner; /* [cells.cap] */
+} pt_links;
+
+/* n-tuplets.  Rows hold every maximal path found by the search; `kept` lists
+ * the rows that survive duplicate removal. */
+typedef struct {
+  int32_t cap;
+  int32_t* hits;       /* [cap][PT_MAX_HITS] hit indices inside -> out, -1 padded */
+  int32_t* cells;      /* [cap][PT_MAX_HITS-1] cell indices, -1 padded */
+  uint8_t* n;          /* [cap] number of hits */
+  int32_t* count_raw;  /* [1] paths found (may exceed cap) */
+  int32_t* kept;       /* [cap] rows kept by duplicate removal */
+  int32_t* count;      /* [1] number of kept rows */
+} pt_ntuplets;
+
+/* Fitted tracks, one per kept n-tuplet (or per row, see pt_fit_broken_line). */
+typedef struct {
+  int32_t cap;
+  void* params;       /* [cap][5] (kappa, phi0, cot(theta), d0, z0): double for
+                         PT_FIT_F64, float otherwise */
+  void* chi2;         /* [cap] same type */
+  uint8_t* status;    /* [cap] PT_FIT_ST_* bits */
+} pt_tracks;
+
+/* Version of this interface (the value of PT_ABI_VERSION). */
+#define PT_ABI_VERSION 1
+int32_t pt_abi_version(void);
+const char* pt_err_string(pt_err e);
+
+/* Bytes of workspace the calls below need for these sizes.  0 on invalid arguments. */
+size_t pt_workspace_size(const pt_config* cfg, int32_t n_hits, int32_t n_events,
+                         int32_t cells_cap, int32_t links_cap, int32_t tuplets_cap);
+
+/* Doublet building (section 3.2, Table 1).
+ * For every layer pair p, every hit o on its outer layer and every hit i on
+ * its inner layer of the same event, the doublet (i, o, p) is emitted when:
+ *   PhiW  D = Xi Xo + Yi Yo > 0 and |C| <= tan_dphi[p] D, C = Xi Yo - Yi Xo
+ *   ZW    pair_zlo[p] <= Zi <= pair_zhi[p]
+ *   ZIP   Ro - Ri > 0 and |Zi Ro - Zo Ri| <= z0_max (Ro - Ri)
+ *   PT    (4 C) C <= (kappa_max2 (R2i R2o)) L2, L2 = |P_o - P_i|^2
+ * for the cuts in cut_mask, with X, Y, Z the hit coordinates in double,
+ * R2 = X X + Y Y and R = sqrt(R2), evaluated exactly as parenthesised
+ * without contraction.  Candidate inner hits come from azimuth bins around
+ * the outer hit (the binned window of Table 1), widened by one bin so that the
+ * result equals the all-pairs definition.
+ * Requires a workspace of pt_workspace_size(cfg, hits->n_hits, hits->n_events, ...). */
+pt_err pt_build_doublets(const pt_hits* hits, const pt_config* cfg, pt_cells* cells,
+                         uint32_t* status, pt_workspace ws, pt_stream stream);
+
+/* Cell linking (section 3.2: doublets sharing a hit tested for a triplet).
+ * For c' = (h0, h1) and c = (h1, h2), the link c' -> c is made when
+ *   R-Z   A A <= theta2 ((ar ar + az az) (br br + bz bz)),
+ *         ar = R1 - R0, az = Z1 - Z0, br = R2 - R1, bz = Z2 - Z1, A = ar bz - az br,
+ *         theta2 from the barrel value when h2 is on a barrel layer, else the end-cap value;
+ *   beam  with u = P1 - P0, v = P2 - P0 (x, y) and Dd = 2 (ux vy - uy vx):
+ *         Dd == 0: (X0 vy - Y0 vx)^2 <= rmax^2 (vx^2 + vy^2);
+ *         else cx = (U2 vy - V2 uy) / Dd, cy = (V2 ux - U2 vx) / Dd, U2 = |u|^2,
+ *         V2 = |v|^2, rho2 = cx^2 + cy^2, c2 = (X0 + cx)^2 + (Y0 + cy)^2 and
+ *         |sqrt(c2) - sqrt(rho2)| <= rmax,
+ *         rmax the BPix1 value when h0 is on layer 0, else the other value;
+ * in double, as parenthesised, without contraction.  cells must be the
+ * output of pt_build_doublets for the same hits (only min(count, cap) used). */
+pt_err pt_link_cells(const pt_hits* hits, const pt_config* cfg, const pt_cells* cells,
+                     pt_links* links, uint32_t* status, pt_workspace ws, pt_stream stream);
+
+/* n-tuplet search and duplicate removal (section 3.2, section 3.3).
+ * Root cells: inner hit on a layer of root_always_mask, or of
+ * root_if_free_mask with has_inner == 0.  From every root a depth-first
+ * search follows outer links; a path is emitted when its last cell has no
+ * outer link or it has max_hits hits (then PT_ST_TRUNCATED counts it), and
+ * it has at least min_hits hits.  A row is kept unless one of its cells
+ * belongs to a row with more hits. */
+pt_err pt_find_ntuplets(const pt_hits* hits, const pt_config* cfg, const pt_cells* cells,
+                        const pt_links* links, pt_ntuplets* tuplets, uint32_t* status,
+                        pt_workspace ws, pt_stream stream);
+
+/* Broken-line fit (section 3.4), one GPU thread per track.
+ * Tracks are the kept rows of `tuplets` (tuplets->kept != NULL: track i is row
+ * kept[i], i < count[0]) or, with kept == NULL, rows 0..count[0]-1.  The
+ * number of tracks is read on the device; at most min(tuplets->cap, tracks->cap)
+ * are fitted.  Hit k of a track is P_k = hit + module_offsets[module] when
+ * module_offsets (device float [n_modules][3]) is not NULL.
+ * Steps: a circle through hits 0, n/2 and n-1 (pre-fit); arc lengths s_k and
+ * left offsets u_k of every hit along it; slope t and momentum
+ * p = min(p_T sqrt(1+t^2), p_cap); Highland scattering at the inner hits with
+ * material x_over_x0 times the path length (1/sin(theta) barrel,
+ * 1/|cos(theta)| disks), kink variances theta0^2 (1+t^2) transverse and
+ * theta0^2 (1+t^2)^2 in S-Z; measurement variances sigma_rphi^2 and
+ * sigma_z^2 (barrel) or (sigma_r t)^2 (disks); the circle broken-line solve
+ * for offsets and the curvature correction, the S-Z broken-line solve; the
+ * perigee (kappa, phi0, cot(theta), d0, z0) with respect to the origin and
+ * chi2 = circle + line chi^2 at the optimum (2n - 5 degrees of freedom).
+ * Hits must be ordered along the track; tracks that are not get NaN
+ * parameters and PT_FIT_ST_BAD_ORDER. */
+pt_err pt_fit_broken_line(const pt_hits* hits, const pt_config* cfg, const pt_ntuplets* tuplets,
+                          const float* module_offsets, int32_t precision, pt_tracks* tracks,
+                          uint32_t* status, pt_workspace ws, pt_stream stream);
+
+/* Adjoint of pt_fit_broken_line (same tracks, same precision).  With the
+ * upstream gradients g_params (device float [cap][5]) and g_chi2 (device
+ * float [cap], may be NULL), adds
+ *   grad_hits[h]    += sum over tracks t containing h of J_t(h)^T (g_params[t], g_chi2[t])
+ *   grad_offsets[m] += sum over hits h on module m of the same
+ * where J_t(h) = d(kappa, phi0, cot, d0, z0, chi2)_t / d(x, y, z)_h of the
+ * whole fit, including its dependence through the pre-fit and the scattering
+ * weights.  The forward fit is recomputed, not stored.  grad_hits is device
+ * float [n_hits][3] (may be NULL), grad_offsets device double [n_modules][3]
+ * (may be NULL); both are accumulated into.  Tracks whose fit fails add
+ * nothing. */
+pt_err pt_fit_broken_line_bwd(const pt_hits* hits, const pt_config* cfg,
+                              const pt_ntuplets* tuplets, const float* module_offsets,
+                              int32_t precision, const float* g_params, const float* g_chi2,
+                              float* grad_hits, double* grad_offsets, uint32_t* status,
+                              pt_workspace ws, pt_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Batched plans: one hipGraph per step.
+ *
+ * A plan runs the whole path -- pt_build_doublets, pt_link_cells,
+ * pt_find_ntuplets, pt_fit_broken_line and, when created with_adjoint,
+ * pt_fit_broken_line_bwd -- over all events of a batch as one graph launch.
+ * pt_plan_create allocates the plan's workspace (this and pt_plan_destroy are
+ * the only calls that allocate or free device memory) and a private,
+ * default-priority capture stream.  The first pt_plan_run, and every run whose
+ * arguments (pointers, sizes, capacities) differ from the captured ones,
+ * records the step into a graph; every run then launches the graph on
+ * `stream`.  Arguments have the meaning of the individual calls; g_params is
+ * required when with_adjoint is set.  A plan is not thread-safe.  Sizes above
+ * the ones given at creation return PT_ERR_ARG. */
+typedef struct pt_plan_s* pt_plan;
+pt_err pt_plan_create(const pt_config* cfg, int32_t n_hits_max, int32_t n_events_max, int32_t cells_cap,
+                      int32_t links_cap, int32_t tuplets_cap, int32_t precision, int32_t with_adjoint,
+                      pt_plan* plan);
+pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links* links, pt_ntuplets* tuplets,
+                   pt_tracks* tracks, const float* module_offsets, const float* g_params, const float* g_chi2,
+                   float* grad_hits, double* grad_offsets, uint32_t* status, pt_stream stream);
+void pt_plan_destroy(pt_plan plan);
+
+/* Kernel timing (instrumentation).  While enabled, the individual calls (not
+ * graph launches) record a pair of HIP events around their main kernels on
+ * their stream: "doublets_count", "doublets_write", "links", "dfs",
+ * "fit_fwd", "fit_bwd".  pt_timing_read waits for the recorded events and
+ * returns the summed milliseconds and the number of launches since the last
+ * reset (PT_ERR_ARG when the name has no record). */
+void pt_timing_enable(int32_t on);
+void pt_timing_reset(void);
+int32_t pt_timing_read(const char* kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIXELTRACK_H */

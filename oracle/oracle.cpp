@@ -1,10 +1,12 @@
 // CPU oracle of the pixel-track hot path.  TEST INFRASTRUCTURE ONLY.
 //
-// Plain, slow, double precision.  It exists so that tests, the smoke check and
-// the CPU baseline of the benchmark have something obviously correct to compare
-// the GPU library with.  It shares no code with the GPU library and is never
-// called by it.  Built with -ffp-contract=off so that every predicate below is
-// evaluated exactly as parenthesised.
+// Plain and slow: predicates in double precision (the GPU library must
+// reproduce them bit for bit), the fit in extended precision.  It exists so
+// that tests, the smoke check and the CPU baseline of the benchmark have
+// something obviously correct to compare the GPU library with.  It shares no
+// code with the GPU library and is never called by it.  Built with
+// -ffp-contract=off so that every predicate below is evaluated exactly as
+// parenthesised.
 //
 // What it computes (Bocci et al., "Heterogeneous reconstruction of tracks and
 // primary vertices with the CMS pixel tracker"):
@@ -384,6 +386,7 @@ inline Dual log(Dual a) { return {std::log(a.v), a.d / a.v}; }
 inline Dual fabs(Dual a) { return a.v < 0 ? -a : a; }
 inline double val(Dual a) { return a.v; }
 inline double val(double a) { return a; }
+inline double val(long double a) { return static_cast<double>(a); }
 template <class T> inline T cst(double v) { return T(v); }
 template <> inline Dual cst<Dual>(double v) { return mk(v); }
 inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
@@ -396,6 +399,12 @@ using std::atan2;
 using std::fabs;
 using std::log;
 using std::sqrt;
+
+// The fit's values are evaluated in extended precision (x87 long double, 64-bit
+// significand): its plain centre-based pre-fit and dense elimination lose up
+// to ~2e-9 relative on the stiffest forward tracks in double, more than the
+// double-precision GPU path it checks.  Gradients use double dual numbers.
+using Real = long double;
 
 struct FitSettings {
   double K;             // 0.299792458 B / 100: p_T [GeV] = K / |kappa| [1/cm]
@@ -736,7 +745,13 @@ void oracle_fit(const oracle_config* cfg, int64_t n_tracks, const int32_t* tuple
   for (int64_t t = 0; t < n_tracks; ++t) {
     const int n = nhits[t];
     gather(n, tuplets + t * kMaxHits, x, y, z, layer, module, offsets, X, Y, Z, lay);
-    const FitResult<double> r = fit_track<double>(F, n, X, Y, Z, lay);
+    long double XL[kMaxHits], YL[kMaxHits], ZL[kMaxHits];
+    for (int k = 0; k < n; ++k) {
+      XL[k] = X[k];
+      YL[k] = Y[k];
+      ZL[k] = Z[k];
+    }
+    const FitResult<Real> r = fit_track<Real>(F, n, XL, YL, ZL, lay);
     status[t] = static_cast<uint8_t>(r.status);
     double* o = params + 5 * t;
     if (r.status != FIT_OK) {
@@ -744,12 +759,12 @@ void oracle_fit(const oracle_config* cfg, int64_t n_tracks, const int32_t* tuple
       chi2[t] = NAN;
       continue;
     }
-    o[0] = r.kappa;
-    o[1] = r.phi0;
-    o[2] = r.cot;
-    o[3] = r.d0;
-    o[4] = r.z0;
-    chi2[t] = r.chi2;
+    o[0] = static_cast<double>(r.kappa);
+    o[1] = static_cast<double>(r.phi0);
+    o[2] = static_cast<double>(r.cot);
+    o[3] = static_cast<double>(r.d0);
+    o[4] = static_cast<double>(r.z0);
+    chi2[t] = static_cast<double>(r.chi2);
   }
 }
 
@@ -764,9 +779,15 @@ int32_t oracle_fit_debug(const oracle_config* cfg, int32_t n, const double* X, c
   const FitSettings F = fit_settings(*cfg);
   int lay[kMaxHits];
   for (int k = 0; k < n; ++k) lay[k] = layer_k[k];
-  const FitResult<double> r = fit_track<double>(F, n, X, Y, Z, lay);
-  auto cp = [](const std::vector<double>& v, double* dst) {
-    std::copy(v.begin(), v.end(), dst);
+  long double XL[kMaxHits], YL[kMaxHits], ZL[kMaxHits];
+  for (int k = 0; k < n; ++k) {
+    XL[k] = X[k];
+    YL[k] = Y[k];
+    ZL[k] = Z[k];
+  }
+  const FitResult<Real> r = fit_track<Real>(F, n, XL, YL, ZL, lay);
+  auto cp = [](const std::vector<Real>& v, double* dst) {
+    for (size_t i = 0; i < v.size(); ++i) dst[i] = static_cast<double>(v[i]);
   };
   cp(r.s, s);
   cp(r.um, um);
@@ -781,15 +802,15 @@ int32_t oracle_fit_debug(const oracle_config* cfg, int32_t n, const double* X, c
     cp(r.b, b);
     cp(r.N, N);
     cp(r.q, q);
-    scal[0] = r.kappa_pre;
-    scal[1] = r.t_pre;
-    scal[2] = r.p;
-    params[0] = r.kappa;
-    params[1] = r.phi0;
-    params[2] = r.cot;
-    params[3] = r.d0;
-    params[4] = r.z0;
-    params[5] = r.chi2;
+    scal[0] = static_cast<double>(r.kappa_pre);
+    scal[1] = static_cast<double>(r.t_pre);
+    scal[2] = static_cast<double>(r.p);
+    params[0] = static_cast<double>(r.kappa);
+    params[1] = static_cast<double>(r.phi0);
+    params[2] = static_cast<double>(r.cot);
+    params[3] = static_cast<double>(r.d0);
+    params[4] = static_cast<double>(r.z0);
+    params[5] = static_cast<double>(r.chi2);
   }
   return r.status;
 }

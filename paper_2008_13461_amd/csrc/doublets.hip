@@ -1,0 +1,307 @@
+// Doublet building (paper section 3.2, Table 1).
+//
+// Hits are first binned per (event, layer, azimuth bin) by a counting sort
+// (the "tiled data structure along phi" of the paper), with the sorted
+// coordinates promoted to double.  Doublets are then built by one thread per
+// inner hit that loops over the layer pairs starting on its layer and scans
+// the outer hits in the azimuth bins around it.  Two passes -- count, scan,
+// write -- give every inner hit a contiguous, deterministic run of cells
+// without any per-cell atomic: the cells come out grouped by inner hit in the
+// sorted order, and (inner_first, inner_count) index them by hit for the
+// linking step.
+#include "pt_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+// Every decision below is made in double precision exactly as parenthesised:
+// no multiply-add contraction anywhere in this file.
+#pragma clang fp contract(off)
+
+namespace pt {
+
+// The cut predicates of Table 1, as documented in pixeltrack.h.
+__device__ __forceinline__ bool doublet_pass(const DevCfg& k, int p, double Xi, double Yi, double Zi,
+                                             double Ri, double Xo, double Yo, double Zo, double Ro) {
+  const double D = Xi * Xo + Yi * Yo;
+  const double C = Xi * Yo - Yi * Xo;
+  if (k.cut_mask & PT_CUT_PHIW) {
+    if (!(D > 0.0 && fabs(C) <= k.tan_dphi[p] * D)) return false;
+  }
+  if (k.cut_mask & PT_CUT_ZIP) {
+    const double dR = Ro - Ri;
+    if (!(dR > 0.0 && fabs(Zi * Ro - Zo * Ri) <= k.z0_max * dR)) return false;
+  }
+  if (k.cut_mask & PT_CUT_PT) {
+    const double R2i = Xi * Xi + Yi * Yi;
+    const double R2o = Xo * Xo + Yo * Yo;
+    const double dx = Xo - Xi;
+    const double dy = Yo - Yi;
+    const double L2 = dx * dx + dy * dy;
+    if (!((4.0 * C) * C <= (k.kappa_max2 * (R2i * R2o)) * L2)) return false;
+  }
+  return true;
+}
+
+namespace {
+
+template <class T>
+struct HitsIn {
+  int32_t n_hits, n_events;
+  const int32_t* off;
+  const T* x;
+  const T* y;
+  const T* z;
+  const uint8_t* layer;
+};
+
+// Event of hit h: off[e] <= h < off[e+1]; -1 when h is in no event.
+__device__ inline int event_of(const int32_t* off, int n_events, int h) {
+  if (n_events <= 0 || h < off[0] || h >= off[n_events]) return -1;
+  int lo = 0, hi = n_events;  // invariant: off[lo] <= h < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= h) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <class T>
+__global__ void k_hit_keys(HitsIn<T> in, int n_bins, float bin_scale, int32_t* __restrict__ key,
+                           int32_t* __restrict__ rank, int32_t* __restrict__ bin_count,
+                           uint32_t* status) {
+  uint32_t bad = 0;
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < in.n_hits; h += gridDim.x * blockDim.x) {
+    key[h] = -1;
+    const int e = event_of(in.off, in.n_events, h);
+    if (e < 0) continue;
+    const int lay = in.layer[h];
+    const double X = static_cast<double>(in.x[h]);
+    const double Y = static_cast<double>(in.y[h]);
+    const double Z = static_cast<double>(in.z[h]);
+    if (lay >= kLayers || !isfinite(X) || !isfinite(Y) || !isfinite(Z)) {
+      ++bad;
+      continue;
+    }
+    const float phi = atan2f(static_cast<float>(Y), static_cast<float>(X));
+    int b = static_cast<int>((phi + 3.14159265358979f) * bin_scale);
+    b = b < 0 ? 0 : (b >= n_bins ? n_bins - 1 : b);
+    const int k = (e * kLayers + lay) * n_bins + b;
+    key[h] = k;
+    rank[h] = atomicAdd(bin_count + k, 1);
+  }
+  if (bad) {
+    status_add(status, PT_ST_BAD_HITS, bad);
+    status_flag(status, PT_FLAG_BAD_HITS);
+  }
+}
+
+template <class T>
+__global__ void k_scatter(HitsIn<T> in, const int32_t* __restrict__ key, const int32_t* __restrict__ rank,
+                          const int32_t* __restrict__ bin_start, int32_t* __restrict__ sorted_hit,
+                          int32_t* __restrict__ skey, double* __restrict__ sX, double* __restrict__ sY,
+                          double* __restrict__ sZ, double* __restrict__ sR, int32_t* __restrict__ inner_count) {
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < in.n_hits; h += gridDim.x * blockDim.x) {
+    inner_count[h] = 0;
+    const int k = key[h];
+    if (k < 0) continue;
+    const int pos = bin_start[k] + rank[h];
+    const double X = static_cast<double>(in.x[h]);
+    const double Y = static_cast<double>(in.y[h]);
+    sorted_hit[pos] = h;
+    skey[pos] = k;
+    sX[pos] = X;
+    sY[pos] = Y;
+    sZ[pos] = static_cast<double>(in.z[h]);
+    sR[pos] = sqrt(X * X + Y * Y);
+  }
+}
+
+struct DoubletArgs {
+  int32_t n_hits;
+  const int32_t* bin_start;
+  const int32_t* skey;
+  const int32_t* sorted_hit;
+  const double* sX;
+  const double* sY;
+  const double* sZ;
+  const double* sR;
+  int32_t* cnt;            // pass 1: per sorted inner hit
+  const int32_t* off;      // pass 2: scanned counts
+  int32_t cap;
+  int32_t* inner;
+  int32_t* outer;
+  uint8_t* pair;
+  int32_t* inner_first;
+  int32_t* inner_count;
+};
+
+// One thread per sorted inner hit: every pair starting on its layer, every
+// outer hit in the azimuth bins around it.
+template <bool WRITE>
+__global__ void __launch_bounds__(256) k_doublets(DevCfg k, DoubletArgs a) {
+  const int total = a.bin_start[-1];  // valid (sorted) hits
+  const int B = k.n_bins;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.n_hits; j += gridDim.x * blockDim.x) {
+    if (j >= total) {
+      if (!WRITE) a.cnt[j] = 0;
+      continue;
+    }
+    const int key = a.skey[j];
+    const int b = key % B;
+    const int el = key / B;
+    const int lay = el % kLayers;
+    const int e = el / kLayers;
+    const double Xi = a.sX[j], Yi = a.sY[j], Zi = a.sZ[j], Ri = a.sR[j];
+    int count = 0;
+    int wpos = WRITE ? a.off[j] : 0;
+    const int hit_i = WRITE ? a.sorted_hit[j] : 0;
+    const int np = k.n_inner_pairs[lay];
+    for (int s = 0; s < np; ++s) {
+      const int p = k.inner_pairs[lay][s];
+      if (k.cut_mask & PT_CUT_ZW) {
+        if (!(k.zlo[p] <= Zi && Zi <= k.zhi[p])) continue;
+      }
+      const int lo_layer = k.pair_outer[p];
+      const int base = (e * kLayers + lo_layer) * B;
+      const int w = k.pair_wbins[p];
+      int r0a, r0b, r1a = 0, r1b = 0;
+      if (2 * w + 1 >= B) {
+        r0a = a.bin_start[base];
+        r0b = a.bin_start[base + B];
+      } else {
+        int lo = b - w, hi = b + w;
+        if (lo < 0) {
+          r0a = a.bin_start[base + lo + B];
+          r0b = a.bin_start[base + B];
+          r1a = a.bin_start[base];
+          r1b = a.bin_start[base + hi + 1];
+        } else if (hi >= B) {
+          r0a = a.bin_start[base + lo];
+          r0b = a.bin_start[base + B];
+          r1a = a.bin_start[base];
+          r1b = a.bin_start[base + hi - B + 1];
+        } else {
+          r0a = a.bin_start[base + lo];
+          r0b = a.bin_start[base + hi + 1];
+        }
+      }
+#pragma unroll 1
+      for (int r = 0; r < 2; ++r) {
+        const int s0 = r == 0 ? r0a : r1a;
+        const int s1 = r == 0 ? r0b : r1b;
+        for (int o = s0; o < s1; ++o) {
+          if (doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o])) {
+            if (WRITE) {
+              if (wpos < a.cap) {
+                a.inner[wpos] = hit_i;
+                a.outer[wpos] = a.sorted_hit[o];
+                a.pair[wpos] = static_cast<uint8_t>(p);
+              }
+              ++wpos;
+            } else {
+              ++count;
+            }
+          }
+        }
+      }
+    }
+    if (!WRITE) {
+      a.cnt[j] = count;
+    } else {
+      const int first = a.off[j];
+      a.inner_first[hit_i] = first;
+      a.inner_count[hit_i] = a.off[j + 1] - first;
+    }
+  }
+}
+
+__global__ void k_finish_cells(const int32_t* total, int32_t cap, int32_t* count, uint32_t* status) {
+  const int t = *total;
+  *count = t;
+  if (t > cap) status_flag(status, PT_FLAG_CELLS_OVERFLOW);
+}
+
+// bin_start is laid out with one leading word that receives the number of
+// valid hits, so that kernels can read it as bin_start[-1].
+__global__ void k_copy_total(const int32_t* __restrict__ bin_start, int nb, int32_t* __restrict__ dst) {
+  *dst = bin_start[nb];
+}
+
+}  // namespace
+
+size_t ws_doublets(int n_hits, int n_events, int n_bins) {
+  const size_t nb = static_cast<size_t>(n_events) * kLayers * n_bins;
+  Carver c(nullptr);
+  c.take<int32_t>(n_hits);        // key
+  c.take<int32_t>(n_hits);        // rank
+  c.take<int32_t>(nb + 2);        // [total] + bin counts/starts (+ end)
+  c.take<int32_t>(n_hits);        // sorted_hit
+  c.take<int32_t>(n_hits);        // skey
+  c.take<double>(n_hits);         // sX
+  c.take<double>(n_hits);         // sY
+  c.take<double>(n_hits);         // sZ
+  c.take<double>(n_hits);         // sR
+  c.take<int32_t>(n_hits + 1);    // cnt / off
+  const size_t t = scan_tmp_elems(std::max<int64_t>(static_cast<int64_t>(nb), n_hits));
+  c.take<int32_t>(t);
+  return c.off + 256;
+}
+
+template <class T>
+static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, uint32_t* status,
+                           pt_workspace ws, hipStream_t s) {
+  const int n = h.n_hits;
+  const int B = k.n_bins;
+  const int64_t nb = static_cast<int64_t>(h.n_events) * kLayers * B;
+  Carver c(ws.ptr);
+  int32_t* key = c.take<int32_t>(n);
+  int32_t* rank = c.take<int32_t>(n);
+  int32_t* bins = c.take<int32_t>(nb + 2);   // bins[0] = valid hits; bins+1 = counts -> starts
+  int32_t* sorted_hit = c.take<int32_t>(n);
+  int32_t* skey = c.take<int32_t>(n);
+  double* sX = c.take<double>(n);
+  double* sY = c.take<double>(n);
+  double* sZ = c.take<double>(n);
+  double* sR = c.take<double>(n);
+  int32_t* cnt = c.take<int32_t>(n + 1);
+  int32_t* tmp = c.take<int32_t>(scan_tmp_elems(std::max<int64_t>(nb, n)));
+  int32_t* bin_start = bins + 1;
+
+  HitsIn<T> in{n, h.n_events, h.event_offsets, static_cast<const T*>(h.x), static_cast<const T*>(h.y),
+               static_cast<const T*>(h.z), h.layer};
+  if (fill_i32(bins, 0, nb + 2, s) != hipSuccess) return PT_ERR_DEVICE;
+  k_hit_keys<T><<<grid_for(n, 256), 256, 0, s>>>(in, B, k.bin_scale, key, rank, bin_start, status);
+  PT_LAUNCH_CHECK();
+  if (exclusive_scan(bin_start, nb, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  k_copy_total<<<1, 1, 0, s>>>(bin_start, static_cast<int>(nb), bins);
+  PT_LAUNCH_CHECK();
+  k_scatter<T><<<grid_for(n, 256), 256, 0, s>>>(in, key, rank, bin_start, sorted_hit, skey, sX, sY, sZ, sR,
+                                               cells.inner_count);
+  PT_LAUNCH_CHECK();
+
+  DoubletArgs a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, cells.cap, cells.inner,
+                cells.outer, cells.pair, cells.inner_first, cells.inner_count};
+  // bin_start[-1] holds the number of valid hits (sorted positions).
+  const int block = 256;
+  void* tok = timing_begin(s);
+  k_doublets<false><<<grid_for(n, block), block, 0, s>>>(k, a);
+  timing_end(tok, "doublets_count", s);
+  PT_LAUNCH_CHECK();
+  if (exclusive_scan(cnt, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  tok = timing_begin(s);
+  k_doublets<true><<<grid_for(n, block), block, 0, s>>>(k, a);
+  timing_end(tok, "doublets_write", s);
+  PT_LAUNCH_CHECK();
+  k_finish_cells<<<1, 1, 0, s>>>(cnt + n, cells.cap, cells.count, status);
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
+
+pt_err launch_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, uint32_t* status,
+                       pt_workspace ws, hipStream_t s) {
+  if (h.dtype == PT_F64) return run_doublets<double>(h, k, cells, status, ws, s);
+  return run_doublets<float>(h, k, cells, status, ws, s);
+}
+
+}  // namespace pt

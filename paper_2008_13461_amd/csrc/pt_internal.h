@@ -1,0 +1,119 @@
+// Internal declarations shared by the HIP sources of the pixel-track library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/pixeltrack.h"
+
+namespace pt {
+
+constexpr int kWave = 64;
+constexpr int kLayers = PT_N_LAYERS;
+constexpr int kMaxPairs = PT_MAX_PAIRS;
+constexpr int kMaxHits = PT_MAX_HITS;
+constexpr int kMaxPairsPerLayer = 8;
+
+// Constants the kernels use, derived once on the host from pt_config
+// (see the expressions documented in pixeltrack.h).
+struct DevCfg {
+  // doublets
+  double tan_dphi[kMaxPairs];
+  double zlo[kMaxPairs];
+  double zhi[kMaxPairs];
+  double z0_max;
+  double kappa_max2;
+  uint32_t cut_mask;
+  int32_t n_pairs;
+  int32_t n_bins;                       // azimuth bins per layer
+  float bin_scale;                      // n_bins / (2 pi)
+  int32_t pair_inner[kMaxPairs];
+  int32_t pair_outer[kMaxPairs];
+  int32_t pair_wbins[kMaxPairs];        // half window in bins (>= n_bins/2: whole layer)
+  int32_t inner_pairs[kLayers][kMaxPairsPerLayer];  // pairs whose inner layer is l, -1 padded
+  int32_t n_inner_pairs[kLayers];
+  // links
+  double theta2_barrel, theta2_endcap;
+  double rmax_bpix1, rmax_other;
+  uint8_t layer_barrel[kLayers];
+  // n-tuplets
+  uint32_t root_always_mask, root_if_free_mask;
+  int32_t min_hits, max_hits;
+  // fit
+  double K;          // 0.299792458 B / 100
+  double x_over_x0, highland_a, highland_b;
+  double VT, VZ_barrel, VR_disk, p_cap;
+  double f64_threshold;
+  int32_t n_modules;
+};
+
+bool derive_config(const pt_config& c, DevCfg* d);
+
+// ---------------------------------------------------------------------------
+// Workspace carving: every region 256-byte aligned.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+// Workspace needed by each call (bytes); the public size is their maximum.
+size_t ws_doublets(int n_hits, int n_events, int n_bins);
+size_t ws_links(int n_hits, int cells_cap);
+size_t ws_ntuplets(int cells_cap, int tuplets_cap);
+size_t ws_fit(int n_max, int n_modules);
+
+// Device-wide exclusive scan of n int32 values in place; data[n] receives the
+// total.  tmp must hold scan_tmp_elems(n) int32.
+size_t scan_tmp_elems(int64_t n);
+hipError_t exclusive_scan(int32_t* data, int64_t n, int32_t* tmp, hipStream_t s);
+
+// Fill helpers (graph-safe: kernels, not hipMemsetAsync).
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+
+// grid size for grid-stride loops over n items
+inline int grid_for(int64_t n, int block, int max_blocks = 65536) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > max_blocks) g = max_blocks;
+  return static_cast<int>(g);
+}
+
+// Kernel timing hooks (no-ops unless pt_timing_enable(1) and not capturing).
+void* timing_begin(hipStream_t s);
+void timing_end(void* token, const char* name, hipStream_t s);
+extern thread_local bool g_capturing;
+
+#define PT_LAUNCH_CHECK()                        \
+  do {                                           \
+    if (hipGetLastError() != hipSuccess) return PT_ERR_DEVICE; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+__device__ inline void status_flag(uint32_t* st, uint32_t bit) {
+  if (st) atomicOr(st + PT_ST_FLAGS, bit);
+}
+__device__ inline void status_add(uint32_t* st, int word, uint32_t v) {
+  if (st && v) atomicAdd(st + word, v);
+}
+
+// Number of set bits of a wave mask below this lane.
+__device__ inline int lane_prefix(uint64_t mask) {
+  const int lane = __lane_id();
+  const uint64_t below = (lane == 0) ? 0ull : (mask & ((1ull << lane) - 1ull));
+  return __popcll(below);
+}
+
+}  // namespace pt

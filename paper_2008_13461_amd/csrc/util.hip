@@ -1,0 +1,123 @@
+// Device-wide exclusive scan and fill kernels.
+#include "pt_internal.h"
+
+namespace pt {
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kTile = kScanBlock * kScanItems;
+
+// Inclusive scan of one int32 per thread across the block; returns the
+// inclusive value and writes the block total to *total.
+__device__ inline int32_t block_inclusive_scan(int32_t v, int32_t* lds, int32_t* total) {
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  if (lane == kWave - 1) lds[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int w = 0; w < kScanBlock / kWave; ++w) {
+      const int32_t t = lds[w];
+      lds[w] = run;
+      run += t;
+    }
+    lds[kScanBlock / kWave] = run;
+  }
+  __syncthreads();
+  v += lds[wave];
+  *total = lds[kScanBlock / kWave];
+  __syncthreads();
+  return v;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_tile_sums(const int32_t* __restrict__ data, int64_t n,
+                                                          int32_t* __restrict__ sums) {
+  __shared__ int32_t lds[kScanBlock / kWave + 1];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + threadIdx.x * kScanItems;
+  int32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) s += data[base + i];
+  int32_t total;
+  block_inclusive_scan(s, lds, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_tile_scan(int32_t* __restrict__ data, int64_t n,
+                                                          const int32_t* __restrict__ offsets) {
+  __shared__ int32_t lds[kScanBlock / kWave + 1];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + threadIdx.x * kScanItems;
+  int32_t v[kScanItems];
+  int32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? data[base + i] : 0;
+    s += v[i];
+  }
+  int32_t total;
+  const int32_t incl = block_inclusive_scan(s, lds, &total);
+  int32_t run = incl - s + (offsets ? offsets[blockIdx.x] : 0);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) data[base + i] = run;
+    run += v[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+    data[n] = total + (offsets ? offsets[blockIdx.x] : 0);
+}
+
+template <class T>
+__global__ void k_fill(T* __restrict__ p, T v, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+}  // namespace
+
+size_t scan_tmp_elems(int64_t n) {
+  size_t total = 0;
+  while (n > kTile) {
+    const int64_t nb = (n + kTile - 1) / kTile;
+    total += nb + 1;
+    n = nb;
+  }
+  return total + 1;
+}
+
+hipError_t exclusive_scan(int32_t* data, int64_t n, int32_t* tmp, hipStream_t s) {
+  if (n <= 0) {
+    k_fill<int32_t><<<1, 1, 0, s>>>(data, 0, 1);
+    return hipGetLastError();
+  }
+  const int64_t nb = (n + kTile - 1) / kTile;
+  if (nb == 1) {
+    k_tile_scan<<<1, kScanBlock, 0, s>>>(data, n, nullptr);
+    return hipGetLastError();
+  }
+  k_tile_sums<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, tmp);
+  hipError_t e = exclusive_scan(tmp, nb, tmp + nb + 1, s);
+  if (e != hipSuccess) return e;
+  k_tile_scan<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, tmp);
+  return hipGetLastError();
+}
+
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill<int32_t><<<grid_for(n, 256, 4096), 256, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill<uint8_t><<<grid_for(n, 256, 4096), 256, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace pt
