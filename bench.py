@@ -195,9 +195,8 @@ def fit_workload(args):
     bwd_ms, nb = api.timing_read("fit_bwd")
     api.timing_reset()
     nh = ts.nhits.astype(np.int64)
-    n_f64 = int(status[A.PT_ST_FIT_F64].item())
     return dict(t_step=t_step, fwd_ms=fwd_ms / max(nf, 1), bwd_ms=bwd_ms / max(nb, 1), n_tracks=n,
-                n_hits_total=int(nh.sum()), mean_n=float(nh.mean()), nhits=nh, f64_refits=n_f64 // (2 * (steps * 2 + args.warmup)) if False else None)
+                n_hits_total=int(nh.sum()), mean_n=float(nh.mean()), nhits=nh)
 
 
 def cpu_baseline(args, chain):

@@ -135,8 +135,10 @@ typedef struct {
   int32_t n_modules;                  /* rows of the module offset / gradient tables */
   /* performance settings: never change a result */
   int32_t n_phi_bins;                 /* azimuth bins per layer for the pair search; 0 = 128 */
-  int32_t block_doublets;             /* threads per block of the doublet kernel; 0 = 256 */
-  int32_t block_links;                /* threads per block of the link kernel; 0 = 256 */
+  int32_t block_doublets;             /* threads per block of the doublet kernel: 64, 128, 256
+                                         or 512; other values mean 256 */
+  int32_t block_links;                /* threads per block of the link kernel: 128, 256 or 512;
+                                         other values mean 256 */
   double f64_solve_threshold;         /* see PT_FIT_F32_F64SOLVE; <= 0 means 1024 */
 } pt_config;
 
@@ -293,13 +295,14 @@ pt_err pt_fit_broken_line(const pt_hits* hits, const pt_config* cfg, const pt_nt
  * where J_t(h) = d(kappa, phi0, cot, d0, z0, chi2)_t / d(x, y, z)_h of the
  * whole fit, including its dependence through the pre-fit and the scattering
  * weights.  The forward fit is recomputed, not stored.  grad_hits is device
- * float [n_hits][3] (may be NULL), grad_offsets device double [n_modules][3]
- * (may be NULL); both are accumulated into.  Tracks whose fit fails add
- * nothing. */
+ * [n_hits][3], double for PT_FIT_F64 and float otherwise (may be NULL);
+ * grad_offsets is device double [n_modules][3] (may be NULL); both are
+ * accumulated into (atomically: hits may be shared between tracks, so the
+ * order of the additions is not fixed).  Tracks whose fit fails add nothing. */
 pt_err pt_fit_broken_line_bwd(const pt_hits* hits, const pt_config* cfg,
                               const pt_ntuplets* tuplets, const float* module_offsets,
                               int32_t precision, const float* g_params, const float* g_chi2,
-                              float* grad_hits, double* grad_offsets, uint32_t* status,
+                              void* grad_hits, double* grad_offsets, uint32_t* status,
                               pt_workspace ws, pt_stream stream);
 
 /* ------------------------------------------------------------------------
@@ -322,7 +325,7 @@ pt_err pt_plan_create(const pt_config* cfg, int32_t n_hits_max, int32_t n_events
                       pt_plan* plan);
 pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links* links, pt_ntuplets* tuplets,
                    pt_tracks* tracks, const float* module_offsets, const float* g_params, const float* g_chi2,
-                   float* grad_hits, double* grad_offsets, uint32_t* status, pt_stream stream);
+                   void* grad_hits, double* grad_offsets, uint32_t* status, pt_stream stream);
 void pt_plan_destroy(pt_plan plan);
 
 /* Kernel timing (instrumentation).  While enabled, the individual calls (not

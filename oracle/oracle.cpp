@@ -360,31 +360,31 @@ int64_t oracle_ntuplets(const oracle_config* cfg, int32_t n, const uint8_t* laye
 namespace {
 
 struct Dual {
-  double v;  // value
-  double d;  // derivative along the seeded direction
+  long double v;  // value
+  long double d;  // derivative along the seeded direction
 };
-inline Dual mk(double v) { return {v, 0.0}; }
+inline Dual mk(double v) { return {v, 0.0L}; }
 inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
 inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
 inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
 inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
 inline Dual operator/(Dual a, Dual b) {
-  const double q = a.v / b.v;
+  const long double q = a.v / b.v;
   return {q, (a.d - q * b.d) / b.v};
 }
 inline Dual sqrt(Dual a) {
-  const double r = std::sqrt(a.v);
-  return {r, a.d / (2.0 * r)};
+  const long double r = std::sqrt(a.v);
+  return {r, a.d / (2.0L * r)};
 }
-inline Dual asin(Dual a) { return {std::asin(a.v), a.d / std::sqrt(1.0 - a.v * a.v)}; }
-inline Dual atan(Dual a) { return {std::atan(a.v), a.d / (1.0 + a.v * a.v)}; }
+inline Dual asin(Dual a) { return {std::asin(a.v), a.d / std::sqrt(1.0L - a.v * a.v)}; }
+inline Dual atan(Dual a) { return {std::atan(a.v), a.d / (1.0L + a.v * a.v)}; }
 inline Dual atan2(Dual y, Dual x) {
-  const double r2 = x.v * x.v + y.v * y.v;
+  const long double r2 = x.v * x.v + y.v * y.v;
   return {std::atan2(y.v, x.v), (x.v * y.d - y.v * x.d) / r2};
 }
 inline Dual log(Dual a) { return {std::log(a.v), a.d / a.v}; }
 inline Dual fabs(Dual a) { return a.v < 0 ? -a : a; }
-inline double val(Dual a) { return a.v; }
+inline double val(Dual a) { return static_cast<double>(a.v); }
 inline double val(double a) { return a; }
 inline double val(long double a) { return static_cast<double>(a); }
 template <class T> inline T cst(double v) { return T(v); }
@@ -403,7 +403,8 @@ using std::sqrt;
 // The fit's values are evaluated in extended precision (x87 long double, 64-bit
 // significand): its plain centre-based pre-fit and dense elimination lose up
 // to ~2e-9 relative on the stiffest forward tracks in double, more than the
-// double-precision GPU path it checks.  Gradients use double dual numbers.
+// double-precision GPU path it checks.  The dual numbers of the gradient carry
+// extended-precision values and derivatives for the same reason.
 using Real = long double;
 
 struct FitSettings {
@@ -827,15 +828,15 @@ int32_t oracle_fit_jacobian(const oracle_config* cfg, int32_t n, const double* X
   int status = FIT_OK;
   for (int col = 0; col < 3 * n; ++col) {
     for (int k = 0; k < n; ++k) {
-      DX[k] = {X[k], (col == 3 * k + 0) ? 1.0 : 0.0};
-      DY[k] = {Y[k], (col == 3 * k + 1) ? 1.0 : 0.0};
-      DZ[k] = {Z[k], (col == 3 * k + 2) ? 1.0 : 0.0};
+      DX[k] = {X[k], (col == 3 * k + 0) ? 1.0L : 0.0L};
+      DY[k] = {Y[k], (col == 3 * k + 1) ? 1.0L : 0.0L};
+      DZ[k] = {Z[k], (col == 3 * k + 2) ? 1.0L : 0.0L};
     }
     const FitResult<Dual> r = fit_track<Dual>(F, n, DX, DY, DZ, lay);
     status = r.status;
     if (status != FIT_OK) return status;
     const Dual outs[6] = {r.kappa, r.phi0, r.cot, r.d0, r.z0, r.chi2};
-    for (int o = 0; o < 6; ++o) jac[o * 3 * n + col] = outs[o].d;
+    for (int o = 0; o < 6; ++o) jac[o * 3 * n + col] = static_cast<double>(outs[o].d);
   }
   return status;
 }

@@ -139,7 +139,7 @@ struct DoubletArgs {
 // One thread per sorted inner hit: every pair starting on its layer, every
 // outer hit in the azimuth bins around it.
 template <bool WRITE>
-__global__ void __launch_bounds__(256) k_doublets(DevCfg k, DoubletArgs a) {
+__global__ void __launch_bounds__(512) k_doublets(DevCfg k, DoubletArgs a) {
   const int total = a.bin_start[-1];  // valid (sorted) hits
   const int B = k.n_bins;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.n_hits; j += gridDim.x * blockDim.x) {
@@ -283,7 +283,8 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   DoubletArgs a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, cells.cap, cells.inner,
                 cells.outer, cells.pair, cells.inner_first, cells.inner_count};
   // bin_start[-1] holds the number of valid hits (sorted positions).
-  const int block = 256;
+  const int block = (k.block_doublets == 64 || k.block_doublets == 128 || k.block_doublets == 512)
+                        ? k.block_doublets : 256;
   void* tok = timing_begin(s);
   k_doublets<false><<<grid_for(n, block), block, 0, s>>>(k, a);
   timing_end(tok, "doublets_count", s);

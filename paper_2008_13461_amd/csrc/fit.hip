@@ -52,7 +52,7 @@ struct FitArgs {
   // adjoint
   const float* g_params;
   const float* g_chi2;
-  float* grad_hits;
+  void* grad_hits;           // float, or double in the double-precision mode
   double* partials;          // [kBwdBlocks][n_modules * 3]
   uint32_t* status;
 };
@@ -289,7 +289,7 @@ __global__ void k_refit(DevCfg k, FitArgs a) {
 // ---------------------------------------------------------------------------
 // adjoint
 
-template <int N, class S, class HT>
+template <int N, class S, class HT, class GT>
 __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const FitArgs& a, int i, bool fallback,
                                 double* lds_mod, uint32_t& n_redo) {
   fit::State<N, S> f;
@@ -313,10 +313,10 @@ __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const Fit
 #pragma unroll
   for (int kk = 0; kk < N; ++kk) {
     if (a.grad_hits) {
-      float* gh = a.grad_hits + static_cast<int64_t>(hit[kk]) * 3;
-      unsafeAtomicAdd(gh + 0, float(gP[kk][0]));
-      unsafeAtomicAdd(gh + 1, float(gP[kk][1]));
-      unsafeAtomicAdd(gh + 2, float(gP[kk][2]));
+      GT* gh = static_cast<GT*>(a.grad_hits) + static_cast<int64_t>(hit[kk]) * 3;
+      unsafeAtomicAdd(gh + 0, GT(gP[kk][0]));
+      unsafeAtomicAdd(gh + 1, GT(gP[kk][1]));
+      unsafeAtomicAdd(gh + 2, GT(gP[kk][2]));
     }
     if (lds_mod) {
       double* lm = lds_mod + 3 * mod[kk];
@@ -346,7 +346,7 @@ __device__ inline void lds_flush(const double* lds, int n, bool any, double* dst
 // The adjoint of the tracks with NLO..NHI hits.  Grid: kBwdBlocks persistent
 // blocks, block b owning the partial module sums partials[b].  The kernel
 // with FIRST = true runs first and initialises every partial row.
-template <int NLO, int NHI, bool FIRST, class S, class HT>
+template <int NLO, int NHI, bool FIRST, class S, class HT, class GT>
 __global__ void __launch_bounds__(kBlock) k_grad(DevCfg k, FitArgs a, bool fallback) {
   extern __shared__ double lds_mod[];
   const fit::Consts C = consts_of(k);
@@ -360,12 +360,12 @@ __global__ void __launch_bounds__(kBlock) k_grad(DevCfg k, FitArgs a, bool fallb
     int nh;
     const int i = bin_item<NLO, NHI>(a, j, nh);
     any = true;
-    if (NLO <= 3 && 3 <= NHI && nh == 3) grad_one<3, S, HT>(k, C, a, i, fallback, lm, n_redo);
-    if (NLO <= 4 && 4 <= NHI && nh == 4) grad_one<4, S, HT>(k, C, a, i, fallback, lm, n_redo);
-    if (NLO <= 5 && 5 <= NHI && nh == 5) grad_one<5, S, HT>(k, C, a, i, fallback, lm, n_redo);
-    if (NLO <= 6 && 6 <= NHI && nh == 6) grad_one<6, S, HT>(k, C, a, i, fallback, lm, n_redo);
-    if (NLO <= 7 && 7 <= NHI && nh == 7) grad_one<7, S, HT>(k, C, a, i, fallback, lm, n_redo);
-    if (NLO <= 8 && 8 <= NHI && nh == 8) grad_one<8, S, HT>(k, C, a, i, fallback, lm, n_redo);
+    if (NLO <= 3 && 3 <= NHI && nh == 3) grad_one<3, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
+    if (NLO <= 4 && 4 <= NHI && nh == 4) grad_one<4, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
+    if (NLO <= 5 && 5 <= NHI && nh == 5) grad_one<5, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
+    if (NLO <= 6 && 6 <= NHI && nh == 6) grad_one<6, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
+    if (NLO <= 7 && 7 <= NHI && nh == 7) grad_one<7, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
+    if (NLO <= 8 && 8 <= NHI && nh == 8) grad_one<8, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
   }
   if (nm3) lds_flush<FIRST>(lds_mod, nm3, any, a.partials + static_cast<int64_t>(blockIdx.x) * nm3);
 }
@@ -384,12 +384,12 @@ __global__ void __launch_bounds__(kBlock) k_regrad(DevCfg k, FitArgs a) {
     const int i = a.redo[j];
     any = true;
     switch (a.tup_n[track_row(a, i)]) {
-      case 3: grad_one<3, double, HT>(k, C, a, i, false, lm, n_redo); break;
-      case 4: grad_one<4, double, HT>(k, C, a, i, false, lm, n_redo); break;
-      case 5: grad_one<5, double, HT>(k, C, a, i, false, lm, n_redo); break;
-      case 6: grad_one<6, double, HT>(k, C, a, i, false, lm, n_redo); break;
-      case 7: grad_one<7, double, HT>(k, C, a, i, false, lm, n_redo); break;
-      case 8: grad_one<8, double, HT>(k, C, a, i, false, lm, n_redo); break;
+      case 3: grad_one<3, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
+      case 4: grad_one<4, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
+      case 5: grad_one<5, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
+      case 6: grad_one<6, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
+      case 7: grad_one<7, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
+      case 8: grad_one<8, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
       default: break;
     }
   }
@@ -489,15 +489,15 @@ pt_err launch_fit(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const
   return f64in ? run_fit<float, double, float>(k, a, fb, s) : run_fit<float, float, float>(k, a, fb, s);
 }
 
-template <class S, class HT>
+template <class S, class HT, class GT>
 static pt_err run_grad(const DevCfg& k, FitArgs& a, bool fallback, double* grad_offsets, hipStream_t s) {
   const size_t lds = a.partials ? static_cast<size_t>(a.n_modules) * 3 * sizeof(double) : 0;
   const int nm3 = a.n_modules * 3;
   void* tok = timing_begin(s);
-  k_grad<4, 6, true, S, HT><<<kBwdBlocks, kBlock, lds, s>>>(k, a, fallback);
+  k_grad<4, 6, true, S, HT, GT><<<kBwdBlocks, kBlock, lds, s>>>(k, a, fallback);
   timing_end(tok, "fit_bwd", s);
-  k_grad<3, 3, false, S, HT><<<kBwdBlocks, kBlock, lds, s>>>(k, a, fallback);
-  k_grad<7, 8, false, S, HT><<<kBwdBlocks, kBlock, lds, s>>>(k, a, fallback);
+  k_grad<3, 3, false, S, HT, GT><<<kBwdBlocks, kBlock, lds, s>>>(k, a, fallback);
+  k_grad<7, 8, false, S, HT, GT><<<kBwdBlocks, kBlock, lds, s>>>(k, a, fallback);
   PT_LAUNCH_CHECK();
   if (fallback) {
     k_regrad<HT><<<kBwdBlocks, kBlock, lds, s>>>(k, a);
@@ -511,7 +511,7 @@ static pt_err run_grad(const DevCfg& k, FitArgs& a, bool fallback, double* grad_
 }
 
 pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets, int precision,
-                      const float* g_params, const float* g_chi2, float* grad_hits, double* grad_offsets,
+                      const float* g_params, const float* g_chi2, void* grad_hits, double* grad_offsets,
                       int n_max, uint32_t* status, pt_workspace ws, hipStream_t s) {
   FitArgs a = make_args(h, k, T, offsets, n_max, ws, status);
   a.g_params = g_params;
@@ -522,11 +522,12 @@ pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, c
   if (e != PT_OK) return e;
   const bool f64in = h.dtype == PT_F64;
   if (precision == PT_FIT_F64) {
-    return f64in ? run_grad<double, double>(k, a, false, grad_offsets, s)
-                 : run_grad<double, float>(k, a, false, grad_offsets, s);
+    return f64in ? run_grad<double, double, double>(k, a, false, grad_offsets, s)
+                 : run_grad<double, float, double>(k, a, false, grad_offsets, s);
   }
   const bool fb = precision == PT_FIT_F32_F64SOLVE;
-  return f64in ? run_grad<float, double>(k, a, fb, grad_offsets, s) : run_grad<float, float>(k, a, fb, grad_offsets, s);
+  return f64in ? run_grad<float, double, float>(k, a, fb, grad_offsets, s)
+               : run_grad<float, float, float>(k, a, fb, grad_offsets, s);
 }
 
 }  // namespace pt

@@ -149,6 +149,7 @@ struct State {
   S ax, ay, bx, by, cr, la, lb, ld, kp, ux, uy, sb, cb, tx, ty;
   // per hit
   S xt[N], xn[N], s[N], A[N], sq[N], u[N], m[N], wZm[N];
+  double sd[N];  // arc lengths in double (the S-Z residuals and the spacings need them)
   S D[N - 1];
   // slope and momentum
   S t, sec2, pT, p;
@@ -160,6 +161,8 @@ struct State {
   Band<N, false, S> line;
   S xc[N + 1];  // fitted offsets u_0..u_{N-1} and curvature correction
   S wl[N];      // fitted deviations from the pre-fit line
+  S eu[N], ez[N];      // measurement residuals at the optimum
+  S beta[N], gam[N];   // kinks at the inner hits (index j = 1..N-2)
   S chi2;
   S cond;       // conditioning estimate of the transverse system
   // perigee (double)
@@ -193,6 +196,7 @@ PT_HD inline void forward(const Consts& C, State<N, S>& f) {
   // ---- hits in the frame (tangent, normal) at hit 0
   const double tx = double(f.tx), ty = double(f.ty);
   f.xt[0] = f.xn[0] = f.s[0] = f.A[0] = f.u[0] = f.m[0] = S(0);
+  f.sd[0] = 0.0;
   f.sq[0] = S(1);
 #pragma unroll
   for (int k = 1; k < N; ++k) {
@@ -201,15 +205,17 @@ PT_HD inline void forward(const Consts& C, State<N, S>& f) {
     const S xt = S(xtd), xn = S(xnd);
     f.xt[k] = xt;
     f.xn[k] = xn;
-    f.s[k] = (f.kp != S(0)) ? m_atan2(f.kp * xt, S(1) - f.kp * xn) / f.kp : xt;
-    f.A[k] = S(2) * xn - f.kp * (xt * xt + xn * xn);
+    f.sd[k] = (f.kp != S(0)) ? atan2(double(f.kp) * xtd, 1.0 - double(f.kp) * xnd) / double(f.kp) : xtd;
+    f.s[k] = S(f.sd[k]);
+    // A is a small difference of two terms of the size of the sagitta: double
+    f.A[k] = S(2.0 * xnd - double(f.kp) * (xtd * xtd + xnd * xnd));
     const S q = S(1) - f.kp * f.A[k];
     f.sq[k] = m_sqrt(q > S(0) ? q : S(0));
     f.u[k] = f.A[k] / (S(1) + f.sq[k]);
   }
 #pragma unroll
   for (int k = 0; k + 1 < N; ++k) {
-    f.D[k] = f.s[k + 1] - f.s[k];
+    f.D[k] = S(f.sd[k + 1] - f.sd[k]);
     if (!(f.D[k] > S(0))) f.status = ST_BAD_ORDER;
   }
   if (f.status != ST_OK) return;
@@ -243,7 +249,7 @@ PT_HD inline void forward(const Consts& C, State<N, S>& f) {
   for (int k = 0; k < N; ++k) {
     const S VZ = f.barrel[k] ? S(C.VZb) : S(C.VRd) * f.t * f.t;
     f.wZm[k] = S(1) / VZ;
-    if (k > 0) f.m[k] = S(f.rz[k] - double(f.t) * double(f.s[k]));
+    if (k > 0) f.m[k] = S(f.rz[k] - double(f.t) * f.sd[k]);
   }
   // ---- transverse broken line: unknowns u_0..u_{N-1}, dk
   const S wm = S(1) / S(C.VT);
@@ -297,23 +303,86 @@ PT_HD inline void forward(const Consts& C, State<N, S>& f) {
   f.xc[N] = S(0);
   f.circ.solve(f.xc);
   f.line.solve(f.wl);
-  // ---- chi^2 at the optimum
-  S chi = S(0);
+  if constexpr (sizeof(S) < sizeof(double)) {
+    // One step of iterative refinement: the residual of the normal equations
+    // is formed in double, applying the matrix from its definition (weights
+    // times kinks of the current solution, coefficients from the double arc
+    // lengths), and corrected with the single-precision Cholesky factor.  The
+    // float solve alone is limited by the rounding of the assembled matrix,
+    // which shows on badly fitting combinations whose curvature correction
+    // nearly cancels the pre-fit curvature.
+    double rcd[N + 1], rld[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      rcd[i] = double(f.u[i]) * double(wm) - double(wm) * double(f.xc[i]);
+      rld[i] = double(f.m[i]) * double(f.wZm[i]) - double(f.wZm[i]) * double(f.wl[i]);
+    }
+    rcd[N] = 0.0;
+#pragma unroll
+    for (int j = 1; j + 1 < N; ++j) {
+      const double dm = f.sd[j] - f.sd[j - 1], dp = f.sd[j + 1] - f.sd[j];
+      const double cm = 1.0 / dm, cp = 1.0 / dp, c0 = -(cm + cp), ck = -(dm + dp) * 0.5;
+      const double bt = cm * double(f.xc[j - 1]) + c0 * double(f.xc[j]) + cp * double(f.xc[j + 1]) +
+                        ck * double(f.xc[N]);
+      const double gm = cm * double(f.wl[j - 1]) + c0 * double(f.wl[j]) + cp * double(f.wl[j + 1]);
+      const double wb = double(f.wT[j]) * bt, wg = double(f.wZ[j]) * gm;
+      rcd[j - 1] -= wb * cm;
+      rcd[j] -= wb * c0;
+      rcd[j + 1] -= wb * cp;
+      rcd[N] -= wb * ck;
+      rld[j - 1] -= wg * cm;
+      rld[j] -= wg * c0;
+      rld[j + 1] -= wg * cp;
+    }
+    S rc[N + 1], rl[N];
+#pragma unroll
+    for (int i = 0; i <= N; ++i) rc[i] = S(rcd[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) rl[i] = S(rld[i]);
+    f.circ.solve(rc);
+    f.line.solve(rl);
+#pragma unroll
+    for (int i = 0; i <= N; ++i) f.xc[i] = S(double(f.xc[i]) + double(rc[i]));
+#pragma unroll
+    for (int i = 0; i < N; ++i) f.wl[i] = S(double(f.wl[i]) + double(rl[i]));
+  }
+  // ---- residuals and chi^2 at the optimum.  The kinks are formed from the
+  // solution; the measurement residuals come from the normal equations,
+  // e_k = V_k (B^T W kinks)_k, which holds at the optimum and, unlike
+  // u_k - x_k, does not cancel when the scattering weights are small and the
+  // fit follows the measurements closely.
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const S eu = f.u[k] - f.xc[k];
-    const S ez = f.m[k] - f.wl[k];
-    chi += eu * eu * wm + ez * ez * f.wZm[k];
+    f.eu[k] = S(0);
+    f.ez[k] = S(0);
+    f.beta[k] = S(0);
+    f.gam[k] = S(0);
   }
 #pragma unroll
   for (int j = 1; j + 1 < N; ++j) {
     const S cm = S(1) / f.D[j - 1], cp = S(1) / f.D[j];
     const S c0 = -(cm + cp);
     const S ck = -(f.D[j - 1] + f.D[j]) * S(0.5);
-    const S beta = cm * f.xc[j - 1] + c0 * f.xc[j] + cp * f.xc[j + 1] + ck * f.xc[N];
-    const S gam = cm * f.wl[j - 1] + c0 * f.wl[j] + cp * f.wl[j + 1];
-    chi += f.wT[j] * beta * beta + f.wZ[j] * gam * gam;
+    f.beta[j] = cm * f.xc[j - 1] + c0 * f.xc[j] + cp * f.xc[j + 1] + ck * f.xc[N];
+    f.gam[j] = cm * f.wl[j - 1] + c0 * f.wl[j] + cp * f.wl[j + 1];
+    const S wb = f.wT[j] * f.beta[j];
+    const S wg = f.wZ[j] * f.gam[j];
+    f.eu[j - 1] += wb * cm;
+    f.eu[j] += wb * c0;
+    f.eu[j + 1] += wb * cp;
+    f.ez[j - 1] += wg * cm;
+    f.ez[j] += wg * c0;
+    f.ez[j + 1] += wg * cp;
   }
+  S chi = S(0);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    f.eu[k] *= S(C.VT);
+    f.ez[k] /= f.wZm[k];
+    chi += f.eu[k] * f.eu[k] * wm + f.ez[k] * f.ez[k] * f.wZm[k];
+  }
+#pragma unroll
+  for (int j = 1; j + 1 < N; ++j) chi += f.wT[j] * f.beta[j] * f.beta[j] + f.wZ[j] * f.gam[j] * f.gam[j];
   f.chi2 = chi;
   // ---- perigee parameters (double), with the pre-fit tangent renormalised
   const double tn = sqrt(tx * tx + ty * ty);
@@ -474,9 +543,9 @@ PT_HD inline void backward(const Consts& C, const State<N, S>& f, const double g
   const S wm = S(1) / S(C.VT);
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const S eu = f.u[k] - f.xc[k];
+    const S eu = f.eu[k];
     u_b[k] += wm * (S(2) * G2 * eu + lam[k]);
-    const S ez = f.m[k] - f.wl[k];
+    const S ez = f.ez[k];
     m_b[k] += f.wZm[k] * (S(2) * G2 * ez + mu[k]);
     wZm_b[k] += G2 * ez * ez + ez * mu[k];
   }
@@ -486,7 +555,7 @@ PT_HD inline void backward(const Consts& C, const State<N, S>& f, const double g
     const S c0 = -(cm + cp);
     const S ck = -(f.D[j - 1] + f.D[j]) * S(0.5);
     {
-      const S beta = cm * f.xc[j - 1] + c0 * f.xc[j] + cp * f.xc[j + 1] + ck * f.xc[N];
+      const S beta = f.beta[j];
       const S del = cm * lam[j - 1] + c0 * lam[j] + cp * lam[j + 1] + ck * lam[N];
       wT_b[j] += G2 * beta * beta - beta * del;
       const S coef = f.wT[j] * (S(2) * G2 * beta - del);
@@ -500,7 +569,7 @@ PT_HD inline void backward(const Consts& C, const State<N, S>& f, const double g
       D_b[j] += -cp_b * cp * cp - gk * S(0.5);
     }
     {
-      const S gam = cm * f.wl[j - 1] + c0 * f.wl[j] + cp * f.wl[j + 1];
+      const S gam = f.gam[j];
       const S del = cm * mu[j - 1] + c0 * mu[j] + cp * mu[j + 1];
       wZ_b[j] += G2 * gam * gam - gam * del;
       const S coef = f.wZ[j] * (S(2) * G2 * gam - del);

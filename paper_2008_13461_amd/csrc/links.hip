@@ -18,7 +18,6 @@ namespace pt {
 namespace {
 
 constexpr int kLocal = 8;
-constexpr int kBlock = 256;
 
 template <class T>
 struct LinkIn {
@@ -124,17 +123,17 @@ __device__ __forceinline__ void load_triplet(const DevCfg& k, const LinkIn<T>& a
   last = min(first + a.inner_count[h1], a.cells_cap);
 }
 
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_links(DevCfg k, LinkIn<T> a) {
-  __shared__ int32_t s_scan[kBlock / kWave + 1];
+template <class T, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_links(DevCfg k, LinkIn<T> a) {
+  __shared__ int32_t s_scan[BLOCK / kWave + 1];
   __shared__ int32_t s_base;
   const int n = min(*a.cell_count, a.cells_cap);
-  const int stride = gridDim.x * kBlock;
+  const int stride = gridDim.x * BLOCK;
   const int rounds = (n + stride - 1) / stride;
   const int lane = threadIdx.x % kWave;
   const int wave = threadIdx.x / kWave;
   for (int r = 0; r < rounds; ++r) {
-    const int cp = r * stride + blockIdx.x * kBlock + threadIdx.x;
+    const int cp = r * stride + blockIdx.x * BLOCK + threadIdx.x;
     int buf[kLocal];
     int cnt = 0;
     bool overflow = false;
@@ -167,7 +166,7 @@ __global__ void __launch_bounds__(kBlock) k_links(DevCfg k, LinkIn<T> a) {
     __syncthreads();
     if (threadIdx.x == 0) {
       int run = 0;
-      for (int w = 0; w < kBlock / kWave; ++w) {
+      for (int w = 0; w < BLOCK / kWave; ++w) {
         const int x = s_scan[w];
         s_scan[w] = run;
         run += x;
@@ -237,7 +236,6 @@ size_t ws_links(int n_hits, int cells_cap) {
 template <class T>
 static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells, pt_links& L,
                         uint32_t* status, pt_workspace ws, hipStream_t s, int block) {
-  (void)block;
   Carver c(ws.ptr);
   double* R = c.take<double>(h.n_hits);
   int32_t* ovf = c.take<int32_t>(cells.cap);
@@ -253,7 +251,12 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   k_clear_has_inner<<<grid_for(cells.cap, 256, 8192), 256, 0, s>>>(cells.count, cells.cap, L.has_inner);
   PT_LAUNCH_CHECK();
   void* tok = timing_begin(s);
-  k_links<T><<<grid_for(cells.cap, kBlock, 16384), kBlock, 0, s>>>(k, a);
+  if (block == 128)
+    k_links<T, 128><<<grid_for(cells.cap, 128, 32768), 128, 0, s>>>(k, a);
+  else if (block == 512)
+    k_links<T, 512><<<grid_for(cells.cap, 512, 8192), 512, 0, s>>>(k, a);
+  else
+    k_links<T, 256><<<grid_for(cells.cap, 256, 16384), 256, 0, s>>>(k, a);
   timing_end(tok, "links", s);
   PT_LAUNCH_CHECK();
   k_links_overflow<T><<<64, 64, 0, s>>>(k, a);

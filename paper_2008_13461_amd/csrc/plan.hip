@@ -24,7 +24,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
 pt_err launch_fit(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets, int precision,
                   pt_tracks& out, uint32_t* status, pt_workspace ws, hipStream_t s);
 pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets,
-                      int precision, const float* g_params, const float* g_chi2, float* grad_hits,
+                      int precision, const float* g_params, const float* g_chi2, void* grad_hits,
                       double* grad_offsets, int n_max, uint32_t* status, pt_workspace ws, hipStream_t s);
 
 // ---------------------------------------------------------------------------
@@ -169,7 +169,7 @@ void pt_plan_destroy(pt_plan plan) {
 
 static pt_err enqueue_step(Plan* p, const pt_hits* hits, pt_cells* cells, pt_links* links, pt_ntuplets* tuplets,
                            pt_tracks* tracks, const float* offsets, const float* g_params, const float* g_chi2,
-                           float* grad_hits, double* grad_offsets, uint32_t* status, hipStream_t s) {
+                           void* grad_hits, double* grad_offsets, uint32_t* status, hipStream_t s) {
   pt_workspace ws{p->ws, p->ws_bytes};
   pt_err e = launch_doublets(*hits, p->dev, *cells, status, ws, s);
   if (e == PT_OK) e = launch_links(*hits, p->dev, *cells, *links, status, ws, s, p->cfg.block_links);
@@ -183,7 +183,7 @@ static pt_err enqueue_step(Plan* p, const pt_hits* hits, pt_cells* cells, pt_lin
 
 pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links* links, pt_ntuplets* tuplets,
                    pt_tracks* tracks, const float* module_offsets, const float* g_params, const float* g_chi2,
-                   float* grad_hits, double* grad_offsets, uint32_t* status, pt_stream stream) {
+                   void* grad_hits, double* grad_offsets, uint32_t* status, pt_stream stream) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p || !hits || !cells || !links || !tuplets || !tracks) return PT_ERR_ARG;
   if (hits->n_hits > p->n_hits_max || hits->n_events > p->n_events_max || cells->cap > p->cells_cap ||

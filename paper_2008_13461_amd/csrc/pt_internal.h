@@ -47,6 +47,7 @@ struct DevCfg {
   double VT, VZ_barrel, VR_disk, p_cap;
   double f64_threshold;
   int32_t n_modules;
+  int32_t block_doublets;
 };
 
 bool derive_config(const pt_config& c, DevCfg* d);

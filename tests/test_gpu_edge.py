@@ -1,0 +1,161 @@
+"""GPU edge cases: empty inputs, empty events, invalid hits, capacity
+overflow, input permutation, and graph replays of the batched plan."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from synth import config as C
+from synth import events as E
+from tests.helpers import doublet_set, tuplet_set
+
+pytestmark = pytest.mark.gpu
+
+CFG = C.default_config()
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run(h, caps=None, **kw):
+    from tests.gpu_helpers import products, run_chain
+    pipe, hits = run_chain(h, CFG, caps=caps, **kw)
+    return pipe, products(pipe)
+
+
+def test_empty_input():
+    _need_gpu()
+    e = np.zeros(0, np.float32)
+    h = E.Hits(e, e, e, np.zeros(0, np.uint8), np.zeros(0, np.int16), np.zeros(0, np.int32),
+               np.array([0], np.int32))
+    from tests.gpu_helpers import caps_for
+    pipe, prod = _run(h, caps=caps_for(0, 0))
+    assert len(prod["cell_inner"]) == 0 and len(prod["kept_n"]) == 0 and pipe.flags() == 0
+
+
+def test_empty_events_between_events():
+    _need_gpu()
+    ev = E.config3(n_events=2)
+    a = int(ev.event_offsets[1])
+    off = np.array([0, 0, a, a, ev.n_hits, ev.n_hits], np.int32)
+    h = E.Hits(ev.x, ev.y, ev.z, ev.layer, ev.module, ev.track, off)
+    _, got = _run(h)
+    _, ref = _run(ev)
+    assert doublet_set(got["cell_inner"], got["cell_outer"]) == doublet_set(ref["cell_inner"], ref["cell_outer"])
+    assert tuplet_set(got["kept_hits"], got["kept_n"]) == tuplet_set(ref["kept_hits"], ref["kept_n"])
+
+
+def test_invalid_hits_are_skipped_and_counted():
+    _need_gpu()
+    from paper_2008_13461_amd import _abi as A
+    h = E.config2()
+    x, y, z, layer = h.x.copy(), h.y.copy(), h.z.copy(), h.layer.copy()
+    rng = np.random.default_rng(5)
+    bad_nan = rng.choice(h.n_hits, 30, replace=False)
+    x[bad_nan[:10]] = np.nan
+    z[bad_nan[10:20]] = np.inf
+    layer[bad_nan[20:]] = 12
+    hb = E.Hits(x, y, z, layer, h.module, h.track, h.event_offsets)
+    pipe, got = _run(hb)
+    assert pipe.flags() & A.PT_FLAG_BAD_HITS
+    assert int(pipe.status[A.PT_ST_BAD_HITS].item()) == 30
+    good = np.setdiff1d(np.arange(h.n_hits), bad_nan)
+    ref = O.reconstruct_event(CFG, h.x[good], h.y[good], h.z[good], h.layer[good])
+    want = doublet_set(good[ref["cell_inner"]], good[ref["cell_outer"]])
+    assert doublet_set(got["cell_inner"], got["cell_outer"]) == want
+    want_t = {tuple(good[list(t)].tolist()) for t in tuplet_set(ref["hits"], ref["n"])}
+    assert tuplet_set(got["kept_hits"], got["kept_n"]) == want_t
+
+
+@pytest.mark.parametrize("which", ["cells", "links", "tuplets"])
+def test_capacity_overflow_is_flagged(which):
+    _need_gpu()
+    from paper_2008_13461_amd import _abi as A
+    from tests.gpu_helpers import caps_for
+    h = E.config2()
+    full_pipe, full = _run(h)
+    n_cells = len(full["cell_inner"])
+    n_links = len(full["link_in"])
+    n_raw = len(full["raw_n"])
+    caps = caps_for(h.n_hits, 1)
+    if which == "cells":
+        caps["cells_cap"] = n_cells // 2
+        flag = A.PT_FLAG_CELLS_OVERFLOW
+    elif which == "links":
+        caps["links_cap"] = n_links // 2
+        flag = A.PT_FLAG_LINKS_OVERFLOW
+    else:
+        caps["tuplets_cap"] = n_raw // 2
+        flag = A.PT_FLAG_TUPLETS_OVERFLOW
+    pipe, got = _run(h, caps=caps)
+    assert pipe.flags() & flag
+    if which == "cells":
+        assert int(pipe.cells.count.item()) == n_cells      # the size needed is reported
+    if which == "links":
+        assert int(pipe.links.count.item()) == n_links
+    if which == "tuplets":
+        assert int(pipe.tuplets.count_raw.item()) == n_raw
+
+
+def test_permuted_hits_give_the_same_sets():
+    _need_gpu()
+    h = E.config2()
+    perm = np.random.default_rng(11).permutation(h.n_hits)
+    hp = E.Hits(h.x[perm], h.y[perm], h.z[perm], h.layer[perm], h.module[perm], h.track[perm], h.event_offsets)
+    _, a = _run(h)
+    _, b = _run(hp)
+    # map permuted indices back to the original ones
+    d_b = {(int(perm[i]), int(perm[o])) for i, o in zip(b["cell_inner"], b["cell_outer"])}
+    assert d_b == doublet_set(a["cell_inner"], a["cell_outer"])
+    t_b = {tuple(perm[list(t)].tolist()) for t in tuplet_set(b["kept_hits"], b["kept_n"])}
+    assert t_b == tuplet_set(a["kept_hits"], a["kept_n"])
+
+
+def test_plan_graph_replays_match_eager():
+    """Several replays of the captured step, with eager work in between, each
+    checked against the eager calls."""
+    _need_gpu()
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from tests.gpu_helpers import caps_for
+    h = E.config3(n_events=4)
+    caps = caps_for(h.n_hits, h.n_events)
+    cfg = A.make_config(CFG)
+    hits = api.Hits.from_host(h)
+    off = torch.from_numpy(E.module_offsets()).cuda()
+    gp, gc = (torch.from_numpy(a).cuda() for a in E.cotangents(3, caps["tuplets_cap"]))
+    # eager reference
+    pipe = api.Pipeline(CFG, **caps)
+    pipe.reconstruct(hits, offsets=off)
+    gh_ref = torch.zeros((h.n_hits, 3), dtype=torch.float32, device="cuda")
+    pipe.backward(hits, gp, gc, gh_ref, None, offsets=off)
+    torch.cuda.synchronize()
+    ref_t = tuplet_set(*(t.cpu().numpy() for t in pipe.tuplets.kept_rows()))
+    nk = int(pipe.tuplets.count.item())
+    ref_rows = pipe.tuplets.kept_rows()[0].cpu().numpy()
+    ref_p = pipe.tracks.params[:nk].cpu().numpy()
+    order_ref = np.lexsort(ref_rows.T[::-1])
+    plan = api.Plan(cfg, precision=A.PT_FIT_F32_F64SOLVE, with_adjoint=True, **caps)
+    cells = api.Cells.empty(caps["cells_cap"], h.n_hits)
+    links = api.Links.empty(caps["links_cap"], caps["cells_cap"])
+    tup = api.Tuplets.empty(caps["tuplets_cap"])
+    tracks = api.Tracks.empty(caps["tuplets_cap"], A.PT_FIT_F32_F64SOLVE)
+    status = api.new_status()
+    for rep in range(4):
+        gh = torch.zeros((h.n_hits, 3), dtype=torch.float32, device="cuda")
+        plan.run(hits, cells, links, tup, tracks, status, offsets=off, g_params=gp, g_chi2=gc, grad_hits=gh)
+        torch.cuda.synchronize()
+        got_rows = tup.kept_rows()[0].cpu().numpy()
+        assert tuplet_set(got_rows, tup.kept_rows()[1].cpu().numpy()) == ref_t, rep
+        got_p = tracks.params[:nk].cpu().numpy()
+        order = np.lexsort(got_rows.T[::-1])
+        assert np.array_equal(got_rows[order], ref_rows[order_ref])
+        assert np.allclose(got_p[order], ref_p[order_ref], rtol=0, atol=0, equal_nan=True)
+        # hit gradients: same sums up to the order of float atomic additions
+        assert torch.allclose(gh, gh_ref, rtol=1e-5, atol=1e-6)
+        # eager work between replays
+        pipe.reconstruct(hits, offsets=off)
+        torch.cuda.synchronize()

@@ -38,7 +38,8 @@ def _run_fit(ts, precision, offsets, with_grad=False, g=None):
     if with_grad:
         gp = torch.from_numpy(g[0]).cuda()
         gc = torch.from_numpy(g[1]).cuda()
-        gh = torch.zeros((h.n_hits, 3), dtype=torch.float32, device="cuda")
+        gdt = torch.float64 if precision == A.PT_FIT_F64 else torch.float32
+        gh = torch.zeros((h.n_hits, 3), dtype=gdt, device="cuda")
         go = torch.zeros((C.N_MODULES, 3), dtype=torch.float64, device="cuda")
         api.fit_broken_line_bwd(hits, cfg, tup, off, precision, gp, gc, gh, go, status, ws)
         out["grad_hits"] = gh.cpu().numpy().astype(np.float64)
