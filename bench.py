@@ -28,6 +28,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "events/s at PU200, batched vs per-event; fit fwd+bwd tracks/s vs HBM roofline"
+# fp64 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (T ops/s)
+FP64_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+LINK_OPS_PER_CANDIDATE = 7.0
+# cell geometry (read 8, write 24 + 4 rank + 9 link resets) + index (read 8 + 24 + 4, write 48 record)
+LINK_INDEX_BYTES_PER_CELL = 129.0
+# radius (read x, y as float, write R) 16 + in-cell counts (fill 4, scan read/write 8)
+LINK_INDEX_BYTES_PER_HIT = 28.0
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
@@ -135,7 +142,8 @@ def chain_workload(args):
     torch.cuda.synchronize()
     api.timing_enable(False)
     kern = {}
-    for name in ("doublets_count", "doublets_write", "links", "dfs", "fit_fwd", "fit_bwd"):
+    for name in ("doublets_count", "doublets_write", "link_index", "links", "link_emit", "roots", "dfs", "dedup",
+                 "fit_fwd", "fit_bwd"):
         ms, n = api.timing_read(name)
         if n:
             kern[name] = ms / n
@@ -281,12 +289,21 @@ def main():
     if dominant in ("fit_fwd", "fit_bwd"):
         pass
     if dominant == "links":
-        # R-Z test of every candidate (c', c): 15 double operations, the circle test for the few that pass
-        flops = 15.0 * cnt["link_candidates"]
-        achieved = flops / (kern["links"] * 1e-3) / 1e12
-        roof = {"kernel": "k_links", "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                "note": "fp64 operations of the R-Z test per candidate pair x candidates / kernel time"}
+        # R-Z test of every candidate (c', c): 7 double-precision VALU operations
+        # (2 mul, 1 sub, 3 mul, 1 compare) against the VALU issue rate for
+        # double operations without multiply-add
+        ops = LINK_OPS_PER_CANDIDATE * cnt["link_candidates"]
+        achieved = ops / (kern["links"] * 1e-3) / 1e12
+        roof = {"kernel": "k_link_hits", "bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TOPS,
+                "unit": "TOP/s", "frac": achieved / FP64_VALU_PEAK_TOPS, "traffic": None,
+                "note": "7 fp64 ops per candidate pair x candidates / kernel time; peak = 256 CU x 4 SIMD x "
+                        "16 lanes x 2.4 GHz (one fp64 op per lane per clock, no FMA: contraction is off)"}
+    elif dominant == "link_index":
+        byts = LINK_INDEX_BYTES_PER_CELL * cnt["doublets"] + LINK_INDEX_BYTES_PER_HIT * cnt["hits"]
+        achieved = byts / (kern["link_index"] * 1e-3) / 1e9
+        roof = {"kernel": "link_index", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "note": f"{LINK_INDEX_BYTES_PER_CELL:.0f} B per cell + {LINK_INDEX_BYTES_PER_HIT:.0f} B per hit / time of the index kernels"}
     elif dominant in ("doublets_count", "doublets_write"):
         byts = 32.0 * cnt["hits"] + (9.0 * cnt["doublets"] if dominant == "doublets_write" else 0.0)
         achieved = byts / (kern[dominant] * 1e-3) / 1e9

@@ -63,9 +63,10 @@ enum { PT_F32 = 0, PT_F64 = 1 };
  *                       positions relative to the first hit, their local frame
  *                       coordinates) and the final perigee conversion are
  *                       formed in double, where single precision would cancel.
- *  PT_FIT_F32_F64SOLVE  as PT_FIT_F32, but the two broken-line band solves of a
- *                       track are done in double when its conditioning
- *                       estimate exceeds pt_config.f64_solve_threshold. */
+ *  PT_FIT_F32_F64SOLVE  as PT_FIT_F32, but a track is fitted again in double
+ *                       when its conditioning estimate exceeds
+ *                       pt_config.f64_solve_threshold or when its
+ *                       single-precision solve breaks down. */
 enum { PT_FIT_F64 = 0, PT_FIT_F32 = 1, PT_FIT_F32_F64SOLVE = 2 };
 
 /* Doublet cuts of Table 1 (bits of pt_config.cut_mask). */
@@ -137,8 +138,8 @@ typedef struct {
   int32_t n_phi_bins;                 /* azimuth bins per layer for the pair search; 0 = 128 */
   int32_t block_doublets;             /* threads per block of the doublet kernel: 64, 128, 256
                                          or 512; other values mean 256 */
-  int32_t block_links;                /* threads per block of the link kernel: 128, 256 or 512;
-                                         other values mean 256 */
+  int32_t block_links;                /* threads per block of the link sweep (one wavefront per
+                                         middle hit): 64, 128 or 256; other values mean 64 */
   double f64_solve_threshold;         /* see PT_FIT_F32_F64SOLVE; <= 0 means 1024 */
 } pt_config;
 
@@ -330,8 +331,10 @@ void pt_plan_destroy(pt_plan plan);
 
 /* Kernel timing (instrumentation).  While enabled, the individual calls (not
  * graph launches) record a pair of HIP events around their main kernels on
- * their stream: "doublets_count", "doublets_write", "links", "dfs",
- * "fit_fwd", "fit_bwd".  pt_timing_read waits for the recorded events and
+ * their stream: "doublets_count", "doublets_write", "link_index" (cell
+ * geometry and the index of cells by outer hit), "links" (the triplet sweep),
+ * "link_emit" (placing the links), "roots", "dfs" (both search passes),
+ * "dedup", "fit_fwd", "fit_bwd".  pt_timing_read waits for the recorded events and
  * returns the summed milliseconds and the number of launches since the last
  * reset (PT_ERR_ARG when the name has no record). */
 void pt_timing_enable(int32_t on);

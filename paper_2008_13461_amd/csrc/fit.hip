@@ -185,7 +185,9 @@ __device__ inline void fit_one(const DevCfg& k, const fit::Consts& C, const FitA
   if (ok) fit::forward<N, S>(C, f);
   OT* P = static_cast<OT*>(a.params) + static_cast<int64_t>(i) * 5;
   int st = ok ? f.status : fit::ST_FAILED;
-  if (st == fit::ST_OK && fallback && double(f.cond) > C.thr) {
+  // Stiff systems, and systems whose single-precision solve broke down, are
+  // solved again in double.
+  if (fallback && ok && (st == fit::ST_FAILED || (st == fit::ST_OK && double(f.cond) > C.thr))) {
     const int slot = atomicAdd(a.redo_count, 1);
     a.redo[slot] = i;
     ++n_redo;
@@ -296,13 +298,13 @@ __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const Fit
   int hit[N], mod[N];
   if (!load_track<N, S, HT>(a, k.layer_barrel, track_row(a, i), f, hit, mod)) return;
   fit::forward<N, S>(C, f);
-  if (f.status != fit::ST_OK) return;
-  if (fallback && double(f.cond) > C.thr) {
+  if (fallback && (f.status == fit::ST_FAILED || (f.status == fit::ST_OK && double(f.cond) > C.thr))) {
     const int slot = atomicAdd(a.redo_count, 1);
     a.redo[slot] = i;
     ++n_redo;
     return;
   }
+  if (f.status != fit::ST_OK) return;
   double g[6];
   const float* gp = a.g_params + static_cast<int64_t>(i) * 5;
 #pragma unroll

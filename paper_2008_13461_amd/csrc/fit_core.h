@@ -145,8 +145,10 @@ struct State {
   double P0x, P0y, P0z;
   double rx[N], ry[N], rz[N];
   bool barrel[N];
-  // pre-fit
-  S ax, ay, bx, by, cr, la, lb, ld, kp, ux, uy, sb, cb, tx, ty;
+  // pre-fit circle, in double in both precisions: it is the linearisation
+  // point of the fit, and an error in it leaks into the fitted curvature of
+  // tracks far from it
+  double ax, ay, bx, by, cr, la, lb, ld, kp, ux, uy, sb, cb, tx, ty;
   // per hit
   S xt[N], xn[N], s[N], A[N], sq[N], u[N], m[N], wZm[N];
   double sd[N];  // arc lengths in double (the S-Z residuals and the spacings need them)
@@ -176,21 +178,21 @@ PT_HD inline void forward(const Consts& C, State<N, S>& f) {
   constexpr int b = N / 2;
   f.status = ST_OK;
   // ---- pre-fit circle through hits 0, b, N-1
-  f.ax = S(f.rx[b]);
-  f.ay = S(f.ry[b]);
-  f.bx = S(f.rx[N - 1]);
-  f.by = S(f.ry[N - 1]);
+  f.ax = f.rx[b];
+  f.ay = f.ry[b];
+  f.bx = f.rx[N - 1];
+  f.by = f.ry[N - 1];
   f.cr = f.ax * f.by - f.ay * f.bx;
   f.la = m_sqrt(f.ax * f.ax + f.ay * f.ay);
   f.lb = m_sqrt(f.bx * f.bx + f.by * f.by);
-  const S dx = f.bx - f.ax, dy = f.by - f.ay;
+  const double dx = f.bx - f.ax, dy = f.by - f.ay;
   f.ld = m_sqrt(dx * dx + dy * dy);
-  f.kp = S(2) * f.cr / (f.la * f.lb * f.ld);
+  f.kp = 2.0 * f.cr / (f.la * f.lb * f.ld);
   f.ux = f.bx / f.lb;
   f.uy = f.by / f.lb;
-  f.sb = f.kp * f.lb * S(0.5);
-  const S c2 = S(1) - f.sb * f.sb;
-  f.cb = m_sqrt(c2 > S(0) ? c2 : S(0));
+  f.sb = f.kp * f.lb * 0.5;
+  const double c2 = 1.0 - f.sb * f.sb;
+  f.cb = m_sqrt(c2 > 0.0 ? c2 : 0.0);
   f.tx = f.ux * f.cb + f.uy * f.sb;
   f.ty = -f.ux * f.sb + f.uy * f.cb;
   // ---- hits in the frame (tangent, normal) at hit 0

@@ -1,15 +1,30 @@
 // Cell linking (paper section 3.2: doublets that share a hit are tested for
 // a compatible triplet).
 //
-// One thread per inner cell c' = (h0, h1).  Its candidates are the cells that
-// start on h1, a contiguous run thanks to the grouping of the doublet step.
-// The cheap division-free R-Z alignment test runs first; the circle test
-// (divisions and square roots) only for the few candidates that pass it.  A
-// thread keeps up to kLocal links in registers; the block then reserves space
-// for all of its links with one atomic, so that every cell's outer links are
-// contiguous (out_start, out_count) without a global sort.  Cells with more
-// than kLocal links are finished by a second, rarely used kernel.
+// The candidates are all pairs (c', c) of cells meeting on a middle hit h1:
+// c' = (h0, h1) ends there, c = (h1, h2) starts there.  At pileup 200 there
+// are billions of them and only about 2% pass the R-Z alignment test, so the
+// step is organised around that test:
+//
+//  1. k_cell_geom: every cell's R-Z segment (dr, dz) and its squared length,
+//     once, in cell order; the length carries the sign of the barrel/end-cap
+//     class of the cell's outer hit (the class of h2 selects theta).  Each
+//     cell also takes a rank among the cells ending on its outer hit.
+//  2. exclusive scan of the per-hit in-cell counts, then k_by_outer: an
+//     index of the cells by outer hit, one 48-byte record per cell holding
+//     what the triplet tests need from c' (segment, length, h0 position).
+//  3. k_link_hits: one wavefront per middle hit.  Lanes hold the in-cells;
+//     the out-cells (a contiguous run, grouped by inner hit by the doublet
+//     step) are swept in a uniform loop whose loads are wave-uniform, so the
+//     R-Z test of 64 pairs costs a handful of double-precision instructions
+//     and no per-pair gather.  Pairs that pass are queued in LDS and the
+//     beam-spot test (divisions, square roots) runs on full waves of queued
+//     pairs.  Links of an in-cell collect in LDS, are sorted by out-cell and
+//     written as one contiguous run per in-cell, with one atomic reservation
+//     per wave.  In-cells with more than kLocal links go to k_links_overflow.
 #include "pt_internal.h"
+
+#include <algorithm>
 
 // Every decision below is made in double precision exactly as parenthesised.
 #pragma clang fp contract(off)
@@ -17,204 +32,446 @@
 namespace pt {
 namespace {
 
-constexpr int kLocal = 8;
+constexpr int kLocal = 8;        // links an in-cell keeps in LDS before the overflow path
+constexpr int kUnroll = 4;       // out-cells tested per step of the sweep
+constexpr int kSegment = 1 << 24;  // out-cells per queue segment (offsets fit beside the lane)
 
-template <class T>
-struct LinkIn {
-  int32_t n_hits;
-  const T* x;
-  const T* y;
-  const T* z;
-  const uint8_t* layer;
-  const double* R;          // per hit, sqrt(X X + Y Y)
-  const int32_t* cell_inner;
-  const int32_t* cell_outer;
-  const int32_t* cell_count;
-  int32_t cells_cap;
-  const int32_t* inner_first;
-  const int32_t* inner_count;
-  int32_t links_cap;
-  int32_t* in_cell;
-  int32_t* out_cell;
-  int32_t* links_count;
-  int32_t* out_start;
-  int32_t* out_count;
-  uint8_t* has_inner;
-  int32_t* ovf;             // cells with more than kLocal links
-  int32_t* ovf_count;
-  uint32_t* status;
+// What the triplet tests need from an in-cell c' = (h0, h1).
+struct alignas(16) InCell {
+  double ar, az, La;  // R1 - R0, Z1 - Z0, ar ar + az az
+  double X0, Y0;      // transverse position of h0
+  int32_t cell;
+  int32_t bpix1;      // h0 on layer 0
 };
+static_assert(sizeof(InCell) == 48, "InCell layout");
 
-template <class T>
-__global__ void k_radius(LinkIn<T> a, double* __restrict__ R) {
-  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < a.n_hits; h += gridDim.x * blockDim.x) {
-    const double X = static_cast<double>(a.x[h]);
-    const double Y = static_cast<double>(a.y[h]);
-    R[h] = sqrt(X * X + Y * Y);
-  }
+// The R-Z test, with the out-cell's segment (br, bz) and length Lb.
+__device__ __forceinline__ bool rz_pass(double ar, double az, double La, double br, double bz, double Lb,
+                                        double theta2) {
+  const double A = ar * bz - az * br;
+  return A * A <= theta2 * (La * Lb);
 }
 
-__global__ void k_clear_has_inner(const int32_t* cell_count, int32_t cap, uint8_t* __restrict__ has_inner) {
-  const int n = min(*cell_count, cap);
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) has_inner[c] = 0;
-}
-
-// The triplet predicates documented in pixeltrack.h.  The R-Z part uses the
-// per-hit radii; the beam-spot part the transverse coordinates.
-struct Triplet {
-  double X0, Y0, Z0, R0, X1, Y1, Z1, R1;
-  double ar, az, La;  // R-Z segment h0 -> h1 and its squared length
-  double rmax;
-};
-
-__device__ __forceinline__ bool rz_pass(const Triplet& t, double theta2, double R2, double Z2) {
-  const double br = R2 - t.R1;
-  const double bz = Z2 - t.Z1;
-  const double A = t.ar * bz - t.az * br;
-  return A * A <= theta2 * (t.La * (br * br + bz * bz));
-}
-
-__device__ __forceinline__ bool beam_pass(const Triplet& t, double X2, double Y2) {
-  const double ux = t.X1 - t.X0, uy = t.Y1 - t.Y0;
-  const double vx = X2 - t.X0, vy = Y2 - t.Y0;
+// The beam-spot test of the circle through the three hits.
+__device__ __forceinline__ bool beam_pass(double X0, double Y0, double X1, double Y1, double X2, double Y2,
+                                          double rmax) {
+  const double ux = X1 - X0, uy = Y1 - Y0;
+  const double vx = X2 - X0, vy = Y2 - Y0;
   const double Dd = 2.0 * (ux * vy - uy * vx);
   if (Dd == 0.0) {
-    const double cr = t.X0 * vy - t.Y0 * vx;
-    return cr * cr <= (t.rmax * t.rmax) * (vx * vx + vy * vy);
+    const double cr = X0 * vy - Y0 * vx;
+    return cr * cr <= (rmax * rmax) * (vx * vx + vy * vy);
   }
   const double U2 = ux * ux + uy * uy;
   const double V2 = vx * vx + vy * vy;
   const double cx = (U2 * vy - V2 * uy) / Dd;
   const double cy = (V2 * ux - U2 * vx) / Dd;
   const double rho2 = cx * cx + cy * cy;
-  const double Cx = t.X0 + cx, Cy = t.Y0 + cy;
+  const double Cx = X0 + cx, Cy = Y0 + cy;
   const double c2 = Cx * Cx + Cy * Cy;
-  return fabs(sqrt(c2) - sqrt(rho2)) <= t.rmax;
+  return fabs(sqrt(c2) - sqrt(rho2)) <= rmax;
+}
+
+// Orders the LDS traffic of one wavefront (its lanes run in lockstep, so a
+// compiler barrier is all that is needed between a write and a read by
+// another lane).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <class T>
-__device__ __forceinline__ bool link_pass(const DevCfg& k, const LinkIn<T>& a, const Triplet& t, int c) {
-  const int h2 = a.cell_outer[c];
-  const double Z2 = static_cast<double>(a.z[h2]);
-  const double R2 = a.R[h2];
-  const double theta2 = k.layer_barrel[a.layer[h2]] ? k.theta2_barrel : k.theta2_endcap;
-  if (!rz_pass(t, theta2, R2, Z2)) return false;
-  return beam_pass(t, static_cast<double>(a.x[h2]), static_cast<double>(a.y[h2]));
+__global__ void k_radius(int n, const T* __restrict__ x, const T* __restrict__ y, double* __restrict__ R) {
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n; h += gridDim.x * blockDim.x) {
+    const double X = static_cast<double>(x[h]);
+    const double Y = static_cast<double>(y[h]);
+    R[h] = sqrt(X * X + Y * Y);
+  }
 }
 
 template <class T>
-__device__ __forceinline__ void load_triplet(const DevCfg& k, const LinkIn<T>& a, int cp, Triplet& t,
-                                             int& first, int& last) {
-  const int h0 = a.cell_inner[cp];
-  const int h1 = a.cell_outer[cp];
-  t.X0 = static_cast<double>(a.x[h0]);
-  t.Y0 = static_cast<double>(a.y[h0]);
-  t.Z0 = static_cast<double>(a.z[h0]);
-  t.R0 = a.R[h0];
-  t.X1 = static_cast<double>(a.x[h1]);
-  t.Y1 = static_cast<double>(a.y[h1]);
-  t.Z1 = static_cast<double>(a.z[h1]);
-  t.R1 = a.R[h1];
-  t.ar = t.R1 - t.R0;
-  t.az = t.Z1 - t.Z0;
-  t.La = t.ar * t.ar + t.az * t.az;
-  t.rmax = (a.layer[h0] == 0) ? k.rmax_bpix1 : k.rmax_other;
-  first = a.inner_first[h1];
-  last = min(first + a.inner_count[h1], a.cells_cap);
-}
+struct GeomArgs {
+  const int32_t* cell_count;
+  int32_t cells_cap;
+  const int32_t* inner;
+  const int32_t* outer;
+  const T* z;
+  const uint8_t* layer;
+  const double* R;
+  double* dr;
+  double* dz;
+  double* Ls;          // +L (outer hit on a barrel layer) or -L
+  int32_t* rank;       // rank among the cells ending on the same hit
+  int32_t* n_in;       // [n_hits + 1] cells ending on each hit
+  int32_t* out_start;
+  int32_t* out_count;
+  uint8_t* has_inner;
+};
 
-template <class T, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) k_links(DevCfg k, LinkIn<T> a) {
-  __shared__ int32_t s_scan[BLOCK / kWave + 1];
-  __shared__ int32_t s_base;
+constexpr int kGeomBlock = 256;
+constexpr int kGeomItems = 16;
+constexpr int kGeomChunk = kGeomBlock * kGeomItems;  // cells per block; also the hash table size
+static_assert((kGeomChunk & (kGeomChunk - 1)) == 0, "hash table size must be a power of two");
+
+// Cell geometry, and each cell's rank among the cells ending on its outer
+// hit.  The ranks are taken per block: the block's cells are grouped by
+// outer hit in an LDS hash table, each group reserves its run with one
+// global atomic, and a cell's rank is the run start plus its rank in the
+// group.  Cells of neighbouring inner hits share most outer hits, so this
+// takes far fewer global atomics than one per cell.
+template <class T>
+__global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> a) {
+  __shared__ int32_t s_key[kGeomChunk];    // outer hit of the slot, -1 when free
+  __shared__ int32_t s_cnt[kGeomChunk];    // cells in the slot, then the slot's global run start
+  __shared__ int32_t s_cell[kGeomChunk];   // per cell: slot | rank in the slot << 12
+  static_assert(kGeomChunk <= 4096, "slot and rank are packed in 12 bits each");
   const int n = min(*a.cell_count, a.cells_cap);
-  const int stride = gridDim.x * BLOCK;
-  const int rounds = (n + stride - 1) / stride;
-  const int lane = threadIdx.x % kWave;
-  const int wave = threadIdx.x / kWave;
-  for (int r = 0; r < rounds; ++r) {
-    const int cp = r * stride + blockIdx.x * BLOCK + threadIdx.x;
-    int buf[kLocal];
-    int cnt = 0;
-    bool overflow = false;
-    if (cp < n) {
-      Triplet t;
-      int first, last;
-      load_triplet(k, a, cp, t, first, last);
-      for (int c = first; c < last; ++c) {
-        if (link_pass(k, a, t, c)) {
-          if (cnt < kLocal) buf[cnt] = c;
-          ++cnt;
-        }
-      }
-      if (cnt > kLocal) {
-        overflow = true;
-        const int slot = atomicAdd(a.ovf_count, 1);
-        a.ovf[slot] = cp;
-        a.out_count[cp] = 0;
-      }
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kGeomChunk;
+  if (base >= n) return;
+  for (int i = threadIdx.x; i < kGeomChunk; i += kGeomBlock) {
+    s_key[i] = -1;
+    s_cnt[i] = 0;
+  }
+  __syncthreads();
+  for (int i = 0; i < kGeomItems; ++i) {
+    const int loc = i * kGeomBlock + threadIdx.x;
+    const int64_t c64 = base + loc;
+    if (c64 >= n) break;
+    const int c = static_cast<int>(c64);
+    const int h0 = a.inner[c];
+    const int h1 = a.outer[c];
+    const double dr = a.R[h1] - a.R[h0];
+    const double dz = static_cast<double>(a.z[h1]) - static_cast<double>(a.z[h0]);
+    const double L = dr * dr + dz * dz;
+    a.dr[c] = dr;
+    a.dz[c] = dz;
+    a.Ls[c] = k.layer_barrel[a.layer[h1]] ? L : -L;
+    a.out_start[c] = 0;
+    a.out_count[c] = 0;
+    a.has_inner[c] = 0;
+    // linear probing; the table has a slot for every cell of the block
+    int slot = static_cast<int>((static_cast<uint32_t>(h1) * 2654435761u) >> 20) & (kGeomChunk - 1);
+    while (true) {
+      const int prev = atomicCAS(&s_key[slot], -1, h1);
+      if (prev == -1 || prev == h1) break;
+      slot = (slot + 1) & (kGeomChunk - 1);
     }
-    const int mine = overflow ? 0 : cnt;
-    // block-wide exclusive prefix of `mine`
-    int v = mine;
+    const int r = atomicAdd(&s_cnt[slot], 1);
+    s_cell[loc] = slot | (r << 12);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kGeomChunk; i += kGeomBlock) {
+    const int key = s_key[i];
+    if (key >= 0) s_cnt[i] = atomicAdd(a.n_in + key, s_cnt[i]);
+  }
+  __syncthreads();
+  for (int i = 0; i < kGeomItems; ++i) {
+    const int loc = i * kGeomBlock + threadIdx.x;
+    const int64_t c64 = base + loc;
+    if (c64 >= n) break;
+    const int v = s_cell[loc];
+    a.rank[c64] = s_cnt[v & (kGeomChunk - 1)] + (v >> 12);
+  }
+}
+
+template <class T>
+__global__ void k_by_outer(const int32_t* __restrict__ cell_count, int32_t cells_cap,
+                           const int32_t* __restrict__ inner, const int32_t* __restrict__ outer,
+                           const T* __restrict__ x, const T* __restrict__ y, const uint8_t* __restrict__ layer,
+                           const double* __restrict__ dr, const double* __restrict__ dz,
+                           const double* __restrict__ Ls, const int32_t* __restrict__ rank,
+                           const int32_t* __restrict__ first_in, InCell* __restrict__ rec) {
+  const int n = min(*cell_count, cells_cap);
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const int h0 = inner[c];
+    InCell r;
+    r.ar = dr[c];
+    r.az = dz[c];
+    r.La = fabs(Ls[c]);
+    r.X0 = static_cast<double>(x[h0]);
+    r.Y0 = static_cast<double>(y[h0]);
+    r.cell = c;
+    r.bpix1 = layer[h0] == 0;
+    rec[first_in[outer[c]] + rank[c]] = r;
+  }
+}
+
+// Per-wave LDS of k_link_hits.
+struct WaveLds {
+  int32_t queue[2 * kWave];      // queued pairs: out-cell offset << 6 | in-cell lane
+  double X0[kWave], Y0[kWave];
+  int32_t bpix1[kWave];
+  int32_t cnt[kWave];            // links found per in-cell lane
+  int32_t found[kWave * kLocal]; // their out-cells
+};
+
+template <class T>
+struct HitArgs {
+  int32_t n_hits;
+  const T* x;
+  const T* y;
+  const int32_t* cell_count;
+  int32_t cells_cap;
+  const int32_t* outer;
+  const int32_t* inner_first;
+  const int32_t* inner_count;
+  const int32_t* first_in;
+  const InCell* rec;
+  int32_t* lcnt;      // [cells_cap + 1] links of each in-cell record (scanned afterwards)
+  int32_t* spill;     // [cells_cap][kLocal] their out-cells, ascending (when at most kLocal)
+  int32_t* ovf;       // in-cells with more than kLocal links
+  int32_t* ovf_count;
+};
+
+// Beam-spot test of the first nq queued pairs, one per lane; cb is the first
+// out-cell of the segment the queued offsets refer to.
+template <class T>
+__device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a, WaveLds& L, int nq, int cb,
+                                           double X1, double Y1) {
+  const int lane = __lane_id();
+  if (lane < nq) {
+    const int e = L.queue[lane];
+    const int j = e >> 6;
+    const int li = e & (kWave - 1);
+    const int h2 = a.outer[cb + j];
+    const double rmax = L.bpix1[li] ? k.rmax_bpix1 : k.rmax_other;
+    if (beam_pass(L.X0[li], L.Y0[li], X1, Y1, static_cast<double>(a.x[h2]), static_cast<double>(a.y[h2]),
+                  rmax)) {
+      const int slot = atomicAdd(&L.cnt[li], 1);
+      if (slot < kLocal) L.found[li * kLocal + slot] = cb + j;
+    }
+  }
+}
+
+// One wavefront per middle hit; WAVES independent wavefronts per block.
+template <class T, int WAVES>
+__global__ void __launch_bounds__(WAVES * kWave)
+    k_link_hits(DevCfg k, HitArgs<T> a, const double* __restrict__ gdr, const double* __restrict__ gdz,
+                const double* __restrict__ gLs) {
+  __shared__ WaveLds lds[WAVES];
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  const int lane = __lane_id();
+  WaveLds& L = lds[wave];
+  const int h1 = blockIdx.x * WAVES + wave;
+  if (h1 >= a.n_hits) return;
+  const int ib = a.first_in[h1];
+  const int ie = a.first_in[h1 + 1];
+  if (ie <= ib) return;
+  const int n_cells = min(*a.cell_count, a.cells_cap);
+  const int cb = a.inner_first[h1];
+  const int nb = min(cb + a.inner_count[h1], n_cells) - cb;
+  if (a.inner_count[h1] <= 0 || nb <= 0) {  // no out-cells: no links
+    for (int r = ib + lane; r < ie; r += kWave) a.lcnt[r] = 0;
+    return;
+  }
+  const double X1 = static_cast<double>(a.x[h1]);
+  const double Y1 = static_cast<double>(a.y[h1]);
+  const double th2b = k.theta2_barrel, th2e = k.theta2_endcap;
+
+  for (int base = ib; base < ie; base += kWave) {
+    const int m = min(kWave, ie - base);
+    // in-cell of this lane (NaN makes the R-Z test fail for idle lanes)
+    double ar = __builtin_nan(""), az = __builtin_nan(""), La = __builtin_nan("");
+    int cell = -1;
+    if (lane < m) {
+      const InCell r = a.rec[base + lane];
+      ar = r.ar;
+      az = r.az;
+      La = r.La;
+      cell = r.cell;
+      L.X0[lane] = r.X0;
+      L.Y0[lane] = r.Y0;
+      L.bpix1[lane] = r.bpix1;
+    }
+    L.cnt[lane] = 0;
+    wave_sync();
+
+    // Sweep the out-cells in segments short enough for the packed queue
+    // entries (offset << 6 | lane).
+    for (int sb = 0; sb < nb; sb += kSegment) {
+      const int cs = cb + sb;
+      const int ns = min(kSegment, nb - sb);
+      int qn = 0;  // queued pairs (uniform)
+      // Queues the passing lanes of out-cell j; runs a beam batch when a full
+      // wave of pairs is waiting.
+      auto append = [&](int j, bool pass, uint64_t mk) {
+        if (pass) L.queue[qn + lane_prefix(mk)] = (j << 6) | lane;
+        qn += __popcll(mk);
+        if (qn >= kWave) {
+          wave_sync();
+          beam_batch(k, a, L, kWave, cs, X1, Y1);
+          qn -= kWave;
+          const int t = (lane < qn) ? L.queue[kWave + lane] : 0;
+          wave_sync();
+          if (lane < qn) L.queue[lane] = t;
+          wave_sync();
+        }
+      };
+      int j = 0;
+      // the loads of the next group are issued before the tests of this one
+      double pdr[kUnroll], pdz[kUnroll], pLs[kUnroll];
+      if (kUnroll <= ns) {
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int o = __shfl_up(v, d, kWave);
-      if (lane >= d) v += o;
-    }
-    if (lane == kWave - 1) s_scan[wave] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int run = 0;
-      for (int w = 0; w < BLOCK / kWave; ++w) {
-        const int x = s_scan[w];
-        s_scan[w] = run;
-        run += x;
-      }
-      s_base = run ? atomicAdd(a.links_count, run) : 0;
-    }
-    __syncthreads();
-    const int pos = s_base + s_scan[wave] + v - mine;
-    __syncthreads();
-    if (cp < n && !overflow) {
-      a.out_start[cp] = pos;
-      a.out_count[cp] = cnt;
-      for (int i = 0; i < cnt; ++i) {
-        const int c = buf[i];
-        a.has_inner[c] = 1;
-        if (pos + i < a.links_cap) {
-          a.in_cell[pos + i] = cp;
-          a.out_cell[pos + i] = c;
+        for (int u = 0; u < kUnroll; ++u) {
+          pdr[u] = gdr[cs + u];
+          pdz[u] = gdz[cs + u];
+          pLs[u] = gLs[cs + u];
         }
+      }
+      for (; j + kUnroll <= ns; j += kUnroll) {
+        double cdr[kUnroll], cdz[kUnroll], cLs[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          cdr[u] = pdr[u];
+          cdz[u] = pdz[u];
+          cLs[u] = pLs[u];
+        }
+        if (j + 2 * kUnroll <= ns) {
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int c = cs + j + kUnroll + u;
+            pdr[u] = gdr[c];
+            pdz[u] = gdz[c];
+            pLs[u] = gLs[c];
+          }
+        }
+        bool pass[kUnroll];
+        uint64_t mk[kUnroll];
+        uint64_t any = 0;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const double theta2 = (__double2hiint(cLs[u]) < 0) ? th2e : th2b;  // end-cap outer hit: negative
+          pass[u] = rz_pass(ar, az, La, cdr[u], cdz[u], fabs(cLs[u]), theta2);
+          mk[u] = __ballot(pass[u]);
+          any |= mk[u];
+        }
+        if (any) {
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u)
+            if (mk[u]) append(j + u, pass[u], mk[u]);
+        }
+      }
+      for (; j < ns; ++j) {
+        const int c = cs + j;
+        const double Ls = gLs[c];
+        const double theta2 = (__double2hiint(Ls) < 0) ? th2e : th2b;  // end-cap outer hit: negative
+        const bool pass = rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2);
+        const uint64_t mk = __ballot(pass);
+        if (mk) append(j, pass, mk);
+      }
+      if (qn > 0) {
+        wave_sync();
+        beam_batch(k, a, L, qn, cs, X1, Y1);
+      }
+      wave_sync();
+    }
+
+    // record the link count of each in-cell, and its links sorted by out-cell
+    // when they fit the spill row; positions come from a scan afterwards
+    const int n = (lane < m) ? L.cnt[lane] : 0;
+    const int r = base + lane;
+    if (lane < m) {
+      a.lcnt[r] = n;
+      if (n > kLocal) {
+        const int slot = atomicAdd(a.ovf_count, 1);
+        a.ovf[slot] = cell;
+      }
+    }
+    if (n > 0 && n <= kLocal) {
+      int f[kLocal];
+#pragma unroll
+      for (int q = 0; q < kLocal; ++q) f[q] = (q < n) ? L.found[lane * kLocal + q] : INT32_MAX;
+#pragma unroll
+      for (int i = 1; i < kLocal; ++i) {
+#pragma unroll
+        for (int q = kLocal - 1; q >= i; --q) {
+          const int lo = min(f[q - 1], f[q]);
+          const int hi = max(f[q - 1], f[q]);
+          f[q - 1] = lo;
+          f[q] = hi;
+        }
+      }
+      int32_t* sp = a.spill + static_cast<int64_t>(r) * kLocal;
+#pragma unroll
+      for (int q = 0; q < kLocal; ++q)
+        if (q < n) sp[q] = f[q];
+    }
+    wave_sync();
+  }
+}
+
+// Places the links of every in-cell at its scanned position.
+struct EmitArgs {
+  const int32_t* cell_count;
+  int32_t cells_cap;
+  const int32_t* lcnt;   // scanned: first link of each record; lcnt[n] = total
+  const int32_t* spill;
+  const InCell* rec;
+  int32_t links_cap;
+  int32_t* in_cell;
+  int32_t* out_cell;
+  int32_t* out_start;
+  int32_t* out_count;
+  uint8_t* has_inner;
+};
+
+__global__ void k_link_emit(EmitArgs a) {
+  const int n = min(*a.cell_count, a.cells_cap);
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const int pos = a.lcnt[r];
+    const int cnt = a.lcnt[r + 1] - pos;
+    if (cnt == 0) continue;
+    const int cell = a.rec[r].cell;
+    a.out_start[cell] = pos;
+    a.out_count[cell] = cnt;
+    if (cnt > kLocal) continue;  // written by k_links_overflow
+    const int32_t* sp = a.spill + static_cast<int64_t>(r) * kLocal;
+    for (int q = 0; q < cnt; ++q) {
+      const int c = sp[q];
+      a.has_inner[c] = 1;
+      if (pos + q < a.links_cap) {
+        a.in_cell[pos + q] = cell;
+        a.out_cell[pos + q] = c;
       }
     }
   }
 }
 
-// Cells with more than kLocal outer links: count, reserve, then write.
+// In-cells with more than kLocal links: one thread each recomputes its links
+// and writes them at the position the scan gave it.
 template <class T>
-__global__ void k_links_overflow(DevCfg k, LinkIn<T> a) {
+__global__ void k_links_overflow(DevCfg k, HitArgs<T> a, const int32_t* __restrict__ inner,
+                                 const uint8_t* __restrict__ layer, const double* __restrict__ gdr,
+                                 const double* __restrict__ gdz, const double* __restrict__ gLs,
+                                 const int32_t* __restrict__ out_start, int32_t links_cap,
+                                 int32_t* __restrict__ in_cell, int32_t* __restrict__ out_cell,
+                                 uint8_t* __restrict__ has_inner) {
   const int m = *a.ovf_count;
+  const int n_cells = min(*a.cell_count, a.cells_cap);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
     const int cp = a.ovf[i];
-    Triplet t;
-    int first, last;
-    load_triplet(k, a, cp, t, first, last);
-    int cnt = 0;
-    for (int c = first; c < last; ++c) cnt += link_pass(k, a, t, c) ? 1 : 0;
-    const int pos = atomicAdd(a.links_count, cnt);
-    a.out_start[cp] = pos;
-    a.out_count[cp] = cnt;
-    int w = pos;
+    const int h0 = inner[cp];
+    const int h1 = a.outer[cp];
+    const double ar = gdr[cp], az = gdz[cp], La = fabs(gLs[cp]);
+    const double X0 = static_cast<double>(a.x[h0]), Y0 = static_cast<double>(a.y[h0]);
+    const double X1 = static_cast<double>(a.x[h1]), Y1 = static_cast<double>(a.y[h1]);
+    const double rmax = layer[h0] == 0 ? k.rmax_bpix1 : k.rmax_other;
+    const int first = a.inner_first[h1];
+    const int last = min(first + a.inner_count[h1], n_cells);
+    int w = out_start[cp];
     for (int c = first; c < last; ++c) {
-      if (link_pass(k, a, t, c)) {
-        a.has_inner[c] = 1;
-        if (w < a.links_cap) {
-          a.in_cell[w] = cp;
-          a.out_cell[w] = c;
-        }
-        ++w;
+      const double Ls = gLs[c];
+      const double theta2 = __builtin_signbit(Ls) ? k.theta2_endcap : k.theta2_barrel;
+      if (!rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2)) continue;
+      const int h2 = a.outer[c];
+      if (!beam_pass(X0, Y0, X1, Y1, static_cast<double>(a.x[h2]), static_cast<double>(a.y[h2]), rmax)) continue;
+      has_inner[c] = 1;
+      if (w < links_cap) {
+        in_cell[w] = cp;
+        out_cell[w] = c;
       }
+      ++w;
     }
   }
 }
@@ -226,41 +483,101 @@ __global__ void k_finish_links(const int32_t* count, int32_t cap, uint32_t* stat
 }  // namespace
 
 size_t ws_links(int n_hits, int cells_cap) {
+  const int64_t scan_n = std::max<int64_t>(n_hits, cells_cap);
   Carver c(nullptr);
-  c.take<double>(n_hits);
-  c.take<int32_t>(cells_cap);
-  c.take<int32_t>(1);
+  c.take<double>(n_hits);                   // R
+  c.take<double>(cells_cap);                // dr
+  c.take<double>(cells_cap);                // dz
+  c.take<double>(cells_cap);                // Ls
+  c.take<int32_t>(cells_cap);               // rank, then the overflow list
+  c.take<int32_t>(1);                       // overflow count
+  c.take<int32_t>(static_cast<size_t>(n_hits) + 1);     // in-cell counts -> first_in
+  c.take<int32_t>(static_cast<size_t>(cells_cap) + 1);  // links per record -> first link
+  c.take<int32_t>(scan_tmp_elems(scan_n));
+  c.take<InCell>(cells_cap);                // by-outer records
+  c.take<int32_t>(static_cast<size_t>(cells_cap) * kLocal);  // spilled links
   return c.off + 256;
+}
+
+template <class T, int WAVES>
+static void launch_hits(const DevCfg& k, const HitArgs<T>& a, const double* dr, const double* dz,
+                        const double* Ls, hipStream_t s) {
+  const int64_t blocks = (static_cast<int64_t>(a.n_hits) + WAVES - 1) / WAVES;
+  k_link_hits<T, WAVES><<<static_cast<unsigned>(blocks < 1 ? 1 : blocks), WAVES * kWave, 0, s>>>(k, a, dr, dz,
+                                                                                                 Ls);
+}
+
+__global__ void k_copy_links_total(const int32_t* __restrict__ lcnt, const int32_t* __restrict__ cell_count,
+                                   int32_t cells_cap, int32_t* __restrict__ links_count) {
+  *links_count = lcnt[min(*cell_count, cells_cap)];
 }
 
 template <class T>
 static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells, pt_links& L,
                         uint32_t* status, pt_workspace ws, hipStream_t s, int block) {
+  const int n = h.n_hits;
+  const int64_t scan_n = std::max<int64_t>(n, cells.cap);
   Carver c(ws.ptr);
-  double* R = c.take<double>(h.n_hits);
-  int32_t* ovf = c.take<int32_t>(cells.cap);
+  double* R = c.take<double>(n);
+  double* dr = c.take<double>(cells.cap);
+  double* dz = c.take<double>(cells.cap);
+  double* Ls = c.take<double>(cells.cap);
+  int32_t* rank = c.take<int32_t>(cells.cap);
   int32_t* ovf_count = c.take<int32_t>(1);
-  LinkIn<T> a{h.n_hits, static_cast<const T*>(h.x), static_cast<const T*>(h.y), static_cast<const T*>(h.z),
-              h.layer, R, cells.inner, cells.outer, cells.count, cells.cap, cells.inner_first,
-              cells.inner_count, L.cap, L.in_cell, L.out_cell, L.count, L.out_start, L.out_count,
-              L.has_inner, ovf, ovf_count, status};
-  if (fill_i32(L.count, 0, 1, s) != hipSuccess) return PT_ERR_DEVICE;
+  int32_t* first_in = c.take<int32_t>(static_cast<size_t>(n) + 1);
+  int32_t* lcnt = c.take<int32_t>(static_cast<size_t>(cells.cap) + 1);
+  int32_t* tmp = c.take<int32_t>(scan_tmp_elems(scan_n));
+  InCell* rec = c.take<InCell>(cells.cap);
+  int32_t* spill = c.take<int32_t>(static_cast<size_t>(cells.cap) * kLocal);
+  int32_t* ovf = rank;  // the ranks are dead once the index is built
+  const T* x = static_cast<const T*>(h.x);
+  const T* y = static_cast<const T*>(h.y);
+  const T* z = static_cast<const T*>(h.z);
+
   if (fill_i32(ovf_count, 0, 1, s) != hipSuccess) return PT_ERR_DEVICE;
-  k_radius<T><<<grid_for(h.n_hits, 256), 256, 0, s>>>(a, R);
-  PT_LAUNCH_CHECK();
-  k_clear_has_inner<<<grid_for(cells.cap, 256, 8192), 256, 0, s>>>(cells.count, cells.cap, L.has_inner);
-  PT_LAUNCH_CHECK();
+  if (fill_i32(first_in, 0, static_cast<int64_t>(n) + 1, s) != hipSuccess) return PT_ERR_DEVICE;
   void* tok = timing_begin(s);
-  if (block == 128)
-    k_links<T, 128><<<grid_for(cells.cap, 128, 32768), 128, 0, s>>>(k, a);
-  else if (block == 512)
-    k_links<T, 512><<<grid_for(cells.cap, 512, 8192), 512, 0, s>>>(k, a);
-  else
-    k_links<T, 256><<<grid_for(cells.cap, 256, 16384), 256, 0, s>>>(k, a);
+  if (n > 0) {
+    k_radius<T><<<grid_for(n, 256), 256, 0, s>>>(n, x, y, R);
+    PT_LAUNCH_CHECK();
+  }
+  GeomArgs<T> g{cells.count, cells.cap, cells.inner, cells.outer, z, h.layer, R, dr, dz, Ls, rank, first_in,
+                L.out_start, L.out_count, L.has_inner};
+  const int64_t geom_blocks = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kGeomChunk - 1) / kGeomChunk);
+  k_cell_geom<T><<<static_cast<unsigned>(geom_blocks), kGeomBlock, 0, s>>>(k, g);
+  PT_LAUNCH_CHECK();
+  if (exclusive_scan(first_in, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  k_by_outer<T><<<grid_for(cells.cap, 256, 16384), 256, 0, s>>>(cells.count, cells.cap, cells.inner,
+                                                                cells.outer, x, y, h.layer, dr, dz, Ls, rank,
+                                                                first_in, rec);
+  PT_LAUNCH_CHECK();
+  timing_end(tok, "link_index", s);
+
+  HitArgs<T> a{n, x, y, cells.count, cells.cap, cells.outer, cells.inner_first, cells.inner_count, first_in,
+               rec, lcnt, spill, ovf, ovf_count};
+  tok = timing_begin(s);
+  if (n > 0) {
+    if (block == 128)
+      launch_hits<T, 2>(k, a, dr, dz, Ls, s);
+    else if (block == 256)
+      launch_hits<T, 4>(k, a, dr, dz, Ls, s);
+    else
+      launch_hits<T, 1>(k, a, dr, dz, Ls, s);
+    PT_LAUNCH_CHECK();
+  }
   timing_end(tok, "links", s);
+  tok = timing_begin(s);
+  if (exclusive_scan_dev(lcnt, cells.cap, cells.count, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  EmitArgs e{cells.count, cells.cap, lcnt, spill, rec, L.cap, L.in_cell, L.out_cell, L.out_start, L.out_count,
+             L.has_inner};
+  k_link_emit<<<grid_for(cells.cap, 256, 16384), 256, 0, s>>>(e);
   PT_LAUNCH_CHECK();
-  k_links_overflow<T><<<64, 64, 0, s>>>(k, a);
+  k_links_overflow<T><<<64, 64, 0, s>>>(k, a, cells.inner, h.layer, dr, dz, Ls, L.out_start, L.cap, L.in_cell,
+                                        L.out_cell, L.has_inner);
   PT_LAUNCH_CHECK();
+  k_copy_links_total<<<1, 1, 0, s>>>(lcnt, cells.count, cells.cap, L.count);
+  PT_LAUNCH_CHECK();
+  timing_end(tok, "link_emit", s);
   k_finish_links<<<1, 1, 0, s>>>(L.count, L.cap, status);
   PT_LAUNCH_CHECK();
   return PT_OK;

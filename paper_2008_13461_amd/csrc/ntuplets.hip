@@ -2,13 +2,20 @@
 // the cell graph, maximal paths only) and duplicate removal (section 3.3:
 // among tracks sharing a hit doublet only those with the most hits stay).
 //
-// Roots are collected first (cells without outer links are skipped: their
-// path has two hits, below any useful minimum).  One thread per root walks
-// the graph with an explicit stack of at most max_hits - 1 cells.  Duplicate
-// removal is order independent: every row raises the per-cell maximum of its
-// length with atomicMax, then a row is kept when it attains the maximum on
-// every one of its cells.
+// No output position comes from a shared counter (same-address atomics
+// serialise on the device):
+//  - roots: each block counts the roots of a chunk of cells, a scan places
+//    the chunks, and the block writes its roots in cell order;
+//  - search: one thread per root walks the graph with an explicit stack of
+//    at most max_hits - 1 cells, first counting the paths it emits, then,
+//    after a scan over the roots, writing them at their final rows.  Rows
+//    therefore come out in root order and, per root, in search order.
+// Duplicate removal is order independent: every row raises the per-cell
+// maximum of its length with atomicMax, then a row is kept when it attains
+// the maximum on every one of its cells.
 #include "pt_internal.h"
+
+#include <algorithm>
 
 namespace pt {
 namespace {
@@ -39,17 +46,26 @@ struct TupIn {
   uint32_t* status;
 };
 
-// Append `take` items per thread to a global list with one atomic per block.
-__device__ inline int block_reserve(int take, int32_t* counter, int32_t* s_scan, int32_t* s_base) {
+constexpr int kRootItems = 16;                   // cells per thread of the root kernels
+constexpr int kRootChunk = kBlock * kRootItems;  // cells per block
+
+__device__ inline bool is_root(const DevCfg& k, const TupIn& a, int c) {
+  if (a.out_count[c] <= 0) return false;  // a root without outer links makes a 2-hit path
+  const int L = a.layer[a.cell_inner[c]];
+  return ((k.root_always_mask >> L) & 1u) || (((k.root_if_free_mask >> L) & 1u) && !a.has_inner[c]);
+}
+
+// Block-wide exclusive prefix of v; *total receives the block sum.
+__device__ inline int block_exclusive(int v, int32_t* s_scan, int* total) {
   const int lane = threadIdx.x % kWave;
   const int wave = threadIdx.x / kWave;
-  int v = take;
+  int incl = v;
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
-    const int o = __shfl_up(v, d, kWave);
-    if (lane >= d) v += o;
+    const int o = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += o;
   }
-  if (lane == kWave - 1) s_scan[wave] = v;
+  if (lane == kWave - 1) s_scan[wave] = incl;
   __syncthreads();
   if (threadIdx.x == 0) {
     int run = 0;
@@ -58,33 +74,50 @@ __device__ inline int block_reserve(int take, int32_t* counter, int32_t* s_scan,
       s_scan[w] = run;
       run += x;
     }
-    *s_base = run ? atomicAdd(counter, run) : 0;
+    s_scan[kBlock / kWave] = run;
   }
   __syncthreads();
-  const int pos = *s_base + s_scan[wave] + v - take;
+  const int ex = s_scan[wave] + incl - v;
+  *total = s_scan[kBlock / kWave];
   __syncthreads();
-  return pos;
+  return ex;
 }
 
-__global__ void __launch_bounds__(kBlock) k_roots(DevCfg k, TupIn a) {
+__global__ void __launch_bounds__(kBlock) k_root_count(DevCfg k, TupIn a, int32_t* __restrict__ chunk_roots) {
   __shared__ int32_t s_scan[kBlock / kWave + 1];
-  __shared__ int32_t s_base;
   const int n = min(*a.cell_count, a.cells_cap);
-  const int stride = gridDim.x * kBlock;
-  const int rounds = (n + stride - 1) / stride;
-  for (int r = 0; r < rounds; ++r) {
-    const int c = r * stride + blockIdx.x * kBlock + threadIdx.x;
-    bool root = false;
-    if (c < n && a.out_count[c] > 0) {
-      const int L = a.layer[a.cell_inner[c]];
-      root = ((k.root_always_mask >> L) & 1u) || (((k.root_if_free_mask >> L) & 1u) && !a.has_inner[c]);
-    }
-    const int pos = block_reserve(root ? 1 : 0, a.n_roots, s_scan, &s_base);
-    if (root) a.roots[pos] = c;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
+  int cnt = 0;
+  for (int i = 0; i < kRootItems; ++i) {
+    const int64_t c = base + i * kBlock + threadIdx.x;
+    if (c < n && is_root(k, a, static_cast<int>(c))) ++cnt;
+  }
+  int total;
+  block_exclusive(cnt, s_scan, &total);
+  if (threadIdx.x == 0) chunk_roots[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kBlock) k_root_write(DevCfg k, TupIn a, const int32_t* __restrict__ chunk_first) {
+  __shared__ int32_t s_scan[kBlock / kWave + 1];
+  const int n = min(*a.cell_count, a.cells_cap);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
+  if (base >= n) return;
+  int at = chunk_first[blockIdx.x];
+  for (int i = 0; i < kRootItems; ++i) {
+    const int64_t c = base + i * kBlock + threadIdx.x;
+    const bool root = c < n && is_root(k, a, static_cast<int>(c));
+    int total;
+    const int pos = at + block_exclusive(root ? 1 : 0, s_scan, &total);
+    if (root) a.roots[pos] = static_cast<int>(c);
+    at += total;
   }
 }
 
-__global__ void k_dfs(DevCfg k, TupIn a) {
+// Depth-first search from each root.  COUNT: paths[i] = rows root i emits
+// (and the truncation count); otherwise the rows are written from row
+// first_row[i] on.
+template <bool COUNT>
+__global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths) {
   const int nr = *a.n_roots;
   uint32_t truncated = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += gridDim.x * blockDim.x) {
@@ -93,6 +126,7 @@ __global__ void k_dfs(DevCfg k, TupIn a) {
     stack[0] = a.roots[i];
     next[0] = 0;
     int depth = 0;
+    int row = COUNT ? 0 : paths[i];
     while (depth >= 0) {
       const int c = stack[depth];
       const int oc = a.out_count[c];
@@ -107,10 +141,9 @@ __global__ void k_dfs(DevCfg k, TupIn a) {
       const int nh = depth + 3;  // hits of the path root..child
       const int coc = a.out_count[child];
       if (coc == 0 || nh == k.max_hits) {
-        if (coc > 0) ++truncated;
+        if (COUNT && coc > 0) ++truncated;
         if (nh >= k.min_hits) {
-          const int row = atomicAdd(a.count_raw, 1);
-          if (row < a.cap) {
+          if (!COUNT && row < a.cap) {
             int32_t* H = a.hits + static_cast<int64_t>(row) * kMaxHits;
             int32_t* C = a.cells + static_cast<int64_t>(row) * (kMaxHits - 1);
             H[0] = a.cell_inner[stack[0]];
@@ -124,6 +157,7 @@ __global__ void k_dfs(DevCfg k, TupIn a) {
             for (int d = depth + 2; d < kMaxHits - 1; ++d) C[d] = -1;
             a.n[row] = static_cast<uint8_t>(nh);
           }
+          ++row;
         }
       } else {
         ++depth;
@@ -131,11 +165,17 @@ __global__ void k_dfs(DevCfg k, TupIn a) {
         next[depth] = 0;
       }
     }
+    if (COUNT) paths[i] = row;
   }
-  if (truncated) {
-    status_add(a.status, PT_ST_TRUNCATED, truncated);
-    status_flag(a.status, PT_FLAG_TRUNCATED);
+  if (COUNT) {
+    const uint32_t total = wave_status_add(a.status, PT_ST_TRUNCATED, truncated);
+    if (total && __lane_id() == 0) status_flag(a.status, PT_FLAG_TRUNCATED);
   }
+}
+
+__global__ void k_copy_total_rows(const int32_t* __restrict__ paths, const int32_t* __restrict__ n_roots,
+                                  int32_t* __restrict__ count_raw) {
+  *count_raw = paths[*n_roots];
 }
 
 __global__ void k_clear_maxn(TupIn a) {
@@ -152,26 +192,45 @@ __global__ void k_maxn(TupIn a) {
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_keep(TupIn a) {
+__device__ inline bool keep_row(const TupIn& a, int t) {
+  const int nh = a.n[t];
+  const int32_t* C = a.cells + static_cast<int64_t>(t) * (kMaxHits - 1);
+  for (int d = 0; d < nh - 1; ++d)
+    if (a.max_n[C[d]] != nh) return false;
+  return true;
+}
+
+__global__ void __launch_bounds__(kBlock) k_keep_count(TupIn a, int32_t* __restrict__ chunk_kept) {
   __shared__ int32_t s_scan[kBlock / kWave + 1];
-  __shared__ int32_t s_base;
   const int rows = min(*a.count_raw, a.cap);
-  const int stride = gridDim.x * kBlock;
-  const int rounds = (rows + stride - 1) / stride;
-  for (int r = 0; r < rounds; ++r) {
-    const int t = r * stride + blockIdx.x * kBlock + threadIdx.x;
-    bool keep = false;
-    if (t < rows) {
-      keep = true;
-      const int nh = a.n[t];
-      const int32_t* C = a.cells + static_cast<int64_t>(t) * (kMaxHits - 1);
-      for (int d = 0; d < nh - 1; ++d)
-        if (a.max_n[C[d]] != nh) keep = false;
-    }
-    const int pos = block_reserve(keep ? 1 : 0, a.count, s_scan, &s_base);
-    if (keep) a.kept[pos] = t;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
+  int cnt = 0;
+  for (int i = 0; i < kRootItems; ++i) {
+    const int64_t t = base + i * kBlock + threadIdx.x;
+    if (t < rows && keep_row(a, static_cast<int>(t))) ++cnt;
+  }
+  int total;
+  block_exclusive(cnt, s_scan, &total);
+  if (threadIdx.x == 0) chunk_kept[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kBlock) k_keep_write(TupIn a, const int32_t* __restrict__ chunk_first) {
+  __shared__ int32_t s_scan[kBlock / kWave + 1];
+  const int rows = min(*a.count_raw, a.cap);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
+  if (base >= rows) return;
+  int at = chunk_first[blockIdx.x];
+  for (int i = 0; i < kRootItems; ++i) {
+    const int64_t t = base + i * kBlock + threadIdx.x;
+    const bool keep = t < rows && keep_row(a, static_cast<int>(t));
+    int total;
+    const int pos = at + block_exclusive(keep ? 1 : 0, s_scan, &total);
+    if (keep) a.kept[pos] = static_cast<int>(t);
+    at += total;
   }
 }
+
+__global__ void k_copy_total(const int32_t* __restrict__ src, int32_t* __restrict__ dst) { *dst = *src; }
 
 __global__ void k_finish_tuplets(const int32_t* count_raw, int32_t cap, uint32_t* status) {
   if (*count_raw > cap) status_flag(status, PT_FLAG_TUPLETS_OVERFLOW);
@@ -180,38 +239,65 @@ __global__ void k_finish_tuplets(const int32_t* count_raw, int32_t cap, uint32_t
 }  // namespace
 
 size_t ws_ntuplets(int cells_cap, int tuplets_cap) {
-  (void)tuplets_cap;
+  const int64_t chunks = std::max<int64_t>(
+      1, std::max<int64_t>((static_cast<int64_t>(cells_cap) + kRootChunk - 1) / kRootChunk,
+                           (static_cast<int64_t>(tuplets_cap) + kRootChunk - 1) / kRootChunk));
+  const int64_t scan_n = std::max<int64_t>(chunks, cells_cap);
   Carver c(nullptr);
-  c.take<int32_t>(cells_cap);  // roots
-  c.take<int32_t>(1);          // n_roots
-  c.take<int32_t>(cells_cap);  // max_n
+  c.take<int32_t>(cells_cap);      // roots
+  c.take<int32_t>(chunks + 1);     // roots (then kept rows) per chunk -> chunk offsets (+ total)
+  c.take<int32_t>(static_cast<size_t>(cells_cap) + 1);  // paths per root -> first row (+ total)
+  c.take<int32_t>(cells_cap);      // max_n
+  c.take<int32_t>(scan_tmp_elems(scan_n));
   return c.off + 256;
 }
 
 pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells, const pt_links& L,
                        pt_ntuplets& T, uint32_t* status, pt_workspace ws, hipStream_t s) {
+  const int64_t chunks = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kRootChunk - 1) / kRootChunk);
+  const int64_t chunks_max = std::max<int64_t>(chunks, (static_cast<int64_t>(T.cap) + kRootChunk - 1) / kRootChunk);
+  const int64_t scan_n = std::max<int64_t>(chunks_max, cells.cap);
   Carver c(ws.ptr);
   int32_t* roots = c.take<int32_t>(cells.cap);
-  int32_t* n_roots = c.take<int32_t>(1);
+  int32_t* chunk_roots = c.take<int32_t>(chunks_max + 1);
+  int32_t* paths = c.take<int32_t>(static_cast<size_t>(cells.cap) + 1);
   int32_t* max_n = c.take<int32_t>(cells.cap);
+  int32_t* tmp = c.take<int32_t>(scan_tmp_elems(scan_n));
+  int32_t* n_roots = chunk_roots + chunks;  // the scan's total
   TupIn a{h.layer, cells.inner, cells.outer, cells.count, cells.cap, L.out_start, L.out_count, L.out_cell,
           L.has_inner, L.cap, roots, n_roots, T.cap, T.hits, T.cells, T.n, T.count_raw, T.kept, T.count,
           max_n, status};
-  if (fill_i32(n_roots, 0, 1, s) != hipSuccess) return PT_ERR_DEVICE;
-  if (fill_i32(T.count_raw, 0, 1, s) != hipSuccess) return PT_ERR_DEVICE;
-  if (fill_i32(T.count, 0, 1, s) != hipSuccess) return PT_ERR_DEVICE;
-  k_roots<<<grid_for(cells.cap, kBlock, 16384), kBlock, 0, s>>>(k, a);
-  PT_LAUNCH_CHECK();
   void* tok = timing_begin(s);
-  k_dfs<<<grid_for(cells.cap, 128, 8192), 128, 0, s>>>(k, a);
+  k_root_count<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots);
+  PT_LAUNCH_CHECK();
+  if (exclusive_scan(chunk_roots, chunks, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  k_root_write<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots);
+  PT_LAUNCH_CHECK();
+  timing_end(tok, "roots", s);
+  tok = timing_begin(s);
+  k_dfs<true><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths);
+  PT_LAUNCH_CHECK();
+  if (exclusive_scan_dev(paths, cells.cap, n_roots, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  k_dfs<false><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths);
   timing_end(tok, "dfs", s);
   PT_LAUNCH_CHECK();
+  // rows found = paths[n_roots] (the scan's total)
+  k_copy_total_rows<<<1, 1, 0, s>>>(paths, n_roots, T.count_raw);
+  PT_LAUNCH_CHECK();
+  tok = timing_begin(s);
   k_clear_maxn<<<grid_for(cells.cap, 256, 8192), 256, 0, s>>>(a);
   PT_LAUNCH_CHECK();
   k_maxn<<<grid_for(T.cap, 256, 8192), 256, 0, s>>>(a);
   PT_LAUNCH_CHECK();
-  k_keep<<<grid_for(T.cap, kBlock, 8192), kBlock, 0, s>>>(a);
+  const int64_t row_chunks = std::max<int64_t>(1, (static_cast<int64_t>(T.cap) + kRootChunk - 1) / kRootChunk);
+  k_keep_count<<<static_cast<unsigned>(row_chunks), kBlock, 0, s>>>(a, chunk_roots);
   PT_LAUNCH_CHECK();
+  if (exclusive_scan(chunk_roots, row_chunks, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  k_keep_write<<<static_cast<unsigned>(row_chunks), kBlock, 0, s>>>(a, chunk_roots);
+  PT_LAUNCH_CHECK();
+  k_copy_total<<<1, 1, 0, s>>>(chunk_roots + row_chunks, T.count);
+  PT_LAUNCH_CHECK();
+  timing_end(tok, "dedup", s);
   k_finish_tuplets<<<1, 1, 0, s>>>(T.count_raw, T.cap, status);
   PT_LAUNCH_CHECK();
   return PT_OK;

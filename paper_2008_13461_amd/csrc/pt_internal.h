@@ -77,6 +77,9 @@ size_t ws_fit(int n_max, int n_modules);
 // total.  tmp must hold scan_tmp_elems(n) int32.
 size_t scan_tmp_elems(int64_t n);
 hipError_t exclusive_scan(int32_t* data, int64_t n, int32_t* tmp, hipStream_t s);
+// The same over the first min(*n_dev, n) values, n_dev a device count; the
+// total goes to data[min(*n_dev, n)].
+hipError_t exclusive_scan_dev(int32_t* data, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s);
 
 // Fill helpers (graph-safe: kernels, not hipMemsetAsync).
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
@@ -110,11 +113,20 @@ __device__ inline void status_add(uint32_t* st, int word, uint32_t v) {
   if (st && v) atomicAdd(st + word, v);
 }
 
+// status_add summed over the wavefront first: one atomic per wavefront.  All
+// lanes of the wavefront must call it.
+// Returns the wavefront's total.
+__device__ inline uint32_t wave_status_add(uint32_t* st, int word, uint32_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  if (__lane_id() == 0) status_add(st, word, v);
+  return v;
+}
+
 // Number of set bits of a wave mask below this lane.
 __device__ inline int lane_prefix(uint64_t mask) {
-  const int lane = __lane_id();
-  const uint64_t below = (lane == 0) ? 0ull : (mask & ((1ull << lane) - 1ull));
-  return __popcll(below);
+  return static_cast<int>(__builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u)));
 }
 
 }  // namespace pt

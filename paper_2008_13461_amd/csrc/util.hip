@@ -36,23 +36,40 @@ __device__ inline int32_t block_inclusive_scan(int32_t v, int32_t* lds, int32_t*
   return v;
 }
 
+// n_dev, when given, holds the number of items actually present (<= n).
+__device__ inline int64_t items(int64_t n, const int32_t* n_dev) {
+  if (!n_dev) return n;
+  const int64_t m = *n_dev;
+  return m < 0 ? 0 : (m < n ? m : n);
+}
+
 __global__ void __launch_bounds__(kScanBlock) k_tile_sums(const int32_t* __restrict__ data, int64_t n,
+                                                          const int32_t* __restrict__ n_dev,
                                                           int32_t* __restrict__ sums) {
   __shared__ int32_t lds[kScanBlock / kWave + 1];
+  n = items(n, n_dev);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + threadIdx.x * kScanItems;
   int32_t s = 0;
+  if (static_cast<int64_t>(blockIdx.x) * kTile < n) {
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i)
-    if (base + i < n) s += data[base + i];
+    for (int i = 0; i < kScanItems; ++i)
+      if (base + i < n) s += data[base + i];
+  }
   int32_t total;
   block_inclusive_scan(s, lds, &total);
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
 __global__ void __launch_bounds__(kScanBlock) k_tile_scan(int32_t* __restrict__ data, int64_t n,
+                                                          const int32_t* __restrict__ n_dev,
                                                           const int32_t* __restrict__ offsets) {
   __shared__ int32_t lds[kScanBlock / kWave + 1];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + threadIdx.x * kScanItems;
+  n = items(n, n_dev);
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * kTile;
+  // the block holding the last item (block 0 when there is none) writes the total
+  const int64_t last_block = n > 0 ? (n - 1) / kTile : 0;
+  if (static_cast<int64_t>(blockIdx.x) > last_block) return;
+  const int64_t base = first + threadIdx.x * kScanItems;
   int32_t v[kScanItems];
   int32_t s = 0;
 #pragma unroll
@@ -68,7 +85,7 @@ __global__ void __launch_bounds__(kScanBlock) k_tile_scan(int32_t* __restrict__ 
     if (base + i < n) data[base + i] = run;
     run += v[i];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+  if (static_cast<int64_t>(blockIdx.x) == last_block && threadIdx.x == 0)
     data[n] = total + (offsets ? offsets[blockIdx.x] : 0);
 }
 
@@ -91,21 +108,25 @@ size_t scan_tmp_elems(int64_t n) {
   return total + 1;
 }
 
-hipError_t exclusive_scan(int32_t* data, int64_t n, int32_t* tmp, hipStream_t s) {
+hipError_t exclusive_scan_dev(int32_t* data, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s) {
   if (n <= 0) {
     k_fill<int32_t><<<1, 1, 0, s>>>(data, 0, 1);
     return hipGetLastError();
   }
   const int64_t nb = (n + kTile - 1) / kTile;
   if (nb == 1) {
-    k_tile_scan<<<1, kScanBlock, 0, s>>>(data, n, nullptr);
+    k_tile_scan<<<1, kScanBlock, 0, s>>>(data, n, n_dev, nullptr);
     return hipGetLastError();
   }
-  k_tile_sums<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, tmp);
-  hipError_t e = exclusive_scan(tmp, nb, tmp + nb + 1, s);
+  k_tile_sums<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, n_dev, tmp);
+  hipError_t e = exclusive_scan_dev(tmp, nb, nullptr, tmp + nb + 1, s);
   if (e != hipSuccess) return e;
-  k_tile_scan<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, tmp);
+  k_tile_scan<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, n_dev, tmp);
   return hipGetLastError();
+}
+
+hipError_t exclusive_scan(int32_t* data, int64_t n, int32_t* tmp, hipStream_t s) {
+  return exclusive_scan_dev(data, n, nullptr, tmp, s);
 }
 
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
