@@ -2,13 +2,13 @@
 //
 // Hits are first binned per (event, layer, azimuth bin) by a counting sort
 // (the "tiled data structure along phi" of the paper), with the sorted
-// coordinates promoted to double.  Doublets are then built by one thread per
-// inner hit that loops over the layer pairs starting on its layer and scans
-// the outer hits in the azimuth bins around it.  Two passes -- count, scan,
-// write -- give every inner hit a contiguous, deterministic run of cells
-// without any per-cell atomic: the cells come out grouped by inner hit in the
-// sorted order, and (inner_first, inner_count) index them by hit for the
-// linking step.
+// coordinates promoted to double.  Doublets are then built by one wavefront
+// per inner hit that loops over the layer pairs starting on its layer and
+// scans the outer hits in the azimuth bins around it, one outer hit per lane.
+// Two passes -- count, scan, write -- give every inner hit a contiguous,
+// deterministic run of cells without any per-cell atomic: the cells come out
+// grouped by inner hit in the sorted order (pair order, then window order),
+// and (inner_first, inner_count) index them by hit for the linking step.
 #include "pt_internal.h"
 
 #include <algorithm>
@@ -136,78 +136,91 @@ struct DoubletArgs {
   int32_t* inner_count;
 };
 
-// One thread per sorted inner hit: every pair starting on its layer, every
-// outer hit in the azimuth bins around it.
-template <bool WRITE>
-__global__ void __launch_bounds__(512) k_doublets(DevCfg k, DoubletArgs a) {
-  const int total = a.bin_start[-1];  // valid (sorted) hits
+// The azimuth-bin ranges of the outer layer of pair p scanned for an inner
+// hit in bin b: [r0a, r0b) and [r1a, r1b) (the second one non-empty when the
+// window wraps around phi = +-pi).
+__device__ inline void window_ranges(const DevCfg& k, const int32_t* bin_start, int p, int e, int b,
+                                     int& r0a, int& r0b, int& r1a, int& r1b) {
   const int B = k.n_bins;
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.n_hits; j += gridDim.x * blockDim.x) {
-    if (j >= total) {
-      if (!WRITE) a.cnt[j] = 0;
-      continue;
+  const int base = (e * kLayers + k.pair_outer[p]) * B;
+  const int w = k.pair_wbins[p];
+  r1a = r1b = 0;
+  if (2 * w + 1 >= B) {
+    r0a = bin_start[base];
+    r0b = bin_start[base + B];
+    return;
+  }
+  const int lo = b - w, hi = b + w;
+  if (lo < 0) {
+    r0a = bin_start[base + lo + B];
+    r0b = bin_start[base + B];
+    r1a = bin_start[base];
+    r1b = bin_start[base + hi + 1];
+  } else if (hi >= B) {
+    r0a = bin_start[base + lo];
+    r0b = bin_start[base + B];
+    r1a = bin_start[base];
+    r1b = bin_start[base + hi - B + 1];
+  } else {
+    r0a = bin_start[base + lo];
+    r0b = bin_start[base + hi + 1];
+  }
+}
+
+// One wavefront per sorted inner hit: its coordinates are wave-uniform, the
+// lanes take consecutive outer hits of each window (coalesced loads), and the
+// passing ones are compacted with a ballot, so that the cells of the inner
+// hit are written as one contiguous, coalesced run.  COUNT = false writes the
+// cells at the scanned offsets, in pair order then window order.
+template <bool WRITE, int WAVES>
+__global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArgs a) {
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  const int lane = __lane_id();
+  const int j = blockIdx.x * WAVES + wave;
+  if (j >= a.n_hits) return;
+  const int total = a.bin_start[-1];  // valid (sorted) hits
+  if (j >= total) {
+    if (!WRITE && lane == 0) a.cnt[j] = 0;
+    return;
+  }
+  const int B = k.n_bins;
+  const int key = a.skey[j];
+  const int b = key % B;
+  const int el = key / B;
+  const int lay = el % kLayers;
+  const int e = el / kLayers;
+  const double Xi = a.sX[j], Yi = a.sY[j], Zi = a.sZ[j], Ri = a.sR[j];
+  int pos = WRITE ? a.off[j] : 0;  // uniform
+  const int hit_i = WRITE ? a.sorted_hit[j] : 0;
+  const int np = k.n_inner_pairs[lay];
+  for (int q = 0; q < np; ++q) {
+    const int p = k.inner_pairs[lay][q];
+    if (k.cut_mask & PT_CUT_ZW) {
+      if (!(k.zlo[p] <= Zi && Zi <= k.zhi[p])) continue;
     }
-    const int key = a.skey[j];
-    const int b = key % B;
-    const int el = key / B;
-    const int lay = el % kLayers;
-    const int e = el / kLayers;
-    const double Xi = a.sX[j], Yi = a.sY[j], Zi = a.sZ[j], Ri = a.sR[j];
-    int count = 0;
-    int wpos = WRITE ? a.off[j] : 0;
-    const int hit_i = WRITE ? a.sorted_hit[j] : 0;
-    const int np = k.n_inner_pairs[lay];
-    for (int s = 0; s < np; ++s) {
-      const int p = k.inner_pairs[lay][s];
-      if (k.cut_mask & PT_CUT_ZW) {
-        if (!(k.zlo[p] <= Zi && Zi <= k.zhi[p])) continue;
-      }
-      const int lo_layer = k.pair_outer[p];
-      const int base = (e * kLayers + lo_layer) * B;
-      const int w = k.pair_wbins[p];
-      int r0a, r0b, r1a = 0, r1b = 0;
-      if (2 * w + 1 >= B) {
-        r0a = a.bin_start[base];
-        r0b = a.bin_start[base + B];
-      } else {
-        int lo = b - w, hi = b + w;
-        if (lo < 0) {
-          r0a = a.bin_start[base + lo + B];
-          r0b = a.bin_start[base + B];
-          r1a = a.bin_start[base];
-          r1b = a.bin_start[base + hi + 1];
-        } else if (hi >= B) {
-          r0a = a.bin_start[base + lo];
-          r0b = a.bin_start[base + B];
-          r1a = a.bin_start[base];
-          r1b = a.bin_start[base + hi - B + 1];
-        } else {
-          r0a = a.bin_start[base + lo];
-          r0b = a.bin_start[base + hi + 1];
-        }
-      }
-#pragma unroll 1
-      for (int r = 0; r < 2; ++r) {
-        const int s0 = r == 0 ? r0a : r1a;
-        const int s1 = r == 0 ? r0b : r1b;
-        for (int o = s0; o < s1; ++o) {
-          if (doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o])) {
-            if (WRITE) {
-              if (wpos < a.cap) {
-                a.inner[wpos] = hit_i;
-                a.outer[wpos] = a.sorted_hit[o];
-                a.pair[wpos] = static_cast<uint8_t>(p);
-              }
-              ++wpos;
-            } else {
-              ++count;
-            }
+    int ra[2], rb[2];
+    window_ranges(k, a.bin_start, p, e, b, ra[0], rb[0], ra[1], rb[1]);
+    for (int r = 0; r < 2; ++r) {
+      for (int o0 = ra[r]; o0 < rb[r]; o0 += kWave) {
+        const int o = o0 + lane;
+        bool pass = false;
+        if (o < rb[r]) pass = doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
+        const uint64_t m = __ballot(pass);
+        if (WRITE && pass) {
+          const int w = pos + lane_prefix(m);
+          if (w < a.cap) {
+            a.inner[w] = hit_i;
+            a.outer[w] = a.sorted_hit[o];
+            a.pair[w] = static_cast<uint8_t>(p);
           }
         }
+        pos += __popcll(m);
       }
     }
+  }
+  if (lane == 0) {
     if (!WRITE) {
-      a.cnt[j] = count;
+      a.cnt[j] = pos;
     } else {
       const int first = a.off[j];
       a.inner_first[hit_i] = first;
@@ -248,6 +261,24 @@ size_t ws_doublets(int n_hits, int n_events, int n_bins) {
   return c.off + 256;
 }
 
+template <bool WRITE>
+static void launch_doublets(const DevCfg& k, const DoubletArgs& a, int n, int block, hipStream_t s) {
+  const int64_t hits = std::max(n, 1);
+  switch (block) {
+    case 64:
+      k_doublets<WRITE, 1><<<static_cast<unsigned>(hits), 64, 0, s>>>(k, a);
+      break;
+    case 128:
+      k_doublets<WRITE, 2><<<static_cast<unsigned>((hits + 1) / 2), 128, 0, s>>>(k, a);
+      break;
+    case 512:
+      k_doublets<WRITE, 8><<<static_cast<unsigned>((hits + 7) / 8), 512, 0, s>>>(k, a);
+      break;
+    default:
+      k_doublets<WRITE, 4><<<static_cast<unsigned>((hits + 3) / 4), 256, 0, s>>>(k, a);
+  }
+}
+
 template <class T>
 static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, uint32_t* status,
                            pt_workspace ws, hipStream_t s) {
@@ -286,12 +317,12 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   const int block = (k.block_doublets == 64 || k.block_doublets == 128 || k.block_doublets == 512)
                         ? k.block_doublets : 256;
   void* tok = timing_begin(s);
-  k_doublets<false><<<grid_for(n, block), block, 0, s>>>(k, a);
+  launch_doublets<false>(k, a, n, block, s);
   timing_end(tok, "doublets_count", s);
   PT_LAUNCH_CHECK();
   if (exclusive_scan(cnt, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  k_doublets<true><<<grid_for(n, block), block, 0, s>>>(k, a);
+  launch_doublets<true>(k, a, n, block, s);
   timing_end(tok, "doublets_write", s);
   PT_LAUNCH_CHECK();
   k_finish_cells<<<1, 1, 0, s>>>(cnt + n, cells.cap, cells.count, status);

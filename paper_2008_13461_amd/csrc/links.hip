@@ -6,22 +6,25 @@
 // are billions of them and only about 2% pass the R-Z alignment test, so the
 // step is organised around that test:
 //
-//  1. k_cell_geom: every cell's R-Z segment (dr, dz) and its squared length,
+//  1. k_hit_table: (X, Y, Z, R) of every hit in double, one 32-byte entry.
+//  2. k_cell_geom: every cell's R-Z segment (dr, dz) and its squared length,
 //     once, in cell order; the length carries the sign of the barrel/end-cap
 //     class of the cell's outer hit (the class of h2 selects theta).  Each
-//     cell also takes a rank among the cells ending on its outer hit.
-//  2. exclusive scan of the per-hit in-cell counts, then k_by_outer: an
-//     index of the cells by outer hit, one 48-byte record per cell holding
-//     what the triplet tests need from c' (segment, length, h0 position).
-//  3. k_link_hits: one wavefront per middle hit.  Lanes hold the in-cells;
+//     cell also takes a rank among the cells ending on its outer hit, with
+//     the atomics aggregated per block in an LDS hash table.
+//  3. exclusive scan of the per-hit in-cell counts, then k_by_outer: an
+//     index of the cells by outer hit, 8 bytes per cell (cell, inner hit).
+//  4. k_link_hits: one wavefront per middle hit.  Lanes hold the in-cells;
 //     the out-cells (a contiguous run, grouped by inner hit by the doublet
 //     step) are swept in a uniform loop whose loads are wave-uniform, so the
 //     R-Z test of 64 pairs costs a handful of double-precision instructions
 //     and no per-pair gather.  Pairs that pass are queued in LDS and the
 //     beam-spot test (divisions, square roots) runs on full waves of queued
-//     pairs.  Links of an in-cell collect in LDS, are sorted by out-cell and
-//     written as one contiguous run per in-cell, with one atomic reservation
-//     per wave.  In-cells with more than kLocal links go to k_links_overflow.
+//     pairs.  Each in-cell's link count is recorded, with its links sorted by
+//     out-cell when there are at most kLocal of them.
+//  5. a scan of the counts places every in-cell's links (no shared counter:
+//     same-address atomics serialise), k_link_emit writes them, and
+//     k_links_overflow recomputes the few in-cells with more than kLocal.
 #include "pt_internal.h"
 
 #include <algorithm>
@@ -36,14 +39,14 @@ constexpr int kLocal = 8;        // links an in-cell keeps in LDS before the ove
 constexpr int kUnroll = 4;       // out-cells tested per step of the sweep
 constexpr int kSegment = 1 << 24;  // out-cells per queue segment (offsets fit beside the lane)
 
-// What the triplet tests need from an in-cell c' = (h0, h1).
-struct alignas(16) InCell {
-  double ar, az, La;  // R1 - R0, Z1 - Z0, ar ar + az az
-  double X0, Y0;      // transverse position of h0
+// Index entry of an in-cell c' = (h0, h1): its cell index, and its inner hit
+// with the BPix1 flag in the top bit.  The triplet tests rebuild the R-Z
+// segment from the hit table with the same operations as k_cell_geom.
+struct InCell {
   int32_t cell;
-  int32_t bpix1;      // h0 on layer 0
+  int32_t h0b;
 };
-static_assert(sizeof(InCell) == 48, "InCell layout");
+constexpr int32_t kBpix1Bit = static_cast<int32_t>(0x80000000u);
 
 // The R-Z test, with the out-cell's segment (br, bz) and length Lb.
 __device__ __forceinline__ bool rz_pass(double ar, double az, double La, double br, double bz, double Lb,
@@ -81,12 +84,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Hit table: (X, Y, Z, R) in double, one 32-byte entry per hit, R = sqrt(X X + Y Y).
 template <class T>
-__global__ void k_radius(int n, const T* __restrict__ x, const T* __restrict__ y, double* __restrict__ R) {
+__global__ void k_hit_table(int n, const T* __restrict__ x, const T* __restrict__ y, const T* __restrict__ z,
+                            double4* __restrict__ hx) {
   for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n; h += gridDim.x * blockDim.x) {
     const double X = static_cast<double>(x[h]);
     const double Y = static_cast<double>(y[h]);
-    R[h] = sqrt(X * X + Y * Y);
+    hx[h] = make_double4(X, Y, static_cast<double>(z[h]), sqrt(X * X + Y * Y));
   }
 }
 
@@ -96,9 +101,8 @@ struct GeomArgs {
   int32_t cells_cap;
   const int32_t* inner;
   const int32_t* outer;
-  const T* z;
   const uint8_t* layer;
-  const double* R;
+  const double4* hx;
   double* dr;
   double* dz;
   double* Ls;          // +L (outer hit on a barrel layer) or -L
@@ -141,8 +145,10 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
     const int c = static_cast<int>(c64);
     const int h0 = a.inner[c];
     const int h1 = a.outer[c];
-    const double dr = a.R[h1] - a.R[h0];
-    const double dz = static_cast<double>(a.z[h1]) - static_cast<double>(a.z[h0]);
+    const double4 P0 = a.hx[h0];
+    const double4 P1 = a.hx[h1];
+    const double dr = P1.w - P0.w;
+    const double dz = P1.z - P0.z;
     const double L = dr * dr + dz * dz;
     a.dr[c] = dr;
     a.dz[c] = dz;
@@ -175,24 +181,16 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
   }
 }
 
-template <class T>
 __global__ void k_by_outer(const int32_t* __restrict__ cell_count, int32_t cells_cap,
                            const int32_t* __restrict__ inner, const int32_t* __restrict__ outer,
-                           const T* __restrict__ x, const T* __restrict__ y, const uint8_t* __restrict__ layer,
-                           const double* __restrict__ dr, const double* __restrict__ dz,
-                           const double* __restrict__ Ls, const int32_t* __restrict__ rank,
+                           const uint8_t* __restrict__ layer, const int32_t* __restrict__ rank,
                            const int32_t* __restrict__ first_in, InCell* __restrict__ rec) {
   const int n = min(*cell_count, cells_cap);
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
     const int h0 = inner[c];
     InCell r;
-    r.ar = dr[c];
-    r.az = dz[c];
-    r.La = fabs(Ls[c]);
-    r.X0 = static_cast<double>(x[h0]);
-    r.Y0 = static_cast<double>(y[h0]);
     r.cell = c;
-    r.bpix1 = layer[h0] == 0;
+    r.h0b = h0 | (layer[h0] == 0 ? kBpix1Bit : 0);
     rec[first_in[outer[c]] + rank[c]] = r;
   }
 }
@@ -209,8 +207,7 @@ struct WaveLds {
 template <class T>
 struct HitArgs {
   int32_t n_hits;
-  const T* x;
-  const T* y;
+  const double4* hx;
   const int32_t* cell_count;
   int32_t cells_cap;
   const int32_t* outer;
@@ -234,10 +231,9 @@ __device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a,
     const int e = L.queue[lane];
     const int j = e >> 6;
     const int li = e & (kWave - 1);
-    const int h2 = a.outer[cb + j];
+    const double4 P2 = a.hx[a.outer[cb + j]];
     const double rmax = L.bpix1[li] ? k.rmax_bpix1 : k.rmax_other;
-    if (beam_pass(L.X0[li], L.Y0[li], X1, Y1, static_cast<double>(a.x[h2]), static_cast<double>(a.y[h2]),
-                  rmax)) {
+    if (beam_pass(L.X0[li], L.Y0[li], X1, Y1, P2.x, P2.y, rmax)) {
       const int slot = atomicAdd(&L.cnt[li], 1);
       if (slot < kLocal) L.found[li * kLocal + slot] = cb + j;
     }
@@ -265,8 +261,8 @@ __global__ void __launch_bounds__(WAVES * kWave)
     for (int r = ib + lane; r < ie; r += kWave) a.lcnt[r] = 0;
     return;
   }
-  const double X1 = static_cast<double>(a.x[h1]);
-  const double Y1 = static_cast<double>(a.y[h1]);
+  const double4 P1 = a.hx[h1];
+  const double X1 = P1.x, Y1 = P1.y;
   const double th2b = k.theta2_barrel, th2e = k.theta2_endcap;
 
   for (int base = ib; base < ie; base += kWave) {
@@ -276,13 +272,14 @@ __global__ void __launch_bounds__(WAVES * kWave)
     int cell = -1;
     if (lane < m) {
       const InCell r = a.rec[base + lane];
-      ar = r.ar;
-      az = r.az;
-      La = r.La;
+      const double4 P0 = a.hx[r.h0b & ~kBpix1Bit];
+      ar = P1.w - P0.w;  // as in k_cell_geom
+      az = P1.z - P0.z;
+      La = ar * ar + az * az;
       cell = r.cell;
-      L.X0[lane] = r.X0;
-      L.Y0[lane] = r.Y0;
-      L.bpix1[lane] = r.bpix1;
+      L.X0[lane] = P0.x;
+      L.Y0[lane] = P0.y;
+      L.bpix1[lane] = (r.h0b & kBpix1Bit) != 0;
     }
     L.cnt[lane] = 0;
     wave_sync();
@@ -454,8 +451,8 @@ __global__ void k_links_overflow(DevCfg k, HitArgs<T> a, const int32_t* __restri
     const int h0 = inner[cp];
     const int h1 = a.outer[cp];
     const double ar = gdr[cp], az = gdz[cp], La = fabs(gLs[cp]);
-    const double X0 = static_cast<double>(a.x[h0]), Y0 = static_cast<double>(a.y[h0]);
-    const double X1 = static_cast<double>(a.x[h1]), Y1 = static_cast<double>(a.y[h1]);
+    const double4 P0 = a.hx[h0], P1 = a.hx[h1];
+    const double X0 = P0.x, Y0 = P0.y, X1 = P1.x, Y1 = P1.y;
     const double rmax = layer[h0] == 0 ? k.rmax_bpix1 : k.rmax_other;
     const int first = a.inner_first[h1];
     const int last = min(first + a.inner_count[h1], n_cells);
@@ -464,8 +461,8 @@ __global__ void k_links_overflow(DevCfg k, HitArgs<T> a, const int32_t* __restri
       const double Ls = gLs[c];
       const double theta2 = __builtin_signbit(Ls) ? k.theta2_endcap : k.theta2_barrel;
       if (!rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2)) continue;
-      const int h2 = a.outer[c];
-      if (!beam_pass(X0, Y0, X1, Y1, static_cast<double>(a.x[h2]), static_cast<double>(a.y[h2]), rmax)) continue;
+      const double4 P2 = a.hx[a.outer[c]];
+      if (!beam_pass(X0, Y0, X1, Y1, P2.x, P2.y, rmax)) continue;
       has_inner[c] = 1;
       if (w < links_cap) {
         in_cell[w] = cp;
@@ -485,7 +482,7 @@ __global__ void k_finish_links(const int32_t* count, int32_t cap, uint32_t* stat
 size_t ws_links(int n_hits, int cells_cap) {
   const int64_t scan_n = std::max<int64_t>(n_hits, cells_cap);
   Carver c(nullptr);
-  c.take<double>(n_hits);                   // R
+  c.take<double4>(n_hits);                  // hit table
   c.take<double>(cells_cap);                // dr
   c.take<double>(cells_cap);                // dz
   c.take<double>(cells_cap);                // Ls
@@ -518,7 +515,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   const int n = h.n_hits;
   const int64_t scan_n = std::max<int64_t>(n, cells.cap);
   Carver c(ws.ptr);
-  double* R = c.take<double>(n);
+  double4* hx = c.take<double4>(n);
   double* dr = c.take<double>(cells.cap);
   double* dz = c.take<double>(cells.cap);
   double* Ls = c.take<double>(cells.cap);
@@ -538,22 +535,21 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   if (fill_i32(first_in, 0, static_cast<int64_t>(n) + 1, s) != hipSuccess) return PT_ERR_DEVICE;
   void* tok = timing_begin(s);
   if (n > 0) {
-    k_radius<T><<<grid_for(n, 256), 256, 0, s>>>(n, x, y, R);
+    k_hit_table<T><<<grid_for(n, 256), 256, 0, s>>>(n, x, y, z, hx);
     PT_LAUNCH_CHECK();
   }
-  GeomArgs<T> g{cells.count, cells.cap, cells.inner, cells.outer, z, h.layer, R, dr, dz, Ls, rank, first_in,
+  GeomArgs<T> g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, hx, dr, dz, Ls, rank, first_in,
                 L.out_start, L.out_count, L.has_inner};
   const int64_t geom_blocks = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kGeomChunk - 1) / kGeomChunk);
   k_cell_geom<T><<<static_cast<unsigned>(geom_blocks), kGeomBlock, 0, s>>>(k, g);
   PT_LAUNCH_CHECK();
   if (exclusive_scan(first_in, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
-  k_by_outer<T><<<grid_for(cells.cap, 256, 16384), 256, 0, s>>>(cells.count, cells.cap, cells.inner,
-                                                                cells.outer, x, y, h.layer, dr, dz, Ls, rank,
-                                                                first_in, rec);
+  k_by_outer<<<grid_for(cells.cap, 256, 16384), 256, 0, s>>>(cells.count, cells.cap, cells.inner, cells.outer,
+                                                             h.layer, rank, first_in, rec);
   PT_LAUNCH_CHECK();
   timing_end(tok, "link_index", s);
 
-  HitArgs<T> a{n, x, y, cells.count, cells.cap, cells.outer, cells.inner_first, cells.inner_count, first_in,
+  HitArgs<T> a{n, hx, cells.count, cells.cap, cells.outer, cells.inner_first, cells.inner_count, first_in,
                rec, lcnt, spill, ovf, ovf_count};
   tok = timing_begin(s);
   if (n > 0) {
