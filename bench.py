@@ -30,13 +30,32 @@ sys.path.insert(0, ROOT)
 METRIC = "events/s at PU200, batched vs per-event; fit fwd+bwd tracks/s vs HBM roofline"
 # fp64 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (T ops/s)
 FP64_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# timing regions (one kernel each, see pixeltrack.h) in step order
+TIMED = ("doublets_count", "doublets_write", "cell_geom", "link_by_outer", "links", "link_emit", "root_count",
+         "root_write", "dfs_count", "dfs_write", "dedup", "fit_fwd", "fit_bwd")
+# source file of each timed kernel (for the traffic record)
+KERNEL_SOURCE = {"doublets_count": "doublets.hip", "doublets_write": "doublets.hip", "cell_geom": "links.hip",
+                 "link_by_outer": "links.hip", "links": "links.hip", "link_emit": "links.hip",
+                 "root_count": "ntuplets.hip", "root_write": "ntuplets.hip", "dfs_count": "ntuplets.hip",
+                 "dfs_write": "ntuplets.hip", "fit_fwd": "fit.hip", "fit_bwd": "fit.hip"}
+KERNEL_SYMBOL = {"doublets_count": "k_doublets<false>", "doublets_write": "k_doublets<true>",
+                 "cell_geom": "k_cell_geom", "link_by_outer": "k_by_outer", "links": "k_link_hits",
+                 "link_emit": "k_link_emit", "root_count": "k_root_count", "root_write": "k_root_write",
+                 "dfs_count": "k_dfs<true>", "dfs_write": "k_dfs<false>", "fit_fwd": "k_fit<4,6>",
+                 "fit_bwd": "k_grad<4,6>"}
+# Algorithmic work per unit, for the roofline of whichever kernel dominates:
+#  links: the R-Z test of every candidate pair, 7 fp64 VALU operations
+#    (A = ar bz - az br: 2 mul + 1 sub; A A; La Lb; theta2 (La Lb); compare)
+#  cell_geom: per cell read inner, outer (8 B), write dr, dz, Ls (24 B), rank
+#    (4 B), and the reset out_start, out_count, has_inner (9 B)
+#  link_by_outer: per cell read outer, inner, rank (12 B), layer of h0 (1 B),
+#    first_in of h1 (4 B), write the 8-byte entry
+#  doublets_write: per cell write inner, outer, pair (9 B)
 LINK_OPS_PER_CANDIDATE = 7.0
-# cell geometry (read 8, write 24 + 4 rank + 9 link resets) + index (read 8 + 24 + 4, write 48 record)
-LINK_INDEX_BYTES_PER_CELL = 129.0
-# radius (read x, y as float, write R) 16 + in-cell counts (fill 4, scan read/write 8)
-LINK_INDEX_BYTES_PER_HIT = 28.0
+CELL_GEOM_BYTES_PER_CELL = 45.0
+BY_OUTER_BYTES_PER_CELL = 25.0
+DOUBLET_BYTES_PER_CELL = 9.0
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
@@ -142,8 +161,7 @@ def chain_workload(args):
     torch.cuda.synchronize()
     api.timing_enable(False)
     kern = {}
-    for name in ("doublets_count", "doublets_write", "link_index", "links", "link_emit", "roots", "dfs", "dedup",
-                 "fit_fwd", "fit_bwd"):
+    for name in TIMED:
         ms, n = api.timing_read(name)
         if n:
             kern[name] = ms / n
@@ -235,6 +253,85 @@ def cpu_baseline(args, chain):
                        f"n-tuplets, dedup, fit, dual-number gradient of {tracks} tracks), {dt:.1f} s, 1 thread")
 
 
+def traffic_record(name):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (profiles/pu200_step_counters.txt), or None when the kernel's source file
+    has changed since the counters were taken."""
+    import hashlib
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "pu200_step_counters.txt")
+    src = KERNEL_SOURCE.get(name)
+    if src is None or not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(os.path.join(here, "paper_2008_13461_amd", "csrc", src), "rb").read()).hexdigest()
+    for line in open(path):
+        if not line.startswith("traffic "):
+            continue
+        f = dict(kv.split("=", 1) for kv in line.split()[1:])
+        if f.get("kernel") == name and f.get("sha256") == sha:
+            return float(f["fetch_bytes"]) + float(f["write_bytes"])
+    return None
+
+
+def roofline(kern, cnt):
+    """Roofline object of the dominant timed kernel of the step."""
+    if not kern:
+        return None
+    name = max(kern, key=kern.get)
+    sec = kern[name] * 1e-3
+    roof = {"kernel": KERNEL_SYMBOL.get(name, name), "timing_region": name}
+    if name == "links":
+        achieved = LINK_OPS_PER_CANDIDATE * cnt["link_candidates"] / sec / 1e12
+        roof.update(bound="alu", achieved=achieved, peak=FP64_VALU_PEAK_TOPS, unit="TOP/s",
+                    frac=achieved / FP64_VALU_PEAK_TOPS,
+                    note="7 fp64 VALU ops per candidate pair x candidates / kernel time; peak = 256 CU x 4 SIMD x "
+                         "16 lanes x 2.4 GHz, one fp64 op per lane per clock (no FMA: contraction is off)")
+    else:
+        per_cell = {"cell_geom": CELL_GEOM_BYTES_PER_CELL, "link_by_outer": BY_OUTER_BYTES_PER_CELL,
+                    "doublets_write": DOUBLET_BYTES_PER_CELL}.get(name)
+        achieved = per_cell * cnt["doublets"] / sec / 1e9 if per_cell else None
+        roof.update(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS if achieved else None)
+    t = traffic_record(name)
+    roof["traffic"] = t
+    roof["traffic_unit"] = "bytes per launch (FETCH_SIZE and WRITE_SIZE, copy-calibrated)"
+    return roof
+
+
+def profile_run(args):
+    """Two eager passes of the batched step, then two copies of 1 GiB: the copy
+    kernel's FETCH_SIZE / WRITE_SIZE against its known 2^30 bytes read and
+    written calibrate the traffic counters."""
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from synth import config as C
+    from synth import events as E
+
+    h = E.config5(n_events=args.events)
+    cp = caps(h.n_hits, h.n_events)
+    pipe = api.Pipeline(C.default_config(), precision=A.PT_FIT_F32_F64SOLVE, n_phi_bins=args.bins, **cp)
+    hits = api.Hits.from_host(h)
+    offsets = torch.from_numpy(E.module_offsets()).cuda()
+    gp_np, gc_np = E.cotangents(5, cp["tuplets_cap"])
+    g_params = torch.from_numpy(gp_np).cuda()
+    g_chi2 = torch.from_numpy(gc_np).cuda()
+    grad_hits = torch.zeros((h.n_hits, 3), dtype=torch.float32, device="cuda")
+    for rep in range(2):
+        pipe.reconstruct(hits, offsets=offsets)
+        pipe.backward(hits, g_params, g_chi2, grad_hits, None, offsets=offsets)
+        torch.cuda.synchronize()
+        log(f"profile pass {rep}: flags {pipe.flags()}")
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("profile copies done (2^30 bytes read and written each)")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +342,9 @@ def main():
     ap.add_argument("--bins", type=int, default=0, help="azimuth bins per layer (0: tuned default)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="only two eager passes of the batched step (reconstruction + adjoint) and two 1 GiB "
+                         "copies, for profiler counter runs; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); events shard across GPUs with no "
@@ -258,6 +358,9 @@ def main():
     from paper_2008_13461_amd import _abi as A
 
     A.load()
+    if args.profile:
+        profile_run(args)
+        return
     chain = chain_workload(args)
     fit = fit_workload(args)
 
@@ -284,35 +387,7 @@ def main():
                      "bytes_per_track": (fwd_bytes + bwd_bytes) / fit["n_tracks"]},
     }
 
-    # roofline of the dominant kernel of the step
-    roof = None
-    if dominant in ("fit_fwd", "fit_bwd"):
-        pass
-    if dominant == "links":
-        # R-Z test of every candidate (c', c): 7 double-precision VALU operations
-        # (2 mul, 1 sub, 3 mul, 1 compare) against the VALU issue rate for
-        # double operations without multiply-add
-        ops = LINK_OPS_PER_CANDIDATE * cnt["link_candidates"]
-        achieved = ops / (kern["links"] * 1e-3) / 1e12
-        roof = {"kernel": "k_link_hits", "bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TOPS,
-                "unit": "TOP/s", "frac": achieved / FP64_VALU_PEAK_TOPS, "traffic": None,
-                "note": "7 fp64 ops per candidate pair x candidates / kernel time; peak = 256 CU x 4 SIMD x "
-                        "16 lanes x 2.4 GHz (one fp64 op per lane per clock, no FMA: contraction is off)"}
-    elif dominant == "link_index":
-        byts = LINK_INDEX_BYTES_PER_CELL * cnt["doublets"] + LINK_INDEX_BYTES_PER_HIT * cnt["hits"]
-        achieved = byts / (kern["link_index"] * 1e-3) / 1e9
-        roof = {"kernel": "link_index", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "note": f"{LINK_INDEX_BYTES_PER_CELL:.0f} B per cell + {LINK_INDEX_BYTES_PER_HIT:.0f} B per hit / time of the index kernels"}
-    elif dominant in ("doublets_count", "doublets_write"):
-        byts = 32.0 * cnt["hits"] + (9.0 * cnt["doublets"] if dominant == "doublets_write" else 0.0)
-        achieved = byts / (kern[dominant] * 1e-3) / 1e9
-        roof = {"kernel": "k_doublets", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    elif dominant is not None:
-        roof = {"kernel": dominant, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None}
-
+    roof = roofline(kern, cnt)
     out = {
         "metric": METRIC,
         "value": value,

@@ -181,12 +181,88 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
   }
 }
 
-__global__ void k_by_outer(const int32_t* __restrict__ cell_count, int32_t cells_cap,
-                           const int32_t* __restrict__ inner, const int32_t* __restrict__ outer,
-                           const uint8_t* __restrict__ layer, const int32_t* __restrict__ rank,
-                           const int32_t* __restrict__ first_in, InCell* __restrict__ rec) {
+// Index entries of the cells by outer hit.  Works on the same chunks as
+// k_cell_geom, whose groups (cells of the chunk ending on one hit) hold
+// consecutive ranks: the chunk's cells are staged in LDS in (group, rank)
+// order, so that each group is written as one contiguous run.
+__global__ void __launch_bounds__(kGeomBlock)
+    k_by_outer(const int32_t* __restrict__ cell_count, int32_t cells_cap, const int32_t* __restrict__ inner,
+               const int32_t* __restrict__ outer, const uint8_t* __restrict__ layer,
+               const int32_t* __restrict__ rank, const int32_t* __restrict__ first_in, InCell* __restrict__ rec) {
+  __shared__ int32_t s_key[kGeomChunk];   // outer hit of the slot; then the staged cells
+  __shared__ int32_t s_cnt[kGeomChunk];   // cells in the slot; then the slot's first staging index
+  __shared__ int32_t s_min[kGeomChunk];   // lowest rank in the slot (the group's first rank)
+  __shared__ int32_t s_slot[kGeomChunk];  // slot of each cell of the chunk
+  __shared__ int32_t s_scan[kGeomBlock / kWave + 1];
   const int n = min(*cell_count, cells_cap);
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kGeomChunk;
+  if (base >= n) return;
+  const int m = static_cast<int>(min<int64_t>(kGeomChunk, n - base));
+  for (int i = threadIdx.x; i < kGeomChunk; i += kGeomBlock) {
+    s_key[i] = -1;
+    s_cnt[i] = 0;
+    s_min[i] = INT32_MAX;
+  }
+  __syncthreads();
+  for (int loc = threadIdx.x; loc < m; loc += kGeomBlock) {
+    const int c = static_cast<int>(base + loc);
+    const int h1 = outer[c];
+    int slot = static_cast<int>((static_cast<uint32_t>(h1) * 2654435761u) >> 20) & (kGeomChunk - 1);
+    while (true) {
+      const int prev = atomicCAS(&s_key[slot], -1, h1);
+      if (prev == -1 || prev == h1) break;
+      slot = (slot + 1) & (kGeomChunk - 1);
+    }
+    atomicAdd(&s_cnt[slot], 1);
+    atomicMin(&s_min[slot], rank[c]);
+    s_slot[loc] = slot;
+  }
+  __syncthreads();
+  // exclusive scan of the slot counts: kGeomItems consecutive slots per thread
+  {
+    const int t0 = threadIdx.x * kGeomItems;
+    int v[kGeomItems];
+    int sum = 0;
+#pragma unroll
+    for (int i = 0; i < kGeomItems; ++i) {
+      v[i] = s_cnt[t0 + i];
+      sum += v[i];
+    }
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    int incl = sum;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) s_scan[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int run = 0;
+      for (int w = 0; w < kGeomBlock / kWave; ++w) {
+        const int x = s_scan[w];
+        s_scan[w] = run;
+        run += x;
+      }
+    }
+    __syncthreads();
+    int run = s_scan[wave] + incl - sum;
+#pragma unroll
+    for (int i = 0; i < kGeomItems; ++i) {
+      s_cnt[t0 + i] = run;
+      run += v[i];
+    }
+  }
+  __syncthreads();
+  // stage the cells in (group, rank) order; the hash keys are no longer needed
+  for (int loc = threadIdx.x; loc < m; loc += kGeomBlock) {
+    const int c = static_cast<int>(base + loc);
+    const int slot = s_slot[loc];
+    s_key[s_cnt[slot] + (rank[c] - s_min[slot])] = c;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += kGeomBlock) {
+    const int c = s_key[i];
     const int h0 = inner[c];
     InCell r;
     r.cell = c;
@@ -533,21 +609,23 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
 
   if (fill_i32(ovf_count, 0, 1, s) != hipSuccess) return PT_ERR_DEVICE;
   if (fill_i32(first_in, 0, static_cast<int64_t>(n) + 1, s) != hipSuccess) return PT_ERR_DEVICE;
-  void* tok = timing_begin(s);
   if (n > 0) {
     k_hit_table<T><<<grid_for(n, 256), 256, 0, s>>>(n, x, y, z, hx);
     PT_LAUNCH_CHECK();
   }
+  void* tok = timing_begin(s);
   GeomArgs<T> g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, hx, dr, dz, Ls, rank, first_in,
                 L.out_start, L.out_count, L.has_inner};
   const int64_t geom_blocks = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kGeomChunk - 1) / kGeomChunk);
   k_cell_geom<T><<<static_cast<unsigned>(geom_blocks), kGeomBlock, 0, s>>>(k, g);
+  timing_end(tok, "cell_geom", s);
   PT_LAUNCH_CHECK();
   if (exclusive_scan(first_in, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
-  k_by_outer<<<grid_for(cells.cap, 256, 16384), 256, 0, s>>>(cells.count, cells.cap, cells.inner, cells.outer,
-                                                             h.layer, rank, first_in, rec);
+  tok = timing_begin(s);
+  k_by_outer<<<static_cast<unsigned>(geom_blocks), kGeomBlock, 0, s>>>(cells.count, cells.cap, cells.inner,
+                                                                       cells.outer, h.layer, rank, first_in, rec);
+  timing_end(tok, "link_by_outer", s);
   PT_LAUNCH_CHECK();
-  timing_end(tok, "link_index", s);
 
   HitArgs<T> a{n, hx, cells.count, cells.cap, cells.outer, cells.inner_first, cells.inner_count, first_in,
                rec, lcnt, spill, ovf, ovf_count};
@@ -562,18 +640,18 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
     PT_LAUNCH_CHECK();
   }
   timing_end(tok, "links", s);
-  tok = timing_begin(s);
   if (exclusive_scan_dev(lcnt, cells.cap, cells.count, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  tok = timing_begin(s);
   EmitArgs e{cells.count, cells.cap, lcnt, spill, rec, L.cap, L.in_cell, L.out_cell, L.out_start, L.out_count,
              L.has_inner};
   k_link_emit<<<grid_for(cells.cap, 256, 16384), 256, 0, s>>>(e);
+  timing_end(tok, "link_emit", s);
   PT_LAUNCH_CHECK();
   k_links_overflow<T><<<64, 64, 0, s>>>(k, a, cells.inner, h.layer, dr, dz, Ls, L.out_start, L.cap, L.in_cell,
                                         L.out_cell, L.has_inner);
   PT_LAUNCH_CHECK();
   k_copy_links_total<<<1, 1, 0, s>>>(lcnt, cells.count, cells.cap, L.count);
   PT_LAUNCH_CHECK();
-  timing_end(tok, "link_emit", s);
   k_finish_links<<<1, 1, 0, s>>>(L.count, L.cap, status);
   PT_LAUNCH_CHECK();
   return PT_OK;

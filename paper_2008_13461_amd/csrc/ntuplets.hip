@@ -269,17 +269,21 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
           max_n, status};
   void* tok = timing_begin(s);
   k_root_count<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots);
+  timing_end(tok, "root_count", s);
   PT_LAUNCH_CHECK();
   if (exclusive_scan(chunk_roots, chunks, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  tok = timing_begin(s);
   k_root_write<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots);
+  timing_end(tok, "root_write", s);
   PT_LAUNCH_CHECK();
-  timing_end(tok, "roots", s);
   tok = timing_begin(s);
   k_dfs<true><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths);
+  timing_end(tok, "dfs_count", s);
   PT_LAUNCH_CHECK();
   if (exclusive_scan_dev(paths, cells.cap, n_roots, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  tok = timing_begin(s);
   k_dfs<false><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths);
-  timing_end(tok, "dfs", s);
+  timing_end(tok, "dfs_write", s);
   PT_LAUNCH_CHECK();
   // rows found = paths[n_roots] (the scan's total)
   k_copy_total_rows<<<1, 1, 0, s>>>(paths, n_roots, T.count_raw);
