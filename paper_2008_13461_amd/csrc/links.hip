@@ -108,7 +108,6 @@ struct GeomArgs {
   double* Ls;          // +L (outer hit on a barrel layer) or -L
   int32_t* rank;       // rank among the cells ending on the same hit
   int32_t* n_in;       // [n_hits + 1] cells ending on each hit
-  int32_t* out_start;
   int32_t* out_count;
   uint8_t* has_inner;
 };
@@ -153,8 +152,7 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
     a.dr[c] = dr;
     a.dz[c] = dz;
     a.Ls[c] = k.layer_barrel[a.layer[h1]] ? L : -L;
-    a.out_start[c] = 0;
-    a.out_count[c] = 0;
+    a.out_count[c] = 0;  // out_start is only read where out_count > 0
     a.has_inner[c] = 0;
     // linear probing; the table has a slot for every cell of the block
     int slot = static_cast<int>((static_cast<uint32_t>(h1) * 2654435761u) >> 20) & (kGeomChunk - 1);
@@ -615,7 +613,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   }
   void* tok = timing_begin(s);
   GeomArgs<T> g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, hx, dr, dz, Ls, rank, first_in,
-                L.out_start, L.out_count, L.has_inner};
+                L.out_count, L.has_inner};
   const int64_t geom_blocks = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kGeomChunk - 1) / kGeomChunk);
   k_cell_geom<T><<<static_cast<unsigned>(geom_blocks), kGeomBlock, 0, s>>>(k, g);
   timing_end(tok, "cell_geom", s);
