@@ -80,9 +80,18 @@ def chain_workload(args):
     h = E.config5(n_events=args.events)
     off_np = E.module_offsets()
     log(f"generated {h.n_events} events, {h.n_hits} hits in {time.time() - t0:.1f}s")
-    cfg = A.make_config(cfg_d, n_phi_bins=args.bins)
     cp = caps(h.n_hits, h.n_events)
     hits = api.Hits.from_host(h)
+    if args.bins:
+        perf = dict(n_phi_bins=args.bins)
+    else:
+        # bin count and block sizes for this batch shape (never change a result)
+        from paper_2008_13461_amd import autotune
+
+        t0 = time.time()
+        perf = autotune.tune(cfg_d, hits, cp, cache=None)
+        log(f"autotuned {perf} in {time.time() - t0:.1f}s")
+    cfg = A.make_config(cfg_d, **perf)
     offsets = torch.from_numpy(off_np).cuda()
     cells = api.Cells.empty(cp["cells_cap"], h.n_hits)
     links = api.Links.empty(cp["links_cap"], cp["cells_cap"])
@@ -123,6 +132,24 @@ def chain_workload(args):
     if int(cells.count.item()) != n_cells or int(tup.count.item()) != n_trk:
         raise RuntimeError("graph replay changed the products")
 
+    # the same step with the hits copied from pinned host memory first
+    host = [t.cpu().pin_memory() for t in (hits.x, hits.y, hits.z, hits.layer, hits.module, hits.event_offsets)]
+    dev = (hits.x, hits.y, hits.z, hits.layer, hits.module, hits.event_offsets)
+
+    def step_h2d():
+        for d, hsrc in zip(dev, host):
+            d.copy_(hsrc, non_blocking=True)
+        step()
+
+    step_h2d()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_h2d()
+    torch.cuda.synchronize()
+    t_h2d = (time.perf_counter() - t0) / args.steps
+    log(f"batched with the host-to-device copy of the hits: {t_h2d * 1e3:.3f} ms per step")
+
     # per-event form: the same calls event by event, no graph
     ev_hits = []
     for e in range(h.n_events):
@@ -131,7 +158,7 @@ def chain_workload(args):
                                 torch.tensor([0, b - a], dtype=torch.int32, device="cuda")))
     max_ev = max(x.n_hits for x in ev_hits)
     cpe = caps(max_ev, 1)
-    pipe = api.Pipeline(cfg_d, precision=A.PT_FIT_F32_F64SOLVE, n_phi_bins=args.bins, **cpe)
+    pipe = api.Pipeline(cfg_d, precision=A.PT_FIT_F32_F64SOLVE, **perf, **cpe)
     gh_e = torch.zeros((max_ev, 3), dtype=torch.float32, device="cuda")
 
     def per_event_pass():
@@ -153,7 +180,7 @@ def chain_workload(args):
     # kernel durations (HIP events on the call stream), eager calls of the same step
     api.timing_reset()
     api.timing_enable(True)
-    pipe_b = api.Pipeline(cfg_d, precision=A.PT_FIT_F32_F64SOLVE, n_phi_bins=args.bins, **cp)
+    pipe_b = api.Pipeline(cfg_d, precision=A.PT_FIT_F32_F64SOLVE, **perf, **cp)
     kt_steps = max(3, args.steps // 2)
     for _ in range(kt_steps):
         pipe_b.reconstruct(hits, offsets=offsets)
@@ -171,8 +198,53 @@ def chain_workload(args):
     n_cand = int(pipe_b.cells.inner_count[co.long()].sum().item())
     counts = dict(hits=h.n_hits, doublets=n_cells, links=n_links, ntuplets=n_raw, tracks=n_trk,
                   link_candidates=n_cand)
-    return dict(t_batched=t_batched, t_per_event=t_per_event, kernels_ms=kern, counts=counts, n_events=h.n_events,
-                hits_np=h, cfg_d=cfg_d)
+    del pipe_b, pipe, plan
+    torch.cuda.empty_cache()
+    mixed = mixed_pileup(args, cfg_d, perf) if args.mixed_events else None
+    return dict(t_batched=t_batched, t_per_event=t_per_event, t_h2d=t_h2d, kernels_ms=kern, counts=counts,
+                n_events=h.n_events, hits_np=h, cfg_d=cfg_d, perf=perf, mixed=mixed)
+
+
+def mixed_pileup(args, cfg_d, perf):
+    """256 events with pileup uniform in 20..200 in one batch (graph replays)."""
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from synth import events as E
+
+    h = E.config3(n_events=args.mixed_events)
+    cp = caps(h.n_hits, h.n_events)
+    hits = api.Hits.from_host(h)
+    cells = api.Cells.empty(cp["cells_cap"], h.n_hits)
+    links = api.Links.empty(cp["links_cap"], cp["cells_cap"])
+    tup = api.Tuplets.empty(cp["tuplets_cap"])
+    tracks = api.Tracks.empty(cp["tuplets_cap"], A.PT_FIT_F32_F64SOLVE)
+    status = api.new_status()
+    plan = api.Plan(A.make_config(cfg_d, **perf), precision=A.PT_FIT_F32_F64SOLVE, with_adjoint=False, **cp)
+
+    def step():
+        plan.run(hits, cells, links, tup, tracks, status)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    flags = int(status[A.PT_ST_FLAGS].item()) & 0xFFFFFFFF
+    if flags & (A.PT_FLAG_CELLS_OVERFLOW | A.PT_FLAG_LINKS_OVERFLOW | A.PT_FLAG_TUPLETS_OVERFLOW):
+        raise RuntimeError(f"capacity overflow in the mixed-pileup batch (flags {flags:#x})")
+    steps = max(3, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    out = dict(events=h.n_events, hits=h.n_hits, doublets=int(cells.count.item()), tracks=int(tup.count.item()),
+               ms_per_step=t * 1e3, events_per_s=h.n_events / t,
+               workload=f"{h.n_events} events, pileup uniform in 20..200, forward path (no adjoint), one hipGraph")
+    log(f"mixed pileup: {h.n_events} events, {h.n_hits} hits, {t * 1e3:.3f} ms per step")
+    del plan, cells, links, tup, tracks, hits
+    torch.cuda.empty_cache()
+    return out
 
 
 def fit_workload(args):
@@ -300,7 +372,8 @@ def roofline(kern, cnt):
 
 
 def profile_run(args):
-    """Two eager passes of the batched step, then two copies of 1 GiB: the copy
+    """Two eager passes of the batched step (with the settings the bench
+    tunes), then two copies of 1 GiB: the copy
     kernel's FETCH_SIZE / WRITE_SIZE against its known 2^30 bytes read and
     written calibrate the traffic counters."""
     import torch
@@ -312,8 +385,15 @@ def profile_run(args):
 
     h = E.config5(n_events=args.events)
     cp = caps(h.n_hits, h.n_events)
-    pipe = api.Pipeline(C.default_config(), precision=A.PT_FIT_F32_F64SOLVE, n_phi_bins=args.bins, **cp)
     hits = api.Hits.from_host(h)
+    if args.bins:
+        perf = dict(n_phi_bins=args.bins)
+    else:
+        from paper_2008_13461_amd import autotune
+
+        perf = autotune.tune(C.default_config(), hits, cp, cache=None)
+        log(f"autotuned {perf}")
+    pipe = api.Pipeline(C.default_config(), precision=A.PT_FIT_F32_F64SOLVE, **perf, **cp)
     offsets = torch.from_numpy(E.module_offsets()).cuda()
     gp_np, gc_np = E.cotangents(5, cp["tuplets_cap"])
     g_params = torch.from_numpy(gp_np).cuda()
@@ -342,6 +422,8 @@ def main():
     ap.add_argument("--bins", type=int, default=0, help="azimuth bins per layer (0: tuned default)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-events", type=int, default=256,
+                    help="events of the mixed-pileup batch also reported (0: skip)")
     ap.add_argument("--profile", action="store_true",
                     help="only two eager passes of the batched step (reconstruction + adjoint) and two 1 GiB "
                          "copies, for profiler counter runs; prints no JSON")
@@ -405,6 +487,9 @@ def main():
                                "full path with fit adjoint, one hipGraph per step",
                    "events": n_ev, "hits": cnt["hits"], "parallelism": "single GPU"},
         "per_event_events_per_s": per_event,
+        "events_per_s_with_h2d": n_ev / chain["t_h2d"],
+        "tuned": chain["perf"],
+        "mixed_pileup": chain["mixed"],
         "batched_over_per_event": value / per_event,
         "tracks_per_s": cnt["tracks"] / chain["t_batched"],
         "counts_per_batch": cnt,

@@ -21,7 +21,7 @@ from . import api
 
 CANDIDATES = {
     "n_phi_bins": (64, 128, 256, 512),
-    "block_doublets": (128, 256),
+    "block_doublets": (64, 128, 256, 512),
     "block_links": (64, 128, 256),
 }
 DEFAULT = {"n_phi_bins": 128, "block_doublets": 256, "block_links": 64}

@@ -273,6 +273,7 @@ __global__ void __launch_bounds__(kGeomBlock)
 struct WaveLds {
   int32_t queue[2 * kWave];      // queued pairs: out-cell offset << 6 | in-cell lane
   double X0[kWave], Y0[kWave];
+  double ar[kWave], az[kWave], La[kWave];  // in-cell segments, for the transposed sweep
   int32_t bpix1[kWave];
   int32_t cnt[kWave];            // links found per in-cell lane
   int32_t found[kWave * kLocal]; // their out-cells
@@ -356,6 +357,15 @@ __global__ void __launch_bounds__(WAVES * kWave)
       L.bpix1[lane] = (r.h0b & kBpix1Bit) != 0;
     }
     L.cnt[lane] = 0;
+    // A partial pass with few in-cells sweeps the other way round: lanes over
+    // the out-cells, the in-cells (from LDS) in a wave-uniform loop.
+    const int out_blocks = (nb + kWave - 1) / kWave;
+    const bool transposed = m < kWave && static_cast<int64_t>(m) * out_blocks < nb;
+    if (transposed) {
+      L.ar[lane] = ar;
+      L.az[lane] = az;
+      L.La[lane] = La;
+    }
     wave_sync();
 
     // Sweep the out-cells in segments short enough for the packed queue
@@ -366,8 +376,8 @@ __global__ void __launch_bounds__(WAVES * kWave)
       int qn = 0;  // queued pairs (uniform)
       // Queues the passing lanes of out-cell j; runs a beam batch when a full
       // wave of pairs is waiting.
-      auto append = [&](int j, bool pass, uint64_t mk) {
-        if (pass) L.queue[qn + lane_prefix(mk)] = (j << 6) | lane;
+      auto append = [&](int j, int li, bool pass, uint64_t mk) {
+        if (pass) L.queue[qn + lane_prefix(mk)] = (j << 6) | li;
         qn += __popcll(mk);
         if (qn >= kWave) {
           wave_sync();
@@ -379,6 +389,31 @@ __global__ void __launch_bounds__(WAVES * kWave)
           wave_sync();
         }
       };
+      if (transposed) {
+        for (int ob = 0; ob < ns; ob += kWave) {
+          const int j = ob + lane;
+          const bool valid = j < ns;
+          double br = 0.0, bz = 0.0, Lb = 0.0, theta2 = 0.0;
+          if (valid) {
+            const double Ls = gLs[cs + j];
+            br = gdr[cs + j];
+            bz = gdz[cs + j];
+            Lb = fabs(Ls);
+            theta2 = __builtin_signbit(Ls) ? th2e : th2b;  // end-cap outer hit: negative
+          }
+          for (int i = 0; i < m; ++i) {
+            const bool pass = valid && rz_pass(L.ar[i], L.az[i], L.La[i], br, bz, Lb, theta2);
+            const uint64_t mk = __ballot(pass);
+            if (mk) append(j, i, pass, mk);
+          }
+        }
+        if (qn > 0) {
+          wave_sync();
+          beam_batch(k, a, L, qn, cs, X1, Y1);
+        }
+        wave_sync();
+        continue;
+      }
       int j = 0;
       // the loads of the next group are issued before the tests of this one
       double pdr[kUnroll], pdz[kUnroll], pLs[kUnroll];
@@ -420,7 +455,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
         if (any) {
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u)
-            if (mk[u]) append(j + u, pass[u], mk[u]);
+            if (mk[u]) append(j + u, lane, pass[u], mk[u]);
         }
       }
       for (; j < ns; ++j) {
@@ -429,7 +464,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
         const double theta2 = (__double2hiint(Ls) < 0) ? th2e : th2b;  // end-cap outer hit: negative
         const bool pass = rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2);
         const uint64_t mk = __ballot(pass);
-        if (mk) append(j, pass, mk);
+        if (mk) append(j, lane, pass, mk);
       }
       if (qn > 0) {
         wave_sync();

@@ -227,3 +227,25 @@ def test_inner_cell_with_many_links_takes_the_overflow_path():
     assert link_set(got["cell_inner"], got["cell_outer"], got["link_in"], got["link_out"]) == rl
     _link_layout_ok(pipe)
     assert tuplet_set(got["kept_hits"], got["kept_n"]) == tuplet_set(ref["hits"], ref["n"])
+
+
+def test_autotuned_settings_give_the_same_products():
+    """The autotuner only picks performance settings: the tuned run produces
+    the same doublets, links and kept n-tuplets as the defaults."""
+    _need_gpu()
+    from paper_2008_13461_amd import api, autotune
+    from tests.gpu_helpers import caps_for
+    from tests.helpers import link_set
+    h = E.config2()
+    caps = caps_for(h.n_hits, h.n_events)
+    hits = api.Hits.from_host(h)
+    perf = autotune.tune(CFG, hits, caps, repeats=1, cache=None)
+    assert set(perf) == set(autotune.CANDIDATES)
+    for name, v in perf.items():
+        assert v in autotune.CANDIDATES[name]
+    _, a = _run(h)
+    _, b = _run(h, **perf)
+    assert doublet_set(a["cell_inner"], a["cell_outer"]) == doublet_set(b["cell_inner"], b["cell_outer"])
+    assert link_set(a["cell_inner"], a["cell_outer"], a["link_in"], a["link_out"]) == \
+        link_set(b["cell_inner"], b["cell_outer"], b["link_in"], b["link_out"])
+    assert tuplet_set(a["kept_hits"], a["kept_n"]) == tuplet_set(b["kept_hits"], b["kept_n"])
