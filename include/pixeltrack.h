@@ -332,8 +332,9 @@ void pt_plan_destroy(pt_plan plan);
 /* Kernel timing (instrumentation).  While enabled, the individual calls (not
  * graph launches) record a pair of HIP events around their main kernels on
  * their stream, one kernel each unless noted: "doublets_count",
- * "doublets_write", "cell_geom" (cell segments and ranks), "link_by_outer"
- * (the index of cells by outer hit), "links" (the triplet sweep),
+ * "doublets_write", "cell_geom" (cell segments and the index of cells by
+ * outer hit), "link_segments" (placing the index segments), "links" (the
+ * triplet sweep),
  * "link_emit" (placing the links), "root_count", "root_write", "dfs_count",
  * "dfs_write", "dedup" (several kernels), "fit_fwd", "fit_bwd".  pt_timing_read waits for the recorded events and
  * returns the summed milliseconds and the number of launches since the last

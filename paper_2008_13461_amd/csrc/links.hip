@@ -38,6 +38,7 @@ namespace {
 constexpr int kLocal = 8;        // links an in-cell keeps in LDS before the overflow path
 constexpr int kUnroll = 4;       // out-cells tested per step of the sweep
 constexpr int kSegment = 1 << 24;  // out-cells per queue segment (offsets fit beside the lane)
+constexpr int kSegWin = 2 * 64;    // in-cell segments of a hit handled per window
 
 // Index entry of an in-cell c' = (h0, h1): its cell index, and its inner hit
 // with the BPix1 flag in the top bit.  The triplet tests rebuild the R-Z
@@ -106,8 +107,11 @@ struct GeomArgs {
   double* dr;
   double* dz;
   double* Ls;          // +L (outer hit on a barrel layer) or -L
-  int32_t* rank;       // rank among the cells ending on the same hit
-  int32_t* n_in;       // [n_hits + 1] cells ending on each hit
+  InCell* ent;         // the block's cells grouped by outer hit, in the block's own range
+  int4* grp;           // per block: its groups (outer hit, first entry, cells, slot in the hit's list)
+  int32_t* n_grp;      // per block: number of groups
+  int32_t* n_seg;      // [n_hits + 1] groups ending on each hit
+  int32_t* lcnt;       // cleared here (link counts of the entries)
   int32_t* out_count;
   uint8_t* has_inner;
 };
@@ -117,17 +121,22 @@ constexpr int kGeomItems = 16;
 constexpr int kGeomChunk = kGeomBlock * kGeomItems;  // cells per block; also the hash table size
 static_assert((kGeomChunk & (kGeomChunk - 1)) == 0, "hash table size must be a power of two");
 
-// Cell geometry, and each cell's rank among the cells ending on its outer
-// hit.  The ranks are taken per block: the block's cells are grouped by
-// outer hit in an LDS hash table, each group reserves its run with one
-// global atomic, and a cell's rank is the run start plus its rank in the
-// group.  Cells of neighbouring inner hits share most outer hits, so this
-// takes far fewer global atomics than one per cell.
+// Cell geometry and the index of cells by outer hit.  Each block takes a
+// chunk of kGeomChunk consecutive cells (neighbouring inner hits, which share
+// most outer hits), groups them by outer hit in an LDS hash table, and writes
+// them as index entries grouped by outer hit into the chunk's own range of
+// `ent` (contiguous writes).  Each group becomes one segment of its outer
+// hit's in-cell list: the hit's segment count is taken with one global
+// atomic per group, and the segment itself is placed by k_seg_scatter once
+// the counts are scanned.  out_count, has_inner and the link counts are
+// cleared here (out_start is only read where out_count > 0).
 template <class T>
 __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> a) {
   __shared__ int32_t s_key[kGeomChunk];    // outer hit of the slot, -1 when free
-  __shared__ int32_t s_cnt[kGeomChunk];    // cells in the slot, then the slot's global run start
+  __shared__ int32_t s_cnt[kGeomChunk];    // cells in the slot
+  __shared__ int32_t s_pos[kGeomChunk];    // the slot's first entry (low 16 bits: group index)
   __shared__ int32_t s_cell[kGeomChunk];   // per cell: slot | rank in the slot << 12
+  __shared__ int32_t s_scan[kGeomBlock / kWave + 1];
   static_assert(kGeomChunk <= 4096, "slot and rank are packed in 12 bits each");
   const int n = min(*a.cell_count, a.cells_cap);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kGeomChunk;
@@ -152,8 +161,9 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
     a.dr[c] = dr;
     a.dz[c] = dz;
     a.Ls[c] = k.layer_barrel[a.layer[h1]] ? L : -L;
-    a.out_count[c] = 0;  // out_start is only read where out_count > 0
+    a.out_count[c] = 0;
     a.has_inner[c] = 0;
+    a.lcnt[c] = 0;
     // linear probing; the table has a slot for every cell of the block
     int slot = static_cast<int>((static_cast<uint32_t>(h1) * 2654435761u) >> 20) & (kGeomChunk - 1);
     while (true) {
@@ -165,65 +175,16 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
     s_cell[loc] = slot | (r << 12);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kGeomChunk; i += kGeomBlock) {
-    const int key = s_key[i];
-    if (key >= 0) s_cnt[i] = atomicAdd(a.n_in + key, s_cnt[i]);
-  }
-  __syncthreads();
-  for (int i = 0; i < kGeomItems; ++i) {
-    const int loc = i * kGeomBlock + threadIdx.x;
-    const int64_t c64 = base + loc;
-    if (c64 >= n) break;
-    const int v = s_cell[loc];
-    a.rank[c64] = s_cnt[v & (kGeomChunk - 1)] + (v >> 12);
-  }
-}
-
-// Index entries of the cells by outer hit.  Works on the same chunks as
-// k_cell_geom, whose groups (cells of the chunk ending on one hit) hold
-// consecutive ranks: the chunk's cells are staged in LDS in (group, rank)
-// order, so that each group is written as one contiguous run.
-__global__ void __launch_bounds__(kGeomBlock)
-    k_by_outer(const int32_t* __restrict__ cell_count, int32_t cells_cap, const int32_t* __restrict__ inner,
-               const int32_t* __restrict__ outer, const uint8_t* __restrict__ layer,
-               const int32_t* __restrict__ rank, const int32_t* __restrict__ first_in, InCell* __restrict__ rec) {
-  __shared__ int32_t s_key[kGeomChunk];   // outer hit of the slot; then the staged cells
-  __shared__ int32_t s_cnt[kGeomChunk];   // cells in the slot; then the slot's first staging index
-  __shared__ int32_t s_min[kGeomChunk];   // lowest rank in the slot (the group's first rank)
-  __shared__ int32_t s_slot[kGeomChunk];  // slot of each cell of the chunk
-  __shared__ int32_t s_scan[kGeomBlock / kWave + 1];
-  const int n = min(*cell_count, cells_cap);
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kGeomChunk;
-  if (base >= n) return;
-  const int m = static_cast<int>(min<int64_t>(kGeomChunk, n - base));
-  for (int i = threadIdx.x; i < kGeomChunk; i += kGeomBlock) {
-    s_key[i] = -1;
-    s_cnt[i] = 0;
-    s_min[i] = INT32_MAX;
-  }
-  __syncthreads();
-  for (int loc = threadIdx.x; loc < m; loc += kGeomBlock) {
-    const int c = static_cast<int>(base + loc);
-    const int h1 = outer[c];
-    int slot = static_cast<int>((static_cast<uint32_t>(h1) * 2654435761u) >> 20) & (kGeomChunk - 1);
-    while (true) {
-      const int prev = atomicCAS(&s_key[slot], -1, h1);
-      if (prev == -1 || prev == h1) break;
-      slot = (slot + 1) & (kGeomChunk - 1);
-    }
-    atomicAdd(&s_cnt[slot], 1);
-    atomicMin(&s_min[slot], rank[c]);
-    s_slot[loc] = slot;
-  }
-  __syncthreads();
-  // exclusive scan of the slot counts: kGeomItems consecutive slots per thread
+  // one scan gives every slot its first entry (high half) and its group
+  // index (low half): kGeomItems consecutive slots per thread
+  int ngroups;
   {
     const int t0 = threadIdx.x * kGeomItems;
     int v[kGeomItems];
     int sum = 0;
 #pragma unroll
     for (int i = 0; i < kGeomItems; ++i) {
-      v[i] = s_cnt[t0 + i];
+      v[i] = (s_cnt[t0 + i] << 16) | (s_key[t0 + i] >= 0 ? 1 : 0);
       sum += v[i];
     }
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -242,30 +203,51 @@ __global__ void __launch_bounds__(kGeomBlock)
         s_scan[w] = run;
         run += x;
       }
+      s_scan[kGeomBlock / kWave] = run;
     }
     __syncthreads();
     int run = s_scan[wave] + incl - sum;
 #pragma unroll
     for (int i = 0; i < kGeomItems; ++i) {
-      s_cnt[t0 + i] = run;
+      s_pos[t0 + i] = run;
       run += v[i];
     }
+    ngroups = s_scan[kGeomBlock / kWave] & 0xFFFF;
   }
   __syncthreads();
-  // stage the cells in (group, rank) order; the hash keys are no longer needed
-  for (int loc = threadIdx.x; loc < m; loc += kGeomBlock) {
-    const int c = static_cast<int>(base + loc);
-    const int slot = s_slot[loc];
-    s_key[s_cnt[slot] + (rank[c] - s_min[slot])] = c;
+  for (int i = threadIdx.x; i < kGeomChunk; i += kGeomBlock) {
+    const int key = s_key[i];
+    if (key < 0) continue;
+    const int pv = s_pos[i];
+    const int slot_in_list = atomicAdd(a.n_seg + key, 1);
+    a.grp[base + (pv & 0xFFFF)] = make_int4(key, static_cast<int>(base) + (pv >> 16), s_cnt[i], slot_in_list);
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < m; i += kGeomBlock) {
-    const int c = s_key[i];
-    const int h0 = inner[c];
-    InCell r;
-    r.cell = c;
-    r.h0b = h0 | (layer[h0] == 0 ? kBpix1Bit : 0);
-    rec[first_in[outer[c]] + rank[c]] = r;
+  if (threadIdx.x == 0) a.n_grp[blockIdx.x] = ngroups;
+  for (int i = 0; i < kGeomItems; ++i) {
+    const int loc = i * kGeomBlock + threadIdx.x;
+    const int64_t c64 = base + loc;
+    if (c64 >= n) break;
+    const int v = s_cell[loc];
+    const int h0 = a.inner[c64];
+    InCell e;
+    e.cell = static_cast<int>(c64);
+    e.h0b = h0 | (a.layer[h0] == 0 ? kBpix1Bit : 0);
+    a.ent[base + (s_pos[v & (kGeomChunk - 1)] >> 16) + (v >> 12)] = e;
+  }
+}
+
+// Places every group as a segment (first entry, cells) of its outer hit's
+// list, at the hit's scanned segment offset plus the group's slot.
+__global__ void k_seg_scatter(const int32_t* __restrict__ cell_count, int32_t cells_cap,
+                              const int4* __restrict__ grp, const int32_t* __restrict__ n_grp,
+                              const int32_t* __restrict__ seg_first, int2* __restrict__ seg) {
+  const int n = min(*cell_count, cells_cap);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kGeomChunk;
+  if (base >= n) return;
+  const int g_n = n_grp[blockIdx.x];
+  for (int g = threadIdx.x; g < g_n; g += blockDim.x) {
+    const int4 e = grp[base + g];
+    seg[seg_first[e.x] + e.w] = make_int2(e.y, e.z);
   }
 }
 
@@ -277,6 +259,8 @@ struct WaveLds {
   int32_t bpix1[kWave];
   int32_t cnt[kWave];            // links found per in-cell lane
   int32_t found[kWave * kLocal]; // their out-cells
+  int32_t sfirst[kSegWin];       // a window of the hit's segments: first entry ...
+  int32_t spre[kSegWin + 1];     // ... and the in-cells before each (exclusive prefix)
 };
 
 template <class T>
@@ -288,9 +272,10 @@ struct HitArgs {
   const int32_t* outer;
   const int32_t* inner_first;
   const int32_t* inner_count;
-  const int32_t* first_in;
-  const InCell* rec;
-  int32_t* lcnt;      // [cells_cap + 1] links of each in-cell record (scanned afterwards)
+  const int32_t* seg_first;  // [n_hits + 1] first segment of each hit's in-cell list
+  const int2* seg;           // segments: (first entry, entries)
+  const InCell* ent;         // index entries
+  int32_t* lcnt;      // [cells_cap + 1] links of each entry, zero on entry (scanned afterwards)
   int32_t* spill;     // [cells_cap][kLocal] their out-cells, ascending (when at most kLocal)
   int32_t* ovf;       // in-cells with more than kLocal links
   int32_t* ovf_count;
@@ -326,184 +311,221 @@ __global__ void __launch_bounds__(WAVES * kWave)
   WaveLds& L = lds[wave];
   const int h1 = blockIdx.x * WAVES + wave;
   if (h1 >= a.n_hits) return;
-  const int ib = a.first_in[h1];
-  const int ie = a.first_in[h1 + 1];
-  if (ie <= ib) return;
+  const int sb = a.seg_first[h1];
+  const int se = a.seg_first[h1 + 1];
+  if (se <= sb) return;
   const int n_cells = min(*a.cell_count, a.cells_cap);
   const int cb = a.inner_first[h1];
   const int nb = min(cb + a.inner_count[h1], n_cells) - cb;
-  if (a.inner_count[h1] <= 0 || nb <= 0) {  // no out-cells: no links
-    for (int r = ib + lane; r < ie; r += kWave) a.lcnt[r] = 0;
-    return;
-  }
+  if (a.inner_count[h1] <= 0 || nb <= 0) return;  // no out-cells: no links (counts are zero)
   const double4 P1 = a.hx[h1];
   const double X1 = P1.x, Y1 = P1.y;
   const double th2b = k.theta2_barrel, th2e = k.theta2_endcap;
 
-  for (int base = ib; base < ie; base += kWave) {
-    const int m = min(kWave, ie - base);
-    // in-cell of this lane (NaN makes the R-Z test fail for idle lanes)
-    double ar = __builtin_nan(""), az = __builtin_nan(""), La = __builtin_nan("");
-    int cell = -1;
-    if (lane < m) {
-      const InCell r = a.rec[base + lane];
-      const double4 P0 = a.hx[r.h0b & ~kBpix1Bit];
-      ar = P1.w - P0.w;  // as in k_cell_geom
-      az = P1.z - P0.z;
-      La = ar * ar + az * az;
-      cell = r.cell;
-      L.X0[lane] = P0.x;
-      L.Y0[lane] = P0.y;
-      L.bpix1[lane] = (r.h0b & kBpix1Bit) != 0;
+  for (int sw = sb; sw < se; sw += kSegWin) {
+    // a window of the hit's segments and the prefix of their sizes
+    const int wn = min(kSegWin, se - sw);
+    int c0 = 0, c1 = 0;
+    if (lane < wn) {
+      const int2 g = a.seg[sw + lane];
+      L.sfirst[lane] = g.x;
+      c0 = g.y;
     }
-    L.cnt[lane] = 0;
-    // A partial pass with few in-cells sweeps the other way round: lanes over
-    // the out-cells, the in-cells (from LDS) in a wave-uniform loop.
-    const int out_blocks = (nb + kWave - 1) / kWave;
-    const bool transposed = m < kWave && static_cast<int64_t>(m) * out_blocks < nb;
-    if (transposed) {
-      L.ar[lane] = ar;
-      L.az[lane] = az;
-      L.La[lane] = La;
+    if (kWave + lane < wn) {
+      const int2 g = a.seg[sw + kWave + lane];
+      L.sfirst[kWave + lane] = g.x;
+      c1 = g.y;
     }
+    int i0 = c0, i1 = c1;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o0 = __shfl_up(i0, d, kWave);
+      const int o1 = __shfl_up(i1, d, kWave);
+      if (lane >= d) {
+        i0 += o0;
+        i1 += o1;
+      }
+    }
+    const int t0 = __shfl(i0, kWave - 1, kWave);
+    const int aw = __builtin_amdgcn_readfirstlane(t0 + __shfl(i1, kWave - 1, kWave));  // in-cells of the window
+    L.spre[lane] = i0 - c0;
+    L.spre[kWave + lane] = t0 + i1 - c1;
+    wave_sync();
+    if (lane == 0) L.spre[wn] = aw;
     wave_sync();
 
-    // Sweep the out-cells in segments short enough for the packed queue
-    // entries (offset << 6 | lane).
-    for (int sb = 0; sb < nb; sb += kSegment) {
-      const int cs = cb + sb;
-      const int ns = min(kSegment, nb - sb);
-      int qn = 0;  // queued pairs (uniform)
-      // Queues the passing lanes of out-cell j; runs a beam batch when a full
-      // wave of pairs is waiting.
-      auto append = [&](int j, int li, bool pass, uint64_t mk) {
-        if (pass) L.queue[qn + lane_prefix(mk)] = (j << 6) | li;
-        qn += __popcll(mk);
-        if (qn >= kWave) {
-          wave_sync();
-          beam_batch(k, a, L, kWave, cs, X1, Y1);
-          qn -= kWave;
-          const int t = (lane < qn) ? L.queue[kWave + lane] : 0;
-          wave_sync();
-          if (lane < qn) L.queue[lane] = t;
-          wave_sync();
+    for (int base = 0; base < aw; base += kWave) {
+      const int m = min(kWave, aw - base);
+      // in-cell of this lane (NaN makes the R-Z test fail for idle lanes)
+      double ar = __builtin_nan(""), az = __builtin_nan(""), La = __builtin_nan("");
+      int cell = -1;
+      int r = -1;  // its index entry
+      if (lane < m) {
+        const int idx = base + lane;
+        int lo = 0, hi = wn;  // spre[lo] <= idx < spre[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (L.spre[mid] <= idx) lo = mid; else hi = mid;
         }
-      };
+        r = L.sfirst[lo] + (idx - L.spre[lo]);
+        const InCell e = a.ent[r];
+        const double4 P0 = a.hx[e.h0b & ~kBpix1Bit];
+        ar = P1.w - P0.w;  // as in k_cell_geom
+        az = P1.z - P0.z;
+        La = ar * ar + az * az;
+        cell = e.cell;
+        L.X0[lane] = P0.x;
+        L.Y0[lane] = P0.y;
+        L.bpix1[lane] = (e.h0b & kBpix1Bit) != 0;
+      }
+      L.cnt[lane] = 0;
+      // A partial pass with few in-cells sweeps the other way round: lanes over
+      // the out-cells, the in-cells (from LDS) in a wave-uniform loop.
+      const int out_blocks = (nb + kWave - 1) / kWave;
+      const bool transposed = m < kWave && static_cast<int64_t>(m) * out_blocks < nb;
       if (transposed) {
-        for (int ob = 0; ob < ns; ob += kWave) {
-          const int j = ob + lane;
-          const bool valid = j < ns;
-          double br = 0.0, bz = 0.0, Lb = 0.0, theta2 = 0.0;
-          if (valid) {
-            const double Ls = gLs[cs + j];
-            br = gdr[cs + j];
-            bz = gdz[cs + j];
-            Lb = fabs(Ls);
-            theta2 = __builtin_signbit(Ls) ? th2e : th2b;  // end-cap outer hit: negative
+        L.ar[lane] = ar;
+        L.az[lane] = az;
+        L.La[lane] = La;
+      }
+      wave_sync();
+
+      // Sweep the out-cells in segments short enough for the packed queue
+      // entries (offset << 6 | lane).
+      for (int jb = 0; jb < nb; jb += kSegment) {
+        const int cs = cb + jb;
+        const int ns = min(kSegment, nb - jb);
+        int qn = 0;  // queued pairs (uniform)
+        // Queues the passing lanes of out-cell j; runs a beam batch when a full
+        // wave of pairs is waiting.
+        auto append = [&](int j, int li, bool pass, uint64_t mk) {
+          if (pass) L.queue[qn + lane_prefix(mk)] = (j << 6) | li;
+          qn += __popcll(mk);
+          if (qn >= kWave) {
+            wave_sync();
+            beam_batch(k, a, L, kWave, cs, X1, Y1);
+            qn -= kWave;
+            const int t = (lane < qn) ? L.queue[kWave + lane] : 0;
+            wave_sync();
+            if (lane < qn) L.queue[lane] = t;
+            wave_sync();
           }
-          for (int i = 0; i < m; ++i) {
-            const bool pass = valid && rz_pass(L.ar[i], L.az[i], L.La[i], br, bz, Lb, theta2);
-            const uint64_t mk = __ballot(pass);
-            if (mk) append(j, i, pass, mk);
+        };
+        if (transposed) {
+          for (int ob = 0; ob < ns; ob += kWave) {
+            const int j = ob + lane;
+            const bool valid = j < ns;
+            double br = 0.0, bz = 0.0, Lb = 0.0, theta2 = 0.0;
+            if (valid) {
+              const double Ls = gLs[cs + j];
+              br = gdr[cs + j];
+              bz = gdz[cs + j];
+              Lb = fabs(Ls);
+              theta2 = __builtin_signbit(Ls) ? th2e : th2b;  // end-cap outer hit: negative
+            }
+            for (int i = 0; i < m; ++i) {
+              const bool pass = valid && rz_pass(L.ar[i], L.az[i], L.La[i], br, bz, Lb, theta2);
+              const uint64_t mk = __ballot(pass);
+              if (mk) append(j, i, pass, mk);
+            }
           }
+          if (qn > 0) {
+            wave_sync();
+            beam_batch(k, a, L, qn, cs, X1, Y1);
+          }
+          wave_sync();
+          continue;
+        }
+        int j = 0;
+        // the loads of the next group are issued before the tests of this one
+        double pdr[kUnroll], pdz[kUnroll], pLs[kUnroll];
+        if (kUnroll <= ns) {
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            pdr[u] = gdr[cs + u];
+            pdz[u] = gdz[cs + u];
+            pLs[u] = gLs[cs + u];
+          }
+        }
+        for (; j + kUnroll <= ns; j += kUnroll) {
+          double cdr[kUnroll], cdz[kUnroll], cLs[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            cdr[u] = pdr[u];
+            cdz[u] = pdz[u];
+            cLs[u] = pLs[u];
+          }
+          if (j + 2 * kUnroll <= ns) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+              const int c = cs + j + kUnroll + u;
+              pdr[u] = gdr[c];
+              pdz[u] = gdz[c];
+              pLs[u] = gLs[c];
+            }
+          }
+          bool pass[kUnroll];
+          uint64_t mk[kUnroll];
+          uint64_t any = 0;
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const double theta2 = (__double2hiint(cLs[u]) < 0) ? th2e : th2b;  // end-cap outer hit: negative
+            pass[u] = rz_pass(ar, az, La, cdr[u], cdz[u], fabs(cLs[u]), theta2);
+            mk[u] = __ballot(pass[u]);
+            any |= mk[u];
+          }
+          if (any) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+              if (mk[u]) append(j + u, lane, pass[u], mk[u]);
+          }
+        }
+        for (; j < ns; ++j) {
+          const int c = cs + j;
+          const double Ls = gLs[c];
+          const double theta2 = (__double2hiint(Ls) < 0) ? th2e : th2b;  // end-cap outer hit: negative
+          const bool pass = rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2);
+          const uint64_t mk = __ballot(pass);
+          if (mk) append(j, lane, pass, mk);
         }
         if (qn > 0) {
           wave_sync();
           beam_batch(k, a, L, qn, cs, X1, Y1);
         }
         wave_sync();
-        continue;
       }
-      int j = 0;
-      // the loads of the next group are issued before the tests of this one
-      double pdr[kUnroll], pdz[kUnroll], pLs[kUnroll];
-      if (kUnroll <= ns) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          pdr[u] = gdr[cs + u];
-          pdz[u] = gdz[cs + u];
-          pLs[u] = gLs[cs + u];
+
+      // record the link count of each in-cell, and its links sorted by out-cell
+      // when they fit the spill row; positions come from a scan afterwards
+      const int n = (lane < m) ? L.cnt[lane] : 0;
+      if (n > 0) {
+        a.lcnt[r] = n;
+        if (n > kLocal) {
+          const int slot = atomicAdd(a.ovf_count, 1);
+          a.ovf[slot] = cell;
         }
       }
-      for (; j + kUnroll <= ns; j += kUnroll) {
-        double cdr[kUnroll], cdz[kUnroll], cLs[kUnroll];
+      if (n > 0 && n <= kLocal) {
+        int f[kLocal];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          cdr[u] = pdr[u];
-          cdz[u] = pdz[u];
-          cLs[u] = pLs[u];
-        }
-        if (j + 2 * kUnroll <= ns) {
+        for (int q = 0; q < kLocal; ++q) f[q] = (q < n) ? L.found[lane * kLocal + q] : INT32_MAX;
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            const int c = cs + j + kUnroll + u;
-            pdr[u] = gdr[c];
-            pdz[u] = gdz[c];
-            pLs[u] = gLs[c];
+        for (int i = 1; i < kLocal; ++i) {
+#pragma unroll
+          for (int q = kLocal - 1; q >= i; --q) {
+            const int lo = min(f[q - 1], f[q]);
+            const int hi = max(f[q - 1], f[q]);
+            f[q - 1] = lo;
+            f[q] = hi;
           }
         }
-        bool pass[kUnroll];
-        uint64_t mk[kUnroll];
-        uint64_t any = 0;
+        int32_t* sp = a.spill + static_cast<int64_t>(r) * kLocal;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const double theta2 = (__double2hiint(cLs[u]) < 0) ? th2e : th2b;  // end-cap outer hit: negative
-          pass[u] = rz_pass(ar, az, La, cdr[u], cdz[u], fabs(cLs[u]), theta2);
-          mk[u] = __ballot(pass[u]);
-          any |= mk[u];
-        }
-        if (any) {
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u)
-            if (mk[u]) append(j + u, lane, pass[u], mk[u]);
-        }
-      }
-      for (; j < ns; ++j) {
-        const int c = cs + j;
-        const double Ls = gLs[c];
-        const double theta2 = (__double2hiint(Ls) < 0) ? th2e : th2b;  // end-cap outer hit: negative
-        const bool pass = rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2);
-        const uint64_t mk = __ballot(pass);
-        if (mk) append(j, lane, pass, mk);
-      }
-      if (qn > 0) {
-        wave_sync();
-        beam_batch(k, a, L, qn, cs, X1, Y1);
+        for (int q = 0; q < kLocal; ++q)
+          if (q < n) sp[q] = f[q];
       }
       wave_sync();
     }
-
-    // record the link count of each in-cell, and its links sorted by out-cell
-    // when they fit the spill row; positions come from a scan afterwards
-    const int n = (lane < m) ? L.cnt[lane] : 0;
-    const int r = base + lane;
-    if (lane < m) {
-      a.lcnt[r] = n;
-      if (n > kLocal) {
-        const int slot = atomicAdd(a.ovf_count, 1);
-        a.ovf[slot] = cell;
-      }
-    }
-    if (n > 0 && n <= kLocal) {
-      int f[kLocal];
-#pragma unroll
-      for (int q = 0; q < kLocal; ++q) f[q] = (q < n) ? L.found[lane * kLocal + q] : INT32_MAX;
-#pragma unroll
-      for (int i = 1; i < kLocal; ++i) {
-#pragma unroll
-        for (int q = kLocal - 1; q >= i; --q) {
-          const int lo = min(f[q - 1], f[q]);
-          const int hi = max(f[q - 1], f[q]);
-          f[q - 1] = lo;
-          f[q] = hi;
-        }
-      }
-      int32_t* sp = a.spill + static_cast<int64_t>(r) * kLocal;
-#pragma unroll
-      for (int q = 0; q < kLocal; ++q)
-        if (q < n) sp[q] = f[q];
-    }
-    wave_sync();
   }
 }
 
@@ -513,7 +535,7 @@ struct EmitArgs {
   int32_t cells_cap;
   const int32_t* lcnt;   // scanned: first link of each record; lcnt[n] = total
   const int32_t* spill;
-  const InCell* rec;
+  const InCell* ent;
   int32_t links_cap;
   int32_t* in_cell;
   int32_t* out_cell;
@@ -528,7 +550,7 @@ __global__ void k_link_emit(EmitArgs a) {
     const int pos = a.lcnt[r];
     const int cnt = a.lcnt[r + 1] - pos;
     if (cnt == 0) continue;
-    const int cell = a.rec[r].cell;
+    const int cell = a.ent[r].cell;
     a.out_start[cell] = pos;
     a.out_count[cell] = cnt;
     if (cnt > kLocal) continue;  // written by k_links_overflow
@@ -590,18 +612,22 @@ __global__ void k_finish_links(const int32_t* count, int32_t cap, uint32_t* stat
 
 size_t ws_links(int n_hits, int cells_cap) {
   const int64_t scan_n = std::max<int64_t>(n_hits, cells_cap);
+  const int64_t chunks = std::max<int64_t>(1, (static_cast<int64_t>(cells_cap) + kGeomChunk - 1) / kGeomChunk);
   Carver c(nullptr);
   c.take<double4>(n_hits);                  // hit table
   c.take<double>(cells_cap);                // dr
   c.take<double>(cells_cap);                // dz
   c.take<double>(cells_cap);                // Ls
-  c.take<int32_t>(cells_cap);               // rank, then the overflow list
-  c.take<int32_t>(1);                       // overflow count
-  c.take<int32_t>(static_cast<size_t>(n_hits) + 1);     // in-cell counts -> first_in
-  c.take<int32_t>(static_cast<size_t>(cells_cap) + 1);  // links per record -> first link
+  c.take<InCell>(cells_cap);                // index entries
+  c.take<int4>(cells_cap);                  // groups of each block
+  c.take<int32_t>(chunks);                  // groups per block
+  c.take<int32_t>(static_cast<size_t>(n_hits) + 1);     // segments per hit -> first segment
+  c.take<int2>(cells_cap);                  // segments
+  c.take<int32_t>(static_cast<size_t>(cells_cap) + 1);  // links per entry -> first link
   c.take<int32_t>(scan_tmp_elems(scan_n));
-  c.take<InCell>(cells_cap);                // by-outer records
   c.take<int32_t>(static_cast<size_t>(cells_cap) * kLocal);  // spilled links
+  c.take<int32_t>(cells_cap);               // overflow list
+  c.take<int32_t>(1);                       // overflow count
   return c.off + 256;
 }
 
@@ -623,45 +649,46 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
                         uint32_t* status, pt_workspace ws, hipStream_t s, int block) {
   const int n = h.n_hits;
   const int64_t scan_n = std::max<int64_t>(n, cells.cap);
+  const int64_t chunks = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kGeomChunk - 1) / kGeomChunk);
   Carver c(ws.ptr);
   double4* hx = c.take<double4>(n);
   double* dr = c.take<double>(cells.cap);
   double* dz = c.take<double>(cells.cap);
   double* Ls = c.take<double>(cells.cap);
-  int32_t* rank = c.take<int32_t>(cells.cap);
-  int32_t* ovf_count = c.take<int32_t>(1);
-  int32_t* first_in = c.take<int32_t>(static_cast<size_t>(n) + 1);
+  InCell* ent = c.take<InCell>(cells.cap);
+  int4* grp = c.take<int4>(cells.cap);
+  int32_t* n_grp = c.take<int32_t>(chunks);
+  int32_t* seg_first = c.take<int32_t>(static_cast<size_t>(n) + 1);
+  int2* seg = c.take<int2>(cells.cap);
   int32_t* lcnt = c.take<int32_t>(static_cast<size_t>(cells.cap) + 1);
   int32_t* tmp = c.take<int32_t>(scan_tmp_elems(scan_n));
-  InCell* rec = c.take<InCell>(cells.cap);
   int32_t* spill = c.take<int32_t>(static_cast<size_t>(cells.cap) * kLocal);
-  int32_t* ovf = rank;  // the ranks are dead once the index is built
+  int32_t* ovf = c.take<int32_t>(cells.cap);
+  int32_t* ovf_count = c.take<int32_t>(1);
   const T* x = static_cast<const T*>(h.x);
   const T* y = static_cast<const T*>(h.y);
   const T* z = static_cast<const T*>(h.z);
 
   if (fill_i32(ovf_count, 0, 1, s) != hipSuccess) return PT_ERR_DEVICE;
-  if (fill_i32(first_in, 0, static_cast<int64_t>(n) + 1, s) != hipSuccess) return PT_ERR_DEVICE;
+  if (fill_i32(seg_first, 0, static_cast<int64_t>(n) + 1, s) != hipSuccess) return PT_ERR_DEVICE;
   if (n > 0) {
     k_hit_table<T><<<grid_for(n, 256), 256, 0, s>>>(n, x, y, z, hx);
     PT_LAUNCH_CHECK();
   }
   void* tok = timing_begin(s);
-  GeomArgs<T> g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, hx, dr, dz, Ls, rank, first_in,
-                L.out_count, L.has_inner};
-  const int64_t geom_blocks = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kGeomChunk - 1) / kGeomChunk);
-  k_cell_geom<T><<<static_cast<unsigned>(geom_blocks), kGeomBlock, 0, s>>>(k, g);
+  GeomArgs<T> g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, hx, dr, dz, Ls, ent, grp, n_grp,
+                seg_first, lcnt, L.out_count, L.has_inner};
+  k_cell_geom<T><<<static_cast<unsigned>(chunks), kGeomBlock, 0, s>>>(k, g);
   timing_end(tok, "cell_geom", s);
   PT_LAUNCH_CHECK();
-  if (exclusive_scan(first_in, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  if (exclusive_scan(seg_first, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  k_by_outer<<<static_cast<unsigned>(geom_blocks), kGeomBlock, 0, s>>>(cells.count, cells.cap, cells.inner,
-                                                                       cells.outer, h.layer, rank, first_in, rec);
-  timing_end(tok, "link_by_outer", s);
+  k_seg_scatter<<<static_cast<unsigned>(chunks), 256, 0, s>>>(cells.count, cells.cap, grp, n_grp, seg_first, seg);
+  timing_end(tok, "link_segments", s);
   PT_LAUNCH_CHECK();
 
-  HitArgs<T> a{n, hx, cells.count, cells.cap, cells.outer, cells.inner_first, cells.inner_count, first_in,
-               rec, lcnt, spill, ovf, ovf_count};
+  HitArgs<T> a{n, hx, cells.count, cells.cap, cells.outer, cells.inner_first, cells.inner_count, seg_first, seg,
+               ent, lcnt, spill, ovf, ovf_count};
   tok = timing_begin(s);
   if (n > 0) {
     if (block == 128)
@@ -675,7 +702,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   timing_end(tok, "links", s);
   if (exclusive_scan_dev(lcnt, cells.cap, cells.count, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  EmitArgs e{cells.count, cells.cap, lcnt, spill, rec, L.cap, L.in_cell, L.out_cell, L.out_start, L.out_count,
+  EmitArgs e{cells.count, cells.cap, lcnt, spill, ent, L.cap, L.in_cell, L.out_cell, L.out_start, L.out_count,
              L.has_inner};
   k_link_emit<<<grid_for(cells.cap, 256, 16384), 256, 0, s>>>(e);
   timing_end(tok, "link_emit", s);
