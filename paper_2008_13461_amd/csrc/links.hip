@@ -132,10 +132,10 @@ static_assert((kGeomChunk & (kGeomChunk - 1)) == 0, "hash table size must be a p
 // cleared here (out_start is only read where out_count > 0).
 template <class T>
 __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> a) {
-  __shared__ int32_t s_key[kGeomChunk];    // outer hit of the slot, -1 when free
-  __shared__ int32_t s_cnt[kGeomChunk];    // cells in the slot
-  __shared__ int32_t s_pos[kGeomChunk];    // the slot's first entry (low 16 bits: group index)
-  __shared__ int32_t s_cell[kGeomChunk];   // per cell: slot | rank in the slot << 12
+  __shared__ int32_t s_key[kGeomChunk];      // outer hit of the slot, -1 when free
+  __shared__ int32_t s_pos[kGeomChunk + 1];  // cells in the slot; after the scan its first entry
+                                             // << 16 | its group index
+  __shared__ int32_t s_cell[kGeomChunk];     // per cell: slot | rank in the slot << 12
   __shared__ int32_t s_scan[kGeomBlock / kWave + 1];
   static_assert(kGeomChunk <= 4096, "slot and rank are packed in 12 bits each");
   const int n = min(*a.cell_count, a.cells_cap);
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
   if (base >= n) return;
   for (int i = threadIdx.x; i < kGeomChunk; i += kGeomBlock) {
     s_key[i] = -1;
-    s_cnt[i] = 0;
+    s_pos[i] = 0;
   }
   __syncthreads();
   for (int i = 0; i < kGeomItems; ++i) {
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
       if (prev == -1 || prev == h1) break;
       slot = (slot + 1) & (kGeomChunk - 1);
     }
-    const int r = atomicAdd(&s_cnt[slot], 1);
+    const int r = atomicAdd(&s_pos[slot], 1);
     s_cell[loc] = slot | (r << 12);
   }
   __syncthreads();
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
     int sum = 0;
 #pragma unroll
     for (int i = 0; i < kGeomItems; ++i) {
-      v[i] = (s_cnt[t0 + i] << 16) | (s_key[t0 + i] >= 0 ? 1 : 0);
+      v[i] = (s_pos[t0 + i] << 16) | (s_key[t0 + i] >= 0 ? 1 : 0);
       sum += v[i];
     }
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -204,12 +204,13 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
         run += x;
       }
       s_scan[kGeomBlock / kWave] = run;
+      s_pos[kGeomChunk] = run;
     }
     __syncthreads();
     int run = s_scan[wave] + incl - sum;
 #pragma unroll
     for (int i = 0; i < kGeomItems; ++i) {
-      s_pos[t0 + i] = run;
+      s_pos[t0 + i] = run;  // each thread rewrites only the slots it read
       run += v[i];
     }
     ngroups = s_scan[kGeomBlock / kWave] & 0xFFFF;
@@ -219,8 +220,9 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
     const int key = s_key[i];
     if (key < 0) continue;
     const int pv = s_pos[i];
+    const int cells = (s_pos[i + 1] >> 16) - (pv >> 16);  // empty slots add nothing
     const int slot_in_list = atomicAdd(a.n_seg + key, 1);
-    a.grp[base + (pv & 0xFFFF)] = make_int4(key, static_cast<int>(base) + (pv >> 16), s_cnt[i], slot_in_list);
+    a.grp[base + (pv & 0xFFFF)] = make_int4(key, static_cast<int>(base) + (pv >> 16), cells, slot_in_list);
   }
   if (threadIdx.x == 0) a.n_grp[blockIdx.x] = ngroups;
   for (int i = 0; i < kGeomItems; ++i) {
@@ -261,6 +263,7 @@ struct WaveLds {
   int32_t found[kWave * kLocal]; // their out-cells
   int32_t sfirst[kSegWin];       // a window of the hit's segments: first entry ...
   int32_t spre[kSegWin + 1];     // ... and the in-cells before each (exclusive prefix)
+  int32_t segat[kWave];          // segment starting at each in-cell of a pass, or -1
 };
 
 template <class T>
@@ -360,14 +363,28 @@ __global__ void __launch_bounds__(WAVES * kWave)
       double ar = __builtin_nan(""), az = __builtin_nan(""), La = __builtin_nan("");
       int cell = -1;
       int r = -1;  // its index entry
+      // segment of each lane's in-cell: every segment overlapping the pass
+      // marks its first in-cell in it, then a prefix maximum over the lanes
+      L.segat[lane] = -1;
+      wave_sync();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int sg = h * kWave + lane;
+        if (sg < wn) {
+          const int lo = L.spre[sg] - base, hi = L.spre[sg + 1] - base;
+          if (hi > 0 && lo < kWave) L.segat[lo > 0 ? lo : 0] = sg;
+        }
+      }
+      wave_sync();
+      int sg = L.segat[lane];
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(sg, d, kWave);
+        if (lane >= d) sg = max(sg, o);
+      }
       if (lane < m) {
         const int idx = base + lane;
-        int lo = 0, hi = wn;  // spre[lo] <= idx < spre[hi]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (L.spre[mid] <= idx) lo = mid; else hi = mid;
-        }
-        r = L.sfirst[lo] + (idx - L.spre[lo]);
+        r = L.sfirst[sg] + (idx - L.spre[sg]);
         const InCell e = a.ent[r];
         const double4 P0 = a.hx[e.h0b & ~kBpix1Bit];
         ar = P1.w - P0.w;  // as in k_cell_geom
