@@ -249,3 +249,39 @@ def test_autotuned_settings_give_the_same_products():
     assert link_set(a["cell_inner"], a["cell_outer"], a["link_in"], a["link_out"]) == \
         link_set(b["cell_inner"], b["cell_outer"], b["link_in"], b["link_out"])
     assert tuplet_set(a["kept_hits"], a["kept_n"]) == tuplet_set(b["kept_hits"], b["kept_n"])
+
+
+def _cone_event(n0=200, n1=5000, n2=5, seed=9):
+    """A narrow cone with n0 hits on BPix1, n1 on BPix2 and n2 on BPix3:
+    every BPix1-BPix2 pair is a doublet (~n0 n1 cells), so each block of
+    4096 consecutive cells holds the cells of about one BPix1 hit and every
+    BPix2 hit collects its n0 in-cells from about n0 different blocks -- more
+    index segments than the sweep handles in one window."""
+    rng = np.random.default_rng(seed)
+    cot = 0.5
+    rows = []
+    for lay, n, dphi, dz in ((0, n0, 0.002, 0.05), (1, n1, 0.003, 0.1), (2, n2, 0.003, 0.1)):
+        R = C.BARREL_R[lay]
+        phi = 0.3 + rng.uniform(-dphi, dphi, n)
+        z = R * cot + rng.uniform(-dz, dz, n)
+        rows.append((R * np.cos(phi), R * np.sin(phi), z, np.full(n, lay, np.uint8)))
+    x, y, z, layer = (np.concatenate(v) for v in zip(*rows))
+    perm = rng.permutation(len(x))
+    n = len(x)
+    return E.Hits(x[perm].astype(np.float32), y[perm].astype(np.float32), z[perm].astype(np.float32), layer[perm],
+                  np.zeros(n, np.int16), np.arange(n, dtype=np.int32), np.array([0, n], np.int32))
+
+
+def test_hits_with_in_cells_from_many_blocks():
+    _need_gpu()
+    from tests.helpers import link_set
+    h = _cone_event()
+    ref = O.reconstruct_event(CFG, h.x, h.y, h.z, h.layer)
+    assert len(ref["cell_inner"]) > 900_000 and len(ref["link_in"]) > 0
+    caps = dict(n_hits=h.n_hits, n_events=1, cells_cap=1_200_000, links_cap=2_000_000, tuplets_cap=4096)
+    pipe, got = _run(h, caps=caps)
+    assert pipe.flags() == 0
+    assert doublet_set(got["cell_inner"], got["cell_outer"]) == doublet_set(ref["cell_inner"], ref["cell_outer"])
+    assert link_set(got["cell_inner"], got["cell_outer"], got["link_in"], got["link_out"]) == \
+        link_set(ref["cell_inner"], ref["cell_outer"], ref["link_in"], ref["link_out"])
+    _link_layout_ok(pipe)
