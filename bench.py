@@ -79,15 +79,7 @@ def chain_workload(args):
     log(f"generated {h.n_events} events, {h.n_hits} hits in {time.time() - t0:.1f}s")
     cp = caps(h.n_hits, h.n_events)
     hits = api.Hits.from_host(h)
-    if args.bins:
-        perf = dict(n_phi_bins=args.bins)
-    else:
-        # bin count and block sizes for this batch shape (never change a result)
-        from paper_2008_13461_amd import autotune
-
-        t0 = time.time()
-        perf = autotune.tune(cfg_d, hits, cp, cache=None)
-        log(f"autotuned {perf} in {time.time() - t0:.1f}s")
+    perf = settings(args, cfg_d, hits, cp)
     cfg = A.make_config(cfg_d, **perf)
     offsets = torch.from_numpy(off_np).cuda()
     cells = api.Cells.empty(cp["cells_cap"], h.n_hits)
@@ -367,6 +359,26 @@ def roofline(kern, cnt):
     return roof
 
 
+def settings(args, cfg_d, hits, cp):
+    """Bin count and block sizes: the ones given, else autotuned for this
+    batch shape (they never change a result)."""
+    if args.bins or args.block_doublets or args.block_links:
+        from paper_2008_13461_amd import autotune
+
+        perf = dict(autotune.DEFAULT)
+        for name, v in (("n_phi_bins", args.bins), ("block_doublets", args.block_doublets),
+                        ("block_links", args.block_links)):
+            if v:
+                perf[name] = v
+        return perf
+    from paper_2008_13461_amd import autotune
+
+    t0 = time.time()
+    perf = autotune.tune(cfg_d, hits, cp, cache=None)
+    log(f"autotuned {perf} in {time.time() - t0:.1f}s")
+    return perf
+
+
 def profile_run(args):
     """Two eager passes of the batched step (with the settings the bench
     tunes), then two copies of 1 GiB: the copy
@@ -382,13 +394,7 @@ def profile_run(args):
     h = E.config5(n_events=args.events)
     cp = caps(h.n_hits, h.n_events)
     hits = api.Hits.from_host(h)
-    if args.bins:
-        perf = dict(n_phi_bins=args.bins)
-    else:
-        from paper_2008_13461_amd import autotune
-
-        perf = autotune.tune(C.default_config(), hits, cp, cache=None)
-        log(f"autotuned {perf}")
+    perf = settings(args, C.default_config(), hits, cp)
     pipe = api.Pipeline(C.default_config(), precision=A.PT_FIT_F32_F64SOLVE, **perf, **cp)
     offsets = torch.from_numpy(E.module_offsets()).cuda()
     gp_np, gc_np = E.cotangents(5, cp["tuplets_cap"])
@@ -415,7 +421,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events", type=int, default=64)
     ap.add_argument("--fit-tracks", type=int, default=1_000_000)
-    ap.add_argument("--bins", type=int, default=0, help="azimuth bins per layer (0: tuned default)")
+    ap.add_argument("--bins", type=int, default=0, help="azimuth bins per layer (0: autotuned)")
+    ap.add_argument("--block-doublets", type=int, default=0, help="doublet kernel block size (0: autotuned)")
+    ap.add_argument("--block-links", type=int, default=0, help="link sweep block size (0: autotuned)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-events", type=int, default=256,

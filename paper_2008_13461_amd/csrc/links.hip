@@ -20,8 +20,8 @@
 //     R-Z test of 64 pairs costs a handful of double-precision instructions
 //     and no per-pair gather.  Pairs that pass are queued in LDS and the
 //     beam-spot test (divisions, square roots) runs on full waves of queued
-//     pairs.  Each in-cell's link count is recorded, with its links sorted by
-//     out-cell when there are at most kLocal of them.
+//     pairs.  Each in-cell's link count is recorded, with its links when
+//     there are at most kLocal of them.
 //  5. a scan of the counts places every in-cell's links (no shared counter:
 //     same-address atomics serialise), k_link_emit writes them, and
 //     k_links_overflow recomputes the few in-cells with more than kLocal.
@@ -125,7 +125,7 @@ static_assert((kGeomChunk & (kGeomChunk - 1)) == 0, "hash table size must be a p
 // chunk of kGeomChunk consecutive cells (neighbouring inner hits, which share
 // most outer hits), groups them by outer hit in an LDS hash table, and writes
 // them as index entries grouped by outer hit into the chunk's own range of
-// `ent` (contiguous writes).  Each group becomes one segment of its outer
+// `ent` (staged in LDS, then written contiguously).  Each group becomes one segment of its outer
 // hit's in-cell list: the hit's segment count is taken with one global
 // atomic per group, and the segment itself is placed by k_seg_scatter once
 // the counts are scanned.  out_count, has_inner and the link counts are
@@ -225,16 +225,20 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
     a.grp[base + (pv & 0xFFFF)] = make_int4(key, static_cast<int>(base) + (pv >> 16), cells, slot_in_list);
   }
   if (threadIdx.x == 0) a.n_grp[blockIdx.x] = ngroups;
-  for (int i = 0; i < kGeomItems; ++i) {
-    const int loc = i * kGeomBlock + threadIdx.x;
-    const int64_t c64 = base + loc;
-    if (c64 >= n) break;
+  __syncthreads();  // the hash keys are dead: their array stages the entry order
+  const int m = static_cast<int>(min<int64_t>(kGeomChunk, n - base));
+  for (int loc = threadIdx.x; loc < m; loc += kGeomBlock) {
     const int v = s_cell[loc];
-    const int h0 = a.inner[c64];
+    s_key[(s_pos[v & (kGeomChunk - 1)] >> 16) + (v >> 12)] = loc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += kGeomBlock) {  // the chunk's entries, contiguous
+    const int c = static_cast<int>(base) + s_key[i];
+    const int h0 = a.inner[c];
     InCell e;
-    e.cell = static_cast<int>(c64);
+    e.cell = c;
     e.h0b = h0 | (a.layer[h0] == 0 ? kBpix1Bit : 0);
-    a.ent[base + (s_pos[v & (kGeomChunk - 1)] >> 16) + (v >> 12)] = e;
+    a.ent[base + i] = e;
   }
 }
 
@@ -512,8 +516,8 @@ __global__ void __launch_bounds__(WAVES * kWave)
         wave_sync();
       }
 
-      // record the link count of each in-cell, and its links sorted by out-cell
-      // when they fit the spill row; positions come from a scan afterwards
+      // record the link count of each in-cell, and its links when they fit
+      // the spill row; positions come from a scan afterwards
       const int n = (lane < m) ? L.cnt[lane] : 0;
       if (n > 0) {
         a.lcnt[r] = n;
@@ -522,24 +526,9 @@ __global__ void __launch_bounds__(WAVES * kWave)
           a.ovf[slot] = cell;
         }
       }
-      if (n > 0 && n <= kLocal) {
-        int f[kLocal];
-#pragma unroll
-        for (int q = 0; q < kLocal; ++q) f[q] = (q < n) ? L.found[lane * kLocal + q] : INT32_MAX;
-#pragma unroll
-        for (int i = 1; i < kLocal; ++i) {
-#pragma unroll
-          for (int q = kLocal - 1; q >= i; --q) {
-            const int lo = min(f[q - 1], f[q]);
-            const int hi = max(f[q - 1], f[q]);
-            f[q - 1] = lo;
-            f[q] = hi;
-          }
-        }
+      if (n > 0 && n <= kLocal) {  // sorted by k_link_emit
         int32_t* sp = a.spill + static_cast<int64_t>(r) * kLocal;
-#pragma unroll
-        for (int q = 0; q < kLocal; ++q)
-          if (q < n) sp[q] = f[q];
+        for (int q = 0; q < n; ++q) sp[q] = L.found[lane * kLocal + q];
       }
       wave_sync();
     }
@@ -571,9 +560,21 @@ __global__ void k_link_emit(EmitArgs a) {
     a.out_start[cell] = pos;
     a.out_count[cell] = cnt;
     if (cnt > kLocal) continue;  // written by k_links_overflow
+    // the sweep records links in the order their beam-spot tests finished:
+    // sort them by out-cell
     const int32_t* sp = a.spill + static_cast<int64_t>(r) * kLocal;
+    int f[kLocal];
     for (int q = 0; q < cnt; ++q) {
-      const int c = sp[q];
+      const int v = sp[q];
+      int at = q;
+      while (at > 0 && f[at - 1] > v) {
+        f[at] = f[at - 1];
+        --at;
+      }
+      f[at] = v;
+    }
+    for (int q = 0; q < cnt; ++q) {
+      const int c = f[q];
       a.has_inner[c] = 1;
       if (pos + q < a.links_cap) {
         a.in_cell[pos + q] = cell;
