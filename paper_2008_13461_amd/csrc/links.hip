@@ -38,7 +38,7 @@ namespace {
 constexpr int kLocal = 8;        // links an in-cell keeps in LDS before the overflow path
 constexpr int kUnroll = 4;       // out-cells tested per step of the sweep
 constexpr int kSegment = 1 << 24;  // out-cells per queue segment (offsets fit beside the lane)
-constexpr int kSegWin = 2 * 64;    // in-cell segments of a hit handled per window
+constexpr int kSegWin = 64;        // in-cell segments of a hit handled per window (one per lane)
 
 // Index entry of an in-cell c' = (h0, h1): its cell index, and its inner hit
 // with the BPix1 flag in the top bit.  The triplet tests rebuild the R-Z
@@ -332,31 +332,20 @@ __global__ void __launch_bounds__(WAVES * kWave)
   for (int sw = sb; sw < se; sw += kSegWin) {
     // a window of the hit's segments and the prefix of their sizes
     const int wn = min(kSegWin, se - sw);
-    int c0 = 0, c1 = 0;
+    int c0 = 0;
     if (lane < wn) {
       const int2 g = a.seg[sw + lane];
       L.sfirst[lane] = g.x;
       c0 = g.y;
     }
-    if (kWave + lane < wn) {
-      const int2 g = a.seg[sw + kWave + lane];
-      L.sfirst[kWave + lane] = g.x;
-      c1 = g.y;
-    }
-    int i0 = c0, i1 = c1;
+    int i0 = c0;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
       const int o0 = __shfl_up(i0, d, kWave);
-      const int o1 = __shfl_up(i1, d, kWave);
-      if (lane >= d) {
-        i0 += o0;
-        i1 += o1;
-      }
+      if (lane >= d) i0 += o0;
     }
-    const int t0 = __shfl(i0, kWave - 1, kWave);
-    const int aw = __builtin_amdgcn_readfirstlane(t0 + __shfl(i1, kWave - 1, kWave));  // in-cells of the window
+    const int aw = __builtin_amdgcn_readfirstlane(__shfl(i0, kWave - 1, kWave));  // in-cells of the window
     L.spre[lane] = i0 - c0;
-    L.spre[kWave + lane] = t0 + i1 - c1;
     wave_sync();
     if (lane == 0) L.spre[wn] = aw;
     wave_sync();
@@ -371,13 +360,9 @@ __global__ void __launch_bounds__(WAVES * kWave)
       // marks its first in-cell in it, then a prefix maximum over the lanes
       L.segat[lane] = -1;
       wave_sync();
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int sg = h * kWave + lane;
-        if (sg < wn) {
-          const int lo = L.spre[sg] - base, hi = L.spre[sg + 1] - base;
-          if (hi > 0 && lo < kWave) L.segat[lo > 0 ? lo : 0] = sg;
-        }
+      if (lane < wn) {
+        const int lo = L.spre[lane] - base, hi = L.spre[lane + 1] - base;
+        if (hi > 0 && lo < kWave) L.segat[lo > 0 ? lo : 0] = lane;
       }
       wave_sync();
       int sg = L.segat[lane];
