@@ -138,3 +138,22 @@ def test_batched_equals_per_event():
         ci = full["cell_inner"]
         s2 = (ci >= a) & (ci < b)
         assert doublet_set(ci[s2] - a, full["cell_outer"][s2] - a) == doublet_set(one["cell_inner"], one["cell_outer"])
+
+
+def test_cut_set_without_zip():
+    """Doublet cuts without ZIP (as in the loose cut sets of Table 2): cells may
+    then run inwards (dr <= 0), which the link sweep must handle without its
+    angle windows.  Same sets as the oracle."""
+    _need_gpu()
+    from tests.gpu_helpers import caps_for, products, run_chain
+    cfg = C.default_config(cut_mask=C.CUT_PHIW | C.CUT_ZW | C.CUT_PT)
+    h = E.config2()
+    pipe, _ = run_chain(h, cfg, caps=caps_for(h.n_hits, 1, cells_per_hit=400, links_frac=0.5))
+    assert pipe.flags() == 0
+    prod = products(pipe)
+    ci, co = prod["cell_inner"], prod["cell_outer"]
+    ref = O.reconstruct_event(cfg, h.x, h.y, h.z, h.layer)
+    assert doublet_set(ci, co) == doublet_set(ref["cell_inner"], ref["cell_outer"])
+    assert link_set(ci, co, prod["link_in"], prod["link_out"]) == \
+        link_set(ref["cell_inner"], ref["cell_outer"], ref["link_in"], ref["link_out"])
+    assert tuplet_set(prod["kept_hits"], prod["kept_n"]) == tuplet_set(ref["hits"], ref["n"])
