@@ -122,20 +122,20 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths) {
   uint32_t truncated = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += gridDim.x * blockDim.x) {
     int stack[kMaxHits];   // cells of the current path
-    int next[kMaxHits];    // next outer link to follow at each depth
-    stack[0] = a.roots[i];
-    next[0] = 0;
+    int next[kMaxHits];    // next outer link to follow at each depth (absolute link index) ...
+    int end[kMaxHits];     // ... and the end of that cell's links
+    const int root = a.roots[i];
+    stack[0] = root;
+    next[0] = a.out_start[root];
+    end[0] = next[0] + a.out_count[root];
     int depth = 0;
     int row = COUNT ? 0 : paths[i];
     while (depth >= 0) {
-      const int c = stack[depth];
-      const int oc = a.out_count[c];
-      if (next[depth] >= oc) {
+      if (next[depth] >= end[depth]) {
         --depth;
         continue;
       }
-      const int li = a.out_start[c] + next[depth];
-      ++next[depth];
+      const int li = next[depth]++;
       if (li >= a.links_cap) continue;
       const int child = a.out_cell[li];
       const int nh = depth + 3;  // hits of the path root..child
@@ -162,7 +162,8 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths) {
       } else {
         ++depth;
         stack[depth] = child;
-        next[depth] = 0;
+        next[depth] = a.out_start[child];
+        end[depth] = next[depth] + coc;
       }
     }
     if (COUNT) paths[i] = row;
