@@ -10,10 +10,11 @@
 //  2. k_cell_geom: every cell's R-Z segment (dr, dz) and its squared length,
 //     once, in cell order; the length carries the sign of the barrel/end-cap
 //     class of the cell's outer hit (the class of h2 selects theta).  Each
-//     cell also takes a rank among the cells ending on its outer hit, with
-//     the atomics aggregated per block in an LDS hash table.
-//  3. exclusive scan of the per-hit in-cell counts, then k_by_outer: an
-//     index of the cells by outer hit, 8 bytes per cell (cell, inner hit).
+//     chunk of cells is grouped by outer hit in an LDS hash table and written
+//     to the index grouped that way.
+//  3. exclusive scan of the per-hit segment counts, then k_seg_scatter:
+//     each hit's in-cells as a list of segments of the index (8 bytes per
+//     cell: cell, inner hit), one segment per chunk of k_cell_geom.
 //  4. k_link_hits: one wavefront per middle hit.  Lanes hold the in-cells;
 //     the out-cells (a contiguous run, grouped by inner hit by the doublet
 //     step) are swept in a uniform loop whose loads are wave-uniform, so the
@@ -54,6 +55,16 @@ __device__ __forceinline__ bool rz_pass(double ar, double az, double La, double 
                                         double theta2) {
   const double A = ar * bz - az * br;
   return A * A <= theta2 * (La * Lb);
+}
+
+// Class of an out-cell's outer hit from the sign of its signed squared
+// length (negative: end-cap).  Called with wave-uniform values; the empty asm
+// keeps the test a 32-bit scalar compare of the high word instead of a 64-bit
+// vector compare.
+__device__ __forceinline__ bool endcap_outer(double Ls) {
+  int hi = __double2hiint(Ls);
+  asm volatile("" : "+s"(hi));
+  return hi < 0;
 }
 
 // The beam-spot test of the circle through the three hits.
@@ -116,8 +127,8 @@ struct GeomArgs {
   uint8_t* has_inner;
 };
 
-constexpr int kGeomBlock = 256;
-constexpr int kGeomItems = 16;
+constexpr int kGeomBlock = 1024;
+constexpr int kGeomItems = 4;
 constexpr int kGeomChunk = kGeomBlock * kGeomItems;  // cells per block; also the hash table size
 static_assert((kGeomChunk & (kGeomChunk - 1)) == 0, "hash table size must be a power of two");
 
@@ -125,54 +136,70 @@ static_assert((kGeomChunk & (kGeomChunk - 1)) == 0, "hash table size must be a p
 // chunk of kGeomChunk consecutive cells (neighbouring inner hits, which share
 // most outer hits), groups them by outer hit in an LDS hash table, and writes
 // them as index entries grouped by outer hit into the chunk's own range of
-// `ent` (staged in LDS, then written contiguously).  Each group becomes one segment of its outer
-// hit's in-cell list: the hit's segment count is taken with one global
-// atomic per group, and the segment itself is placed by k_seg_scatter once
-// the counts are scanned.  out_count, has_inner and the link counts are
-// cleared here (out_start is only read where out_count > 0).
+// `ent` (staged in LDS, then written contiguously).  Each group becomes one
+// segment of its outer hit's in-cell list: the hit's segment count is taken
+// with one global atomic per group, and the segment itself is placed by
+// k_seg_scatter once the counts are scanned.  out_count, has_inner and the
+// link counts are cleared here (out_start is only read where out_count > 0).
+//
+// Every global load and atomic of the block is issued before its first
+// global store: on this architecture one counter tracks loads and stores
+// alike, so a load issued after a store would wait for the store's write
+// acknowledgement as well.  The geometry is held in registers until the end.
 template <class T>
 __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> a) {
   __shared__ int32_t s_key[kGeomChunk];      // outer hit of the slot, -1 when free
   __shared__ int32_t s_pos[kGeomChunk + 1];  // cells in the slot; after the scan its first entry
                                              // << 16 | its group index
   __shared__ int32_t s_cell[kGeomChunk];     // per cell: slot | rank in the slot << 12
+  __shared__ int32_t s_h0b[kGeomChunk];      // per cell: inner hit | BPix1 bit
   __shared__ int32_t s_scan[kGeomBlock / kWave + 1];
   static_assert(kGeomChunk <= 4096, "slot and rank are packed in 12 bits each");
   const int n = min(*a.cell_count, a.cells_cap);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kGeomChunk;
   if (base >= n) return;
+  const int m = static_cast<int>(min<int64_t>(kGeomChunk, n - base));
   for (int i = threadIdx.x; i < kGeomChunk; i += kGeomBlock) {
     s_key[i] = -1;
     s_pos[i] = 0;
   }
+  // loads of the block's cells, item u = cell base + u * kGeomBlock + thread
+  int h0[kGeomItems], h1[kGeomItems];
+#pragma unroll
+  for (int u = 0; u < kGeomItems; ++u) {
+    const int loc = u * kGeomBlock + threadIdx.x;
+    const int c = static_cast<int>(base) + (loc < m ? loc : 0);
+    h0[u] = a.inner[c];
+    h1[u] = a.outer[c];
+  }
+  double dr[kGeomItems], dz[kGeomItems], Ls[kGeomItems];
+  int32_t h0b[kGeomItems];
+#pragma unroll
+  for (int u = 0; u < kGeomItems; ++u) {
+    const double4 P0 = a.hx[h0[u]];
+    const double4 P1 = a.hx[h1[u]];
+    dr[u] = P1.w - P0.w;
+    dz[u] = P1.z - P0.z;
+    const double L = dr[u] * dr[u] + dz[u] * dz[u];
+    Ls[u] = k.layer_barrel[a.layer[h1[u]]] ? L : -L;
+    h0b[u] = h0[u] | (a.layer[h0[u]] == 0 ? kBpix1Bit : 0);
+  }
   __syncthreads();
-  for (int i = 0; i < kGeomItems; ++i) {
-    const int loc = i * kGeomBlock + threadIdx.x;
-    const int64_t c64 = base + loc;
-    if (c64 >= n) break;
-    const int c = static_cast<int>(c64);
-    const int h0 = a.inner[c];
-    const int h1 = a.outer[c];
-    const double4 P0 = a.hx[h0];
-    const double4 P1 = a.hx[h1];
-    const double dr = P1.w - P0.w;
-    const double dz = P1.z - P0.z;
-    const double L = dr * dr + dz * dz;
-    a.dr[c] = dr;
-    a.dz[c] = dz;
-    a.Ls[c] = k.layer_barrel[a.layer[h1]] ? L : -L;
-    a.out_count[c] = 0;
-    a.has_inner[c] = 0;
-    a.lcnt[c] = 0;
+#pragma unroll
+  for (int u = 0; u < kGeomItems; ++u) {
+    const int loc = u * kGeomBlock + threadIdx.x;
+    if (loc >= m) break;
     // linear probing; the table has a slot for every cell of the block
-    int slot = static_cast<int>((static_cast<uint32_t>(h1) * 2654435761u) >> 20) & (kGeomChunk - 1);
+    const int key = h1[u];
+    int slot = static_cast<int>((static_cast<uint32_t>(key) * 2654435761u) >> 20) & (kGeomChunk - 1);
     while (true) {
-      const int prev = atomicCAS(&s_key[slot], -1, h1);
-      if (prev == -1 || prev == h1) break;
+      const int prev = atomicCAS(&s_key[slot], -1, key);
+      if (prev == -1 || prev == key) break;
       slot = (slot + 1) & (kGeomChunk - 1);
     }
     const int r = atomicAdd(&s_pos[slot], 1);
     s_cell[loc] = slot | (r << 12);
+    s_h0b[loc] = h0b[u];
   }
   __syncthreads();
   // one scan gives every slot its first entry (high half) and its group
@@ -216,29 +243,50 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
     ngroups = s_scan[kGeomBlock / kWave] & 0xFFFF;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kGeomChunk; i += kGeomBlock) {
-    const int key = s_key[i];
-    if (key < 0) continue;
-    const int pv = s_pos[i];
-    const int cells = (s_pos[i + 1] >> 16) - (pv >> 16);  // empty slots add nothing
-    const int slot_in_list = atomicAdd(a.n_seg + key, 1);
-    a.grp[base + (pv & 0xFFFF)] = make_int4(key, static_cast<int>(base) + (pv >> 16), cells, slot_in_list);
+  // the segment slots of the block's groups (stored with the rest at the end)
+  int key[kGeomItems], slot_in_list[kGeomItems], pv[kGeomItems], cells[kGeomItems];
+#pragma unroll
+  for (int u = 0; u < kGeomItems; ++u) {
+    const int i = u * kGeomBlock + threadIdx.x;
+    key[u] = s_key[i];
+    slot_in_list[u] = key[u] >= 0 ? atomicAdd(a.n_seg + key[u], 1) : 0;
+    pv[u] = s_pos[i];
+    cells[u] = (s_pos[i + 1] >> 16) - (pv[u] >> 16);  // empty slots add nothing
   }
-  if (threadIdx.x == 0) a.n_grp[blockIdx.x] = ngroups;
   __syncthreads();  // the hash keys are dead: their array stages the entry order
-  const int m = static_cast<int>(min<int64_t>(kGeomChunk, n - base));
   for (int loc = threadIdx.x; loc < m; loc += kGeomBlock) {
     const int v = s_cell[loc];
     s_key[(s_pos[v & (kGeomChunk - 1)] >> 16) + (v >> 12)] = loc;
   }
   __syncthreads();
+  // every atomic result is taken here, so that no store below waits for another
+  static_assert(kGeomItems == 4, "one operand per item");
+  asm volatile("" ::"v"(slot_in_list[0]), "v"(slot_in_list[1]), "v"(slot_in_list[2]), "v"(slot_in_list[3]));
+#pragma unroll
+  for (int u = 0; u < kGeomItems; ++u) {
+    if (key[u] >= 0)
+      a.grp[base + (pv[u] & 0xFFFF)] =
+          make_int4(key[u], static_cast<int>(base) + (pv[u] >> 16), cells[u], slot_in_list[u]);
+  }
+  if (threadIdx.x == 0) a.n_grp[blockIdx.x] = ngroups;
   for (int i = threadIdx.x; i < m; i += kGeomBlock) {  // the chunk's entries, contiguous
-    const int c = static_cast<int>(base) + s_key[i];
-    const int h0 = a.inner[c];
+    const int loc = s_key[i];
     InCell e;
-    e.cell = c;
-    e.h0b = h0 | (a.layer[h0] == 0 ? kBpix1Bit : 0);
+    e.cell = static_cast<int>(base) + loc;
+    e.h0b = s_h0b[loc];
     a.ent[base + i] = e;
+  }
+#pragma unroll
+  for (int u = 0; u < kGeomItems; ++u) {
+    const int loc = u * kGeomBlock + threadIdx.x;
+    if (loc >= m) break;
+    const int c = static_cast<int>(base) + loc;
+    a.dr[c] = dr[u];
+    a.dz[c] = dz[u];
+    a.Ls[c] = Ls[u];
+    a.out_count[c] = 0;
+    a.has_inner[c] = 0;
+    a.lcnt[c] = 0;
   }
 }
 
@@ -475,7 +523,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
           uint64_t any = 0;
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
-            const double theta2 = (__double2hiint(cLs[u]) < 0) ? th2e : th2b;  // end-cap outer hit: negative
+            const double theta2 = endcap_outer(cLs[u]) ? th2e : th2b;
             pass[u] = rz_pass(ar, az, La, cdr[u], cdz[u], fabs(cLs[u]), theta2);
             mk[u] = __ballot(pass[u]);
             any |= mk[u];
@@ -489,7 +537,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
         for (; j < ns; ++j) {
           const int c = cs + j;
           const double Ls = gLs[c];
-          const double theta2 = (__double2hiint(Ls) < 0) ? th2e : th2b;  // end-cap outer hit: negative
+          const double theta2 = endcap_outer(Ls) ? th2e : th2b;
           const bool pass = rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2);
           const uint64_t mk = __ballot(pass);
           if (mk) append(j, lane, pass, mk);
