@@ -172,8 +172,15 @@ __device__ inline void window_ranges(const DevCfg& k, const int32_t* bin_start, 
 // passing ones are compacted with a ballot, so that the cells of the inner
 // hit are written as one contiguous, coalesced run.  COUNT = false writes the
 // cells at the scanned offsets, in pair order then window order.
+// Outer hits a wavefront of the write pass gathers in LDS before it stores
+// them: its stores come after its loads, so no load of the window scan waits
+// for a store's acknowledgement (one counter tracks both on this GPU).
+constexpr int kStage = 512;
+
 template <bool WRITE, int WAVES>
 __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArgs a) {
+  __shared__ int32_t s_out[WRITE ? WAVES : 1][WRITE ? kStage : 1];
+  __shared__ uint8_t s_pair[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = __lane_id();
   const int j = blockIdx.x * WAVES + wave;
@@ -190,8 +197,26 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   const int lay = el % kLayers;
   const int e = el / kLayers;
   const double Xi = a.sX[j], Yi = a.sY[j], Zi = a.sZ[j], Ri = a.sR[j];
-  int pos = WRITE ? a.off[j] : 0;  // uniform
+  const int first = WRITE ? a.off[j] : 0;
+  const int last = WRITE ? a.off[j + 1] : 0;
+  int pos = first;  // uniform: next cell position (write pass) or count
   const int hit_i = WRITE ? a.sorted_hit[j] : 0;
+  int staged = 0;                   // uniform: staged cells, to be written from pos on
+  // stores the staged cells, consecutive positions on consecutive lanes
+  auto flush = [&]() {
+    wave_sync();
+    for (int i = lane; i < staged; i += kWave) {
+      const int w = pos + i;
+      if (w < a.cap) {
+        a.inner[w] = hit_i;
+        a.outer[w] = s_out[wave][i];
+        a.pair[w] = s_pair[wave][i];
+      }
+    }
+    wave_sync();
+    pos += staged;
+    staged = 0;
+  };
   const int np = k.n_inner_pairs[lay];
   for (int q = 0; q < np; ++q) {
     const int p = k.inner_pairs[lay][q];
@@ -206,25 +231,27 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
         bool pass = false;
         if (o < rb[r]) pass = doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
         const uint64_t m = __ballot(pass);
-        if (WRITE && pass) {
-          const int w = pos + lane_prefix(m);
-          if (w < a.cap) {
-            a.inner[w] = hit_i;
-            a.outer[w] = a.sorted_hit[o];
-            a.pair[w] = static_cast<uint8_t>(p);
+        if (WRITE) {
+          if (staged + kWave > kStage) flush();
+          if (pass) {
+            const int at = staged + lane_prefix(m);
+            s_out[wave][at] = a.sorted_hit[o];
+            s_pair[wave][at] = static_cast<uint8_t>(p);
           }
+          staged += __popcll(m);
+        } else {
+          pos += __popcll(m);
         }
-        pos += __popcll(m);
       }
     }
   }
+  if (WRITE) flush();
   if (lane == 0) {
     if (!WRITE) {
       a.cnt[j] = pos;
     } else {
-      const int first = a.off[j];
       a.inner_first[hit_i] = first;
-      a.inner_count[hit_i] = a.off[j + 1] - first;
+      a.inner_count[hit_i] = last - first;
     }
   }
 }

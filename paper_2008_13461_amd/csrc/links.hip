@@ -87,15 +87,6 @@ __device__ __forceinline__ bool beam_pass(double X0, double Y0, double X1, doubl
   return fabs(sqrt(c2) - sqrt(rho2)) <= rmax;
 }
 
-// Orders the LDS traffic of one wavefront (its lanes run in lockstep, so a
-// compiler barrier is all that is needed between a write and a read by
-// another lane).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Hit table: (X, Y, Z, R) in double, one 32-byte entry per hit, R = sqrt(X X + Y Y).
 template <class T>
 __global__ void k_hit_table(int n, const T* __restrict__ x, const T* __restrict__ y, const T* __restrict__ z,
@@ -583,36 +574,52 @@ struct EmitArgs {
   uint8_t* has_inner;
 };
 
-__global__ void k_link_emit(EmitArgs a) {
+// One thread per index entry: its loads (count, cell, spilled links) are all
+// issued before its stores, so no load waits for a store's acknowledgement.
+__device__ __forceinline__ void cmp_swap(int& x, int& y) {
+  const int lo = min(x, y), hi = max(x, y);
+  x = lo;
+  y = hi;
+}
+
+__global__ void __launch_bounds__(256) k_link_emit(EmitArgs a) {
   const int n = min(*a.cell_count, a.cells_cap);
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
-    const int pos = a.lcnt[r];
-    const int cnt = a.lcnt[r + 1] - pos;
-    if (cnt == 0) continue;
-    const int cell = a.ent[r].cell;
-    a.out_start[cell] = pos;
-    a.out_count[cell] = cnt;
-    if (cnt > kLocal) continue;  // written by k_links_overflow
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int pos = a.lcnt[r];
+  const int cnt = a.lcnt[r + 1] - pos;
+  if (cnt == 0) return;
+  const int cell = a.ent[r].cell;
+  static_assert(kLocal == 8, "one sorting network for eight links");
+  int f[kLocal];
+  if (cnt <= kLocal) {
     // the sweep records links in the order their beam-spot tests finished:
-    // sort them by out-cell
-    const int32_t* sp = a.spill + static_cast<int64_t>(r) * kLocal;
-    int f[kLocal];
-    for (int q = 0; q < cnt; ++q) {
-      const int v = sp[q];
-      int at = q;
-      while (at > 0 && f[at - 1] > v) {
-        f[at] = f[at - 1];
-        --at;
-      }
-      f[at] = v;
-    }
-    for (int q = 0; q < cnt; ++q) {
-      const int c = f[q];
-      a.has_inner[c] = 1;
-      if (pos + q < a.links_cap) {
-        a.in_cell[pos + q] = cell;
-        a.out_cell[pos + q] = c;
-      }
+    // sort them by out-cell (empty places sort last)
+    const int4* sp = reinterpret_cast<const int4*>(a.spill + r * kLocal);
+    const int4 q0 = sp[0];
+    const int4 q1 = cnt > 4 ? sp[1] : make_int4(0, 0, 0, 0);
+    const int v[kLocal] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+    for (int q = 0; q < kLocal; ++q) f[q] = q < cnt ? v[q] : INT_MAX;
+    // Batcher's odd-even merge sort of eight keys (19 compare-exchanges)
+    cmp_swap(f[0], f[1]); cmp_swap(f[2], f[3]); cmp_swap(f[4], f[5]); cmp_swap(f[6], f[7]);
+    cmp_swap(f[0], f[2]); cmp_swap(f[1], f[3]); cmp_swap(f[4], f[6]); cmp_swap(f[5], f[7]);
+    cmp_swap(f[1], f[2]); cmp_swap(f[5], f[6]);
+    cmp_swap(f[0], f[4]); cmp_swap(f[1], f[5]); cmp_swap(f[2], f[6]); cmp_swap(f[3], f[7]);
+    cmp_swap(f[2], f[4]); cmp_swap(f[3], f[5]);
+    cmp_swap(f[1], f[2]); cmp_swap(f[3], f[4]); cmp_swap(f[5], f[6]);
+  }
+  a.out_start[cell] = pos;
+  a.out_count[cell] = cnt;
+  if (cnt > kLocal) return;  // written by k_links_overflow
+#pragma unroll
+  for (int q = 0; q < kLocal; ++q) {
+    if (q >= cnt) break;
+    const int c = f[q];
+    a.has_inner[c] = 1;
+    if (pos + q < a.links_cap) {
+      a.in_cell[pos + q] = cell;
+      a.out_cell[pos + q] = c;
     }
   }
 }
@@ -755,7 +762,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   tok = timing_begin(s);
   EmitArgs e{cells.count, cells.cap, lcnt, spill, ent, L.cap, L.in_cell, L.out_cell, L.out_start, L.out_count,
              L.has_inner};
-  k_link_emit<<<grid_for(cells.cap, 256, 16384), 256, 0, s>>>(e);
+  k_link_emit<<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + 255) / 256), 256, 0, s>>>(e);
   timing_end(tok, "link_emit", s);
   PT_LAUNCH_CHECK();
   k_links_overflow<T><<<64, 64, 0, s>>>(k, a, cells.inner, h.layer, dr, dz, Ls, L.out_start, L.cap, L.in_cell,

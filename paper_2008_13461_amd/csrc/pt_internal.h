@@ -129,4 +129,13 @@ __device__ inline int lane_prefix(uint64_t mask) {
                                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u)));
 }
 
+// Orders the LDS traffic of one wavefront (its lanes run in lockstep, so a
+// compiler barrier is all that is needed between a write and a read by
+// another lane).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 }  // namespace pt
