@@ -624,18 +624,26 @@ __global__ void __launch_bounds__(256) k_link_emit(EmitArgs a) {
   }
 }
 
-// In-cells with more than kLocal links: one thread each recomputes its links
-// and writes them at the position the scan gave it.
+// In-cells with more than kLocal links: one wavefront each recomputes its
+// links, lanes over the out-cells of its middle hit (in order, so the
+// compacted links come out sorted), staged in LDS and written at the
+// position the scan gave the in-cell once the sweep's loads are done.
+constexpr int kOvfWaves = 4;
+constexpr int kOvfStage = 256;
+
 template <class T>
-__global__ void k_links_overflow(DevCfg k, HitArgs<T> a, const int32_t* __restrict__ inner,
-                                 const uint8_t* __restrict__ layer, const double* __restrict__ gdr,
-                                 const double* __restrict__ gdz, const double* __restrict__ gLs,
-                                 const int32_t* __restrict__ out_start, int32_t links_cap,
-                                 int32_t* __restrict__ in_cell, int32_t* __restrict__ out_cell,
-                                 uint8_t* __restrict__ has_inner) {
+__global__ void __launch_bounds__(kOvfWaves * kWave)
+    k_links_overflow(DevCfg k, HitArgs<T> a, const int32_t* __restrict__ inner, const uint8_t* __restrict__ layer,
+                     const double* __restrict__ gdr, const double* __restrict__ gdz,
+                     const double* __restrict__ gLs, const int32_t* __restrict__ out_start, int32_t links_cap,
+                     int32_t* __restrict__ in_cell, int32_t* __restrict__ out_cell,
+                     uint8_t* __restrict__ has_inner) {
+  __shared__ int32_t s_link[kOvfWaves][kOvfStage];
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  const int lane = __lane_id();
   const int m = *a.ovf_count;
   const int n_cells = min(*a.cell_count, a.cells_cap);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * kOvfWaves + wave; i < m; i += gridDim.x * kOvfWaves) {
     const int cp = a.ovf[i];
     const int h0 = inner[cp];
     const int h1 = a.outer[cp];
@@ -645,20 +653,40 @@ __global__ void k_links_overflow(DevCfg k, HitArgs<T> a, const int32_t* __restri
     const double rmax = layer[h0] == 0 ? k.rmax_bpix1 : k.rmax_other;
     const int first = a.inner_first[h1];
     const int last = min(first + a.inner_count[h1], n_cells);
-    int w = out_start[cp];
-    for (int c = first; c < last; ++c) {
-      const double Ls = gLs[c];
-      const double theta2 = __builtin_signbit(Ls) ? k.theta2_endcap : k.theta2_barrel;
-      if (!rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2)) continue;
-      const double4 P2 = a.hx[a.outer[c]];
-      if (!beam_pass(X0, Y0, X1, Y1, P2.x, P2.y, rmax)) continue;
-      has_inner[c] = 1;
-      if (w < links_cap) {
-        in_cell[w] = cp;
-        out_cell[w] = c;
+    int w = out_start[cp];  // uniform: position of the next link to write
+    int staged = 0;         // uniform
+    auto flush = [&]() {
+      wave_sync();
+      for (int q = lane; q < staged; q += kWave) {
+        const int c = s_link[wave][q];
+        has_inner[c] = 1;
+        if (w + q < links_cap) {
+          in_cell[w + q] = cp;
+          out_cell[w + q] = c;
+        }
       }
-      ++w;
+      wave_sync();
+      w += staged;
+      staged = 0;
+    };
+    for (int c0 = first; c0 < last; c0 += kWave) {
+      const int c = c0 + lane;
+      bool pass = false;
+      if (c < last) {
+        const double Ls = gLs[c];
+        const double theta2 = __builtin_signbit(Ls) ? k.theta2_endcap : k.theta2_barrel;
+        pass = rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2);
+        if (pass) {
+          const double4 P2 = a.hx[a.outer[c]];
+          pass = beam_pass(X0, Y0, X1, Y1, P2.x, P2.y, rmax);
+        }
+      }
+      const uint64_t mk = __ballot(pass);
+      if (staged + kWave > kOvfStage) flush();
+      if (pass) s_link[wave][staged + lane_prefix(mk)] = c;
+      staged += __popcll(mk);
     }
+    flush();
   }
 }
 
@@ -765,8 +793,8 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   k_link_emit<<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + 255) / 256), 256, 0, s>>>(e);
   timing_end(tok, "link_emit", s);
   PT_LAUNCH_CHECK();
-  k_links_overflow<T><<<64, 64, 0, s>>>(k, a, cells.inner, h.layer, dr, dz, Ls, L.out_start, L.cap, L.in_cell,
-                                        L.out_cell, L.has_inner);
+  k_links_overflow<T><<<1024, kOvfWaves * kWave, 0, s>>>(k, a, cells.inner, h.layer, dr, dz, Ls, L.out_start, L.cap,
+                                                         L.in_cell, L.out_cell, L.has_inner);
   PT_LAUNCH_CHECK();
   k_copy_links_total<<<1, 1, 0, s>>>(lcnt, cells.count, cells.cap, L.count);
   PT_LAUNCH_CHECK();

@@ -5,7 +5,7 @@ namespace pt {
 namespace {
 
 constexpr int kScanBlock = 256;
-constexpr int kScanItems = 8;
+constexpr int kScanItems = 16;
 constexpr int kTile = kScanBlock * kScanItems;
 
 // Inclusive scan of one int32 per thread across the block; returns the
@@ -43,23 +43,40 @@ __device__ inline int64_t items(int64_t n, const int32_t* n_dev) {
   return m < 0 ? 0 : (m < n ? m : n);
 }
 
+// Sum of each tile (the order does not matter: consecutive threads read
+// consecutive items).
 __global__ void __launch_bounds__(kScanBlock) k_tile_sums(const int32_t* __restrict__ data, int64_t n,
                                                           const int32_t* __restrict__ n_dev,
                                                           int32_t* __restrict__ sums) {
   __shared__ int32_t lds[kScanBlock / kWave + 1];
   n = items(n, n_dev);
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + threadIdx.x * kScanItems;
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * kTile;
+  if (first >= n) {  // a tile past the end
+    if (threadIdx.x == 0) sums[blockIdx.x] = 0;
+    return;
+  }
   int32_t s = 0;
-  if (static_cast<int64_t>(blockIdx.x) * kTile < n) {
+  if (first + kTile <= n) {
+    int32_t v[kScanItems];
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i)
-      if (base + i < n) s += data[base + i];
+    for (int i = 0; i < kScanItems; ++i) v[i] = data[first + i * kScanBlock + threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) s += v[i];
+  } else {
+    for (int i = 0; i < kScanItems; ++i) {
+      const int64_t at = first + i * kScanBlock + threadIdx.x;
+      if (at < n) s += data[at];
+    }
   }
   int32_t total;
   block_inclusive_scan(s, lds, &total);
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
+// Scan of each tile plus its offset; each thread takes kScanItems
+// consecutive items, read and written as 16-byte vectors when VEC (data
+// 16-byte aligned) and the tile is full.
+template <bool VEC>
 __global__ void __launch_bounds__(kScanBlock) k_tile_scan(int32_t* __restrict__ data, int64_t n,
                                                           const int32_t* __restrict__ n_dev,
                                                           const int32_t* __restrict__ offsets) {
@@ -70,20 +87,42 @@ __global__ void __launch_bounds__(kScanBlock) k_tile_scan(int32_t* __restrict__ 
   const int64_t last_block = n > 0 ? (n - 1) / kTile : 0;
   if (static_cast<int64_t>(blockIdx.x) > last_block) return;
   const int64_t base = first + threadIdx.x * kScanItems;
+  const bool full = VEC && first + kTile <= n;
   int32_t v[kScanItems];
+  if (full) {
+    const int4* p = reinterpret_cast<const int4*>(data + base);
+#pragma unroll
+    for (int i = 0; i < kScanItems / 4; ++i) {
+      const int4 q = p[i];
+      v[4 * i] = q.x;
+      v[4 * i + 1] = q.y;
+      v[4 * i + 2] = q.z;
+      v[4 * i + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) v[i] = (base + i < n) ? data[base + i] : 0;
+  }
   int32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < n) ? data[base + i] : 0;
-    s += v[i];
-  }
+  for (int i = 0; i < kScanItems; ++i) s += v[i];
   int32_t total;
   const int32_t incl = block_inclusive_scan(s, lds, &total);
   int32_t run = incl - s + (offsets ? offsets[blockIdx.x] : 0);
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < n) data[base + i] = run;
-    run += v[i];
+    const int32_t x = v[i];
+    v[i] = run;
+    run += x;
+  }
+  if (full) {
+    int4* p = reinterpret_cast<int4*>(data + base);
+#pragma unroll
+    for (int i = 0; i < kScanItems / 4; ++i) p[i] = make_int4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+      if (base + i < n) data[base + i] = v[i];
   }
   if (static_cast<int64_t>(blockIdx.x) == last_block && threadIdx.x == 0)
     data[n] = total + (offsets ? offsets[blockIdx.x] : 0);
@@ -114,14 +153,21 @@ hipError_t exclusive_scan_dev(int32_t* data, int64_t n, const int32_t* n_dev, in
     return hipGetLastError();
   }
   const int64_t nb = (n + kTile - 1) / kTile;
+  const bool vec = reinterpret_cast<uintptr_t>(data) % 16 == 0;
   if (nb == 1) {
-    k_tile_scan<<<1, kScanBlock, 0, s>>>(data, n, n_dev, nullptr);
+    if (vec)
+      k_tile_scan<true><<<1, kScanBlock, 0, s>>>(data, n, n_dev, nullptr);
+    else
+      k_tile_scan<false><<<1, kScanBlock, 0, s>>>(data, n, n_dev, nullptr);
     return hipGetLastError();
   }
   k_tile_sums<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, n_dev, tmp);
   hipError_t e = exclusive_scan_dev(tmp, nb, nullptr, tmp + nb + 1, s);
   if (e != hipSuccess) return e;
-  k_tile_scan<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, n_dev, tmp);
+  if (vec)
+    k_tile_scan<true><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, n_dev, tmp);
+  else
+    k_tile_scan<false><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, n_dev, tmp);
   return hipGetLastError();
 }
 
