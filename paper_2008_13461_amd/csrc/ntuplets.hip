@@ -83,34 +83,82 @@ __device__ inline int block_exclusive(int v, int32_t* s_scan, int* total) {
   return ex;
 }
 
+// Root flags of the kRootItems cells of this thread in a chunk (cell
+// base + i * kBlock + thread), with every load of the chunk issued up front.
+__device__ inline void root_flags(const DevCfg& k, const TupIn& a, int64_t base, int n, bool (&f)[kRootItems]) {
+  int oc[kRootItems], hi[kRootItems];
+  uint8_t free_[kRootItems];
+#pragma unroll
+  for (int i = 0; i < kRootItems; ++i) {
+    const int64_t c = base + i * kBlock + threadIdx.x;
+    const int cc = c < n ? static_cast<int>(c) : 0;
+    oc[i] = c < n ? a.out_count[cc] : 0;
+    hi[i] = a.cell_inner[cc];
+    free_[i] = !a.has_inner[cc];
+  }
+#pragma unroll
+  for (int i = 0; i < kRootItems; ++i) {
+    // a root without outer links makes a 2-hit path
+    const int L = a.layer[hi[i]];
+    f[i] = oc[i] > 0 && (((k.root_always_mask >> L) & 1u) || (((k.root_if_free_mask >> L) & 1u) && free_[i]));
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_root_count(DevCfg k, TupIn a, int32_t* __restrict__ chunk_roots) {
   __shared__ int32_t s_scan[kBlock / kWave + 1];
   const int n = min(*a.cell_count, a.cells_cap);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
-  int cnt = 0;
-  for (int i = 0; i < kRootItems; ++i) {
-    const int64_t c = base + i * kBlock + threadIdx.x;
-    if (c < n && is_root(k, a, static_cast<int>(c))) ++cnt;
+  if (base >= n) {
+    if (threadIdx.x == 0) chunk_roots[blockIdx.x] = 0;
+    return;
   }
+  bool f[kRootItems];
+  root_flags(k, a, base, n, f);
+  int cnt = 0;
+#pragma unroll
+  for (int i = 0; i < kRootItems; ++i) cnt += f[i] ? 1 : 0;
   int total;
   block_exclusive(cnt, s_scan, &total);
   if (threadIdx.x == 0) chunk_roots[blockIdx.x] = total;
 }
 
+// Writes the chunk's roots in cell order: the position of a root is the
+// chunk's offset, plus the roots of the (item, wavefront) groups before its
+// own (cell order is item, then wavefront, then lane), plus its rank in the
+// wavefront's ballot.
 __global__ void __launch_bounds__(kBlock) k_root_write(DevCfg k, TupIn a, const int32_t* __restrict__ chunk_first) {
-  __shared__ int32_t s_scan[kBlock / kWave + 1];
+  constexpr int kWaves = kBlock / kWave;
+  static_assert(kRootItems * kWaves == kWave, "one lane per (item, wavefront) group");
+  __shared__ int32_t s_grp[kRootItems * kWaves];
   const int n = min(*a.cell_count, a.cells_cap);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
   if (base >= n) return;
-  int at = chunk_first[blockIdx.x];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int at = chunk_first[blockIdx.x];
+  bool f[kRootItems];
+  root_flags(k, a, base, n, f);
+  int rank[kRootItems];
+#pragma unroll
   for (int i = 0; i < kRootItems; ++i) {
-    const int64_t c = base + i * kBlock + threadIdx.x;
-    const bool root = c < n && is_root(k, a, static_cast<int>(c));
-    int total;
-    const int pos = at + block_exclusive(root ? 1 : 0, s_scan, &total);
-    if (root) a.roots[pos] = static_cast<int>(c);
-    at += total;
+    const uint64_t m = __ballot(f[i]);
+    rank[i] = lane_prefix(m);
+    if (lane == 0) s_grp[i * kWaves + wave] = __popcll(m);
   }
+  __syncthreads();
+  if (wave == 0) {
+    const int v = s_grp[lane];
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    s_grp[lane] = incl - v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kRootItems; ++i)
+    if (f[i]) a.roots[at + s_grp[i * kWaves + wave] + rank[i]] = static_cast<int>(base + i * kBlock + threadIdx.x);
 }
 
 // Depth-first search from each root.  COUNT: paths[i] = rows root i emits
