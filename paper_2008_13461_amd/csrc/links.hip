@@ -22,7 +22,8 @@
 //     and no per-pair gather.  Pairs that pass are queued in LDS and the
 //     beam-spot test (divisions, square roots) runs on full waves of queued
 //     pairs.  Each in-cell's link count is recorded, with its links when
-//     there are at most kLocal of them.
+//     there are at most kLocal of them, and the hit's out-cells that gained
+//     an inner link are flagged (has_inner) in one coalesced run.
 //  5. a scan of the counts places every in-cell's links (no shared counter:
 //     same-address atomics serialise), k_link_emit writes them, and
 //     k_links_overflow recomputes the few in-cells with more than kLocal.
@@ -40,6 +41,7 @@ constexpr int kLocal = 8;        // links an in-cell keeps in LDS before the ove
 constexpr int kUnroll = 4;       // out-cells tested per step of the sweep
 constexpr int kSegment = 1 << 24;  // out-cells per queue segment (offsets fit beside the lane)
 constexpr int kSegWin = 64;        // in-cell segments of a hit handled per window (one per lane)
+constexpr int kHinBits = 2048;     // out-cells of a hit whose has_inner flag is gathered in LDS
 
 // Index entry of an in-cell c' = (h0, h1): its cell index, and its inner hit
 // with the BPix1 flag in the top bit.  The triplet tests rebuild the R-Z
@@ -307,6 +309,7 @@ struct WaveLds {
   int32_t sfirst[kSegWin];       // a window of the hit's segments: first entry ...
   int32_t spre[kSegWin + 1];     // ... and the in-cells before each (exclusive prefix)
   int32_t segat[kWave];          // segment starting at each in-cell of a pass, or -1
+  uint32_t hin[kHinBits / 32];   // out-cells of the hit with an inner link (first kHinBits)
 };
 
 template <class T>
@@ -325,13 +328,15 @@ struct HitArgs {
   int32_t* spill;     // [cells_cap][kLocal] their out-cells, ascending (when at most kLocal)
   int32_t* ovf;       // in-cells with more than kLocal links
   int32_t* ovf_count;
+  uint8_t* has_inner;  // set for every out-cell with a link (zero on entry)
 };
 
 // Beam-spot test of the first nq queued pairs, one per lane; cb is the first
 // out-cell of the segment the queued offsets refer to.
 template <class T>
+// hb is the offset of cb in the hit's out-cells (for the has_inner bits).
 __device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a, WaveLds& L, int nq, int cb,
-                                           double X1, double Y1) {
+                                           int hb, double X1, double Y1) {
   const int lane = __lane_id();
   if (lane < nq) {
     const int e = L.queue[lane];
@@ -342,6 +347,11 @@ __device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a,
     if (beam_pass(L.X0[li], L.Y0[li], X1, Y1, P2.x, P2.y, rmax)) {
       const int slot = atomicAdd(&L.cnt[li], 1);
       if (slot < kLocal) L.found[li * kLocal + slot] = cb + j;
+      const int bit = hb + j;
+      if (bit < kHinBits)
+        atomicOr(&L.hin[bit >> 5], 1u << (bit & 31));
+      else
+        a.has_inner[cb + j] = 1;
     }
   }
 }
@@ -367,6 +377,8 @@ __global__ void __launch_bounds__(WAVES * kWave)
   const double4 P1 = a.hx[h1];
   const double X1 = P1.x, Y1 = P1.y;
   const double th2b = k.theta2_barrel, th2e = k.theta2_endcap;
+  const int nh = min(nb, kHinBits);  // out-cells whose has_inner bit is kept in LDS
+  for (int w = lane; w < (nh + 31) / 32; w += kWave) L.hin[w] = 0;
 
   for (int sw = sb; sw < se; sw += kSegWin) {
     // a window of the hit's segments and the prefix of their sizes
@@ -448,7 +460,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
           qn += __popcll(mk);
           if (qn >= kWave) {
             wave_sync();
-            beam_batch(k, a, L, kWave, cs, X1, Y1);
+            beam_batch(k, a, L, kWave, cs, jb, X1, Y1);
             qn -= kWave;
             const int t = (lane < qn) ? L.queue[kWave + lane] : 0;
             wave_sync();
@@ -476,7 +488,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
           }
           if (qn > 0) {
             wave_sync();
-            beam_batch(k, a, L, qn, cs, X1, Y1);
+            beam_batch(k, a, L, qn, cs, jb, X1, Y1);
           }
           wave_sync();
           continue;
@@ -535,7 +547,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
         }
         if (qn > 0) {
           wave_sync();
-          beam_batch(k, a, L, qn, cs, X1, Y1);
+          beam_batch(k, a, L, qn, cs, jb, X1, Y1);
         }
         wave_sync();
       }
@@ -557,6 +569,8 @@ __global__ void __launch_bounds__(WAVES * kWave)
       wave_sync();
     }
   }
+  // the hit's out-cells with an inner link, one coalesced run of flags
+  for (int j = lane; j < nh; j += kWave) a.has_inner[cb + j] = (L.hin[j >> 5] >> (j & 31)) & 1u;
 }
 
 // Places the links of every in-cell at its scanned position.
@@ -571,7 +585,6 @@ struct EmitArgs {
   int32_t* out_cell;
   int32_t* out_start;
   int32_t* out_count;
-  uint8_t* has_inner;
 };
 
 // One thread per index entry: its loads (count, cell, spilled links) are all
@@ -616,7 +629,6 @@ __global__ void __launch_bounds__(256) k_link_emit(EmitArgs a) {
   for (int q = 0; q < kLocal; ++q) {
     if (q >= cnt) break;
     const int c = f[q];
-    a.has_inner[c] = 1;
     if (pos + q < a.links_cap) {
       a.in_cell[pos + q] = cell;
       a.out_cell[pos + q] = c;
@@ -636,8 +648,7 @@ __global__ void __launch_bounds__(kOvfWaves * kWave)
     k_links_overflow(DevCfg k, HitArgs<T> a, const int32_t* __restrict__ inner, const uint8_t* __restrict__ layer,
                      const double* __restrict__ gdr, const double* __restrict__ gdz,
                      const double* __restrict__ gLs, const int32_t* __restrict__ out_start, int32_t links_cap,
-                     int32_t* __restrict__ in_cell, int32_t* __restrict__ out_cell,
-                     uint8_t* __restrict__ has_inner) {
+                     int32_t* __restrict__ in_cell, int32_t* __restrict__ out_cell) {
   __shared__ int32_t s_link[kOvfWaves][kOvfStage];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = __lane_id();
@@ -659,7 +670,6 @@ __global__ void __launch_bounds__(kOvfWaves * kWave)
       wave_sync();
       for (int q = lane; q < staged; q += kWave) {
         const int c = s_link[wave][q];
-        has_inner[c] = 1;
         if (w + q < links_cap) {
           in_cell[w + q] = cp;
           out_cell[w + q] = c;
@@ -774,7 +784,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   PT_LAUNCH_CHECK();
 
   HitArgs<T> a{n, hx, cells.count, cells.cap, cells.outer, cells.inner_first, cells.inner_count, seg_first, seg,
-               ent, lcnt, spill, ovf, ovf_count};
+               ent, lcnt, spill, ovf, ovf_count, L.has_inner};
   tok = timing_begin(s);
   if (n > 0) {
     if (block == 128)
@@ -788,13 +798,12 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   timing_end(tok, "links", s);
   if (exclusive_scan_dev(lcnt, cells.cap, cells.count, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  EmitArgs e{cells.count, cells.cap, lcnt, spill, ent, L.cap, L.in_cell, L.out_cell, L.out_start, L.out_count,
-             L.has_inner};
+  EmitArgs e{cells.count, cells.cap, lcnt, spill, ent, L.cap, L.in_cell, L.out_cell, L.out_start, L.out_count};
   k_link_emit<<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + 255) / 256), 256, 0, s>>>(e);
   timing_end(tok, "link_emit", s);
   PT_LAUNCH_CHECK();
   k_links_overflow<T><<<1024, kOvfWaves * kWave, 0, s>>>(k, a, cells.inner, h.layer, dr, dz, Ls, L.out_start, L.cap,
-                                                         L.in_cell, L.out_cell, L.has_inner);
+                                                         L.in_cell, L.out_cell);
   PT_LAUNCH_CHECK();
   k_copy_links_total<<<1, 1, 0, s>>>(lcnt, cells.count, cells.cap, L.count);
   PT_LAUNCH_CHECK();
