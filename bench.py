@@ -31,27 +31,28 @@ METRIC = "events/s at PU200, batched vs per-event; fit fwd+bwd tracks/s vs HBM r
 # fp64 VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (T ops/s)
 FP64_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # timing regions (one kernel each, see pixeltrack.h) in step order
-TIMED = ("doublets_count", "doublets_write", "cell_geom", "link_segments", "links", "link_emit", "root_count",
+TIMED = ("doublets_count", "doublets_write", "cell_index", "link_segments", "links", "link_emit", "root_count",
          "root_write", "dfs_count", "dfs_write", "dedup", "fit_fwd", "fit_bwd")
 # source file of each timed kernel (for the traffic record)
-KERNEL_SOURCE = {"doublets_count": "doublets.hip", "doublets_write": "doublets.hip", "cell_geom": "links.hip",
+KERNEL_SOURCE = {"doublets_count": "doublets.hip", "doublets_write": "doublets.hip", "cell_index": "links.hip",
                  "link_segments": "links.hip", "links": "links.hip", "link_emit": "links.hip",
                  "root_count": "ntuplets.hip", "root_write": "ntuplets.hip", "dfs_count": "ntuplets.hip",
                  "dfs_write": "ntuplets.hip", "fit_fwd": "fit.hip", "fit_bwd": "fit.hip"}
 KERNEL_SYMBOL = {"doublets_count": "k_doublets<false>", "doublets_write": "k_doublets<true>",
-                 "cell_geom": "k_cell_geom", "link_segments": "k_seg_scatter", "links": "k_link_hits",
+                 "cell_index": "k_cell_index", "link_segments": "k_seg_scatter", "links": "k_link_hits",
                  "link_emit": "k_link_emit", "root_count": "k_root_count", "root_write": "k_root_write",
                  "dfs_count": "k_dfs<true>", "dfs_write": "k_dfs<false>", "fit_fwd": "k_fit<4,6>",
                  "fit_bwd": "k_grad<4,6>"}
 # Algorithmic work per unit, for the roofline of whichever kernel dominates:
 #  links: the R-Z test of every candidate pair, 7 fp64 VALU operations
 #    (A = ar bz - az br: 2 mul + 1 sub; A A; La Lb; theta2 (La Lb); compare)
-#  cell_geom: per cell read inner, outer (8 B), write dr, dz, Ls (24 B), the
-#    8-byte index entry, and clear out_count, has_inner and the link count (9 B)
-#  doublets_write: per cell write inner, outer, pair (9 B)
+#  cell_index: per cell read inner, outer (8 B), write the 8-byte index
+#    entry, and clear out_count, has_inner and the link count (9 B)
+#  doublets_write: per cell write inner, outer, pair and the R-Z segment
+#    dr, dz, ls (9 + 24 B)
 LINK_OPS_PER_CANDIDATE = 7.0
-CELL_GEOM_BYTES_PER_CELL = 49.0
-DOUBLET_BYTES_PER_CELL = 9.0
+CELL_INDEX_BYTES_PER_CELL = 25.0
+DOUBLET_BYTES_PER_CELL = 33.0
 HBM_PEAK_GBS = 8000.0
 
 
@@ -349,7 +350,7 @@ def roofline(kern, cnt):
                     note="7 fp64 VALU ops per candidate pair x candidates / kernel time; peak = 256 CU x 4 SIMD x "
                          "16 lanes x 2.4 GHz, one fp64 op per lane per clock (no FMA: contraction is off)")
     else:
-        per_cell = {"cell_geom": CELL_GEOM_BYTES_PER_CELL, "doublets_write": DOUBLET_BYTES_PER_CELL}.get(name)
+        per_cell = {"cell_index": CELL_INDEX_BYTES_PER_CELL, "doublets_write": DOUBLET_BYTES_PER_CELL}.get(name)
         achieved = per_cell * cnt["doublets"] / sec / 1e9 if per_cell else None
         roof.update(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS if achieved else None)

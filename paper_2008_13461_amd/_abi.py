@@ -31,6 +31,7 @@ PT_FLAG_BAD_HITS = 1 << 3
 PT_FLAG_TRUNCATED = 1 << 4
 PT_FLAG_FIT_BAD_ORDER = 1 << 5
 PT_FLAG_FIT_FAILED = 1 << 6
+PT_SEG_BLOCK = 32
 PT_FIT_OK, PT_FIT_ST_BAD_ORDER, PT_FIT_ST_F64_SOLVE, PT_FIT_ST_FAILED = 0, 1, 2, 4
 
 P = ct.c_void_p
@@ -99,6 +100,7 @@ class pt_cells(ct.Structure):
         ("count", P),
         ("inner_first", P),
         ("inner_count", P),
+        ("seg", P),
     ]
 
 

@@ -136,7 +136,8 @@ pt_err pt_build_doublets(const pt_hits* hits, const pt_config* cfg, pt_cells* ce
   if (!hits_ok(hits) || !cfg || !cells || !derive_config(*cfg, &d)) return PT_ERR_ARG;
   if (cells->cap < 0 || !cells->count || (hits->n_hits > 0 && (!cells->inner_first || !cells->inner_count)))
     return PT_ERR_ARG;
-  if (cells->cap > 0 && (!cells->inner || !cells->outer || !cells->pair)) return PT_ERR_ARG;
+  if (cells->cap > 0 && (!cells->inner || !cells->outer || !cells->pair || !cells->seg))
+    return PT_ERR_ARG;
   if (!ws_ok(ws, ws_doublets(hits->n_hits, hits->n_events, d.n_bins))) return PT_ERR_WORKSPACE;
   return launch_doublets(*hits, d, *cells, status, ws, reinterpret_cast<hipStream_t>(stream));
 }
@@ -146,8 +147,8 @@ pt_err pt_link_cells(const pt_hits* hits, const pt_config* cfg, const pt_cells* 
   DevCfg d;
   if (!hits_ok(hits) || !cfg || !cells || !links || !derive_config(*cfg, &d)) return PT_ERR_ARG;
   if (cells->cap < 0 || links->cap < 0 || !cells->count || !links->count) return PT_ERR_ARG;
-  if (cells->cap > 0 && (!cells->inner || !cells->outer || !links->out_start || !links->out_count ||
-                         !links->has_inner))
+  if (cells->cap > 0 && (!cells->inner || !cells->outer || !cells->seg ||
+                         !links->out_start || !links->out_count || !links->has_inner))
     return PT_ERR_ARG;
   if (hits->n_hits > 0 && (!cells->inner_first || !cells->inner_count)) return PT_ERR_ARG;
   if (links->cap > 0 && (!links->in_cell || !links->out_cell)) return PT_ERR_ARG;

@@ -134,6 +134,7 @@ struct DoubletArgs {
   uint8_t* pair;
   int32_t* inner_first;
   int32_t* inner_count;
+  double* seg;             // R-Z segments of the cells, blocked (write pass)
 };
 
 // The azimuth-bin ranges of the outer layer of pair p scanned for an inner
@@ -202,15 +203,39 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   int pos = first;  // uniform: next cell position (write pass) or count
   const int hit_i = WRITE ? a.sorted_hit[j] : 0;
   int staged = 0;                   // uniform: staged cells, to be written from pos on
-  // stores the staged cells, consecutive positions on consecutive lanes
+  // stores the staged cells (sorted outer hit, pair) with their R-Z
+  // segment, consecutive positions on consecutive lanes, two per lane and
+  // round with the loads of both first
   auto flush = [&]() {
     wave_sync();
-    for (int i = lane; i < staged; i += kWave) {
-      const int w = pos + i;
-      if (w < a.cap) {
-        a.inner[w] = hit_i;
-        a.outer[w] = s_out[wave][i];
-        a.pair[w] = s_pair[wave][i];
+    for (int i0 = 0; i0 < staged; i0 += 2 * kWave) {
+      int o[2], p[2], h[2];
+      double Ro[2], Zo[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int i = min(i0 + u * kWave + lane, staged - 1);
+        o[u] = s_out[wave][i];
+        p[u] = s_pair[wave][i];
+        h[u] = a.sorted_hit[o[u]];
+        Ro[u] = a.sR[o[u]];
+        Zo[u] = a.sZ[o[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int i = i0 + u * kWave + lane;
+        const int w = pos + i;
+        if (i < staged && w < a.cap) {
+          const double dr = Ro[u] - Ri;
+          const double dz = Zo[u] - Zi;
+          const double L = dr * dr + dz * dz;
+          a.inner[w] = hit_i;
+          a.outer[w] = h[u];
+          a.pair[w] = static_cast<uint8_t>(p[u]);
+          double* g = a.seg + seg_at(w);
+          g[0] = dr;
+          g[PT_SEG_BLOCK] = dz;
+          g[2 * PT_SEG_BLOCK] = k.layer_barrel[k.pair_outer[p[u]]] ? L : -L;
+        }
       }
     }
     wave_sync();
@@ -235,7 +260,7 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
           if (staged + kWave > kStage) flush();
           if (pass) {
             const int at = staged + lane_prefix(m);
-            s_out[wave][at] = a.sorted_hit[o];
+            s_out[wave][at] = o;
             s_pair[wave][at] = static_cast<uint8_t>(p);
           }
           staged += __popcll(m);
@@ -339,7 +364,7 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   PT_LAUNCH_CHECK();
 
   DoubletArgs a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, cells.cap, cells.inner,
-                cells.outer, cells.pair, cells.inner_first, cells.inner_count};
+                cells.outer, cells.pair, cells.inner_first, cells.inner_count, cells.seg};
   // bin_start[-1] holds the number of valid hits (sorted positions).
   const int block = (k.block_doublets == 64 || k.block_doublets == 128 || k.block_doublets == 512)
                         ? k.block_doublets : 256;

@@ -7,14 +7,14 @@
 // step is organised around that test:
 //
 //  1. k_hit_table: (X, Y, Z, R) of every hit in double, one 32-byte entry.
-//  2. k_cell_geom: every cell's R-Z segment (dr, dz) and its squared length,
-//     once, in cell order; the length carries the sign of the barrel/end-cap
-//     class of the cell's outer hit (the class of h2 selects theta).  Each
-//     chunk of cells is grouped by outer hit in an LDS hash table and written
-//     to the index grouped that way.
+//     Each cell's R-Z segment (dr, dz) and its squared length, signed by the
+//     barrel/end-cap class of its outer hit (the class of h2 selects theta),
+//     come with the cells from the doublet step.
+//  2. k_cell_index: each chunk of cells is grouped by outer hit in an LDS
+//     hash table and written to the index grouped that way.
 //  3. exclusive scan of the per-hit segment counts, then k_seg_scatter:
 //     each hit's in-cells as a list of segments of the index (8 bytes per
-//     cell: cell, inner hit), one segment per chunk of k_cell_geom.
+//     cell: cell, inner hit), one segment per chunk of k_cell_index.
 //  4. k_link_hits: one wavefront per middle hit.  Lanes hold the in-cells;
 //     the out-cells (a contiguous run, grouped by inner hit by the doublet
 //     step) are swept in a uniform loop whose loads are wave-uniform, so the
@@ -45,7 +45,7 @@ constexpr int kHinBits = 2048;     // out-cells of a hit whose has_inner flag is
 
 // Index entry of an in-cell c' = (h0, h1): its cell index, and its inner hit
 // with the BPix1 flag in the top bit.  The triplet tests rebuild the R-Z
-// segment from the hit table with the same operations as k_cell_geom.
+// segment from the hit table with the same operations as the doublet step.
 struct InCell {
   int32_t cell;
   int32_t h0b;
@@ -100,17 +100,12 @@ __global__ void k_hit_table(int n, const T* __restrict__ x, const T* __restrict_
   }
 }
 
-template <class T>
-struct GeomArgs {
+struct IndexArgs {
   const int32_t* cell_count;
   int32_t cells_cap;
   const int32_t* inner;
   const int32_t* outer;
   const uint8_t* layer;
-  const double4* hx;
-  double* dr;
-  double* dz;
-  double* Ls;          // +L (outer hit on a barrel layer) or -L
   InCell* ent;         // the block's cells grouped by outer hit, in the block's own range
   int4* grp;           // per block: its groups (outer hit, first entry, cells, slot in the hit's list)
   int32_t* n_grp;      // per block: number of groups
@@ -120,13 +115,13 @@ struct GeomArgs {
   uint8_t* has_inner;
 };
 
-constexpr int kGeomBlock = 1024;
-constexpr int kGeomItems = 4;
-constexpr int kGeomChunk = kGeomBlock * kGeomItems;  // cells per block; also the hash table size
-static_assert((kGeomChunk & (kGeomChunk - 1)) == 0, "hash table size must be a power of two");
+constexpr int kIndexBlock = 1024;
+constexpr int kIndexItems = 4;
+constexpr int kIndexChunk = kIndexBlock * kIndexItems;  // cells per block; also the hash table size
+static_assert((kIndexChunk & (kIndexChunk - 1)) == 0, "hash table size must be a power of two");
 
-// Cell geometry and the index of cells by outer hit.  Each block takes a
-// chunk of kGeomChunk consecutive cells (neighbouring inner hits, which share
+// The index of cells by outer hit.  Each block takes a
+// chunk of kIndexChunk consecutive cells (neighbouring inner hits, which share
 // most outer hits), groups them by outer hit in an LDS hash table, and writes
 // them as index entries grouped by outer hit into the chunk's own range of
 // `ent` (staged in LDS, then written contiguously).  Each group becomes one
@@ -138,57 +133,47 @@ static_assert((kGeomChunk & (kGeomChunk - 1)) == 0, "hash table size must be a p
 // Every global load and atomic of the block is issued before its first
 // global store: on this architecture one counter tracks loads and stores
 // alike, so a load issued after a store would wait for the store's write
-// acknowledgement as well.  The geometry is held in registers until the end.
-template <class T>
-__global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> a) {
-  __shared__ int32_t s_key[kGeomChunk];      // outer hit of the slot, -1 when free
-  __shared__ int32_t s_pos[kGeomChunk + 1];  // cells in the slot; after the scan its first entry
+// acknowledgement as well.
+__global__ void __launch_bounds__(kIndexBlock) k_cell_index(IndexArgs a) {
+  __shared__ int32_t s_key[kIndexChunk];      // outer hit of the slot, -1 when free
+  __shared__ int32_t s_pos[kIndexChunk + 1];  // cells in the slot; after the scan its first entry
                                              // << 16 | its group index
-  __shared__ int32_t s_cell[kGeomChunk];     // per cell: slot | rank in the slot << 12
-  __shared__ int32_t s_h0b[kGeomChunk];      // per cell: inner hit | BPix1 bit
-  __shared__ int32_t s_scan[kGeomBlock / kWave + 1];
-  static_assert(kGeomChunk <= 4096, "slot and rank are packed in 12 bits each");
+  __shared__ int32_t s_cell[kIndexChunk];     // per cell: slot | rank in the slot << 12
+  __shared__ int32_t s_h0b[kIndexChunk];      // per cell: inner hit | BPix1 bit
+  __shared__ int32_t s_scan[kIndexBlock / kWave + 1];
+  static_assert(kIndexChunk <= 4096, "slot and rank are packed in 12 bits each");
   const int n = min(*a.cell_count, a.cells_cap);
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kGeomChunk;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kIndexChunk;
   if (base >= n) return;
-  const int m = static_cast<int>(min<int64_t>(kGeomChunk, n - base));
-  for (int i = threadIdx.x; i < kGeomChunk; i += kGeomBlock) {
+  const int m = static_cast<int>(min<int64_t>(kIndexChunk, n - base));
+  for (int i = threadIdx.x; i < kIndexChunk; i += kIndexBlock) {
     s_key[i] = -1;
     s_pos[i] = 0;
   }
-  // loads of the block's cells, item u = cell base + u * kGeomBlock + thread
-  int h0[kGeomItems], h1[kGeomItems];
+  // loads of the block's cells, item u = cell base + u * kIndexBlock + thread
+  int h0[kIndexItems], h1[kIndexItems];
 #pragma unroll
-  for (int u = 0; u < kGeomItems; ++u) {
-    const int loc = u * kGeomBlock + threadIdx.x;
+  for (int u = 0; u < kIndexItems; ++u) {
+    const int loc = u * kIndexBlock + threadIdx.x;
     const int c = static_cast<int>(base) + (loc < m ? loc : 0);
     h0[u] = a.inner[c];
     h1[u] = a.outer[c];
   }
-  double dr[kGeomItems], dz[kGeomItems], Ls[kGeomItems];
-  int32_t h0b[kGeomItems];
+  int32_t h0b[kIndexItems];
 #pragma unroll
-  for (int u = 0; u < kGeomItems; ++u) {
-    const double4 P0 = a.hx[h0[u]];
-    const double4 P1 = a.hx[h1[u]];
-    dr[u] = P1.w - P0.w;
-    dz[u] = P1.z - P0.z;
-    const double L = dr[u] * dr[u] + dz[u] * dz[u];
-    Ls[u] = k.layer_barrel[a.layer[h1[u]]] ? L : -L;
-    h0b[u] = h0[u] | (a.layer[h0[u]] == 0 ? kBpix1Bit : 0);
-  }
+  for (int u = 0; u < kIndexItems; ++u) h0b[u] = h0[u] | (a.layer[h0[u]] == 0 ? kBpix1Bit : 0);
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < kGeomItems; ++u) {
-    const int loc = u * kGeomBlock + threadIdx.x;
+  for (int u = 0; u < kIndexItems; ++u) {
+    const int loc = u * kIndexBlock + threadIdx.x;
     if (loc >= m) break;
     // linear probing; the table has a slot for every cell of the block
     const int key = h1[u];
-    int slot = static_cast<int>((static_cast<uint32_t>(key) * 2654435761u) >> 20) & (kGeomChunk - 1);
+    int slot = static_cast<int>((static_cast<uint32_t>(key) * 2654435761u) >> 20) & (kIndexChunk - 1);
     while (true) {
       const int prev = atomicCAS(&s_key[slot], -1, key);
       if (prev == -1 || prev == key) break;
-      slot = (slot + 1) & (kGeomChunk - 1);
+      slot = (slot + 1) & (kIndexChunk - 1);
     }
     const int r = atomicAdd(&s_pos[slot], 1);
     s_cell[loc] = slot | (r << 12);
@@ -196,14 +181,14 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
   }
   __syncthreads();
   // one scan gives every slot its first entry (high half) and its group
-  // index (low half): kGeomItems consecutive slots per thread
+  // index (low half): kIndexItems consecutive slots per thread
   int ngroups;
   {
-    const int t0 = threadIdx.x * kGeomItems;
-    int v[kGeomItems];
+    const int t0 = threadIdx.x * kIndexItems;
+    int v[kIndexItems];
     int sum = 0;
 #pragma unroll
-    for (int i = 0; i < kGeomItems; ++i) {
+    for (int i = 0; i < kIndexItems; ++i) {
       v[i] = (s_pos[t0 + i] << 16) | (s_key[t0 + i] >= 0 ? 1 : 0);
       sum += v[i];
     }
@@ -218,51 +203,51 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
     __syncthreads();
     if (threadIdx.x == 0) {
       int run = 0;
-      for (int w = 0; w < kGeomBlock / kWave; ++w) {
+      for (int w = 0; w < kIndexBlock / kWave; ++w) {
         const int x = s_scan[w];
         s_scan[w] = run;
         run += x;
       }
-      s_scan[kGeomBlock / kWave] = run;
-      s_pos[kGeomChunk] = run;
+      s_scan[kIndexBlock / kWave] = run;
+      s_pos[kIndexChunk] = run;
     }
     __syncthreads();
     int run = s_scan[wave] + incl - sum;
 #pragma unroll
-    for (int i = 0; i < kGeomItems; ++i) {
+    for (int i = 0; i < kIndexItems; ++i) {
       s_pos[t0 + i] = run;  // each thread rewrites only the slots it read
       run += v[i];
     }
-    ngroups = s_scan[kGeomBlock / kWave] & 0xFFFF;
+    ngroups = s_scan[kIndexBlock / kWave] & 0xFFFF;
   }
   __syncthreads();
   // the segment slots of the block's groups (stored with the rest at the end)
-  int key[kGeomItems], slot_in_list[kGeomItems], pv[kGeomItems], cells[kGeomItems];
+  int key[kIndexItems], slot_in_list[kIndexItems], pv[kIndexItems], cells[kIndexItems];
 #pragma unroll
-  for (int u = 0; u < kGeomItems; ++u) {
-    const int i = u * kGeomBlock + threadIdx.x;
+  for (int u = 0; u < kIndexItems; ++u) {
+    const int i = u * kIndexBlock + threadIdx.x;
     key[u] = s_key[i];
     slot_in_list[u] = key[u] >= 0 ? atomicAdd(a.n_seg + key[u], 1) : 0;
     pv[u] = s_pos[i];
     cells[u] = (s_pos[i + 1] >> 16) - (pv[u] >> 16);  // empty slots add nothing
   }
   __syncthreads();  // the hash keys are dead: their array stages the entry order
-  for (int loc = threadIdx.x; loc < m; loc += kGeomBlock) {
+  for (int loc = threadIdx.x; loc < m; loc += kIndexBlock) {
     const int v = s_cell[loc];
-    s_key[(s_pos[v & (kGeomChunk - 1)] >> 16) + (v >> 12)] = loc;
+    s_key[(s_pos[v & (kIndexChunk - 1)] >> 16) + (v >> 12)] = loc;
   }
   __syncthreads();
   // every atomic result is taken here, so that no store below waits for another
-  static_assert(kGeomItems == 4, "one operand per item");
+  static_assert(kIndexItems == 4, "one operand per item");
   asm volatile("" ::"v"(slot_in_list[0]), "v"(slot_in_list[1]), "v"(slot_in_list[2]), "v"(slot_in_list[3]));
 #pragma unroll
-  for (int u = 0; u < kGeomItems; ++u) {
+  for (int u = 0; u < kIndexItems; ++u) {
     if (key[u] >= 0)
       a.grp[base + (pv[u] & 0xFFFF)] =
           make_int4(key[u], static_cast<int>(base) + (pv[u] >> 16), cells[u], slot_in_list[u]);
   }
   if (threadIdx.x == 0) a.n_grp[blockIdx.x] = ngroups;
-  for (int i = threadIdx.x; i < m; i += kGeomBlock) {  // the chunk's entries, contiguous
+  for (int i = threadIdx.x; i < m; i += kIndexBlock) {  // the chunk's entries, contiguous
     const int loc = s_key[i];
     InCell e;
     e.cell = static_cast<int>(base) + loc;
@@ -270,13 +255,10 @@ __global__ void __launch_bounds__(kGeomBlock) k_cell_geom(DevCfg k, GeomArgs<T> 
     a.ent[base + i] = e;
   }
 #pragma unroll
-  for (int u = 0; u < kGeomItems; ++u) {
-    const int loc = u * kGeomBlock + threadIdx.x;
+  for (int u = 0; u < kIndexItems; ++u) {
+    const int loc = u * kIndexBlock + threadIdx.x;
     if (loc >= m) break;
     const int c = static_cast<int>(base) + loc;
-    a.dr[c] = dr[u];
-    a.dz[c] = dz[u];
-    a.Ls[c] = Ls[u];
     a.out_count[c] = 0;
     a.has_inner[c] = 0;
     a.lcnt[c] = 0;
@@ -289,7 +271,7 @@ __global__ void k_seg_scatter(const int32_t* __restrict__ cell_count, int32_t ce
                               const int4* __restrict__ grp, const int32_t* __restrict__ n_grp,
                               const int32_t* __restrict__ seg_first, int2* __restrict__ seg) {
   const int n = min(*cell_count, cells_cap);
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kGeomChunk;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kIndexChunk;
   if (base >= n) return;
   const int g_n = n_grp[blockIdx.x];
   for (int g = threadIdx.x; g < g_n; g += blockDim.x) {
@@ -359,8 +341,7 @@ __device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a,
 // One wavefront per middle hit; WAVES independent wavefronts per block.
 template <class T, int WAVES>
 __global__ void __launch_bounds__(WAVES * kWave)
-    k_link_hits(DevCfg k, HitArgs<T> a, const double* __restrict__ gdr, const double* __restrict__ gdz,
-                const double* __restrict__ gLs) {
+    k_link_hits(DevCfg k, HitArgs<T> a, const double* __restrict__ seg) {
   __shared__ WaveLds lds[WAVES];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = __lane_id();
@@ -427,7 +408,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
         r = L.sfirst[sg] + (idx - L.spre[sg]);
         const InCell e = a.ent[r];
         const double4 P0 = a.hx[e.h0b & ~kBpix1Bit];
-        ar = P1.w - P0.w;  // as in k_cell_geom
+        ar = P1.w - P0.w;  // as the doublet step computes dr
         az = P1.z - P0.z;
         La = ar * ar + az * az;
         cell = e.cell;
@@ -474,9 +455,10 @@ __global__ void __launch_bounds__(WAVES * kWave)
             const bool valid = j < ns;
             double br = 0.0, bz = 0.0, Lb = 0.0, theta2 = 0.0;
             if (valid) {
-              const double Ls = gLs[cs + j];
-              br = gdr[cs + j];
-              bz = gdz[cs + j];
+              const double* g = seg + seg_at(cs + j);
+              const double Ls = g[2 * PT_SEG_BLOCK];
+              br = g[0];
+              bz = g[PT_SEG_BLOCK];
               Lb = fabs(Ls);
               theta2 = __builtin_signbit(Ls) ? th2e : th2b;  // end-cap outer hit: negative
             }
@@ -493,15 +475,30 @@ __global__ void __launch_bounds__(WAVES * kWave)
           wave_sync();
           continue;
         }
+        // one out-cell at a time (the head before the first group boundary and
+        // the tail)
+        auto single = [&](int j) {
+          const double* g = seg + seg_at(cs + j);
+          const double Ls = g[2 * PT_SEG_BLOCK];
+          const double theta2 = endcap_outer(Ls) ? th2e : th2b;
+          const bool pass = rz_pass(ar, az, La, g[0], g[PT_SEG_BLOCK], fabs(Ls), theta2);
+          const uint64_t mk = __ballot(pass);
+          if (mk) append(j, lane, pass, mk);
+        };
+        // groups of kUnroll out-cells start on multiples of kUnroll, so that a
+        // group's fields are contiguous in its segment block
+        const int head = min(ns, (kUnroll - (cs % kUnroll)) % kUnroll);
         int j = 0;
+        for (; j < head; ++j) single(j);
         // the loads of the next group are issued before the tests of this one
         double pdr[kUnroll], pdz[kUnroll], pLs[kUnroll];
-        if (kUnroll <= ns) {
+        if (j + kUnroll <= ns) {
+          const double* g = seg + seg_at(cs + j);
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
-            pdr[u] = gdr[cs + u];
-            pdz[u] = gdz[cs + u];
-            pLs[u] = gLs[cs + u];
+            pdr[u] = g[u];
+            pdz[u] = g[PT_SEG_BLOCK + u];
+            pLs[u] = g[2 * PT_SEG_BLOCK + u];
           }
         }
         for (; j + kUnroll <= ns; j += kUnroll) {
@@ -513,12 +510,12 @@ __global__ void __launch_bounds__(WAVES * kWave)
             cLs[u] = pLs[u];
           }
           if (j + 2 * kUnroll <= ns) {
+            const double* g = seg + seg_at(cs + j + kUnroll);
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-              const int c = cs + j + kUnroll + u;
-              pdr[u] = gdr[c];
-              pdz[u] = gdz[c];
-              pLs[u] = gLs[c];
+              pdr[u] = g[u];
+              pdz[u] = g[PT_SEG_BLOCK + u];
+              pLs[u] = g[2 * PT_SEG_BLOCK + u];
             }
           }
           bool pass[kUnroll];
@@ -537,14 +534,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
               if (mk[u]) append(j + u, lane, pass[u], mk[u]);
           }
         }
-        for (; j < ns; ++j) {
-          const int c = cs + j;
-          const double Ls = gLs[c];
-          const double theta2 = endcap_outer(Ls) ? th2e : th2b;
-          const bool pass = rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2);
-          const uint64_t mk = __ballot(pass);
-          if (mk) append(j, lane, pass, mk);
-        }
+        for (; j < ns; ++j) single(j);
         if (qn > 0) {
           wave_sync();
           beam_batch(k, a, L, qn, cs, jb, X1, Y1);
@@ -646,8 +636,7 @@ constexpr int kOvfStage = 256;
 template <class T>
 __global__ void __launch_bounds__(kOvfWaves * kWave)
     k_links_overflow(DevCfg k, HitArgs<T> a, const int32_t* __restrict__ inner, const uint8_t* __restrict__ layer,
-                     const double* __restrict__ gdr, const double* __restrict__ gdz,
-                     const double* __restrict__ gLs, const int32_t* __restrict__ out_start, int32_t links_cap,
+                     const double* __restrict__ seg, const int32_t* __restrict__ out_start, int32_t links_cap,
                      int32_t* __restrict__ in_cell, int32_t* __restrict__ out_cell) {
   __shared__ int32_t s_link[kOvfWaves][kOvfStage];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
@@ -658,7 +647,8 @@ __global__ void __launch_bounds__(kOvfWaves * kWave)
     const int cp = a.ovf[i];
     const int h0 = inner[cp];
     const int h1 = a.outer[cp];
-    const double ar = gdr[cp], az = gdz[cp], La = fabs(gLs[cp]);
+    const double* gp = seg + seg_at(cp);
+    const double ar = gp[0], az = gp[PT_SEG_BLOCK], La = fabs(gp[2 * PT_SEG_BLOCK]);
     const double4 P0 = a.hx[h0], P1 = a.hx[h1];
     const double X0 = P0.x, Y0 = P0.y, X1 = P1.x, Y1 = P1.y;
     const double rmax = layer[h0] == 0 ? k.rmax_bpix1 : k.rmax_other;
@@ -683,9 +673,10 @@ __global__ void __launch_bounds__(kOvfWaves * kWave)
       const int c = c0 + lane;
       bool pass = false;
       if (c < last) {
-        const double Ls = gLs[c];
+        const double* g = seg + seg_at(c);
+        const double Ls = g[2 * PT_SEG_BLOCK];
         const double theta2 = __builtin_signbit(Ls) ? k.theta2_endcap : k.theta2_barrel;
-        pass = rz_pass(ar, az, La, gdr[c], gdz[c], fabs(Ls), theta2);
+        pass = rz_pass(ar, az, La, g[0], g[PT_SEG_BLOCK], fabs(Ls), theta2);
         if (pass) {
           const double4 P2 = a.hx[a.outer[c]];
           pass = beam_pass(X0, Y0, X1, Y1, P2.x, P2.y, rmax);
@@ -708,12 +699,9 @@ __global__ void k_finish_links(const int32_t* count, int32_t cap, uint32_t* stat
 
 size_t ws_links(int n_hits, int cells_cap) {
   const int64_t scan_n = std::max<int64_t>(n_hits, cells_cap);
-  const int64_t chunks = std::max<int64_t>(1, (static_cast<int64_t>(cells_cap) + kGeomChunk - 1) / kGeomChunk);
+  const int64_t chunks = std::max<int64_t>(1, (static_cast<int64_t>(cells_cap) + kIndexChunk - 1) / kIndexChunk);
   Carver c(nullptr);
   c.take<double4>(n_hits);                  // hit table
-  c.take<double>(cells_cap);                // dr
-  c.take<double>(cells_cap);                // dz
-  c.take<double>(cells_cap);                // Ls
   c.take<InCell>(cells_cap);                // index entries
   c.take<int4>(cells_cap);                  // groups of each block
   c.take<int32_t>(chunks);                  // groups per block
@@ -728,11 +716,9 @@ size_t ws_links(int n_hits, int cells_cap) {
 }
 
 template <class T, int WAVES>
-static void launch_hits(const DevCfg& k, const HitArgs<T>& a, const double* dr, const double* dz,
-                        const double* Ls, hipStream_t s) {
+static void launch_hits(const DevCfg& k, const HitArgs<T>& a, const double* seg, hipStream_t s) {
   const int64_t blocks = (static_cast<int64_t>(a.n_hits) + WAVES - 1) / WAVES;
-  k_link_hits<T, WAVES><<<static_cast<unsigned>(blocks < 1 ? 1 : blocks), WAVES * kWave, 0, s>>>(k, a, dr, dz,
-                                                                                                 Ls);
+  k_link_hits<T, WAVES><<<static_cast<unsigned>(blocks < 1 ? 1 : blocks), WAVES * kWave, 0, s>>>(k, a, seg);
 }
 
 __global__ void k_copy_links_total(const int32_t* __restrict__ lcnt, const int32_t* __restrict__ cell_count,
@@ -745,12 +731,9 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
                         uint32_t* status, pt_workspace ws, hipStream_t s, int block) {
   const int n = h.n_hits;
   const int64_t scan_n = std::max<int64_t>(n, cells.cap);
-  const int64_t chunks = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kGeomChunk - 1) / kGeomChunk);
+  const int64_t chunks = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kIndexChunk - 1) / kIndexChunk);
   Carver c(ws.ptr);
   double4* hx = c.take<double4>(n);
-  double* dr = c.take<double>(cells.cap);
-  double* dz = c.take<double>(cells.cap);
-  double* Ls = c.take<double>(cells.cap);
   InCell* ent = c.take<InCell>(cells.cap);
   int4* grp = c.take<int4>(cells.cap);
   int32_t* n_grp = c.take<int32_t>(chunks);
@@ -772,10 +755,10 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
     PT_LAUNCH_CHECK();
   }
   void* tok = timing_begin(s);
-  GeomArgs<T> g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, hx, dr, dz, Ls, ent, grp, n_grp,
-                seg_first, lcnt, L.out_count, L.has_inner};
-  k_cell_geom<T><<<static_cast<unsigned>(chunks), kGeomBlock, 0, s>>>(k, g);
-  timing_end(tok, "cell_geom", s);
+  IndexArgs g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, ent, grp, n_grp, seg_first, lcnt,
+              L.out_count, L.has_inner};
+  k_cell_index<<<static_cast<unsigned>(chunks), kIndexBlock, 0, s>>>(g);
+  timing_end(tok, "cell_index", s);
   PT_LAUNCH_CHECK();
   if (exclusive_scan(seg_first, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
@@ -788,11 +771,11 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   tok = timing_begin(s);
   if (n > 0) {
     if (block == 128)
-      launch_hits<T, 2>(k, a, dr, dz, Ls, s);
+      launch_hits<T, 2>(k, a, cells.seg, s);
     else if (block == 256)
-      launch_hits<T, 4>(k, a, dr, dz, Ls, s);
+      launch_hits<T, 4>(k, a, cells.seg, s);
     else
-      launch_hits<T, 1>(k, a, dr, dz, Ls, s);
+      launch_hits<T, 1>(k, a, cells.seg, s);
     PT_LAUNCH_CHECK();
   }
   timing_end(tok, "links", s);
@@ -802,7 +785,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   k_link_emit<<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + 255) / 256), 256, 0, s>>>(e);
   timing_end(tok, "link_emit", s);
   PT_LAUNCH_CHECK();
-  k_links_overflow<T><<<1024, kOvfWaves * kWave, 0, s>>>(k, a, cells.inner, h.layer, dr, dz, Ls, L.out_start, L.cap,
+  k_links_overflow<T><<<1024, kOvfWaves * kWave, 0, s>>>(k, a, cells.inner, h.layer, cells.seg, L.out_start, L.cap,
                                                          L.in_cell, L.out_cell);
   PT_LAUNCH_CHECK();
   k_copy_links_total<<<1, 1, 0, s>>>(lcnt, cells.count, cells.cap, L.count);

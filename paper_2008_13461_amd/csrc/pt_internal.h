@@ -129,6 +129,14 @@ __device__ inline int lane_prefix(uint64_t mask) {
                                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u)));
 }
 
+// Index of cell c's dr in the cells' R-Z segment array (dz and ls follow at
+// +PT_SEG_BLOCK and +2 PT_SEG_BLOCK): blocks of PT_SEG_BLOCK cells hold the
+// three fields one after the other, so that the three streams a reader takes
+// at the same cells fall on different memory channels.
+__host__ __device__ inline int64_t seg_at(int64_t c) {
+  return (c / PT_SEG_BLOCK) * (3 * PT_SEG_BLOCK) + c % PT_SEG_BLOCK;
+}
+
 // Orders the LDS traffic of one wavefront (its lanes run in lockstep, so a
 // compiler barrier is all that is needed between a write and a read by
 // another lane).

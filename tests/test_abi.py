@@ -40,7 +40,7 @@ _STRUCTS = {
                   "block_links", "f64_solve_threshold"],
     "pt_hits": ["n_hits", "n_events", "event_offsets", "dtype", "x", "layer", "module"],
     "pt_workspace": ["ptr", "bytes"],
-    "pt_cells": ["cap", "inner", "pair", "count", "inner_first", "inner_count"],
+    "pt_cells": ["cap", "inner", "pair", "count", "inner_first", "inner_count", "seg"],
     "pt_links": ["cap", "in_cell", "count", "out_start", "out_count", "has_inner"],
     "pt_ntuplets": ["cap", "hits", "n", "count_raw", "kept", "count"],
     "pt_tracks": ["cap", "params", "chi2", "status"],
