@@ -176,15 +176,19 @@ __device__ inline void window_ranges(const DevCfg& k, const int32_t* bin_start, 
 // Outer hits a wavefront of the write pass gathers in LDS before it stores
 // them: its stores come after its loads, so no load of the window scan waits
 // for a store's acknowledgement (one counter tracks both on this GPU).
-constexpr int kStage = 512;
+constexpr int kStage = 256;
+constexpr int kEndcapBit = 0x80;  // in a staged pair: the pair's outer layer is an end-cap
+static_assert(kMaxPairs <= kEndcapBit, "pair indices leave the top bit free");
 
 template <bool WRITE, int WAVES>
 __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArgs a) {
   __shared__ int32_t s_out[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   __shared__ uint8_t s_pair[WRITE ? WAVES : 1][WRITE ? kStage : 1];
+  __shared__ double s_R[WRITE ? WAVES : 1][WRITE ? kStage : 1];  // R and z of the staged outer hits
+  __shared__ double s_Z[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = __lane_id();
-  const int j = blockIdx.x * WAVES + wave;
+  const int j = xcd_block(blockIdx.x, gridDim.x) * WAVES + wave;
   if (j >= a.n_hits) return;
   const int total = a.bin_start[-1];  // valid (sorted) hits
   if (j >= total) {
@@ -203,39 +207,24 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   int pos = first;  // uniform: next cell position (write pass) or count
   const int hit_i = WRITE ? a.sorted_hit[j] : 0;
   int staged = 0;                   // uniform: staged cells, to be written from pos on
-  // stores the staged cells (sorted outer hit, pair) with their R-Z
-  // segment, consecutive positions on consecutive lanes, two per lane and
-  // round with the loads of both first
+  // stores the staged cells (outer hit, pair, outer R and z) with their R-Z
+  // segment, consecutive positions on consecutive lanes
   auto flush = [&]() {
     wave_sync();
-    for (int i0 = 0; i0 < staged; i0 += 2 * kWave) {
-      int o[2], p[2], h[2];
-      double Ro[2], Zo[2];
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int i = min(i0 + u * kWave + lane, staged - 1);
-        o[u] = s_out[wave][i];
-        p[u] = s_pair[wave][i];
-        h[u] = a.sorted_hit[o[u]];
-        Ro[u] = a.sR[o[u]];
-        Zo[u] = a.sZ[o[u]];
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int i = i0 + u * kWave + lane;
-        const int w = pos + i;
-        if (i < staged && w < a.cap) {
-          const double dr = Ro[u] - Ri;
-          const double dz = Zo[u] - Zi;
-          const double L = dr * dr + dz * dz;
-          a.inner[w] = hit_i;
-          a.outer[w] = h[u];
-          a.pair[w] = static_cast<uint8_t>(p[u]);
-          double* g = a.seg + seg_at(w);
-          g[0] = dr;
-          g[PT_SEG_BLOCK] = dz;
-          g[2 * PT_SEG_BLOCK] = k.layer_barrel[k.pair_outer[p[u]]] ? L : -L;
-        }
+    for (int i = lane; i < staged; i += kWave) {
+      const int w = pos + i;
+      if (w < a.cap) {
+        const int p = s_pair[wave][i];  // pair | kEndcapBit when the outer layer is an end-cap
+        const double dr = s_R[wave][i] - Ri;
+        const double dz = s_Z[wave][i] - Zi;
+        const double L = dr * dr + dz * dz;
+        a.inner[w] = hit_i;
+        a.outer[w] = s_out[wave][i];
+        a.pair[w] = static_cast<uint8_t>(p & ~kEndcapBit);
+        double* g = a.seg + seg_at(w);
+        g[0] = dr;
+        g[PT_SEG_BLOCK] = dz;
+        g[2 * PT_SEG_BLOCK] = (p & kEndcapBit) ? -L : L;
       }
     }
     wave_sync();
@@ -248,20 +237,28 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
     if (k.cut_mask & PT_CUT_ZW) {
       if (!(k.zlo[p] <= Zi && Zi <= k.zhi[p])) continue;
     }
+    const bool endcap = WRITE && !k.layer_barrel[k.pair_outer[p]];  // class of the outer hits
     int ra[2], rb[2];
     window_ranges(k, a.bin_start, p, e, b, ra[0], rb[0], ra[1], rb[1]);
     for (int r = 0; r < 2; ++r) {
       for (int o0 = ra[r]; o0 < rb[r]; o0 += kWave) {
         const int o = o0 + lane;
         bool pass = false;
-        if (o < rb[r]) pass = doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
+        double Zo = 0.0, Ro = 0.0;
+        if (o < rb[r]) {
+          Zo = a.sZ[o];
+          Ro = a.sR[o];
+          pass = doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], Zo, Ro);
+        }
         const uint64_t m = __ballot(pass);
         if (WRITE) {
           if (staged + kWave > kStage) flush();
           if (pass) {
             const int at = staged + lane_prefix(m);
-            s_out[wave][at] = o;
-            s_pair[wave][at] = static_cast<uint8_t>(p);
+            s_out[wave][at] = a.sorted_hit[o];
+            s_pair[wave][at] = static_cast<uint8_t>(p | (endcap ? kEndcapBit : 0));
+            s_R[wave][at] = Ro;
+            s_Z[wave][at] = Zo;
           }
           staged += __popcll(m);
         } else {

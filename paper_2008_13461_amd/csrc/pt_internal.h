@@ -137,6 +137,18 @@ __host__ __device__ inline int64_t seg_at(int64_t c) {
   return (c / PT_SEG_BLOCK) * (3 * PT_SEG_BLOCK) + c % PT_SEG_BLOCK;
 }
 
+// Work-group dispatch places consecutive work-group ids on different XCDs
+// (round robin over kXcds), each with its own L2.  xcd_block(b, nb) renumbers
+// the nb work-groups of a 1-D grid so that each XCD takes one contiguous
+// range of the logical ids: neighbouring work-groups, which write
+// neighbouring output, then share an L2 and complete its cache lines there.
+constexpr int kXcds = 8;
+__device__ inline int xcd_block(int b, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x * q + min(x, r) + k;
+}
+
 // Orders the LDS traffic of one wavefront (its lanes run in lockstep, so a
 // compiler barrier is all that is needed between a write and a read by
 // another lane).
