@@ -54,14 +54,24 @@ void* timing_begin(hipStream_t s) {
     delete[] ev;
     return nullptr;
   }
-  hipEventRecord(ev[0], s);
+  if (hipEventRecord(ev[0], s) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    delete[] ev;
+    return nullptr;
+  }
   return ev;
 }
 
 void timing_end(void* tok, const char* name, hipStream_t s) {
   if (!tok) return;
   hipEvent_t* ev = static_cast<hipEvent_t*>(tok);
-  hipEventRecord(ev[1], s);
+  if (hipEventRecord(ev[1], s) != hipSuccess) {  // no record for this launch
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    delete[] ev;
+    return;
+  }
   TimingState& t = timing();
   std::lock_guard<std::mutex> g(t.mu);
   t.recs[name].push_back({ev[0], ev[1]});
@@ -100,8 +110,8 @@ void pt_timing_reset(void) {
   std::lock_guard<std::mutex> g(t.mu);
   for (auto& kv : t.recs)
     for (auto& r : kv.second) {
-      hipEventDestroy(r.a);
-      hipEventDestroy(r.b);
+      (void)hipEventDestroy(r.a);  // cleanup: nothing to recover
+      (void)hipEventDestroy(r.b);
     }
   t.recs.clear();
 }
@@ -149,7 +159,7 @@ pt_err pt_plan_create(const pt_config* cfg, int32_t n_hits_max, int32_t n_events
   p->ws_bytes = pt_workspace_size(cfg, n_hits_max, n_events_max, cells_cap, links_cap, tuplets_cap);
   if (p->ws_bytes == 0 || hipMalloc(&p->ws, p->ws_bytes) != hipSuccess ||
       hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-    if (p->ws) hipFree(p->ws);
+    if (p->ws) (void)hipFree(p->ws);
     delete p;
     return PT_ERR_DEVICE;
   }
@@ -160,10 +170,11 @@ pt_err pt_plan_create(const pt_config* cfg, int32_t n_hits_max, int32_t n_events
 void pt_plan_destroy(pt_plan plan) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return;
-  if (p->exec) hipGraphExecDestroy(p->exec);
-  if (p->graph) hipGraphDestroy(p->graph);
-  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
-  if (p->ws) hipFree(p->ws);
+  // teardown: errors here have no recovery
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->ws) (void)hipFree(p->ws);
   delete p;
 }
 
@@ -206,8 +217,8 @@ pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links*
   add(ptrs, sizeof(ptrs));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!p->exec || key != p->key) {
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     p->exec = nullptr;
     p->graph = nullptr;
     if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PT_ERR_DEVICE;
@@ -218,7 +229,7 @@ pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links*
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
     if (e != PT_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return e;
     }
     if (ce != hipSuccess || !g) return PT_ERR_DEVICE;
