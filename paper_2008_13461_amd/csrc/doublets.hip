@@ -128,6 +128,8 @@ struct DoubletArgs {
   const double* sR;
   int32_t* cnt;            // pass 1: per sorted inner hit
   const int32_t* off;      // pass 2: scanned counts
+  uint64_t* masks;         // [n_hits][kMaskChunks] pass 1: the ballot of each 64-wide group of candidates
+  int32_t* n_chunks;       // [n_hits] pass 1: groups of candidates of each sorted inner hit
   int32_t cap;
   int32_t* inner;
   int32_t* outer;
@@ -177,6 +179,9 @@ __device__ inline void window_ranges(const DevCfg& k, const int32_t* bin_start, 
 // them: its stores come after its loads, so no load of the window scan waits
 // for a store's acknowledgement (one counter tracks both on this GPU).
 constexpr int kStage = 256;
+// Candidate groups per inner hit whose pass masks the count pass keeps for
+// the write pass; a hit with more groups has the rest re-tested.
+constexpr int kMaskChunks = 64;
 constexpr int kEndcapBit = 0x80;  // in a staged pair: the pair's outer layer is an end-cap
 static_assert(kMaxPairs <= kEndcapBit, "pair indices leave the top bit free");
 
@@ -186,13 +191,17 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   __shared__ uint8_t s_pair[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   __shared__ double s_R[WRITE ? WAVES : 1][WRITE ? kStage : 1];  // R and z of the staged outer hits
   __shared__ double s_Z[WRITE ? WAVES : 1][WRITE ? kStage : 1];
+  __shared__ uint64_t s_mask[WAVES][kMaskChunks];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = __lane_id();
   const int j = xcd_block(blockIdx.x, gridDim.x) * WAVES + wave;
   if (j >= a.n_hits) return;
   const int total = a.bin_start[-1];  // valid (sorted) hits
   if (j >= total) {
-    if (!WRITE && lane == 0) a.cnt[j] = 0;
+    if (!WRITE && lane == 0) {
+      a.cnt[j] = 0;
+      a.n_chunks[j] = 0;
+    }
     return;
   }
   const int B = k.n_bins;
@@ -231,6 +240,15 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
     pos += staged;
     staged = 0;
   };
+  // the write pass takes the pass masks of the count pass (same groups, same
+  // order) instead of testing the candidates again
+  int chunk = 0;  // uniform: index of the current group of candidates
+  int kept = 0;   // uniform: groups with a mask from the count pass
+  if (WRITE) {
+    kept = min(a.n_chunks[j], kMaskChunks);
+    if (lane < kept) s_mask[wave][lane] = a.masks[static_cast<int64_t>(j) * kMaskChunks + lane];
+    wave_sync();
+  }
   const int np = k.n_inner_pairs[lay];
   for (int q = 0; q < np; ++q) {
     const int p = k.inner_pairs[lay][q];
@@ -241,36 +259,47 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
     int ra[2], rb[2];
     window_ranges(k, a.bin_start, p, e, b, ra[0], rb[0], ra[1], rb[1]);
     for (int r = 0; r < 2; ++r) {
-      for (int o0 = ra[r]; o0 < rb[r]; o0 += kWave) {
+      for (int o0 = ra[r]; o0 < rb[r]; o0 += kWave, ++chunk) {
         const int o = o0 + lane;
-        bool pass = false;
-        double Zo = 0.0, Ro = 0.0;
-        if (o < rb[r]) {
-          Zo = a.sZ[o];
-          Ro = a.sR[o];
-          pass = doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], Zo, Ro);
-        }
-        const uint64_t m = __ballot(pass);
         if (WRITE) {
+          uint64_t m;
+          bool pass;
+          if (chunk < kept) {
+            m = s_mask[wave][chunk];
+            pass = (m >> lane) & 1u;
+          } else {
+            pass = o < rb[r] && doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
+            m = __ballot(pass);
+          }
           if (staged + kWave > kStage) flush();
           if (pass) {
             const int at = staged + lane_prefix(m);
             s_out[wave][at] = a.sorted_hit[o];
             s_pair[wave][at] = static_cast<uint8_t>(p | (endcap ? kEndcapBit : 0));
-            s_R[wave][at] = Ro;
-            s_Z[wave][at] = Zo;
+            s_R[wave][at] = a.sR[o];
+            s_Z[wave][at] = a.sZ[o];
           }
           staged += __popcll(m);
         } else {
+          const bool pass =
+              o < rb[r] && doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
+          const uint64_t m = __ballot(pass);
+          if (chunk < kMaskChunks && lane == 0) s_mask[wave][chunk] = m;
           pos += __popcll(m);
         }
       }
     }
   }
   if (WRITE) flush();
+  if (!WRITE) {  // the masks, after every load of the scan
+    wave_sync();
+    const int nk = min(chunk, kMaskChunks);
+    if (lane < nk) a.masks[static_cast<int64_t>(j) * kMaskChunks + lane] = s_mask[wave][lane];
+  }
   if (lane == 0) {
     if (!WRITE) {
       a.cnt[j] = pos;
+      a.n_chunks[j] = chunk;
     } else {
       a.inner_first[hit_i] = first;
       a.inner_count[hit_i] = last - first;
@@ -305,6 +334,8 @@ size_t ws_doublets(int n_hits, int n_events, int n_bins) {
   c.take<double>(n_hits);         // sZ
   c.take<double>(n_hits);         // sR
   c.take<int32_t>(n_hits + 1);    // cnt / off
+  c.take<uint64_t>(static_cast<size_t>(n_hits) * kMaskChunks);  // pass masks
+  c.take<int32_t>(n_hits);        // groups per hit
   const size_t t = scan_tmp_elems(std::max<int64_t>(static_cast<int64_t>(nb), n_hits));
   c.take<int32_t>(t);
   return c.off + 256;
@@ -345,6 +376,8 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   double* sZ = c.take<double>(n);
   double* sR = c.take<double>(n);
   int32_t* cnt = c.take<int32_t>(n + 1);
+  uint64_t* masks = c.take<uint64_t>(static_cast<size_t>(n) * kMaskChunks);
+  int32_t* n_chunks = c.take<int32_t>(n);
   int32_t* tmp = c.take<int32_t>(scan_tmp_elems(std::max<int64_t>(nb, n)));
   int32_t* bin_start = bins + 1;
 
@@ -360,7 +393,7 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
                                                cells.inner_count);
   PT_LAUNCH_CHECK();
 
-  DoubletArgs a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, cells.cap, cells.inner,
+  DoubletArgs a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, masks, n_chunks, cells.cap, cells.inner,
                 cells.outer, cells.pair, cells.inner_first, cells.inner_count, cells.seg};
   // bin_start[-1] holds the number of valid hits (sorted positions).
   const int block = (k.block_doublets == 64 || k.block_doublets == 128 || k.block_doublets == 512)
