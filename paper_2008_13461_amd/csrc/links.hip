@@ -69,6 +69,13 @@ __device__ __forceinline__ bool endcap_outer(double Ls) {
   return hi < 0;
 }
 
+// The value of v in lane i (i wave-uniform).
+__device__ __forceinline__ double lane_value(double v, int i) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
+  return __hiloint2double(hi, lo);
+}
+
 // The beam-spot test of the circle through the three hits.
 __device__ __forceinline__ bool beam_pass(double X0, double Y0, double X1, double Y1, double X2, double Y2,
                                           double rmax) {
@@ -283,9 +290,7 @@ __global__ void k_seg_scatter(const int32_t* __restrict__ cell_count, int32_t ce
 // Per-wave LDS of k_link_hits.
 struct WaveLds {
   int32_t queue[2 * kWave];      // queued pairs: out-cell offset << 6 | in-cell lane
-  double X0[kWave], Y0[kWave];
-  double ar[kWave], az[kWave], La[kWave];  // in-cell segments, for the transposed sweep
-  int32_t bpix1[kWave];
+  int32_t h0b[kWave];            // inner hit of each in-cell lane, BPix1 flag in the top bit
   int32_t cnt[kWave];            // links found per in-cell lane
   int32_t found[kWave * kLocal]; // their out-cells
   int32_t sfirst[kSegWin];       // a window of the hit's segments: first entry ...
@@ -324,9 +329,11 @@ __device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a,
     const int e = L.queue[lane];
     const int j = e >> 6;
     const int li = e & (kWave - 1);
+    const int h0b = L.h0b[li];
+    const double4 P0 = a.hx[h0b & ~kBpix1Bit];
     const double4 P2 = a.hx[a.outer[cb + j]];
-    const double rmax = L.bpix1[li] ? k.rmax_bpix1 : k.rmax_other;
-    if (beam_pass(L.X0[li], L.Y0[li], X1, Y1, P2.x, P2.y, rmax)) {
+    const double rmax = (h0b & kBpix1Bit) ? k.rmax_bpix1 : k.rmax_other;
+    if (beam_pass(P0.x, P0.y, X1, Y1, P2.x, P2.y, rmax)) {
       const int slot = atomicAdd(&L.cnt[li], 1);
       if (slot < kLocal) L.found[li * kLocal + slot] = cb + j;
       const int bit = hb + j;
@@ -412,20 +419,13 @@ __global__ void __launch_bounds__(WAVES * kWave)
         az = P1.z - P0.z;
         La = ar * ar + az * az;
         cell = e.cell;
-        L.X0[lane] = P0.x;
-        L.Y0[lane] = P0.y;
-        L.bpix1[lane] = (e.h0b & kBpix1Bit) != 0;
+        L.h0b[lane] = e.h0b;
       }
       L.cnt[lane] = 0;
       // A partial pass with few in-cells sweeps the other way round: lanes over
-      // the out-cells, the in-cells (from LDS) in a wave-uniform loop.
+      // the out-cells, the in-cells (read from their lanes) in a wave-uniform loop.
       const int out_blocks = (nb + kWave - 1) / kWave;
       const bool transposed = m < kWave && static_cast<int64_t>(m) * out_blocks < nb;
-      if (transposed) {
-        L.ar[lane] = ar;
-        L.az[lane] = az;
-        L.La[lane] = La;
-      }
       wave_sync();
 
       // Sweep the out-cells in segments short enough for the packed queue
@@ -463,7 +463,8 @@ __global__ void __launch_bounds__(WAVES * kWave)
               theta2 = __builtin_signbit(Ls) ? th2e : th2b;  // end-cap outer hit: negative
             }
             for (int i = 0; i < m; ++i) {
-              const bool pass = valid && rz_pass(L.ar[i], L.az[i], L.La[i], br, bz, Lb, theta2);
+              const bool pass =
+                  valid && rz_pass(lane_value(ar, i), lane_value(az, i), lane_value(La, i), br, bz, Lb, theta2);
               const uint64_t mk = __ballot(pass);
               if (mk) append(j, i, pass, mk);
             }
