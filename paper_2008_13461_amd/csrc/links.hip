@@ -37,7 +37,8 @@
 namespace pt {
 namespace {
 
-constexpr int kLocal = 8;        // links an in-cell keeps in LDS before the overflow path
+constexpr int kLocal = 7;        // links an in-cell keeps in LDS before the overflow path
+constexpr int kRow = kLocal + 1;  // record of an in-cell with links: its cell, then up to kLocal links
 constexpr int kUnroll = 4;       // out-cells tested per step of the sweep
 constexpr int kSegment = 1 << 24;  // out-cells per queue segment (offsets fit beside the lane)
 constexpr int kSegWin = 64;        // in-cell segments of a hit handled per window (one per lane)
@@ -312,7 +313,7 @@ struct HitArgs {
   const int2* seg;           // segments: (first entry, entries)
   const InCell* ent;         // index entries
   int32_t* lcnt;      // [cells_cap + 1] links of each entry, zero on entry (scanned afterwards)
-  int32_t* spill;     // [cells_cap][kLocal] their out-cells, ascending (when at most kLocal)
+  int32_t* spill;     // [cells_cap][kRow] per entry with links: its cell, then its out-cells (at most kLocal)
   int32_t* ovf;       // in-cells with more than kLocal links
   int32_t* ovf_count;
   uint8_t* has_inner;  // set for every out-cell with a link (zero on entry)
@@ -553,9 +554,11 @@ __global__ void __launch_bounds__(WAVES * kWave)
           a.ovf[slot] = cell;
         }
       }
-      if (n > 0 && n <= kLocal) {  // sorted by k_link_emit
-        int32_t* sp = a.spill + static_cast<int64_t>(r) * kLocal;
-        for (int q = 0; q < n; ++q) sp[q] = L.found[lane * kLocal + q];
+      if (n > 0) {  // the links are sorted by k_link_emit
+        int32_t* sp = a.spill + static_cast<int64_t>(r) * kRow;
+        sp[0] = cell;
+        if (n <= kLocal)
+          for (int q = 0; q < n; ++q) sp[1 + q] = L.found[lane * kLocal + q];
       }
       wave_sync();
     }
@@ -570,7 +573,6 @@ struct EmitArgs {
   int32_t cells_cap;
   const int32_t* lcnt;   // scanned: first link of each record; lcnt[n] = total
   const int32_t* spill;
-  const InCell* ent;
   int32_t links_cap;
   int32_t* in_cell;
   int32_t* out_cell;
@@ -578,8 +580,9 @@ struct EmitArgs {
   int32_t* out_count;
 };
 
-// One thread per index entry: its loads (count, cell, spilled links) are all
-// issued before its stores, so no load waits for a store's acknowledgement.
+// One thread per index entry: its loads (count, then its record: cell and
+// links) are all issued before its stores, so no load waits for a store's
+// acknowledgement.
 __device__ __forceinline__ void cmp_swap(int& x, int& y) {
   const int lo = min(x, y), hi = max(x, y);
   x = lo;
@@ -593,18 +596,18 @@ __global__ void __launch_bounds__(256) k_link_emit(EmitArgs a) {
   const int pos = a.lcnt[r];
   const int cnt = a.lcnt[r + 1] - pos;
   if (cnt == 0) return;
-  const int cell = a.ent[r].cell;
-  static_assert(kLocal == 8, "one sorting network for eight links");
-  int f[kLocal];
+  static_assert(kRow == 8, "one record is two 16-byte vectors, one sorting network for eight keys");
+  const int4* sp = reinterpret_cast<const int4*>(a.spill + r * kRow);
+  const int4 q0 = sp[0];
+  const int cell = q0.x;
+  int f[kRow];
   if (cnt <= kLocal) {
     // the sweep records links in the order their beam-spot tests finished:
     // sort them by out-cell (empty places sort last)
-    const int4* sp = reinterpret_cast<const int4*>(a.spill + r * kLocal);
-    const int4 q0 = sp[0];
-    const int4 q1 = cnt > 4 ? sp[1] : make_int4(0, 0, 0, 0);
-    const int v[kLocal] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    const int4 q1 = cnt > 3 ? sp[1] : make_int4(0, 0, 0, 0);
+    const int v[kRow] = {q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, 0};
 #pragma unroll
-    for (int q = 0; q < kLocal; ++q) f[q] = q < cnt ? v[q] : INT_MAX;
+    for (int q = 0; q < kRow; ++q) f[q] = q < cnt ? v[q] : INT_MAX;
     // Batcher's odd-even merge sort of eight keys (19 compare-exchanges)
     cmp_swap(f[0], f[1]); cmp_swap(f[2], f[3]); cmp_swap(f[4], f[5]); cmp_swap(f[6], f[7]);
     cmp_swap(f[0], f[2]); cmp_swap(f[1], f[3]); cmp_swap(f[4], f[6]); cmp_swap(f[5], f[7]);
@@ -710,7 +713,7 @@ size_t ws_links(int n_hits, int cells_cap) {
   c.take<int2>(cells_cap);                  // segments
   c.take<int32_t>(static_cast<size_t>(cells_cap) + 1);  // links per entry -> first link
   c.take<int32_t>(scan_tmp_elems(scan_n));
-  c.take<int32_t>(static_cast<size_t>(cells_cap) * kLocal);  // spilled links
+  c.take<int32_t>(static_cast<size_t>(cells_cap) * kRow);  // records of the entries with links
   c.take<int32_t>(cells_cap);               // overflow list
   c.take<int32_t>(1);                       // overflow count
   return c.off + 256;
@@ -742,7 +745,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   int2* seg = c.take<int2>(cells.cap);
   int32_t* lcnt = c.take<int32_t>(static_cast<size_t>(cells.cap) + 1);
   int32_t* tmp = c.take<int32_t>(scan_tmp_elems(scan_n));
-  int32_t* spill = c.take<int32_t>(static_cast<size_t>(cells.cap) * kLocal);
+  int32_t* spill = c.take<int32_t>(static_cast<size_t>(cells.cap) * kRow);
   int32_t* ovf = c.take<int32_t>(cells.cap);
   int32_t* ovf_count = c.take<int32_t>(1);
   const T* x = static_cast<const T*>(h.x);
@@ -782,7 +785,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   timing_end(tok, "links", s);
   if (exclusive_scan_dev(lcnt, cells.cap, cells.count, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  EmitArgs e{cells.count, cells.cap, lcnt, spill, ent, L.cap, L.in_cell, L.out_cell, L.out_start, L.out_count};
+  EmitArgs e{cells.count, cells.cap, lcnt, spill, L.cap, L.in_cell, L.out_cell, L.out_start, L.out_count};
   k_link_emit<<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + 255) / 256), 256, 0, s>>>(e);
   timing_end(tok, "link_emit", s);
   PT_LAUNCH_CHECK();
