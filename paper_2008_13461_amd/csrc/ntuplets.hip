@@ -227,9 +227,15 @@ __global__ void k_copy_total_rows(const int32_t* __restrict__ paths, const int32
   *count_raw = paths[*n_roots];
 }
 
+// Clears the per-cell maximum of the cells the rows visit (the only ones
+// read afterwards), instead of all cells.
 __global__ void k_clear_maxn(TupIn a) {
-  const int n = min(*a.cell_count, a.cells_cap);
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) a.max_n[c] = 0;
+  const int rows = min(*a.count_raw, a.cap);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < rows; t += gridDim.x * blockDim.x) {
+    const int nh = a.n[t];
+    const int32_t* C = a.cells + static_cast<int64_t>(t) * (kMaxHits - 1);
+    for (int d = 0; d < nh - 1; ++d) a.max_n[C[d]] = 0;
+  }
 }
 
 __global__ void k_maxn(TupIn a) {
@@ -249,34 +255,68 @@ __device__ inline bool keep_row(const TupIn& a, int t) {
   return true;
 }
 
+// Keep flags of the kRootItems rows of this thread in a chunk (row
+// base + i * kBlock + thread), with every load issued before the tests.
+__device__ inline void keep_flags(const TupIn& a, int64_t base, int rows, bool (&f)[kRootItems]) {
+#pragma unroll
+  for (int i = 0; i < kRootItems; ++i) {
+    const int64_t t = base + i * kBlock + threadIdx.x;
+    f[i] = t < rows && keep_row(a, static_cast<int>(t));
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_keep_count(TupIn a, int32_t* __restrict__ chunk_kept) {
   __shared__ int32_t s_scan[kBlock / kWave + 1];
   const int rows = min(*a.count_raw, a.cap);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
-  int cnt = 0;
-  for (int i = 0; i < kRootItems; ++i) {
-    const int64_t t = base + i * kBlock + threadIdx.x;
-    if (t < rows && keep_row(a, static_cast<int>(t))) ++cnt;
+  if (base >= rows) {
+    if (threadIdx.x == 0) chunk_kept[blockIdx.x] = 0;
+    return;
   }
+  bool f[kRootItems];
+  keep_flags(a, base, rows, f);
+  int cnt = 0;
+#pragma unroll
+  for (int i = 0; i < kRootItems; ++i) cnt += f[i] ? 1 : 0;
   int total;
   block_exclusive(cnt, s_scan, &total);
   if (threadIdx.x == 0) chunk_kept[blockIdx.x] = total;
 }
 
+// Writes the chunk's kept rows in row order, placed like the roots (see
+// k_root_write).
 __global__ void __launch_bounds__(kBlock) k_keep_write(TupIn a, const int32_t* __restrict__ chunk_first) {
-  __shared__ int32_t s_scan[kBlock / kWave + 1];
+  constexpr int kWaves = kBlock / kWave;
+  __shared__ int32_t s_grp[kRootItems * kWaves];
   const int rows = min(*a.count_raw, a.cap);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
   if (base >= rows) return;
-  int at = chunk_first[blockIdx.x];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int at = chunk_first[blockIdx.x];
+  bool f[kRootItems];
+  keep_flags(a, base, rows, f);
+  int rank[kRootItems];
+#pragma unroll
   for (int i = 0; i < kRootItems; ++i) {
-    const int64_t t = base + i * kBlock + threadIdx.x;
-    const bool keep = t < rows && keep_row(a, static_cast<int>(t));
-    int total;
-    const int pos = at + block_exclusive(keep ? 1 : 0, s_scan, &total);
-    if (keep) a.kept[pos] = static_cast<int>(t);
-    at += total;
+    const uint64_t m = __ballot(f[i]);
+    rank[i] = lane_prefix(m);
+    if (lane == 0) s_grp[i * kWaves + wave] = __popcll(m);
   }
+  __syncthreads();
+  if (wave == 0) {
+    const int v = s_grp[lane];
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    s_grp[lane] = incl - v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kRootItems; ++i)
+    if (f[i]) a.kept[at + s_grp[i * kWaves + wave] + rank[i]] = static_cast<int>(base + i * kBlock + threadIdx.x);
 }
 
 __global__ void k_copy_total(const int32_t* __restrict__ src, int32_t* __restrict__ dst) { *dst = *src; }
@@ -338,7 +378,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   k_copy_total_rows<<<1, 1, 0, s>>>(paths, n_roots, T.count_raw);
   PT_LAUNCH_CHECK();
   tok = timing_begin(s);
-  k_clear_maxn<<<grid_for(cells.cap, 256, 8192), 256, 0, s>>>(a);
+  k_clear_maxn<<<grid_for(T.cap, 256, 8192), 256, 0, s>>>(a);
   PT_LAUNCH_CHECK();
   k_maxn<<<grid_for(T.cap, 256, 8192), 256, 0, s>>>(a);
   PT_LAUNCH_CHECK();
