@@ -190,10 +190,11 @@ typedef struct {
 } pt_cells;
 
 /* Cell links c_in -> c_out: c_out starts on the outer hit of c_in.  The links
- * of one inner cell are contiguous: cell c's outer links are out_cell[j] for
- * j in [out_start[c], out_start[c] + out_count[c]) (clipped to cap; out_start
- * is only meaningful when out_count > 0).  has_inner[c] = 1 when some link
- * ends on c.  The per-cell arrays hold the cells' capacity. */
+ * are ordered by inner cell, and those of one inner cell by outer cell: cell
+ * c's outer links are out_cell[j] for j in [out_start[c], out_start[c] +
+ * out_count[c]) (clipped to cap).  has_inner[c] = 1 when some link ends on c.
+ * The per-cell arrays hold the cells' capacity; entries below count[0] of
+ * the cells are written. */
 typedef struct {
   int32_t cap;
   int32_t* in_cell;   /* [cap] */

@@ -24,9 +24,10 @@
 //     pairs.  Each in-cell's link count is recorded, with its links when
 //     there are at most kLocal of them, and the hit's out-cells that gained
 //     an inner link are flagged (has_inner) in one coalesced run.
-//  5. a scan of the counts places every in-cell's links (no shared counter:
-//     same-address atomics serialise), k_link_emit writes them, and
-//     k_links_overflow recomputes the few in-cells with more than kLocal.
+//  5. a scan of the per-cell counts places every in-cell's links, in cell
+//     order (no shared counter: same-address atomics serialise),
+//     k_link_emit writes them and every cell's range, and k_links_overflow
+//     recomputes the few in-cells with more than kLocal.
 #include "pt_internal.h"
 
 #include <algorithm>
@@ -37,8 +38,8 @@
 namespace pt {
 namespace {
 
-constexpr int kLocal = 7;        // links an in-cell keeps in LDS before the overflow path
-constexpr int kRow = kLocal + 1;  // record of an in-cell with links: its cell, then up to kLocal links
+constexpr int kLocal = 8;        // links an in-cell keeps in LDS before the overflow path
+constexpr int kRow = kLocal;     // record of an in-cell with links (by cell): up to kLocal links
 constexpr int kUnroll = 4;       // out-cells tested per step of the sweep
 constexpr int kSegment = 1 << 24;  // out-cells per queue segment (offsets fit beside the lane)
 constexpr int kSegWin = 64;        // in-cell segments of a hit handled per window (one per lane)
@@ -118,8 +119,7 @@ struct IndexArgs {
   int4* grp;           // per block: its groups (outer hit, first entry, cells, slot in the hit's list)
   int32_t* n_grp;      // per block: number of groups
   int32_t* n_seg;      // [n_hits + 1] groups ending on each hit
-  int32_t* lcnt;       // cleared here (link counts of the entries)
-  int32_t* out_count;
+  int32_t* lcnt;       // cleared here (link counts of the cells)
   uint8_t* has_inner;
 };
 
@@ -135,8 +135,8 @@ static_assert((kIndexChunk & (kIndexChunk - 1)) == 0, "hash table size must be a
 // `ent` (staged in LDS, then written contiguously).  Each group becomes one
 // segment of its outer hit's in-cell list: the hit's segment count is taken
 // with one global atomic per group, and the segment itself is placed by
-// k_seg_scatter once the counts are scanned.  out_count, has_inner and the
-// link counts are cleared here (out_start is only read where out_count > 0).
+// k_seg_scatter once the counts are scanned.  has_inner and the link counts
+// are cleared here.
 //
 // Every global load and atomic of the block is issued before its first
 // global store: on this architecture one counter tracks loads and stores
@@ -267,7 +267,6 @@ __global__ void __launch_bounds__(kIndexBlock) k_cell_index(IndexArgs a) {
     const int loc = u * kIndexBlock + threadIdx.x;
     if (loc >= m) break;
     const int c = static_cast<int>(base) + loc;
-    a.out_count[c] = 0;
     a.has_inner[c] = 0;
     a.lcnt[c] = 0;
   }
@@ -312,8 +311,8 @@ struct HitArgs {
   const int32_t* seg_first;  // [n_hits + 1] first segment of each hit's in-cell list
   const int2* seg;           // segments: (first entry, entries)
   const InCell* ent;         // index entries
-  int32_t* lcnt;      // [cells_cap + 1] links of each entry, zero on entry (scanned afterwards)
-  int32_t* spill;     // [cells_cap][kRow] per entry with links: its cell, then its out-cells (at most kLocal)
+  int32_t* lcnt;      // [cells_cap + 1] links of each cell, zero on entry (scanned afterwards)
+  int32_t* spill;     // [cells_cap][kRow] per in-cell with links: its out-cells (at most kLocal)
   int32_t* ovf;       // in-cells with more than kLocal links
   int32_t* ovf_count;
   uint8_t* has_inner;  // set for every out-cell with a link (zero on entry)
@@ -548,17 +547,15 @@ __global__ void __launch_bounds__(WAVES * kWave)
       // the spill row; positions come from a scan afterwards
       const int n = (lane < m) ? L.cnt[lane] : 0;
       if (n > 0) {
-        a.lcnt[r] = n;
+        a.lcnt[cell] = n;
         if (n > kLocal) {
           const int slot = atomicAdd(a.ovf_count, 1);
           a.ovf[slot] = cell;
         }
       }
-      if (n > 0) {  // the links are sorted by k_link_emit
-        int32_t* sp = a.spill + static_cast<int64_t>(r) * kRow;
-        sp[0] = cell;
-        if (n <= kLocal)
-          for (int q = 0; q < n; ++q) sp[1 + q] = L.found[lane * kLocal + q];
+      if (n > 0 && n <= kLocal) {  // the links are sorted by k_link_emit
+        int32_t* sp = a.spill + static_cast<int64_t>(cell) * kRow;
+        for (int q = 0; q < n; ++q) sp[q] = L.found[lane * kLocal + q];
       }
       wave_sync();
     }
@@ -567,12 +564,15 @@ __global__ void __launch_bounds__(WAVES * kWave)
   for (int j = lane; j < nh; j += kWave) a.has_inner[cb + j] = (L.hin[j >> 5] >> (j & 31)) & 1u;
 }
 
-// Places the links of every in-cell at its scanned position.
+// Places the links of every cell at its scanned position: the links come out
+// ordered by in-cell (each cell's run sorted by out-cell), so that the runs of
+// neighbouring cells -- the children of one cell in the n-tuplet search -- are
+// adjacent.
 struct EmitArgs {
   const int32_t* cell_count;
   int32_t cells_cap;
-  const int32_t* lcnt;   // scanned: first link of each record; lcnt[n] = total
-  const int32_t* spill;
+  const int32_t* lcnt;   // scanned: first link of each cell; lcnt[n] = total
+  const int32_t* spill;  // per in-cell with 1..kLocal links: its out-cells
   int32_t links_cap;
   int32_t* in_cell;
   int32_t* out_cell;
@@ -580,32 +580,30 @@ struct EmitArgs {
   int32_t* out_count;
 };
 
-// One thread per index entry: its loads (count, then its record: cell and
-// links) are all issued before its stores, so no load waits for a store's
-// acknowledgement.
 __device__ __forceinline__ void cmp_swap(int& x, int& y) {
   const int lo = min(x, y), hi = max(x, y);
   x = lo;
   y = hi;
 }
 
+// One thread per cell; its loads (range, record) come before its stores, so
+// no load waits for a store's acknowledgement.
 __global__ void __launch_bounds__(256) k_link_emit(EmitArgs a) {
   const int n = min(*a.cell_count, a.cells_cap);
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const int pos = a.lcnt[r];
-  const int cnt = a.lcnt[r + 1] - pos;
-  if (cnt == 0) return;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int pos = a.lcnt[c];
+  const int cnt = a.lcnt[c + 1] - pos;
   static_assert(kRow == 8, "one record is two 16-byte vectors, one sorting network for eight keys");
-  const int4* sp = reinterpret_cast<const int4*>(a.spill + r * kRow);
-  const int4 q0 = sp[0];
-  const int cell = q0.x;
+  const bool local = cnt > 0 && cnt <= kLocal;
   int f[kRow];
-  if (cnt <= kLocal) {
+  if (local) {
     // the sweep records links in the order their beam-spot tests finished:
     // sort them by out-cell (empty places sort last)
-    const int4 q1 = cnt > 3 ? sp[1] : make_int4(0, 0, 0, 0);
-    const int v[kRow] = {q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, 0};
+    const int4* sp = reinterpret_cast<const int4*>(a.spill + c * kRow);
+    const int4 q0 = sp[0];
+    const int4 q1 = cnt > 4 ? sp[1] : make_int4(0, 0, 0, 0);
+    const int v[kRow] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
 #pragma unroll
     for (int q = 0; q < kRow; ++q) f[q] = q < cnt ? v[q] : INT_MAX;
     // Batcher's odd-even merge sort of eight keys (19 compare-exchanges)
@@ -616,16 +614,15 @@ __global__ void __launch_bounds__(256) k_link_emit(EmitArgs a) {
     cmp_swap(f[2], f[4]); cmp_swap(f[3], f[5]);
     cmp_swap(f[1], f[2]); cmp_swap(f[3], f[4]); cmp_swap(f[5], f[6]);
   }
-  a.out_start[cell] = pos;
-  a.out_count[cell] = cnt;
-  if (cnt > kLocal) return;  // written by k_links_overflow
+  a.out_start[c] = pos;
+  a.out_count[c] = cnt;
+  if (!local) return;  // none, or written by k_links_overflow
 #pragma unroll
   for (int q = 0; q < kLocal; ++q) {
     if (q >= cnt) break;
-    const int c = f[q];
     if (pos + q < a.links_cap) {
-      a.in_cell[pos + q] = cell;
-      a.out_cell[pos + q] = c;
+      a.in_cell[pos + q] = static_cast<int>(c);
+      a.out_cell[pos + q] = f[q];
     }
   }
 }
@@ -713,7 +710,7 @@ size_t ws_links(int n_hits, int cells_cap) {
   c.take<int2>(cells_cap);                  // segments
   c.take<int32_t>(static_cast<size_t>(cells_cap) + 1);  // links per entry -> first link
   c.take<int32_t>(scan_tmp_elems(scan_n));
-  c.take<int32_t>(static_cast<size_t>(cells_cap) * kRow);  // records of the entries with links
+  c.take<int32_t>(static_cast<size_t>(cells_cap) * kRow);  // records of the cells with links
   c.take<int32_t>(cells_cap);               // overflow list
   c.take<int32_t>(1);                       // overflow count
   return c.off + 256;
@@ -760,7 +757,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   }
   void* tok = timing_begin(s);
   IndexArgs g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, ent, grp, n_grp, seg_first, lcnt,
-              L.out_count, L.has_inner};
+              L.has_inner};
   k_cell_index<<<static_cast<unsigned>(chunks), kIndexBlock, 0, s>>>(g);
   timing_end(tok, "cell_index", s);
   PT_LAUNCH_CHECK();

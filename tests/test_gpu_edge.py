@@ -167,14 +167,16 @@ def test_plan_graph_replays_match_eager():
 
 def _link_layout_ok(pipe):
     """Every cell's links are one run [out_start, out_start + out_count) whose
-    entries start on that cell, sorted by out-cell; has_inner marks exactly the
-    cells some link ends on."""
+    entries start on that cell, sorted by out-cell, and the runs follow the
+    cell order; has_inner marks exactly the cells some link ends on."""
     li, lo = (t.cpu().numpy() for t in pipe.links.valid())
     n_cells = min(int(pipe.cells.count.item()), pipe.cells.cap)
     start = pipe.links.out_start[:n_cells].cpu().numpy()
     cnt = pipe.links.out_count[:n_cells].cpu().numpy()
     has = pipe.links.has_inner[:n_cells].cpu().numpy()
     assert int(cnt.sum()) == len(li)
+    assert np.all(np.diff(li) >= 0)
+    assert np.array_equal(start[1:], (start + cnt)[:-1])
     for c in np.nonzero(cnt)[0]:
         run = slice(start[c], start[c] + cnt[c])
         assert np.all(li[run] == c)
