@@ -128,8 +128,8 @@ struct DoubletArgs {
   const double* sR;
   int32_t* cnt;            // pass 1: per sorted inner hit
   const int32_t* off;      // pass 2: scanned counts
-  uint64_t* masks;         // [n_hits][kMaskChunks] pass 1: the ballot of each 64-wide group of candidates
-  int32_t* n_chunks;       // [n_hits] pass 1: groups of candidates of each sorted inner hit
+  int4* chunks;            // [n_hits][kMaskChunks] pass 1: the groups of candidates with a passing one
+  int32_t* n_chunks;       // [n_hits] pass 1: how many (-1: more than kMaskChunks)
   int32_t cap;
   int32_t* inner;
   int32_t* outer;
@@ -179,8 +179,10 @@ __device__ inline void window_ranges(const DevCfg& k, const int32_t* bin_start, 
 // them: its stores come after its loads, so no load of the window scan waits
 // for a store's acknowledgement (one counter tracks both on this GPU).
 constexpr int kStage = 256;
-// Candidate groups per inner hit whose pass masks the count pass keeps for
-// the write pass; a hit with more groups has the rest re-tested.
+// Groups of candidates with a passing one that the count pass keeps for the
+// write pass, per inner hit: (ballot of the group, first outer hit, pair |
+// kEndcapBit) in one 16-byte record.  A hit with more such groups is tested
+// again by the write pass.
 constexpr int kMaskChunks = 64;
 constexpr int kEndcapBit = 0x80;  // in a staged pair: the pair's outer layer is an end-cap
 static_assert(kMaxPairs <= kEndcapBit, "pair indices leave the top bit free");
@@ -191,7 +193,7 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   __shared__ uint8_t s_pair[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   __shared__ double s_R[WRITE ? WAVES : 1][WRITE ? kStage : 1];  // R and z of the staged outer hits
   __shared__ double s_Z[WRITE ? WAVES : 1][WRITE ? kStage : 1];
-  __shared__ uint64_t s_mask[WAVES][kMaskChunks];
+  __shared__ int4 s_chunk[WAVES][kMaskChunks];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = __lane_id();
   const int j = xcd_block(blockIdx.x, gridDim.x) * WAVES + wave;
@@ -240,66 +242,87 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
     pos += staged;
     staged = 0;
   };
-  // the write pass takes the pass masks of the count pass (same groups, same
-  // order) instead of testing the candidates again
-  int chunk = 0;  // uniform: index of the current group of candidates
-  int kept = 0;   // uniform: groups with a mask from the count pass
+  // the write pass takes the groups the count pass kept instead of testing
+  // the candidates again
   if (WRITE) {
-    kept = min(a.n_chunks[j], kMaskChunks);
-    if (lane < kept) s_mask[wave][lane] = a.masks[static_cast<int64_t>(j) * kMaskChunks + lane];
-    wave_sync();
+    const int nst = a.n_chunks[j];
+    if (nst >= 0) {
+      if (lane < nst) s_chunk[wave][lane] = a.chunks[static_cast<int64_t>(j) * kMaskChunks + lane];
+      wave_sync();
+      for (int t = 0; t < nst; ++t) {
+        const int4 d = s_chunk[wave][t];
+        const uint64_t m = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.y))) << 32) |
+                           static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.x));
+        const int o0 = __builtin_amdgcn_readfirstlane(d.z);
+        const int pe = __builtin_amdgcn_readfirstlane(d.w);
+        if (staged + kWave > kStage) flush();
+        if ((m >> lane) & 1u) {
+          const int o = o0 + lane;
+          const int at = staged + lane_prefix(m);
+          s_out[wave][at] = a.sorted_hit[o];
+          s_pair[wave][at] = static_cast<uint8_t>(pe);
+          s_R[wave][at] = a.sR[o];
+          s_Z[wave][at] = a.sZ[o];
+        }
+        staged += __popcll(m);
+      }
+      flush();
+      if (lane == 0) {
+        a.inner_first[hit_i] = first;
+        a.inner_count[hit_i] = last - first;
+      }
+      return;
+    }
   }
+  // the count pass, or the write pass of a hit with more groups than kept:
+  // every group of candidates, in pair order, then window order
+  int kept = 0;  // uniform: groups with a passing candidate (count pass)
   const int np = k.n_inner_pairs[lay];
   for (int q = 0; q < np; ++q) {
     const int p = k.inner_pairs[lay][q];
     if (k.cut_mask & PT_CUT_ZW) {
       if (!(k.zlo[p] <= Zi && Zi <= k.zhi[p])) continue;
     }
-    const bool endcap = WRITE && !k.layer_barrel[k.pair_outer[p]];  // class of the outer hits
+    const int pe = p | (k.layer_barrel[k.pair_outer[p]] ? 0 : kEndcapBit);  // and the outer hits' class
     int ra[2], rb[2];
     window_ranges(k, a.bin_start, p, e, b, ra[0], rb[0], ra[1], rb[1]);
     for (int r = 0; r < 2; ++r) {
-      for (int o0 = ra[r]; o0 < rb[r]; o0 += kWave, ++chunk) {
+      for (int o0 = ra[r]; o0 < rb[r]; o0 += kWave) {
         const int o = o0 + lane;
+        const bool pass = o < rb[r] && doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
+        const uint64_t m = __ballot(pass);
         if (WRITE) {
-          uint64_t m;
-          bool pass;
-          if (chunk < kept) {
-            m = s_mask[wave][chunk];
-            pass = (m >> lane) & 1u;
-          } else {
-            pass = o < rb[r] && doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
-            m = __ballot(pass);
-          }
           if (staged + kWave > kStage) flush();
           if (pass) {
             const int at = staged + lane_prefix(m);
             s_out[wave][at] = a.sorted_hit[o];
-            s_pair[wave][at] = static_cast<uint8_t>(p | (endcap ? kEndcapBit : 0));
+            s_pair[wave][at] = static_cast<uint8_t>(pe);
             s_R[wave][at] = a.sR[o];
             s_Z[wave][at] = a.sZ[o];
           }
           staged += __popcll(m);
         } else {
-          const bool pass =
-              o < rb[r] && doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
-          const uint64_t m = __ballot(pass);
-          if (chunk < kMaskChunks && lane == 0) s_mask[wave][chunk] = m;
+          if (m) {
+            if (kept < kMaskChunks && lane == 0)
+              s_chunk[wave][kept] = make_int4(static_cast<int>(static_cast<uint32_t>(m)),
+                                              static_cast<int>(static_cast<uint32_t>(m >> 32)), o0, pe);
+            ++kept;
+          }
           pos += __popcll(m);
         }
       }
     }
   }
   if (WRITE) flush();
-  if (!WRITE) {  // the masks, after every load of the scan
+  if (!WRITE) {  // the kept groups, after every load of the scan
     wave_sync();
-    const int nk = min(chunk, kMaskChunks);
-    if (lane < nk) a.masks[static_cast<int64_t>(j) * kMaskChunks + lane] = s_mask[wave][lane];
+    const int nk = min(kept, kMaskChunks);
+    if (lane < nk) a.chunks[static_cast<int64_t>(j) * kMaskChunks + lane] = s_chunk[wave][lane];
   }
   if (lane == 0) {
     if (!WRITE) {
       a.cnt[j] = pos;
-      a.n_chunks[j] = chunk;
+      a.n_chunks[j] = kept <= kMaskChunks ? kept : -1;
     } else {
       a.inner_first[hit_i] = first;
       a.inner_count[hit_i] = last - first;
@@ -334,7 +357,7 @@ size_t ws_doublets(int n_hits, int n_events, int n_bins) {
   c.take<double>(n_hits);         // sZ
   c.take<double>(n_hits);         // sR
   c.take<int32_t>(n_hits + 1);    // cnt / off
-  c.take<uint64_t>(static_cast<size_t>(n_hits) * kMaskChunks);  // pass masks
+  c.take<int4>(static_cast<size_t>(n_hits) * kMaskChunks);  // kept groups of candidates
   c.take<int32_t>(n_hits);        // groups per hit
   const size_t t = scan_tmp_elems(std::max<int64_t>(static_cast<int64_t>(nb), n_hits));
   c.take<int32_t>(t);
@@ -376,7 +399,7 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   double* sZ = c.take<double>(n);
   double* sR = c.take<double>(n);
   int32_t* cnt = c.take<int32_t>(n + 1);
-  uint64_t* masks = c.take<uint64_t>(static_cast<size_t>(n) * kMaskChunks);
+  int4* chunks = c.take<int4>(static_cast<size_t>(n) * kMaskChunks);
   int32_t* n_chunks = c.take<int32_t>(n);
   int32_t* tmp = c.take<int32_t>(scan_tmp_elems(std::max<int64_t>(nb, n)));
   int32_t* bin_start = bins + 1;
@@ -393,7 +416,7 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
                                                cells.inner_count);
   PT_LAUNCH_CHECK();
 
-  DoubletArgs a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, masks, n_chunks, cells.cap, cells.inner,
+  DoubletArgs a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, chunks, n_chunks, cells.cap, cells.inner,
                 cells.outer, cells.pair, cells.inner_first, cells.inner_count, cells.seg};
   // bin_start[-1] holds the number of valid hits (sorted positions).
   const int block = (k.block_doublets == 64 || k.block_doublets == 128 || k.block_doublets == 512)
