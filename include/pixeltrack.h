@@ -269,7 +269,8 @@ pt_err pt_link_cells(const pt_hits* hits, const pt_config* cfg, const pt_cells* 
 
 /* n-tuplet search and duplicate removal (section 3.2, section 3.3).
  * Root cells: inner hit on a layer of root_always_mask, or of
- * root_if_free_mask with has_inner == 0.  From every root a depth-first
+ * root_if_free_mask with has_inner == 0 (the inner hit's layer is read as
+ * the inner layer of the cell's pair).  From every root a depth-first
  * search follows outer links; a path is emitted when its last cell has no
  * outer link or it has max_hits hits (then PT_ST_TRUNCATED counts it), and
  * it has at least min_hits hits.  A row is kept unless one of its cells

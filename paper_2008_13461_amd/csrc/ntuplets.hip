@@ -23,9 +23,9 @@ namespace {
 constexpr int kBlock = 256;
 
 struct TupIn {
-  const uint8_t* layer;
   const int32_t* cell_inner;
   const int32_t* cell_outer;
+  const uint8_t* cell_pair;
   const int32_t* cell_count;
   int32_t cells_cap;
   const int32_t* out_start;
@@ -48,12 +48,6 @@ struct TupIn {
 
 constexpr int kRootItems = 16;                   // cells per thread of the root kernels
 constexpr int kRootChunk = kBlock * kRootItems;  // cells per block
-
-__device__ inline bool is_root(const DevCfg& k, const TupIn& a, int c) {
-  if (a.out_count[c] <= 0) return false;  // a root without outer links makes a 2-hit path
-  const int L = a.layer[a.cell_inner[c]];
-  return ((k.root_always_mask >> L) & 1u) || (((k.root_if_free_mask >> L) & 1u) && !a.has_inner[c]);
-}
 
 // Block-wide exclusive prefix of v; *total receives the block sum.
 __device__ inline int block_exclusive(int v, int32_t* s_scan, int* total) {
@@ -86,20 +80,21 @@ __device__ inline int block_exclusive(int v, int32_t* s_scan, int* total) {
 // Root flags of the kRootItems cells of this thread in a chunk (cell
 // base + i * kBlock + thread), with every load of the chunk issued up front.
 __device__ inline void root_flags(const DevCfg& k, const TupIn& a, int64_t base, int n, bool (&f)[kRootItems]) {
-  int oc[kRootItems], hi[kRootItems];
-  uint8_t free_[kRootItems];
+  int oc[kRootItems];
+  uint8_t pr[kRootItems], free_[kRootItems];
 #pragma unroll
   for (int i = 0; i < kRootItems; ++i) {
     const int64_t c = base + i * kBlock + threadIdx.x;
     const int cc = c < n ? static_cast<int>(c) : 0;
     oc[i] = c < n ? a.out_count[cc] : 0;
-    hi[i] = a.cell_inner[cc];
+    pr[i] = a.cell_pair[cc];
     free_[i] = !a.has_inner[cc];
   }
 #pragma unroll
   for (int i = 0; i < kRootItems; ++i) {
-    // a root without outer links makes a 2-hit path
-    const int L = a.layer[hi[i]];
+    // a root without outer links makes a 2-hit path; the inner hit's layer is
+    // the inner layer of the cell's pair
+    const int L = k.pair_inner[pr[i]];
     f[i] = oc[i] > 0 && (((k.root_always_mask >> L) & 1u) || (((k.root_if_free_mask >> L) & 1u) && free_[i]));
   }
 }
@@ -353,7 +348,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   int32_t* max_n = c.take<int32_t>(cells.cap);
   int32_t* tmp = c.take<int32_t>(scan_tmp_elems(scan_n));
   int32_t* n_roots = chunk_roots + chunks;  // the scan's total
-  TupIn a{h.layer, cells.inner, cells.outer, cells.count, cells.cap, L.out_start, L.out_count, L.out_cell,
+  TupIn a{cells.inner, cells.outer, cells.pair, cells.count, cells.cap, L.out_start, L.out_count, L.out_cell,
           L.has_inner, L.cap, roots, n_roots, T.cap, T.hits, T.cells, T.n, T.count_raw, T.kept, T.count,
           max_n, status};
   void* tok = timing_begin(s);
