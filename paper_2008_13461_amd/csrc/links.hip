@@ -288,7 +288,7 @@ __global__ void k_seg_scatter(const int32_t* __restrict__ cell_count, int32_t ce
 }
 
 // Per-wave LDS of k_link_hits.
-struct WaveLds {
+struct alignas(16) WaveLds {
   int32_t queue[2 * kWave];      // queued pairs: out-cell offset << 6 | in-cell lane
   int32_t h0b[kWave];            // inner hit of each in-cell lane, BPix1 flag in the top bit
   int32_t cnt[kWave];            // links found per in-cell lane
@@ -554,8 +554,11 @@ __global__ void __launch_bounds__(WAVES * kWave)
         }
       }
       if (n > 0 && n <= kLocal) {  // the links are sorted by k_link_emit
-        int32_t* sp = a.spill + static_cast<int64_t>(cell) * kRow;
-        for (int q = 0; q < n; ++q) sp[q] = L.found[lane * kLocal + q];
+        static_assert(kRow == 8 && kLocal == 8, "a record is two 16-byte vectors");
+        int4* sp = reinterpret_cast<int4*>(a.spill + static_cast<int64_t>(cell) * kRow);
+        const int4* fl = reinterpret_cast<const int4*>(L.found + lane * kLocal);
+        sp[0] = fl[0];  // places past n are never read
+        if (n > 4) sp[1] = fl[1];
       }
       wave_sync();
     }
