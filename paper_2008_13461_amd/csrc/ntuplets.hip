@@ -186,17 +186,10 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths) {
       if (coc == 0 || nh == k.max_hits) {
         if (COUNT && coc > 0) ++truncated;
         if (nh >= k.min_hits) {
-          if (!COUNT && row < a.cap) {
-            int32_t* H = a.hits + static_cast<int64_t>(row) * kMaxHits;
+          if (!COUNT && row < a.cap) {  // the cells of the path (its hits: k_row_hits)
             int32_t* C = a.cells + static_cast<int64_t>(row) * (kMaxHits - 1);
-            H[0] = a.cell_inner[stack[0]];
-            for (int d = 0; d <= depth; ++d) {
-              H[d + 1] = a.cell_outer[stack[d]];
-              C[d] = stack[d];
-            }
-            H[depth + 2] = a.cell_outer[child];
+            for (int d = 0; d <= depth; ++d) C[d] = stack[d];
             C[depth + 1] = child;
-            for (int d = depth + 3; d < kMaxHits; ++d) H[d] = -1;
             for (int d = depth + 2; d < kMaxHits - 1; ++d) C[d] = -1;
             a.n[row] = static_cast<uint8_t>(nh);
           }
@@ -214,6 +207,24 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths) {
   if (COUNT) {
     const uint32_t total = wave_status_add(a.status, PT_ST_TRUNCATED, truncated);
     if (total && __lane_id() == 0) status_flag(a.status, PT_FLAG_TRUNCATED);
+  }
+}
+
+// The hits of every row from its cells (inner hit of the first cell, then
+// the outer hit of each), one thread per row: the search itself stores only
+// the cells it holds in registers.
+__global__ void k_row_hits(TupIn a) {
+  const int rows = min(*a.count_raw, a.cap);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < rows; t += gridDim.x * blockDim.x) {
+    const int nh = a.n[t];
+    const int32_t* C = a.cells + static_cast<int64_t>(t) * (kMaxHits - 1);
+    int h[kMaxHits];
+    h[0] = a.cell_inner[C[0]];
+#pragma unroll
+    for (int d = 0; d < kMaxHits - 1; ++d) h[d + 1] = d < nh - 1 ? a.cell_outer[C[d]] : -1;
+    int32_t* H = a.hits + static_cast<int64_t>(t) * kMaxHits;
+#pragma unroll
+    for (int d = 0; d < kMaxHits; ++d) H[d] = h[d];
   }
 }
 
@@ -371,6 +382,8 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   PT_LAUNCH_CHECK();
   // rows found = paths[n_roots] (the scan's total)
   k_copy_total_rows<<<1, 1, 0, s>>>(paths, n_roots, T.count_raw);
+  PT_LAUNCH_CHECK();
+  k_row_hits<<<grid_for(T.cap, 256, 8192), 256, 0, s>>>(a);
   PT_LAUNCH_CHECK();
   tok = timing_begin(s);
   k_clear_maxn<<<grid_for(T.cap, 256, 8192), 256, 0, s>>>(a);
