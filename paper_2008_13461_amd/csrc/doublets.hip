@@ -249,22 +249,42 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
     if (nst >= 0) {
       if (lane < nst) s_chunk[wave][lane] = a.chunks[static_cast<int64_t>(j) * kMaskChunks + lane];
       wave_sync();
-      for (int t = 0; t < nst; ++t) {
-        const int4 d = s_chunk[wave][t];
-        const uint64_t m = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.y))) << 32) |
-                           static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.x));
-        const int o0 = __builtin_amdgcn_readfirstlane(d.z);
-        const int pe = __builtin_amdgcn_readfirstlane(d.w);
-        if (staged + kWave > kStage) flush();
-        if ((m >> lane) & 1u) {
-          const int o = o0 + lane;
-          const int at = staged + lane_prefix(m);
-          s_out[wave][at] = a.sorted_hit[o];
-          s_pair[wave][at] = static_cast<uint8_t>(pe);
-          s_R[wave][at] = a.sR[o];
-          s_Z[wave][at] = a.sZ[o];
+      // kGroupBatch groups at a time: the gathers of all of them are issued
+      // before any is staged
+      constexpr int kGroupBatch = 4;
+      for (int t0 = 0; t0 < nst; t0 += kGroupBatch) {
+        uint64_t m[kGroupBatch];
+        int pe[kGroupBatch], hit[kGroupBatch];
+        double Ro[kGroupBatch], Zo[kGroupBatch];
+#pragma unroll
+        for (int u = 0; u < kGroupBatch; ++u) {
+          m[u] = 0;
+          pe[u] = 0;
+          if (t0 + u < nst) {  // uniform
+            const int4 d = s_chunk[wave][t0 + u];
+            m[u] = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.y))) << 32) |
+                   static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.x));
+            pe[u] = __builtin_amdgcn_readfirstlane(d.w);
+            const int o = __builtin_amdgcn_readfirstlane(d.z) + lane;
+            if ((m[u] >> lane) & 1u) {
+              hit[u] = a.sorted_hit[o];
+              Ro[u] = a.sR[o];
+              Zo[u] = a.sZ[o];
+            }
+          }
         }
-        staged += __popcll(m);
+#pragma unroll
+        for (int u = 0; u < kGroupBatch; ++u) {
+          if (staged + kWave > kStage) flush();
+          if ((m[u] >> lane) & 1u) {
+            const int at = staged + lane_prefix(m[u]);
+            s_out[wave][at] = hit[u];
+            s_pair[wave][at] = static_cast<uint8_t>(pe[u]);
+            s_R[wave][at] = Ro[u];
+            s_Z[wave][at] = Zo[u];
+          }
+          staged += __popcll(m[u]);
+        }
       }
       flush();
       if (lane == 0) {

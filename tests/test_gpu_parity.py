@@ -157,3 +157,31 @@ def test_cut_set_without_zip():
     assert link_set(ci, co, prod["link_in"], prod["link_out"]) == \
         link_set(ref["cell_inner"], ref["cell_outer"], ref["link_in"], ref["link_out"])
     assert tuplet_set(prod["kept_hits"], prod["kept_n"]) == tuplet_set(ref["hits"], ref["n"])
+
+
+def test_cell_segments_match_their_definition():
+    """pt_cells.seg: each cell's R-Z segment (section 3.2's alignment test
+    reads it), bit for bit as pixeltrack.h defines it from the hits in
+    double: dr = R_outer - R_inner, dz = z_outer - z_inner, ls = dr dr + dz dz,
+    negated for an outer hit on an end-cap layer; blocks of PT_SEG_BLOCK."""
+    _need_gpu()
+    from paper_2008_13461_amd import _abi as A
+    from tests.gpu_helpers import run_chain
+    h = E.config2()
+    pipe, _ = run_chain(h, CFG)
+    n = min(int(pipe.cells.count.item()), pipe.cells.cap)
+    ci = pipe.cells.inner[:n].cpu().numpy()
+    co = pipe.cells.outer[:n].cpu().numpy()
+    seg = pipe.cells.seg.cpu().numpy()
+    B = A.PT_SEG_BLOCK
+    c = np.arange(n)
+    at = (c // B) * (3 * B) + c % B
+    x, y, z = (np.asarray(v, np.float64) for v in (h.x, h.y, h.z))
+    R = np.sqrt(x * x + y * y)
+    dr = R[co] - R[ci]
+    dz = z[co] - z[ci]
+    L = dr * dr + dz * dz
+    barrel = np.asarray(CFG["layer_barrel"], bool)[h.layer[co]]
+    assert np.array_equal(seg[at], dr)
+    assert np.array_equal(seg[at + B], dz)
+    assert np.array_equal(seg[at + 2 * B], np.where(barrel, L, -L))
