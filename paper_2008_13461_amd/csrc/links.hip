@@ -281,9 +281,26 @@ __global__ void k_seg_scatter(const int32_t* __restrict__ cell_count, int32_t ce
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kIndexChunk;
   if (base >= n) return;
   const int g_n = n_grp[blockIdx.x];
-  for (int g = threadIdx.x; g < g_n; g += blockDim.x) {
-    const int4 e = grp[base + g];
-    seg[seg_first[e.x] + e.w] = make_int2(e.y, e.z);
+  // kBatch groups per thread and round, their loads issued before any store
+  constexpr int kBatch = 8;
+  for (int g0 = 0; g0 < g_n; g0 += kBatch * blockDim.x) {
+    int4 e[kBatch];
+    int at[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int g = g0 + u * blockDim.x + threadIdx.x;
+      if (g < g_n) e[u] = grp[base + g];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int g = g0 + u * blockDim.x + threadIdx.x;
+      if (g < g_n) at[u] = seg_first[e[u].x] + e[u].w;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int g = g0 + u * blockDim.x + threadIdx.x;
+      if (g < g_n) seg[at[u]] = make_int2(e[u].y, e[u].z);
+    }
   }
 }
 
