@@ -20,13 +20,14 @@
 
 namespace pt {
 
-// The cut predicates of Table 1, as documented in pixeltrack.h.
-__device__ __forceinline__ bool doublet_pass(const DevCfg& k, int p, double Xi, double Yi, double Zi,
+// The cut predicates of Table 1, as documented in pixeltrack.h (tdphi is
+// tan_dphi of the pair, loaded once per pair by the caller).
+__device__ __forceinline__ bool doublet_pass(const DevCfg& k, double tdphi, double Xi, double Yi, double Zi,
                                              double Ri, double Xo, double Yo, double Zo, double Ro) {
   const double D = Xi * Xo + Yi * Yo;
   const double C = Xi * Yo - Yi * Xo;
   if (k.cut_mask & PT_CUT_PHIW) {
-    if (!(D > 0.0 && fabs(C) <= k.tan_dphi[p] * D)) return false;
+    if (!(D > 0.0 && fabs(C) <= tdphi * D)) return false;
   }
   if (k.cut_mask & PT_CUT_ZIP) {
     const double dR = Ro - Ri;
@@ -304,12 +305,13 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
       if (!(k.zlo[p] <= Zi && Zi <= k.zhi[p])) continue;
     }
     const int pe = p | (k.layer_barrel[k.pair_outer[p]] ? 0 : kEndcapBit);  // and the outer hits' class
+    const double tdphi = k.tan_dphi[p];
     int ra[2], rb[2];
     window_ranges(k, a.bin_start, p, e, b, ra[0], rb[0], ra[1], rb[1]);
     for (int r = 0; r < 2; ++r) {
       for (int o0 = ra[r]; o0 < rb[r]; o0 += kWave) {
         const int o = o0 + lane;
-        const bool pass = o < rb[r] && doublet_pass(k, p, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
+        const bool pass = o < rb[r] && doublet_pass(k, tdphi, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
         const uint64_t m = __ballot(pass);
         if (WRITE) {
           if (staged + kWave > kStage) flush();
