@@ -24,10 +24,11 @@
 //     pairs.  Each in-cell's link count is recorded, with its links when
 //     there are at most kLocal of them, and the hit's out-cells that gained
 //     an inner link are flagged (has_inner) in one coalesced run.
-//  5. a scan of the per-cell counts places every in-cell's links, in cell
-//     order (no shared counter: same-address atomics serialise),
-//     k_link_emit writes them and every cell's range, and k_links_overflow
-//     recomputes the few in-cells with more than kLocal.
+//  5. the counts are recorded straight into out_count; their scan into
+//     out_start places every in-cell's links, in cell order (no shared
+//     counter: same-address atomics serialise), k_link_emit writes the links
+//     of the cells with at most kLocal, and k_links_overflow recomputes the
+//     few in-cells with more.
 #include "pt_internal.h"
 
 #include <algorithm>
@@ -119,7 +120,7 @@ struct IndexArgs {
   int4* grp;           // per block: its groups (outer hit, first entry, cells, slot in the hit's list)
   int32_t* n_grp;      // per block: number of groups
   int32_t* n_seg;      // [n_hits + 1] groups ending on each hit
-  int32_t* lcnt;       // cleared here (link counts of the cells)
+  int32_t* out_count;  // cleared here (link counts of the cells)
   uint8_t* has_inner;
 };
 
@@ -268,7 +269,7 @@ __global__ void __launch_bounds__(kIndexBlock) k_cell_index(IndexArgs a) {
     if (loc >= m) break;
     const int c = static_cast<int>(base) + loc;
     a.has_inner[c] = 0;
-    a.lcnt[c] = 0;
+    a.out_count[c] = 0;
   }
 }
 
@@ -328,7 +329,7 @@ struct HitArgs {
   const int32_t* seg_first;  // [n_hits + 1] first segment of each hit's in-cell list
   const int2* seg;           // segments: (first entry, entries)
   const InCell* ent;         // index entries
-  int32_t* lcnt;      // [cells_cap + 1] links of each cell, zero on entry (scanned afterwards)
+  int32_t* out_count;  // [cells_cap] links of each cell, zero on entry (scanned afterwards)
   int32_t* spill;     // [cells_cap][kRow] per in-cell with links: its out-cells (at most kLocal)
   int32_t* ovf;       // in-cells with more than kLocal links
   int32_t* ovf_count;
@@ -564,7 +565,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
       // the spill row; positions come from a scan afterwards
       const int n = (lane < m) ? L.cnt[lane] : 0;
       if (n > 0) {
-        a.lcnt[cell] = n;
+        a.out_count[cell] = n;
         if (n > kLocal) {
           const int slot = atomicAdd(a.ovf_count, 1);
           a.ovf[slot] = cell;
@@ -591,13 +592,12 @@ __global__ void __launch_bounds__(WAVES * kWave)
 struct EmitArgs {
   const int32_t* cell_count;
   int32_t cells_cap;
-  const int32_t* lcnt;   // scanned: first link of each cell; lcnt[n] = total
-  const int32_t* spill;  // per in-cell with 1..kLocal links: its out-cells
+  const int32_t* out_start;  // first link of each cell (scanned counts)
+  const int32_t* out_count;  // links of each cell
+  const int32_t* spill;      // per in-cell with 1..kLocal links: its out-cells
   int32_t links_cap;
   int32_t* in_cell;
   int32_t* out_cell;
-  int32_t* out_start;
-  int32_t* out_count;
 };
 
 __device__ __forceinline__ void cmp_swap(int& x, int& y) {
@@ -612,12 +612,13 @@ __global__ void __launch_bounds__(256) k_link_emit(EmitArgs a) {
   const int n = min(*a.cell_count, a.cells_cap);
   const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  const int pos = a.lcnt[c];
-  const int cnt = a.lcnt[c + 1] - pos;
+  const int cnt = a.out_count[c];
+  // none, or more than a record holds (written by k_links_overflow)
+  if (cnt <= 0 || cnt > kLocal) return;
+  const int pos = a.out_start[c];
   static_assert(kRow == 8, "one record is two 16-byte vectors, one sorting network for eight keys");
-  const bool local = cnt > 0 && cnt <= kLocal;
   int f[kRow];
-  if (local) {
+  {
     // the sweep records links in the order their beam-spot tests finished:
     // sort them by out-cell (empty places sort last)
     const int4* sp = reinterpret_cast<const int4*>(a.spill + c * kRow);
@@ -634,9 +635,6 @@ __global__ void __launch_bounds__(256) k_link_emit(EmitArgs a) {
     cmp_swap(f[2], f[4]); cmp_swap(f[3], f[5]);
     cmp_swap(f[1], f[2]); cmp_swap(f[3], f[4]); cmp_swap(f[5], f[6]);
   }
-  a.out_start[c] = pos;
-  a.out_count[c] = cnt;
-  if (!local) return;  // none, or written by k_links_overflow
 #pragma unroll
   for (int q = 0; q < kLocal; ++q) {
     if (q >= cnt) break;
@@ -728,7 +726,6 @@ size_t ws_links(int n_hits, int cells_cap) {
   c.take<int32_t>(chunks);                  // groups per block
   c.take<int32_t>(static_cast<size_t>(n_hits) + 1);     // segments per hit -> first segment
   c.take<int2>(cells_cap);                  // segments
-  c.take<int32_t>(static_cast<size_t>(cells_cap) + 1);  // links per entry -> first link
   c.take<int32_t>(scan_tmp_elems(scan_n));
   c.take<int32_t>(static_cast<size_t>(cells_cap) * kRow);  // records of the cells with links
   c.take<int32_t>(cells_cap);               // overflow list
@@ -740,11 +737,6 @@ template <class T, int WAVES>
 static void launch_hits(const DevCfg& k, const HitArgs<T>& a, const double* seg, hipStream_t s) {
   const int64_t blocks = (static_cast<int64_t>(a.n_hits) + WAVES - 1) / WAVES;
   k_link_hits<T, WAVES><<<static_cast<unsigned>(blocks < 1 ? 1 : blocks), WAVES * kWave, 0, s>>>(k, a, seg);
-}
-
-__global__ void k_copy_links_total(const int32_t* __restrict__ lcnt, const int32_t* __restrict__ cell_count,
-                                   int32_t cells_cap, int32_t* __restrict__ links_count) {
-  *links_count = lcnt[min(*cell_count, cells_cap)];
 }
 
 template <class T>
@@ -760,7 +752,6 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   int32_t* n_grp = c.take<int32_t>(chunks);
   int32_t* seg_first = c.take<int32_t>(static_cast<size_t>(n) + 1);
   int2* seg = c.take<int2>(cells.cap);
-  int32_t* lcnt = c.take<int32_t>(static_cast<size_t>(cells.cap) + 1);
   int32_t* tmp = c.take<int32_t>(scan_tmp_elems(scan_n));
   int32_t* spill = c.take<int32_t>(static_cast<size_t>(cells.cap) * kRow);
   int32_t* ovf = c.take<int32_t>(cells.cap);
@@ -776,8 +767,8 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
     PT_LAUNCH_CHECK();
   }
   void* tok = timing_begin(s);
-  IndexArgs g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, ent, grp, n_grp, seg_first, lcnt,
-              L.has_inner};
+  IndexArgs g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, ent, grp, n_grp, seg_first,
+              L.out_count, L.has_inner};
   k_cell_index<<<static_cast<unsigned>(chunks), kIndexBlock, 0, s>>>(g);
   timing_end(tok, "cell_index", s);
   PT_LAUNCH_CHECK();
@@ -788,7 +779,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   PT_LAUNCH_CHECK();
 
   HitArgs<T> a{n, hx, cells.count, cells.cap, cells.outer, cells.inner_first, cells.inner_count, seg_first, seg,
-               ent, lcnt, spill, ovf, ovf_count, L.has_inner};
+               ent, L.out_count, spill, ovf, ovf_count, L.has_inner};
   tok = timing_begin(s);
   if (n > 0) {
     if (block == 128)
@@ -800,16 +791,16 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
     PT_LAUNCH_CHECK();
   }
   timing_end(tok, "links", s);
-  if (exclusive_scan_dev(lcnt, cells.cap, cells.count, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  // first link of each cell, and the number of links
+  if (exclusive_scan_to(L.out_count, L.out_start, cells.cap, cells.count, L.count, tmp, s) != hipSuccess)
+    return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  EmitArgs e{cells.count, cells.cap, lcnt, spill, L.cap, L.in_cell, L.out_cell, L.out_start, L.out_count};
+  EmitArgs e{cells.count, cells.cap, L.out_start, L.out_count, spill, L.cap, L.in_cell, L.out_cell};
   k_link_emit<<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + 255) / 256), 256, 0, s>>>(e);
   timing_end(tok, "link_emit", s);
   PT_LAUNCH_CHECK();
   k_links_overflow<T><<<1024, kOvfWaves * kWave, 0, s>>>(k, a, cells.inner, h.layer, cells.seg, L.out_start, L.cap,
                                                          L.in_cell, L.out_cell);
-  PT_LAUNCH_CHECK();
-  k_copy_links_total<<<1, 1, 0, s>>>(lcnt, cells.count, cells.cap, L.count);
   PT_LAUNCH_CHECK();
   k_finish_links<<<1, 1, 0, s>>>(L.count, L.cap, status);
   PT_LAUNCH_CHECK();

@@ -4,8 +4,9 @@
 //
 // No output position comes from a shared counter (same-address atomics
 // serialise on the device):
-//  - roots: each block counts the roots of a chunk of cells, a scan places
-//    the chunks, and the block writes its roots in cell order;
+//  - roots: each block counts the roots of a chunk of cells and keeps their
+//    flags as a bit mask, a scan places the chunks, and one wavefront per
+//    chunk writes its roots in cell order from the mask;
 //  - search: one thread per root walks the graph with an explicit stack of
 //    at most max_hits - 1 cells, first counting the paths it emits, then,
 //    after a scan over the roots, writing them at their final rows.  Rows
@@ -99,61 +100,72 @@ __device__ inline void root_flags(const DevCfg& k, const TupIn& a, int64_t base,
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_root_count(DevCfg k, TupIn a, int32_t* __restrict__ chunk_roots) {
-  __shared__ int32_t s_scan[kBlock / kWave + 1];
+// Counts the roots of a chunk and stores their flags as a bit mask: bit b of
+// word w is the flag of cell 64 w + b.
+constexpr int kRootWords = kRootChunk / kWave;  // mask words per chunk
+__global__ void __launch_bounds__(kBlock) k_root_count(DevCfg k, TupIn a, int32_t* __restrict__ chunk_roots,
+                                                       uint64_t* __restrict__ bits) {
+  constexpr int kWaves = kBlock / kWave;
+  static_assert(kRootItems * kWaves == kRootWords, "one mask word per (item, wavefront) group");
+  __shared__ uint64_t s_bits[kRootWords];
+  __shared__ int32_t s_cnt[kWaves];
   const int n = min(*a.cell_count, a.cells_cap);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
   if (base >= n) {
     if (threadIdx.x == 0) chunk_roots[blockIdx.x] = 0;
     return;
   }
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   bool f[kRootItems];
   root_flags(k, a, base, n, f);
   int cnt = 0;
 #pragma unroll
-  for (int i = 0; i < kRootItems; ++i) cnt += f[i] ? 1 : 0;
-  int total;
-  block_exclusive(cnt, s_scan, &total);
-  if (threadIdx.x == 0) chunk_roots[blockIdx.x] = total;
+  for (int i = 0; i < kRootItems; ++i) {
+    // item i of this wavefront covers cells base + 64 (i kWaves + wave) + lane
+    const uint64_t m = __ballot(f[i]);
+    cnt += __popcll(m);
+    if (lane == 0) s_bits[i * kWaves + wave] = m;
+  }
+  if (lane == 0) s_cnt[wave] = cnt;
+  __syncthreads();
+  if (threadIdx.x < kRootWords) bits[blockIdx.x * static_cast<int64_t>(kRootWords) + threadIdx.x] = s_bits[threadIdx.x];
+  if (threadIdx.x == 0) {
+    int total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) total += s_cnt[w];
+    chunk_roots[blockIdx.x] = total;
+  }
 }
 
-// Writes the chunk's roots in cell order: the position of a root is the
-// chunk's offset, plus the roots of the (item, wavefront) groups before its
-// own (cell order is item, then wavefront, then lane), plus its rank in the
-// wavefront's ballot.
-__global__ void __launch_bounds__(kBlock) k_root_write(DevCfg k, TupIn a, const int32_t* __restrict__ chunk_first) {
-  constexpr int kWaves = kBlock / kWave;
-  static_assert(kRootItems * kWaves == kWave, "one lane per (item, wavefront) group");
-  __shared__ int32_t s_grp[kRootItems * kWaves];
+// Writes the chunk's roots in cell order from its mask, one wavefront per
+// chunk: lane l holds word l; a root's position is the chunk's offset, plus
+// the roots of the words before its own, plus its rank in its word.
+__global__ void __launch_bounds__(kWave) k_root_write(TupIn a, const uint64_t* __restrict__ bits,
+                                                     const int32_t* __restrict__ chunk_first) {
+  static_assert(kRootWords == kWave, "one mask word per lane");
   const int n = min(*a.cell_count, a.cells_cap);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
   if (base >= n) return;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int at = chunk_first[blockIdx.x];
-  bool f[kRootItems];
-  root_flags(k, a, base, n, f);
-  int rank[kRootItems];
+  const int lane = threadIdx.x;
+  const uint64_t word = bits[blockIdx.x * static_cast<int64_t>(kRootWords) + lane];
+  const int c = __popcll(word);
+  int incl = c;
 #pragma unroll
-  for (int i = 0; i < kRootItems; ++i) {
-    const uint64_t m = __ballot(f[i]);
-    rank[i] = lane_prefix(m);
-    if (lane == 0) s_grp[i * kWaves + wave] = __popcll(m);
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += o;
   }
-  __syncthreads();
-  if (wave == 0) {
-    const int v = s_grp[lane];
-    int incl = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int o = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += o;
-    }
-    s_grp[lane] = incl - v;
+  const int first = chunk_first[blockIdx.x] + incl - c;  // this word's first root
+  uint64_t nz = __ballot(word != 0);
+  while (nz) {
+    const int w = __builtin_ctzll(nz);
+    nz &= nz - 1;
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(word), w);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(word >> 32), w);
+    const uint64_t m = (static_cast<uint64_t>(hi) << 32) | lo;
+    const int at = __builtin_amdgcn_readlane(first, w);
+    if ((m >> lane) & 1u) a.roots[at + lane_prefix(m)] = static_cast<int>(base + w * kWave + lane);
   }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < kRootItems; ++i)
-    if (f[i]) a.roots[at + s_grp[i * kWaves + wave] + rank[i]] = static_cast<int>(base + i * kBlock + threadIdx.x);
 }
 
 // Depth-first search from each root.  COUNT: paths[i] = rows root i emits
@@ -340,6 +352,7 @@ size_t ws_ntuplets(int cells_cap, int tuplets_cap) {
   const int64_t scan_n = std::max<int64_t>(chunks, cells_cap);
   Carver c(nullptr);
   c.take<int32_t>(cells_cap);      // roots
+  c.take<uint64_t>(chunks * kRootWords);  // root flags, one bit per cell
   c.take<int32_t>(chunks + 1);     // roots (then kept rows) per chunk -> chunk offsets (+ total)
   c.take<int32_t>(static_cast<size_t>(cells_cap) + 1);  // paths per root -> first row (+ total)
   c.take<int32_t>(cells_cap);      // max_n
@@ -354,6 +367,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   const int64_t scan_n = std::max<int64_t>(chunks_max, cells.cap);
   Carver c(ws.ptr);
   int32_t* roots = c.take<int32_t>(cells.cap);
+  uint64_t* root_bits = c.take<uint64_t>(chunks_max * kRootWords);
   int32_t* chunk_roots = c.take<int32_t>(chunks_max + 1);
   int32_t* paths = c.take<int32_t>(static_cast<size_t>(cells.cap) + 1);
   int32_t* max_n = c.take<int32_t>(cells.cap);
@@ -363,12 +377,12 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
           L.has_inner, L.cap, roots, n_roots, T.cap, T.hits, T.cells, T.n, T.count_raw, T.kept, T.count,
           max_n, status};
   void* tok = timing_begin(s);
-  k_root_count<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots);
+  k_root_count<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots, root_bits);
   timing_end(tok, "root_count", s);
   PT_LAUNCH_CHECK();
   if (exclusive_scan(chunk_roots, chunks, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  k_root_write<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots);
+  k_root_write<<<static_cast<unsigned>(chunks), kWave, 0, s>>>(a, root_bits, chunk_roots);
   timing_end(tok, "root_write", s);
   PT_LAUNCH_CHECK();
   tok = timing_begin(s);

@@ -80,6 +80,11 @@ hipError_t exclusive_scan(int32_t* data, int64_t n, int32_t* tmp, hipStream_t s)
 // The same over the first min(*n_dev, n) values, n_dev a device count; the
 // total goes to data[min(*n_dev, n)].
 hipError_t exclusive_scan_dev(int32_t* data, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s);
+// Out of place: dst[i] = src[0] + .. + src[i-1] over the first
+// min(*n_dev, n) values (all n when n_dev is null), the total to *total
+// (dst[that count] when total is null).  src may equal dst.
+hipError_t exclusive_scan_to(const int32_t* src, int32_t* dst, int64_t n, const int32_t* n_dev, int32_t* total,
+                             int32_t* tmp, hipStream_t s);
 
 // Fill helpers (graph-safe: kernels, not hipMemsetAsync).
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

@@ -76,10 +76,13 @@ __global__ void __launch_bounds__(kScanBlock) k_tile_sums(const int32_t* __restr
 // Scan of each tile plus its offset; each thread takes kScanItems
 // consecutive items, read and written as 16-byte vectors when VEC (data
 // 16-byte aligned) and the tile is full.
+// src may equal dst.  The total goes to *total_out, or to dst[n] when
+// total_out is null.
 template <bool VEC>
-__global__ void __launch_bounds__(kScanBlock) k_tile_scan(int32_t* __restrict__ data, int64_t n,
+__global__ void __launch_bounds__(kScanBlock) k_tile_scan(const int32_t* src, int32_t* dst, int64_t n,
                                                           const int32_t* __restrict__ n_dev,
-                                                          const int32_t* __restrict__ offsets) {
+                                                          const int32_t* __restrict__ offsets,
+                                                          int32_t* __restrict__ total_out) {
   __shared__ int32_t lds[kScanBlock / kWave + 1];
   n = items(n, n_dev);
   const int64_t first = static_cast<int64_t>(blockIdx.x) * kTile;
@@ -90,7 +93,7 @@ __global__ void __launch_bounds__(kScanBlock) k_tile_scan(int32_t* __restrict__ 
   const bool full = VEC && first + kTile <= n;
   int32_t v[kScanItems];
   if (full) {
-    const int4* p = reinterpret_cast<const int4*>(data + base);
+    const int4* p = reinterpret_cast<const int4*>(src + base);
 #pragma unroll
     for (int i = 0; i < kScanItems / 4; ++i) {
       const int4 q = p[i];
@@ -101,7 +104,7 @@ __global__ void __launch_bounds__(kScanBlock) k_tile_scan(int32_t* __restrict__ 
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) v[i] = (base + i < n) ? data[base + i] : 0;
+    for (int i = 0; i < kScanItems; ++i) v[i] = (base + i < n) ? src[base + i] : 0;
   }
   int32_t s = 0;
 #pragma unroll
@@ -116,16 +119,16 @@ __global__ void __launch_bounds__(kScanBlock) k_tile_scan(int32_t* __restrict__ 
     run += x;
   }
   if (full) {
-    int4* p = reinterpret_cast<int4*>(data + base);
+    int4* p = reinterpret_cast<int4*>(dst + base);
 #pragma unroll
     for (int i = 0; i < kScanItems / 4; ++i) p[i] = make_int4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
   } else {
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i)
-      if (base + i < n) data[base + i] = v[i];
+      if (base + i < n) dst[base + i] = v[i];
   }
   if (static_cast<int64_t>(blockIdx.x) == last_block && threadIdx.x == 0)
-    data[n] = total + (offsets ? offsets[blockIdx.x] : 0);
+    (total_out ? *total_out : dst[n]) = total + (offsets ? offsets[blockIdx.x] : 0);
 }
 
 template <class T>
@@ -147,28 +150,30 @@ size_t scan_tmp_elems(int64_t n) {
   return total + 1;
 }
 
-hipError_t exclusive_scan_dev(int32_t* data, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s) {
+hipError_t exclusive_scan_to(const int32_t* src, int32_t* dst, int64_t n, const int32_t* n_dev, int32_t* total,
+                             int32_t* tmp, hipStream_t s) {
   if (n <= 0) {
-    k_fill<int32_t><<<1, 1, 0, s>>>(data, 0, 1);
+    k_fill<int32_t><<<1, 1, 0, s>>>(total ? total : dst, 0, 1);
     return hipGetLastError();
   }
   const int64_t nb = (n + kTile - 1) / kTile;
-  const bool vec = reinterpret_cast<uintptr_t>(data) % 16 == 0;
-  if (nb == 1) {
-    if (vec)
-      k_tile_scan<true><<<1, kScanBlock, 0, s>>>(data, n, n_dev, nullptr);
-    else
-      k_tile_scan<false><<<1, kScanBlock, 0, s>>>(data, n, n_dev, nullptr);
-    return hipGetLastError();
+  const bool vec = reinterpret_cast<uintptr_t>(src) % 16 == 0 && reinterpret_cast<uintptr_t>(dst) % 16 == 0;
+  const int32_t* offsets = nullptr;
+  if (nb > 1) {
+    k_tile_sums<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(src, n, n_dev, tmp);
+    const hipError_t e = exclusive_scan_dev(tmp, nb, nullptr, tmp + nb + 1, s);
+    if (e != hipSuccess) return e;
+    offsets = tmp;
   }
-  k_tile_sums<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, n_dev, tmp);
-  hipError_t e = exclusive_scan_dev(tmp, nb, nullptr, tmp + nb + 1, s);
-  if (e != hipSuccess) return e;
   if (vec)
-    k_tile_scan<true><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, n_dev, tmp);
+    k_tile_scan<true><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(src, dst, n, n_dev, offsets, total);
   else
-    k_tile_scan<false><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(data, n, n_dev, tmp);
+    k_tile_scan<false><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(src, dst, n, n_dev, offsets, total);
   return hipGetLastError();
+}
+
+hipError_t exclusive_scan_dev(int32_t* data, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s) {
+  return exclusive_scan_to(data, data, n, n_dev, nullptr, tmp, s);
 }
 
 hipError_t exclusive_scan(int32_t* data, int64_t n, int32_t* tmp, hipStream_t s) {
