@@ -185,6 +185,7 @@ constexpr int kStage = 256;
 // kEndcapBit) in one 16-byte record.  A hit with more such groups is tested
 // again by the write pass.
 constexpr int kMaskChunks = 64;
+static_assert(kMaskChunks == kWave, "one kept group per lane");
 constexpr int kEndcapBit = 0x80;  // in a staged pair: the pair's outer layer is an end-cap
 static_assert(kMaxPairs <= kEndcapBit, "pair indices leave the top bit free");
 
@@ -194,11 +195,13 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   __shared__ uint8_t s_pair[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   __shared__ double s_R[WRITE ? WAVES : 1][WRITE ? kStage : 1];  // R and z of the staged outer hits
   __shared__ double s_Z[WRITE ? WAVES : 1][WRITE ? kStage : 1];
-  __shared__ int4 s_chunk[WAVES][kMaskChunks];
+  __shared__ int4 s_chunk[WRITE ? WAVES : 1][WRITE ? kMaskChunks : 1];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = __lane_id();
   const int j = xcd_block(blockIdx.x, gridDim.x) * WAVES + wave;
   if (j >= a.n_hits) return;
+  // count pass: the kept groups of the hit, record t on lane t
+  int4 rec = make_int4(0, 0, 0, 0);
   const int total = a.bin_start[-1];  // valid (sorted) hits
   if (j >= total) {
     if (!WRITE && lane == 0) {
@@ -325,9 +328,9 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
           staged += __popcll(m);
         } else {
           if (m) {
-            if (kept < kMaskChunks && lane == 0)
-              s_chunk[wave][kept] = make_int4(static_cast<int>(static_cast<uint32_t>(m)),
-                                              static_cast<int>(static_cast<uint32_t>(m >> 32)), o0, pe);
+            if (lane == kept)
+              rec = make_int4(static_cast<int>(static_cast<uint32_t>(m)), static_cast<int>(static_cast<uint32_t>(m >> 32)),
+                              o0, pe);
             ++kept;
           }
           pos += __popcll(m);
@@ -337,9 +340,8 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   }
   if (WRITE) flush();
   if (!WRITE) {  // the kept groups, after every load of the scan
-    wave_sync();
     const int nk = min(kept, kMaskChunks);
-    if (lane < nk) a.chunks[static_cast<int64_t>(j) * kMaskChunks + lane] = s_chunk[wave][lane];
+    if (lane < nk) a.chunks[static_cast<int64_t>(j) * kMaskChunks + lane] = rec;
   }
   if (lane == 0) {
     if (!WRITE) {
