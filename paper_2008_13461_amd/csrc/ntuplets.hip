@@ -78,6 +78,15 @@ __device__ inline int block_exclusive(int v, int32_t* s_scan, int* total) {
   return ex;
 }
 
+// A cell with outer links (a root without any makes a 2-hit path) whose
+// inner hit lies on a root layer, or on a layer whose cells are roots when
+// no link ends on them; the inner hit's layer is the inner layer of the
+// cell's pair.
+__device__ inline bool is_root(const DevCfg& k, int out_count, int pair, bool free_) {
+  const int L = k.pair_inner[pair];
+  return out_count > 0 && (((k.root_always_mask >> L) & 1u) || (((k.root_if_free_mask >> L) & 1u) && free_));
+}
+
 // Root flags of the kRootItems cells of this thread in a chunk (cell
 // base + i * kBlock + thread), with every load of the chunk issued up front.
 __device__ inline void root_flags(const DevCfg& k, const TupIn& a, int64_t base, int n, bool (&f)[kRootItems]) {
@@ -92,17 +101,25 @@ __device__ inline void root_flags(const DevCfg& k, const TupIn& a, int64_t base,
     free_[i] = !a.has_inner[cc];
   }
 #pragma unroll
-  for (int i = 0; i < kRootItems; ++i) {
-    // a root without outer links makes a 2-hit path; the inner hit's layer is
-    // the inner layer of the cell's pair
-    const int L = k.pair_inner[pr[i]];
-    f[i] = oc[i] > 0 && (((k.root_always_mask >> L) & 1u) || (((k.root_if_free_mask >> L) & 1u) && free_[i]));
-  }
+  for (int i = 0; i < kRootItems; ++i) f[i] = is_root(k, oc[i], pr[i], free_[i]);
+}
+
+// Spreads the low 16 bits of x to bits 0, 4, .., 60.
+__device__ inline uint64_t spread4(uint64_t x) {
+  x &= 0xFFFFull;
+  x = (x | (x << 24)) & 0x000000FF000000FFull;
+  x = (x | (x << 12)) & 0x000F000F000F000Full;
+  x = (x | (x << 6)) & 0x0303030303030303ull;
+  x = (x | (x << 3)) & 0x1111111111111111ull;
+  return x;
 }
 
 // Counts the roots of a chunk and stores their flags as a bit mask: bit b of
 // word w is the flag of cell 64 w + b.
+// VEC: out_count, cell_pair and has_inner 16- and 4-byte aligned; the full
+// chunks are then read four consecutive cells per thread and load.
 constexpr int kRootWords = kRootChunk / kWave;  // mask words per chunk
+template <bool VEC>
 __global__ void __launch_bounds__(kBlock) k_root_count(DevCfg k, TupIn a, int32_t* __restrict__ chunk_roots,
                                                        uint64_t* __restrict__ bits) {
   constexpr int kWaves = kBlock / kWave;
@@ -116,15 +133,47 @@ __global__ void __launch_bounds__(kBlock) k_root_count(DevCfg k, TupIn a, int32_
     return;
   }
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  bool f[kRootItems];
-  root_flags(k, a, base, n, f);
   int cnt = 0;
+  if (VEC && base + kRootChunk <= n) {
+    // group g: cells base + g 4 kBlock + 4 thread + q, q = 0..3
+    constexpr int kGroups = kRootItems / 4;
+    int4 oc[kGroups];
+    uint32_t pr[kGroups], hin[kGroups];
 #pragma unroll
-  for (int i = 0; i < kRootItems; ++i) {
-    // item i of this wavefront covers cells base + 64 (i kWaves + wave) + lane
-    const uint64_t m = __ballot(f[i]);
-    cnt += __popcll(m);
-    if (lane == 0) s_bits[i * kWaves + wave] = m;
+    for (int g = 0; g < kGroups; ++g) {
+      const int64_t c0 = base + g * 4 * kBlock + 4 * threadIdx.x;
+      oc[g] = *reinterpret_cast<const int4*>(a.out_count + c0);
+      pr[g] = *reinterpret_cast<const uint32_t*>(a.cell_pair + c0);
+      hin[g] = *reinterpret_cast<const uint32_t*>(a.has_inner + c0);
+    }
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+      const int o[4] = {oc[g].x, oc[g].y, oc[g].z, oc[g].w};
+      uint64_t m[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        m[q] = __ballot(is_root(k, o[q], (pr[g] >> (8 * q)) & 0xFF, ((hin[g] >> (8 * q)) & 0xFF) == 0));
+        cnt += __popcll(m[q]);
+      }
+      // the wavefront's 256 cells make mask words g 16 + 4 wave + w, word w
+      // from lanes 16 w .. 16 w + 15 (four cells each)
+      if (lane < 4) {
+        uint64_t word = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) word |= spread4(m[q] >> (16 * lane)) << q;
+        s_bits[g * 4 * kWaves + 4 * wave + lane] = word;
+      }
+    }
+  } else {
+    bool f[kRootItems];
+    root_flags(k, a, base, n, f);
+#pragma unroll
+    for (int i = 0; i < kRootItems; ++i) {
+      // item i of this wavefront covers cells base + 64 (i kWaves + wave) + lane
+      const uint64_t m = __ballot(f[i]);
+      cnt += __popcll(m);
+      if (lane == 0) s_bits[i * kWaves + wave] = m;
+    }
   }
   if (lane == 0) s_cnt[wave] = cnt;
   __syncthreads();
@@ -377,7 +426,12 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
           L.has_inner, L.cap, roots, n_roots, T.cap, T.hits, T.cells, T.n, T.count_raw, T.kept, T.count,
           max_n, status};
   void* tok = timing_begin(s);
-  k_root_count<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots, root_bits);
+  const bool vec = reinterpret_cast<uintptr_t>(L.out_count) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(cells.pair) % 4 == 0 && reinterpret_cast<uintptr_t>(L.has_inner) % 4 == 0;
+  if (vec)
+    k_root_count<true><<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots, root_bits);
+  else
+    k_root_count<false><<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots, root_bits);
   timing_end(tok, "root_count", s);
   PT_LAUNCH_CHECK();
   if (exclusive_scan(chunk_roots, chunks, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
