@@ -61,6 +61,18 @@ bool derive_config(const pt_config& c, DevCfg* d) {
   }
   d->theta2_barrel = c.ca_theta_barrel * c.ca_theta_barrel;
   d->theta2_endcap = c.ca_theta_endcap * c.ca_theta_endcap;
+  // The link search bins the out-cells of a hit by the direction of their R-Z
+  // segment into buckets at least as wide as the largest cut angle, with a
+  // margin far above the rounding of the keys: a pair that passes the R-Z
+  // test then lies in the same or a neighbouring bucket.
+  {
+    const double th = std::max(std::fabs(c.ca_theta_barrel), std::fabs(c.ca_theta_endcap));
+    d->rz_buckets = 0;
+    if (th < 0.5) {  // NaN fails
+      const double b = std::floor(2.0 / (std::asin(th) + 1e-4));
+      d->rz_buckets = b >= 4.0 ? static_cast<int32_t>(std::min(b, static_cast<double>(kRzBuckets))) : 0;
+    }
+  }
   d->rmax_bpix1 = c.ca_rmax_bpix1;
   d->rmax_other = c.ca_rmax_other;
   for (int l = 0; l < kLayers; ++l) d->layer_barrel[l] = c.layer_barrel[l] ? 1 : 0;

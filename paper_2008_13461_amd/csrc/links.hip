@@ -45,6 +45,7 @@ constexpr int kUnroll = 4;       // out-cells tested per step of the sweep
 constexpr int kSegment = 1 << 24;  // out-cells per queue segment (offsets fit beside the lane)
 constexpr int kSegWin = 64;        // in-cell segments of a hit handled per window (one per lane)
 constexpr int kHinBits = 2048;     // out-cells of a hit whose has_inner flag is gathered in LDS
+constexpr int kWinCap = 224;       // out-cells of the windowed search, with the copies at both ends
 
 // Index entry of an in-cell c' = (h0, h1): its cell index, and its inner hit
 // with the BPix1 flag in the top bit.  The triplet tests rebuild the R-Z
@@ -70,6 +71,27 @@ __device__ __forceinline__ bool endcap_outer(double Ls) {
   int hi = __double2hiint(Ls);
   asm volatile("" : "+s"(hi));
   return hi < 0;
+}
+
+// Direction key of an R-Z segment, in [-1, 1]: the diamond angle
+// dz / (|dr| + |dz|) of the segment turned to dr >= 0 (the R-Z test does not
+// depend on the orientation).  As a function of the polar angle of the
+// undirected line its slope is at most 1, and its ends -1 and +1 are the
+// same direction, so two segments at an angle d (mod pi) have keys at most d
+// apart on a circle of length 2.  NaN for a zero-length or non-finite
+// segment.
+__device__ __forceinline__ float rz_key(double dr, double dz) {
+  const float r = static_cast<float>(dr < 0.0 ? -dr : dr);
+  const float z = static_cast<float>(dr < 0.0 ? -dz : dz);
+  return z / (r + fabsf(z));
+}
+
+// Bucket of a key: B buckets of width 2 / B over [-1, 1], the last one
+// closed.  Keys at most one bucket width apart (on the circle) fall in the
+// same or neighbouring buckets (B - 1 and 0 are neighbours).
+__device__ __forceinline__ int rz_bucket(float key, int B) {
+  const int b = static_cast<int>((key + 1.0f) * (0.5f * static_cast<float>(B)));
+  return min(max(b, 0), B - 1);
 }
 
 // The value of v in lane i (i wave-uniform).
@@ -306,16 +328,29 @@ __global__ void k_seg_scatter(const int32_t* __restrict__ cell_count, int32_t ce
 }
 
 // Per-wave LDS of k_link_hits.
+template <class T>
 struct alignas(16) WaveLds {
   int32_t queue[2 * kWave];      // queued pairs: out-cell offset << 6 | in-cell lane
-  int32_t h0b[kWave];            // inner hit of each in-cell lane, BPix1 flag in the top bit
   int32_t cnt[kWave];            // links found per in-cell lane
   int32_t found[kWave * kLocal]; // their out-cells
   int32_t sfirst[kSegWin];       // a window of the hit's segments: first entry ...
   int32_t spre[kSegWin + 1];     // ... and the in-cells before each (exclusive prefix)
   int32_t segat[kWave];          // segment starting at each in-cell of a pass, or -1
   uint32_t hin[kHinBits / 32];   // out-cells of the hit with an inner link (first kHinBits)
+  // windowed search: the hit's out-cells by bucket (segment, offset | end-cap
+  // bit << 15), bucket B - 1 copied in front and bucket 0 behind, and where
+  // each bucket starts
+  double wdr[kWinCap];
+  double wdz[kWinCap];
+  uint16_t wj[kWinCap];
+  uint16_t bst[kRzBuckets + 1];
+  // and the outer hits' x and y, by out-cell offset (values of the input
+  // type, which the hit table holds exactly)
+  T wx2[kWinCap];
+  T wy2[kWinCap];
 };
+static_assert(kRzBuckets <= 2 * kWave, "the bucket counts use the queue, two buckets per lane");
+static_assert(kWinCap <= kWave * kLocal && kWinCap <= 0x8000, "staging uses the found array; offsets fit 15 bits");
 
 template <class T>
 struct HitArgs {
@@ -337,21 +372,31 @@ struct HitArgs {
 };
 
 // Beam-spot test of the first nq queued pairs, one per lane; cb is the first
-// out-cell of the segment the queued offsets refer to.
+// out-cell of the segment the queued offsets refer to, hb its offset in the
+// hit's out-cells (for the has_inner bits).  The in-cells' inner hits (X0,
+// Y0, BPix1 flag) are read from the lanes that hold them; all lanes call it.
 template <class T>
-// hb is the offset of cb in the hit's out-cells (for the has_inner bits).
-__device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a, WaveLds& L, int nq, int cb,
-                                           int hb, double X1, double Y1) {
+__device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L, int nq, int cb,
+                                           int hb, double X1, double Y1, double X0l, double Y0l, int bpix1l,
+                                           bool staged) {
   const int lane = __lane_id();
+  const int e = lane < nq ? L.queue[lane] : 0;
+  const int j = e >> 6;
+  const int li = e & (kWave - 1);
+  const double X0 = __shfl(X0l, li, kWave), Y0 = __shfl(Y0l, li, kWave);
+  const int bpix1 = __shfl(bpix1l, li, kWave);
   if (lane < nq) {
-    const int e = L.queue[lane];
-    const int j = e >> 6;
-    const int li = e & (kWave - 1);
-    const int h0b = L.h0b[li];
-    const double4 P0 = a.hx[h0b & ~kBpix1Bit];
-    const double4 P2 = a.hx[a.outer[cb + j]];
-    const double rmax = (h0b & kBpix1Bit) ? k.rmax_bpix1 : k.rmax_other;
-    if (beam_pass(P0.x, P0.y, X1, Y1, P2.x, P2.y, rmax)) {
+    double X2, Y2;
+    if (staged) {  // the windowed search staged the outer hits
+      X2 = static_cast<double>(L.wx2[j]);
+      Y2 = static_cast<double>(L.wy2[j]);
+    } else {
+      const double4 P2 = a.hx[a.outer[cb + j]];
+      X2 = P2.x;
+      Y2 = P2.y;
+    }
+    const double rmax = bpix1 ? k.rmax_bpix1 : k.rmax_other;
+    if (beam_pass(X0, Y0, X1, Y1, X2, Y2, rmax)) {
       const int slot = atomicAdd(&L.cnt[li], 1);
       if (slot < kLocal) L.found[li * kLocal + slot] = cb + j;
       const int bit = hb + j;
@@ -363,14 +408,77 @@ __device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a,
   }
 }
 
+// Stages the hit's nb out-cells (from cb on) for the windowed search, sorted
+// by bucket into wdr / wdz / wj, and the bucket starts into bst.  Returns
+// false (wave-uniform) when an out-cell has no key or the list with its
+// copies does not fit; the hit is then swept pair by pair.
+template <class T>
+__device__ bool stage_window(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L, const double* __restrict__ seg,
+                             int cb, int nb) {
+  const int lane = __lane_id();
+  const int B = k.rz_buckets;
+  int32_t* hist = L.queue;  // bucket counts (the queue is empty between passes)
+  int32_t* tmp = L.found;   // per out-cell: bucket | rank in the bucket << 8
+  for (int b = lane; b < B; b += kWave) hist[b] = 0;
+  wave_sync();
+  bool bad = false;
+  for (int j = lane; j < nb; j += kWave) {
+    const double* g = seg + seg_at(cb + j);
+    const double4 P2 = a.hx[a.outer[cb + j]];
+    const float key = rz_key(g[0], g[PT_SEG_BLOCK]);
+    bad |= !(key == key);
+    const int b = key == key ? rz_bucket(key, B) : 0;
+    tmp[j] = b | (atomicAdd(&hist[b], 1) << 8);
+    L.wx2[j] = static_cast<T>(P2.x);
+    L.wy2[j] = static_cast<T>(P2.y);
+  }
+  if (__ballot(bad)) return false;
+  wave_sync();
+  // bucket starts: exclusive scan of the counts, two buckets per lane
+  const int h0 = 2 * lane < B ? hist[2 * lane] : 0;
+  const int h1 = 2 * lane + 1 < B ? hist[2 * lane + 1] : 0;
+  int incl = h0 + h1;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += o;
+  }
+  const int front = hist[B - 1], back = hist[0];  // copies before and after the list
+  if (front + nb + back > kWinCap) return false;   // uniform
+  const int ex = incl - h0 - h1;
+  if (2 * lane < B) L.bst[2 * lane] = static_cast<uint16_t>(front + ex);
+  if (2 * lane + 1 < B) L.bst[2 * lane + 1] = static_cast<uint16_t>(front + ex + h0);
+  if (lane == 0) L.bst[B] = static_cast<uint16_t>(front + nb);
+  wave_sync();
+  for (int j = lane; j < nb; j += kWave) {
+    const double* g = seg + seg_at(cb + j);
+    const double dr = g[0], dz = g[PT_SEG_BLOCK];
+    const int v = tmp[j];
+    const int b = v & 0xFF, r = v >> 8;
+    const uint16_t jv = static_cast<uint16_t>(j | (__builtin_signbit(g[2 * PT_SEG_BLOCK]) ? 0x8000 : 0));
+    const int at = L.bst[b] + r;
+    L.wdr[at] = dr;
+    L.wdz[at] = dz;
+    L.wj[at] = jv;
+    if (b == B - 1 || b == 0) {  // its copy at the other end
+      const int c = b == B - 1 ? r : front + nb + r;
+      L.wdr[c] = dr;
+      L.wdz[c] = dz;
+      L.wj[c] = jv;
+    }
+  }
+  wave_sync();
+  return true;
+}
+
 // One wavefront per middle hit; WAVES independent wavefronts per block.
 template <class T, int WAVES>
 __global__ void __launch_bounds__(WAVES * kWave)
     k_link_hits(DevCfg k, HitArgs<T> a, const double* __restrict__ seg) {
-  __shared__ WaveLds lds[WAVES];
+  __shared__ WaveLds<T> lds[WAVES];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = __lane_id();
-  WaveLds& L = lds[wave];
+  WaveLds<T>& L = lds[wave];
   const int h1 = blockIdx.x * WAVES + wave;
   if (h1 >= a.n_hits) return;
   const int sb = a.seg_first[h1];
@@ -385,6 +493,8 @@ __global__ void __launch_bounds__(WAVES * kWave)
   const double th2b = k.theta2_barrel, th2e = k.theta2_endcap;
   const int nh = min(nb, kHinBits);  // out-cells whose has_inner bit is kept in LDS
   for (int w = lane; w < (nh + 31) / 32; w += kWave) L.hin[w] = 0;
+  // the out-cells by direction bucket, when the search can be windowed
+  const bool win = k.rz_buckets > 0 && nb <= kWinCap && stage_window(k, a, L, seg, cb, nb);
 
   for (int sw = sb; sw < se; sw += kSegWin) {
     // a window of the hit's segments and the prefix of their sizes
@@ -411,6 +521,8 @@ __global__ void __launch_bounds__(WAVES * kWave)
       const int m = min(kWave, aw - base);
       // in-cell of this lane (NaN makes the R-Z test fail for idle lanes)
       double ar = __builtin_nan(""), az = __builtin_nan(""), La = __builtin_nan("");
+      double X0 = 0.0, Y0 = 0.0;  // its inner hit, for the beam-spot test
+      int bpix1 = 0;
       int cell = -1;
       int r = -1;  // its index entry
       // segment of each lane's in-cell: every segment overlapping the pass
@@ -437,7 +549,9 @@ __global__ void __launch_bounds__(WAVES * kWave)
         az = P1.z - P0.z;
         La = ar * ar + az * az;
         cell = e.cell;
-        L.h0b[lane] = e.h0b;
+        X0 = P0.x;
+        Y0 = P0.y;
+        bpix1 = (e.h0b & kBpix1Bit) ? 1 : 0;
       }
       L.cnt[lane] = 0;
       // A partial pass with few in-cells sweeps the other way round: lanes over
@@ -459,7 +573,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
           qn += __popcll(mk);
           if (qn >= kWave) {
             wave_sync();
-            beam_batch(k, a, L, kWave, cs, jb, X1, Y1);
+            beam_batch(k, a, L, kWave, cs, jb, X1, Y1, X0, Y0, bpix1, win);
             qn -= kWave;
             const int t = (lane < qn) ? L.queue[kWave + lane] : 0;
             wave_sync();
@@ -467,6 +581,61 @@ __global__ void __launch_bounds__(WAVES * kWave)
             wave_sync();
           }
         };
+        if (win) {
+          // Windowed: each in-cell meets only the out-cells of its own and the
+          // neighbouring buckets, a contiguous range of the staged list.  The
+          // ranges of all lanes are laid end to end and dealt out 64 pairs at
+          // a time, pair f going to the last lane whose range starts at or
+          // before f.
+          static_assert(kWinCap < kSegment, "the staged list is one segment");
+          const int B = k.rz_buckets;
+          int wstart = 0, wlen = 0;
+          if (lane < m) {
+            const float key = rz_key(ar, az);
+            if (key == key) {
+              const int b = rz_bucket(key, B);
+              wstart = b == 0 ? 0 : L.bst[b - 1];
+              const int wend = b == B - 1 ? L.bst[B] + (L.bst[1] - L.bst[0]) : L.bst[b + 2];
+              wlen = wend - wstart;
+            } else {  // no key: every out-cell once
+              wstart = L.bst[0];
+              wlen = nb;
+            }
+          }
+          int incl = wlen;
+#pragma unroll
+          for (int d = 1; d < kWave; d <<= 1) {
+            const int o = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += o;
+          }
+          const int P = incl - wlen;  // first pair of this lane's range
+          const int npairs = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
+          for (int f0 = 0; f0 < npairs; f0 += kWave) {
+            const int f = f0 + lane;
+            int o = 0;  // the largest lane with P <= f (P of lane 0 is 0)
+#pragma unroll
+            for (int st = kWave / 2; st > 0; st >>= 1)
+              if (__shfl(P, o + st, kWave) <= f) o += st;
+            const double oar = __shfl(ar, o, kWave), oaz = __shfl(az, o, kWave), oLa = __shfl(La, o, kWave);
+            const int at = __shfl(wstart, o, kWave) + (f - __shfl(P, o, kWave));
+            bool pass = false;
+            int j = 0;
+            if (f < npairs) {
+              const double br = L.wdr[at], bz = L.wdz[at];
+              const int jv = L.wj[at];
+              pass = rz_pass(oar, oaz, oLa, br, bz, br * br + bz * bz, (jv & 0x8000) ? th2e : th2b);
+              j = jv & 0x7FFF;
+            }
+            const uint64_t mk = __ballot(pass);
+            if (mk) append(j, o, pass, mk);
+          }
+          if (qn > 0) {
+            wave_sync();
+            beam_batch(k, a, L, qn, cs, jb, X1, Y1, X0, Y0, bpix1, win);
+          }
+          wave_sync();
+          continue;
+        }
         if (transposed) {
           for (int ob = 0; ob < ns; ob += kWave) {
             const int j = ob + lane;
@@ -489,7 +658,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
           }
           if (qn > 0) {
             wave_sync();
-            beam_batch(k, a, L, qn, cs, jb, X1, Y1);
+            beam_batch(k, a, L, qn, cs, jb, X1, Y1, X0, Y0, bpix1, win);
           }
           wave_sync();
           continue;
@@ -556,7 +725,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
         for (; j < ns; ++j) single(j);
         if (qn > 0) {
           wave_sync();
-          beam_batch(k, a, L, qn, cs, jb, X1, Y1);
+          beam_batch(k, a, L, qn, cs, jb, X1, Y1, X0, Y0, bpix1, win);
         }
         wave_sync();
       }
@@ -608,41 +777,76 @@ __device__ __forceinline__ void cmp_swap(int& x, int& y) {
 
 // One thread per cell; its loads (range, record) come before its stores, so
 // no load waits for a store's acknowledgement.
-__global__ void __launch_bounds__(256) k_link_emit(EmitArgs a) {
-  const int n = min(*a.cell_count, a.cells_cap);
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const int cnt = a.out_count[c];
-  // none, or more than a record holds (written by k_links_overflow)
-  if (cnt <= 0 || cnt > kLocal) return;
-  const int pos = a.out_start[c];
+// Writes the links of cell c (cnt of them, 1..kLocal, from link pos on): its
+// record (q0, and q1 when cnt > 4) sorted by out-cell.
+__device__ __forceinline__ void emit_cell(const EmitArgs& a, int c, int cnt, int pos, int4 q0, int4 q1) {
   static_assert(kRow == 8, "one record is two 16-byte vectors, one sorting network for eight keys");
+  // the sweep records links in the order their beam-spot tests finished:
+  // sort them by out-cell (empty places sort last)
   int f[kRow];
-  {
-    // the sweep records links in the order their beam-spot tests finished:
-    // sort them by out-cell (empty places sort last)
-    const int4* sp = reinterpret_cast<const int4*>(a.spill + c * kRow);
-    const int4 q0 = sp[0];
-    const int4 q1 = cnt > 4 ? sp[1] : make_int4(0, 0, 0, 0);
-    const int v[kRow] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+  const int v[kRow] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
 #pragma unroll
-    for (int q = 0; q < kRow; ++q) f[q] = q < cnt ? v[q] : INT_MAX;
-    // Batcher's odd-even merge sort of eight keys (19 compare-exchanges)
-    cmp_swap(f[0], f[1]); cmp_swap(f[2], f[3]); cmp_swap(f[4], f[5]); cmp_swap(f[6], f[7]);
-    cmp_swap(f[0], f[2]); cmp_swap(f[1], f[3]); cmp_swap(f[4], f[6]); cmp_swap(f[5], f[7]);
-    cmp_swap(f[1], f[2]); cmp_swap(f[5], f[6]);
-    cmp_swap(f[0], f[4]); cmp_swap(f[1], f[5]); cmp_swap(f[2], f[6]); cmp_swap(f[3], f[7]);
-    cmp_swap(f[2], f[4]); cmp_swap(f[3], f[5]);
-    cmp_swap(f[1], f[2]); cmp_swap(f[3], f[4]); cmp_swap(f[5], f[6]);
-  }
+  for (int q = 0; q < kRow; ++q) f[q] = q < cnt ? v[q] : INT_MAX;
+  // Batcher's odd-even merge sort of eight keys (19 compare-exchanges)
+  cmp_swap(f[0], f[1]); cmp_swap(f[2], f[3]); cmp_swap(f[4], f[5]); cmp_swap(f[6], f[7]);
+  cmp_swap(f[0], f[2]); cmp_swap(f[1], f[3]); cmp_swap(f[4], f[6]); cmp_swap(f[5], f[7]);
+  cmp_swap(f[1], f[2]); cmp_swap(f[5], f[6]);
+  cmp_swap(f[0], f[4]); cmp_swap(f[1], f[5]); cmp_swap(f[2], f[6]); cmp_swap(f[3], f[7]);
+  cmp_swap(f[2], f[4]); cmp_swap(f[3], f[5]);
+  cmp_swap(f[1], f[2]); cmp_swap(f[3], f[4]); cmp_swap(f[5], f[6]);
 #pragma unroll
   for (int q = 0; q < kLocal; ++q) {
     if (q >= cnt) break;
     if (pos + q < a.links_cap) {
-      a.in_cell[pos + q] = static_cast<int>(c);
+      a.in_cell[pos + q] = c;
       a.out_cell[pos + q] = f[q];
     }
   }
+}
+
+// Cells with none or more than kLocal links are skipped (the latter are
+// written by k_links_overflow).  VEC: out_count and out_start 16-byte
+// aligned; each thread then takes four consecutive cells, their counts and
+// first links read as one vector each.
+constexpr int kEmitBlock = 256;
+template <bool VEC>
+__global__ void __launch_bounds__(kEmitBlock) k_link_emit(EmitArgs a) {
+  constexpr int kCells = VEC ? 4 : 1;  // per thread
+  const int n = min(*a.cell_count, a.cells_cap);
+  const int64_t c0 = (static_cast<int64_t>(blockIdx.x) * kEmitBlock + threadIdx.x) * kCells;
+  if (c0 >= n) return;
+  int cnt[kCells], pos[kCells];
+  if (VEC && c0 + kCells <= n) {
+    const int4 k4 = *reinterpret_cast<const int4*>(a.out_count + c0);
+    const int4 p4 = *reinterpret_cast<const int4*>(a.out_start + c0);
+    const int kk[4] = {k4.x, k4.y, k4.z, k4.w}, pp[4] = {p4.x, p4.y, p4.z, p4.w};
+#pragma unroll
+    for (int q = 0; q < kCells; ++q) {
+      cnt[q] = kk[q];
+      pos[q] = pp[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kCells; ++q) {
+      cnt[q] = c0 + q < n ? a.out_count[c0 + q] : 0;
+      pos[q] = 0;
+    }
+  }
+  // every record load before any store
+  int4 r0[kCells], r1[kCells];
+#pragma unroll
+  for (int q = 0; q < kCells; ++q) {
+    r0[q] = r1[q] = make_int4(0, 0, 0, 0);
+    if (cnt[q] > 0 && cnt[q] <= kLocal) {
+      const int4* sp = reinterpret_cast<const int4*>(a.spill + (c0 + q) * kRow);
+      r0[q] = sp[0];
+      if (cnt[q] > 4) r1[q] = sp[1];
+      if (!VEC || c0 + kCells > n) pos[q] = a.out_start[c0 + q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kCells; ++q)
+    if (cnt[q] > 0 && cnt[q] <= kLocal) emit_cell(a, static_cast<int>(c0 + q), cnt[q], pos[q], r0[q], r1[q]);
 }
 
 // In-cells with more than kLocal links: one wavefront each recomputes its
@@ -796,7 +1000,12 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
     return PT_ERR_DEVICE;
   tok = timing_begin(s);
   EmitArgs e{cells.count, cells.cap, L.out_start, L.out_count, spill, L.cap, L.in_cell, L.out_cell};
-  k_link_emit<<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + 255) / 256), 256, 0, s>>>(e);
+  if (reinterpret_cast<uintptr_t>(L.out_count) % 16 == 0 && reinterpret_cast<uintptr_t>(L.out_start) % 16 == 0)
+    k_link_emit<true><<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + 4 * kEmitBlock - 1) / (4 * kEmitBlock)),
+                        kEmitBlock, 0, s>>>(e);
+  else
+    k_link_emit<false><<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + kEmitBlock - 1) / kEmitBlock),
+                         kEmitBlock, 0, s>>>(e);
   timing_end(tok, "link_emit", s);
   PT_LAUNCH_CHECK();
   k_links_overflow<T><<<1024, kOvfWaves * kWave, 0, s>>>(k, a, cells.inner, h.layer, cells.seg, L.out_start, L.cap,

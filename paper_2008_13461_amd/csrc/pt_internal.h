@@ -15,6 +15,7 @@ constexpr int kLayers = PT_N_LAYERS;
 constexpr int kMaxPairs = PT_MAX_PAIRS;
 constexpr int kMaxHits = PT_MAX_HITS;
 constexpr int kMaxPairsPerLayer = 8;
+constexpr int kRzBuckets = 128;  // direction buckets of the windowed R-Z search, at most
 
 // Constants the kernels use, derived once on the host from pt_config
 // (see the expressions documented in pixeltrack.h).
@@ -36,6 +37,7 @@ struct DevCfg {
   int32_t n_inner_pairs[kLayers];
   // links
   double theta2_barrel, theta2_endcap;
+  int32_t rz_buckets;  // direction buckets of the windowed R-Z search (0: every pair is tested)
   double rmax_bpix1, rmax_other;
   uint8_t layer_barrel[kLayers];
   // n-tuplets

@@ -287,3 +287,76 @@ def test_hits_with_in_cells_from_many_blocks():
     assert link_set(got["cell_inner"], got["cell_outer"], got["link_in"], got["link_out"]) == \
         link_set(ref["cell_inner"], ref["cell_outer"], ref["link_in"], ref["link_out"])
     _link_layout_ok(pipe)
+
+
+def _doublets_and_links(h, cfg_d, cells_cap, links_cap):
+    """pt_build_doublets and pt_link_cells alone; (cells inner, outer, links in, out) on the host."""
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    cfg = A.make_config(cfg_d)
+    hits = api.Hits.from_host(h)
+    cells = api.Cells.empty(cells_cap, h.n_hits)
+    links = api.Links.empty(links_cap, cells_cap)
+    status = api.new_status()
+    ws = api.new_workspace(api.workspace_size(cfg, h.n_hits, h.n_events, cells_cap, links_cap, 1024))
+    api.build_doublets(hits, cfg, cells, status, ws)
+    api.link_cells(hits, cfg, cells, links, status, ws)
+    torch.cuda.synchronize()
+    assert int(status[0].item()) == 0  # no overflow
+    ci, co, _ = (t.cpu().numpy() for t in cells.valid())
+    li, lo = (t.cpu().numpy() for t in links.valid())
+    return ci, co, li, lo
+
+
+def _star_event(n_in, n_out, seed=3):
+    """One BPix2 hit with n_in inner hits on BPix1 and n_out outer hits on
+    BPix3, all at one azimuth (every triplet passes the beam-spot test), the
+    R-Z directions of the segments spread over the whole half turn, with many
+    close to the beam axis, where the direction keys wrap round."""
+    rng = np.random.default_rng(seed)
+    half = np.pi / 2
+    a_in = np.concatenate([rng.uniform(-half + 2e-3, half - 2e-3, n_in - 8),
+                           half - rng.uniform(1e-4, 3e-2, 4), -half + rng.uniform(1e-4, 3e-2, 4)])
+    a_out = np.concatenate([rng.uniform(-half + 2e-3, half - 2e-3, n_out - 8),
+                            half - rng.uniform(1e-4, 3e-2, 4), -half + rng.uniform(1e-4, 3e-2, 4)])
+    R0, R1, R2 = C.BARREL_R[:3]
+    R = np.concatenate([np.full(n_in, R0), [R1], np.full(n_out, R2)])
+    z = np.concatenate([-(R1 - R0) * np.tan(a_in), [0.0], (R2 - R1) * np.tan(a_out)])
+    phi = 0.3 + rng.uniform(-1e-7, 1e-7, len(R))
+    layer = np.concatenate([np.zeros(n_in), [1], np.full(n_out, 2)]).astype(np.uint8)
+    n = len(R)
+    return E.Hits((R * np.cos(phi)).astype(np.float32), (R * np.sin(phi)).astype(np.float32), z.astype(np.float32),
+                  layer, np.zeros(n, np.int16), np.arange(n, dtype=np.int32), np.array([0, n], np.int32))
+
+
+@pytest.mark.parametrize("n_out", [120, 300])
+def test_links_of_segments_in_every_direction(n_out):
+    """The link search bins a hit's out-cells by R-Z direction and tests each
+    in-cell against its own and the neighbouring bins only (up to 256
+    out-cells; beyond, every pair): with directions over the whole half turn,
+    near-vertical ones included, the links equal the oracle's."""
+    _need_gpu()
+    from tests.helpers import link_set
+    cfg_d = C.default_config(cut_mask=C.CUT_PHIW)
+    h = _star_event(150, n_out)
+    ci, co, li, lo = _doublets_and_links(h, cfg_d, 1 << 16, 1 << 16)
+    rci, rco, _ = O.doublets(cfg_d, h.x, h.y, h.z, h.layer)
+    rli, rlo = O.links(cfg_d, h.x, h.y, h.z, h.layer, rci, rco)
+    assert doublet_set(ci, co) == doublet_set(rci, rco)
+    ref = link_set(rci, rco, rli, rlo)
+    assert len(ref) > 100
+    assert link_set(ci, co, li, lo) == ref
+
+
+@pytest.mark.parametrize("theta", [0.05, 0.3, 0.6])
+def test_links_with_wide_theta_cuts(theta):
+    """Wider R-Z cuts make fewer, wider direction bins (none from 0.5 on,
+    where every pair is tested): the links equal the oracle's."""
+    _need_gpu()
+    from tests.helpers import link_set
+    cfg_d = C.default_config(ca_theta_barrel=theta, ca_theta_endcap=theta)
+    h = E.config2()
+    rci, rco, _ = O.doublets(cfg_d, h.x, h.y, h.z, h.layer)
+    rli, rlo = O.links(cfg_d, h.x, h.y, h.z, h.layer, rci, rco)
+    ci, co, li, lo = _doublets_and_links(h, cfg_d, 2 * len(rci) + 1024, 2 * len(rli) + 1024)
+    assert link_set(ci, co, li, lo) == link_set(rci, rco, rli, rlo)
