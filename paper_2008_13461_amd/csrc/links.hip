@@ -422,15 +422,28 @@ __device__ bool stage_window(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L
   for (int b = lane; b < B; b += kWave) hist[b] = 0;
   wave_sync();
   bool bad = false;
-  for (int j = lane; j < nb; j += kWave) {
-    const double* g = seg + seg_at(cb + j);
-    const double4 P2 = a.hx[a.outer[cb + j]];
-    const float key = rz_key(g[0], g[PT_SEG_BLOCK]);
-    bad |= !(key == key);
-    const int b = key == key ? rz_bucket(key, B) : 0;
-    tmp[j] = b | (atomicAdd(&hist[b], 1) << 8);
-    L.wx2[j] = static_cast<T>(P2.x);
-    L.wy2[j] = static_cast<T>(P2.y);
+  // out-cell j = r kWave + lane; its segment stays in registers
+  constexpr int kRounds = (kWinCap + kWave - 1) / kWave;
+  double sdr[kRounds], sdz[kRounds];
+  bool send[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int j = r * kWave + lane;
+    sdr[r] = sdz[r] = 0.0;
+    send[r] = false;
+    if (j < nb) {
+      const double* g = seg + seg_at(cb + j);
+      const double4 P2 = a.hx[a.outer[cb + j]];
+      sdr[r] = g[0];
+      sdz[r] = g[PT_SEG_BLOCK];
+      send[r] = __builtin_signbit(g[2 * PT_SEG_BLOCK]);
+      const float key = rz_key(sdr[r], sdz[r]);
+      bad |= !(key == key);
+      const int b = key == key ? rz_bucket(key, B) : 0;
+      tmp[j] = b | (atomicAdd(&hist[b], 1) << 8);
+      L.wx2[j] = static_cast<T>(P2.x);
+      L.wy2[j] = static_cast<T>(P2.y);
+    }
   }
   if (__ballot(bad)) return false;
   wave_sync();
@@ -450,12 +463,14 @@ __device__ bool stage_window(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L
   if (2 * lane + 1 < B) L.bst[2 * lane + 1] = static_cast<uint16_t>(front + ex + h0);
   if (lane == 0) L.bst[B] = static_cast<uint16_t>(front + nb);
   wave_sync();
-  for (int j = lane; j < nb; j += kWave) {
-    const double* g = seg + seg_at(cb + j);
-    const double dr = g[0], dz = g[PT_SEG_BLOCK];
+#pragma unroll
+  for (int q = 0; q < kRounds; ++q) {
+    const int j = q * kWave + lane;
+    if (j >= nb) continue;
+    const double dr = sdr[q], dz = sdz[q];
     const int v = tmp[j];
     const int b = v & 0xFF, r = v >> 8;
-    const uint16_t jv = static_cast<uint16_t>(j | (__builtin_signbit(g[2 * PT_SEG_BLOCK]) ? 0x8000 : 0));
+    const uint16_t jv = static_cast<uint16_t>(j | (send[q] ? 0x8000 : 0));
     const int at = L.bst[b] + r;
     L.wdr[at] = dr;
     L.wdz[at] = dz;
@@ -493,6 +508,9 @@ __global__ void __launch_bounds__(WAVES * kWave)
   const double th2b = k.theta2_barrel, th2e = k.theta2_endcap;
   const int nh = min(nb, kHinBits);  // out-cells whose has_inner bit is kept in LDS
   for (int w = lane; w < (nh + 31) / 32; w += kWave) L.hin[w] = 0;
+  // the first window of the hit's in-cell segments, loaded before the staging
+  int2 seg0 = make_int2(0, 0);
+  if (lane < min(kSegWin, se - sb)) seg0 = a.seg[sb + lane];
   // the out-cells by direction bucket, when the search can be windowed
   const bool win = k.rz_buckets > 0 && nb <= kWinCap && stage_window(k, a, L, seg, cb, nb);
 
@@ -501,7 +519,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
     const int wn = min(kSegWin, se - sw);
     int c0 = 0;
     if (lane < wn) {
-      const int2 g = a.seg[sw + lane];
+      const int2 g = sw == sb ? seg0 : a.seg[sw + lane];
       L.sfirst[lane] = g.x;
       c0 = g.y;
     }

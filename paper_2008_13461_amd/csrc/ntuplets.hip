@@ -228,6 +228,9 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths) {
     int stack[kMaxHits];   // cells of the current path
     int next[kMaxHits];    // next outer link to follow at each depth (absolute link index) ...
     int end[kMaxHits];     // ... and the end of that cell's links
+    // most roots emit no row (their paths are too short): the write pass
+    // skips them, and those whose rows all lie past the capacity
+    if (!COUNT && (paths[i + 1] == paths[i] || paths[i] >= a.cap)) continue;
     const int root = a.roots[i];
     stack[0] = root;
     next[0] = a.out_start[root];
