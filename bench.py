@@ -44,14 +44,17 @@ KERNEL_SYMBOL = {"doublets_count": "k_doublets<false>", "doublets_write": "k_dou
                  "dfs_count": "k_dfs<true>", "dfs_write": "k_dfs<false>", "fit_fwd": "k_fit<4,6>",
                  "fit_bwd": "k_grad<4,6>"}
 # Algorithmic work per unit, for the roofline of whichever kernel dominates:
-#  links: the R-Z test of every candidate pair the search examines, 7 fp64
-#    VALU operations (A = ar bz - az br: 2 mul + 1 sub; A A; La Lb;
-#    theta2 (La Lb); compare)
+#  links: 12 B per candidate pair the search examines (the two segments'
+#    dr, dz as the test needs them, less what the wavefront shares) and 8 B
+#    per link; the R-Z test of an examined pair is 7 fp64 VALU operations
+#    (A = ar bz - az br: 2 mul + 1 sub; A A; La Lb; theta2 (La Lb); compare)
 #  cell_index: per cell read inner, outer (8 B), write the 8-byte index
 #    entry, and clear out_count and has_inner (5 B)
 #  doublets_write: per cell write inner, outer, pair and the R-Z segment
 #    dr, dz, ls (9 + 24 B)
 LINK_OPS_PER_CANDIDATE = 7.0
+LINK_BYTES_PER_CANDIDATE = 12.0
+LINK_BYTES_PER_LINK = 8.0
 LINK_BUCKETS_MAX = 128  # direction buckets of the windowed link search, at most
 LINK_WIN_CAP = 224      # out-cells of a hit it stages (copies included)
 CELL_INDEX_BYTES_PER_CELL = 21.0
@@ -394,13 +397,18 @@ def roofline(kern, cnt):
     sec = kern[name] * 1e-3
     roof = {"kernel": KERNEL_SYMBOL.get(name, name), "timing_region": name}
     if name == "links":
-        achieved = LINK_OPS_PER_CANDIDATE * cnt["link_examined"] / sec / 1e12
-        roof.update(bound="alu", achieved=achieved, peak=FP64_VALU_PEAK_TOPS, unit="TOP/s",
-                    frac=achieved / FP64_VALU_PEAK_TOPS,
-                    all_pairs_rate=LINK_OPS_PER_CANDIDATE * cnt["link_candidates"] / sec / 1e12,
-                    note="7 fp64 VALU ops per examined candidate pair x examined pairs / kernel time; peak = 256 CU "
-                         "x 4 SIMD x 16 lanes x 2.4 GHz, one fp64 op per lane per clock (no FMA: contraction is off); "
-                         "all_pairs_rate counts every pair sharing a hit, most of which the direction buckets skip")
+        nbytes = LINK_BYTES_PER_CANDIDATE * cnt["link_examined"] + LINK_BYTES_PER_LINK * cnt["links"]
+        achieved = nbytes / sec / 1e9
+        alu = LINK_OPS_PER_CANDIDATE * cnt["link_examined"] / sec / 1e12
+        roof.update(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    algorithmic_bytes=nbytes,
+                    alu={"achieved": alu, "peak": FP64_VALU_PEAK_TOPS, "unit": "TOP/s",
+                         "frac": alu / FP64_VALU_PEAK_TOPS},
+                    all_pairs_rate_tops=LINK_OPS_PER_CANDIDATE * cnt["link_candidates"] / sec / 1e12,
+                    note="12 B per examined candidate pair + 8 B per link, over the kernel time; alu: 7 fp64 VALU "
+                         "ops per examined pair against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz (no FMA: contraction "
+                         "is off); all_pairs_rate_tops counts every pair sharing a hit, most of which the direction "
+                         "buckets skip.  The kernel is bound by the latency of its dependent gathers per hit.")
     else:
         per_cell = {"cell_index": CELL_INDEX_BYTES_PER_CELL, "doublets_write": DOUBLET_BYTES_PER_CELL}.get(name)
         achieved = per_cell * cnt["doublets"] / sec / 1e9 if per_cell else None
