@@ -186,13 +186,16 @@ __global__ void __launch_bounds__(kBlock) k_root_count(DevCfg k, TupIn a, int32_
   }
 }
 
-// Writes the chunk's roots in cell order from its mask, one wavefront per
-// chunk: lane l holds word l; a root's position is the chunk's offset, plus
-// the roots of the words before its own, plus its rank in its word.
-__global__ void __launch_bounds__(kWave) k_root_write(TupIn a, const uint64_t* __restrict__ bits,
-                                                     const int32_t* __restrict__ chunk_first) {
+// Writes the indices whose mask bit is set, in order, one wavefront per
+// chunk of kRootChunk indices below min(*n_dev, n_cap): lane l holds word l;
+// an index's position is the chunk's offset, plus the set bits of the words
+// before its own, plus its rank in its word.  Used for the roots (cells) and
+// for the roots that emit rows.
+__global__ void __launch_bounds__(kWave) k_mask_write(const int32_t* __restrict__ n_dev, int32_t n_cap,
+                                                     const uint64_t* __restrict__ bits,
+                                                     const int32_t* __restrict__ chunk_first, int32_t* __restrict__ out) {
   static_assert(kRootWords == kWave, "one mask word per lane");
-  const int n = min(*a.cell_count, a.cells_cap);
+  const int n = min(*n_dev, n_cap);
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
   if (base >= n) return;
   const int lane = threadIdx.x;
@@ -213,7 +216,48 @@ __global__ void __launch_bounds__(kWave) k_root_write(TupIn a, const uint64_t* _
     const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(word >> 32), w);
     const uint64_t m = (static_cast<uint64_t>(hi) << 32) | lo;
     const int at = __builtin_amdgcn_readlane(first, w);
-    if ((m >> lane) & 1u) a.roots[at + lane_prefix(m)] = static_cast<int>(base + w * kWave + lane);
+    if ((m >> lane) & 1u) out[at + lane_prefix(m)] = static_cast<int>(base + w * kWave + lane);
+  }
+}
+
+// The roots that emit a row (paths scanned: root i emits rows
+// [paths[i], paths[i + 1]), kept when some of them lie below the capacity),
+// counted per chunk of kRootChunk roots and flagged in a bit mask as
+// k_root_count does for cells.
+__global__ void __launch_bounds__(kBlock) k_prod_count(TupIn a, const int32_t* __restrict__ paths,
+                                                       int32_t* __restrict__ chunk_count, uint64_t* __restrict__ bits) {
+  constexpr int kWaves = kBlock / kWave;
+  __shared__ uint64_t s_bits[kRootWords];
+  __shared__ int32_t s_cnt[kWaves];
+  const int nr = min(*a.n_roots, a.cells_cap);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
+  if (base >= nr) {
+    if (threadIdx.x == 0) chunk_count[blockIdx.x] = 0;
+    return;
+  }
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  int p0[kRootItems], p1[kRootItems];
+#pragma unroll
+  for (int i = 0; i < kRootItems; ++i) {
+    const int64_t r = base + i * kBlock + threadIdx.x;
+    p0[i] = r < nr ? paths[r] : 0;
+    p1[i] = r < nr ? paths[r + 1] : 0;
+  }
+  int cnt = 0;
+#pragma unroll
+  for (int i = 0; i < kRootItems; ++i) {
+    const uint64_t m = __ballot(p1[i] > p0[i] && p0[i] < a.cap);
+    cnt += __popcll(m);
+    if (lane == 0) s_bits[i * kWaves + wave] = m;
+  }
+  if (lane == 0) s_cnt[wave] = cnt;
+  __syncthreads();
+  if (threadIdx.x < kRootWords) bits[blockIdx.x * static_cast<int64_t>(kRootWords) + threadIdx.x] = s_bits[threadIdx.x];
+  if (threadIdx.x == 0) {
+    int total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) total += s_cnt[w];
+    chunk_count[blockIdx.x] = total;
   }
 }
 
@@ -221,16 +265,17 @@ __global__ void __launch_bounds__(kWave) k_root_write(TupIn a, const uint64_t* _
 // (and the truncation count); otherwise the rows are written from row
 // first_row[i] on.
 template <bool COUNT>
-__global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths) {
-  const int nr = *a.n_roots;
+__global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths, const int32_t* __restrict__ prod,
+                      const int32_t* __restrict__ n_prod) {
+  // the write pass takes only the roots that emit a row below the capacity
+  // (most roots emit none: their paths are too short)
+  const int nr = COUNT ? *a.n_roots : *n_prod;
   uint32_t truncated = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += gridDim.x * blockDim.x) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nr; t += gridDim.x * blockDim.x) {
     int stack[kMaxHits];   // cells of the current path
     int next[kMaxHits];    // next outer link to follow at each depth (absolute link index) ...
     int end[kMaxHits];     // ... and the end of that cell's links
-    // most roots emit no row (their paths are too short): the write pass
-    // skips them, and those whose rows all lie past the capacity
-    if (!COUNT && (paths[i + 1] == paths[i] || paths[i] >= a.cap)) continue;
+    const int i = COUNT ? t : prod[t];
     const int root = a.roots[i];
     stack[0] = root;
     next[0] = a.out_start[root];
@@ -353,8 +398,10 @@ __global__ void __launch_bounds__(kBlock) k_keep_count(TupIn a, int32_t* __restr
   if (threadIdx.x == 0) chunk_kept[blockIdx.x] = total;
 }
 
-// Writes the chunk's kept rows in row order, placed like the roots (see
-// k_root_write).
+// Writes the chunk's kept rows in row order: a row's position is the
+// chunk's offset, plus the kept rows of the (item, wavefront) groups before
+// its own (one wavefront scan of the group counts), plus its rank in its
+// wavefront's ballot.
 __global__ void __launch_bounds__(kBlock) k_keep_write(TupIn a, const int32_t* __restrict__ chunk_first) {
   constexpr int kWaves = kBlock / kWave;
   __shared__ int32_t s_grp[kRootItems * kWaves];
@@ -401,11 +448,14 @@ size_t ws_ntuplets(int cells_cap, int tuplets_cap) {
   const int64_t chunks = std::max<int64_t>(
       1, std::max<int64_t>((static_cast<int64_t>(cells_cap) + kRootChunk - 1) / kRootChunk,
                            (static_cast<int64_t>(tuplets_cap) + kRootChunk - 1) / kRootChunk));
+  const int64_t cells_chunks = std::max<int64_t>(1, (static_cast<int64_t>(cells_cap) + kRootChunk - 1) / kRootChunk);
   const int64_t scan_n = std::max<int64_t>(chunks, cells_cap);
   Carver c(nullptr);
   c.take<int32_t>(cells_cap);      // roots
-  c.take<uint64_t>(chunks * kRootWords);  // root flags, one bit per cell
+  c.take<uint64_t>(chunks * kRootWords);  // root flags, one bit per cell (then per root)
   c.take<int32_t>(chunks + 1);     // roots (then kept rows) per chunk -> chunk offsets (+ total)
+  c.take<int32_t>(cells_cap);      // roots that emit rows
+  c.take<int32_t>(cells_chunks + 1);  // ... per chunk -> chunk offsets (+ total)
   c.take<int32_t>(static_cast<size_t>(cells_cap) + 1);  // paths per root -> first row (+ total)
   c.take<int32_t>(cells_cap);      // max_n
   c.take<int32_t>(scan_tmp_elems(scan_n));
@@ -421,6 +471,8 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   int32_t* roots = c.take<int32_t>(cells.cap);
   uint64_t* root_bits = c.take<uint64_t>(chunks_max * kRootWords);
   int32_t* chunk_roots = c.take<int32_t>(chunks_max + 1);
+  int32_t* prod = c.take<int32_t>(cells.cap);
+  int32_t* chunk_prod = c.take<int32_t>(chunks + 1);
   int32_t* paths = c.take<int32_t>(static_cast<size_t>(cells.cap) + 1);
   int32_t* max_n = c.take<int32_t>(cells.cap);
   int32_t* tmp = c.take<int32_t>(scan_tmp_elems(scan_n));
@@ -439,16 +491,21 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   PT_LAUNCH_CHECK();
   if (exclusive_scan(chunk_roots, chunks, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  k_root_write<<<static_cast<unsigned>(chunks), kWave, 0, s>>>(a, root_bits, chunk_roots);
+  k_mask_write<<<static_cast<unsigned>(chunks), kWave, 0, s>>>(cells.count, cells.cap, root_bits, chunk_roots, roots);
   timing_end(tok, "root_write", s);
   PT_LAUNCH_CHECK();
   tok = timing_begin(s);
-  k_dfs<true><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths);
+  k_dfs<true><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths, nullptr, nullptr);
   timing_end(tok, "dfs_count", s);
   PT_LAUNCH_CHECK();
   if (exclusive_scan_dev(paths, cells.cap, n_roots, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  k_dfs<false><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths);
+  k_prod_count<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(a, paths, chunk_prod, root_bits);
+  PT_LAUNCH_CHECK();
+  if (exclusive_scan(chunk_prod, chunks, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  k_mask_write<<<static_cast<unsigned>(chunks), kWave, 0, s>>>(n_roots, cells.cap, root_bits, chunk_prod, prod);
+  PT_LAUNCH_CHECK();
+  k_dfs<false><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths, prod, chunk_prod + chunks);
   timing_end(tok, "dfs_write", s);
   PT_LAUNCH_CHECK();
   // rows found = paths[n_roots] (the scan's total)
