@@ -495,7 +495,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   timing_end(tok, "root_write", s);
   PT_LAUNCH_CHECK();
   tok = timing_begin(s);
-  k_dfs<true><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths, nullptr, nullptr);
+  k_dfs<true><<<grid_for(cells.cap, 256, 65536), 256, 0, s>>>(k, a, paths, nullptr, nullptr);
   timing_end(tok, "dfs_count", s);
   PT_LAUNCH_CHECK();
   if (exclusive_scan_dev(paths, cells.cap, n_roots, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
