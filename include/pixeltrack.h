@@ -136,8 +136,8 @@ typedef struct {
   int32_t n_modules;                  /* rows of the module offset / gradient tables */
   /* performance settings: never change a result */
   int32_t n_phi_bins;                 /* azimuth bins per layer for the pair search; 0 = 128 */
-  int32_t block_doublets;             /* threads per block of the doublet kernel: 64, 128, 256
-                                         or 512; other values mean 256 */
+  int32_t block_doublets;             /* threads per block of the doublet count pass: 64, 128,
+                                         256 or 512; other values mean 256 */
   int32_t block_links;                /* threads per block of the link sweep (one wavefront per
                                          middle hit): 64, 128 or 256; other values mean 64 */
   double f64_solve_threshold;         /* see PT_FIT_F32_F64SOLVE; <= 0 means 1024 */

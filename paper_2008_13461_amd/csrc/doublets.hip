@@ -186,6 +186,9 @@ constexpr int kStage = 256;
 // again by the write pass.
 constexpr int kMaskChunks = 64;
 static_assert(kMaskChunks == kWave, "one kept group per lane");
+// Threads per block of the write pass, whatever the count pass takes: four
+// single-wavefront hits per block measured fastest for the stores.
+constexpr int kWriteBlock = 256;
 constexpr int kEndcapBit = 0x80;  // in a staged pair: the pair's outer layer is an end-cap
 static_assert(kMaxPairs <= kEndcapBit, "pair indices leave the top bit free");
 
@@ -451,7 +454,7 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   PT_LAUNCH_CHECK();
   if (exclusive_scan(cnt, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  launch_doublets<true>(k, a, n, block, s);
+  launch_doublets<true>(k, a, n, kWriteBlock, s);
   timing_end(tok, "doublets_write", s);
   PT_LAUNCH_CHECK();
   k_finish_cells<<<1, 1, 0, s>>>(cnt + n, cells.cap, cells.count, status);
