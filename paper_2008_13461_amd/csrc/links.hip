@@ -15,15 +15,20 @@
 //  3. exclusive scan of the per-hit segment counts, then k_seg_scatter:
 //     each hit's in-cells as a list of segments of the index (8 bytes per
 //     cell: cell, inner hit), one segment per chunk of k_cell_index.
-//  4. k_link_hits: one wavefront per middle hit.  Lanes hold the in-cells;
-//     the out-cells (a contiguous run, grouped by inner hit by the doublet
-//     step) are swept in a uniform loop whose loads are wave-uniform, so the
-//     R-Z test of 64 pairs costs a handful of double-precision instructions
-//     and no per-pair gather.  Pairs that pass are queued in LDS and the
-//     beam-spot test (divisions, square roots) runs on full waves of queued
-//     pairs.  Each in-cell's link count is recorded, with its links when
-//     there are at most kLocal of them, and the hit's out-cells that gained
-//     an inner link are flagged (has_inner) in one coalesced run.
+//  4. k_link_hits: one wavefront per middle hit.  Lanes hold the in-cells.
+//     The hit's out-cells (a contiguous run, grouped by inner hit by the
+//     doublet step) are binned in LDS by the direction of their R-Z segment,
+//     in bins at least as wide as the cut angle, so that each in-cell is
+//     tested only against the out-cells of its own and the neighbouring bins
+//     (a few percent of the pairs), the examined pairs dealt out 64 at a
+//     time over the lanes.  Hits with too many out-cells for the LDS lists,
+//     and wide cuts, sweep every out-cell in a uniform loop whose loads are
+//     wave-uniform, so the R-Z test of 64 pairs costs a handful of
+//     double-precision instructions.  Pairs that pass are queued in LDS and
+//     the beam-spot test (divisions, square roots) runs on full waves of
+//     queued pairs.  Each in-cell's link count is recorded, with its links
+//     when there are at most kLocal of them, and the hit's out-cells that
+//     gained an inner link are flagged (has_inner) in one coalesced run.
 //  5. the counts are recorded straight into out_count; their scan into
 //     out_start places every in-cell's links, in cell order (no shared
 //     counter: same-address atomics serialise), k_link_emit writes the links
