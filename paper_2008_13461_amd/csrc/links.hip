@@ -633,12 +633,29 @@ __global__ void __launch_bounds__(WAVES * kWave)
           }
           const int P = incl - wlen;  // first pair of this lane's range
           const int npairs = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
+          // the pass set-up's segment marks are free now: they hold the
+          // lane whose range starts at each place of a step, and a bit set
+          // of those places
+          uint8_t* starter = reinterpret_cast<uint8_t*>(L.segat);
+          uint32_t* starts = reinterpret_cast<uint32_t*>(L.segat) + kWave / 4;
+          static_assert(kWave / 4 + 2 <= kWave, "both fit the segment marks");
+          int carry = 0;  // the lane owning the last pair of the previous step
           for (int f0 = 0; f0 < npairs; f0 += kWave) {
             const int f = f0 + lane;
-            int o = 0;  // the largest lane with P <= f (P of lane 0 is 0)
-#pragma unroll
-            for (int st = kWave / 2; st > 0; st >>= 1)
-              if (__shfl(P, o + st, kWave) <= f) o += st;
+            if (lane < 2) starts[lane] = 0;
+            wave_sync();
+            const int rel = P - f0;
+            if (wlen > 0 && rel >= 0 && rel < kWave) {
+              starter[rel] = static_cast<uint8_t>(lane);
+              atomicOr(&starts[rel >> 5], 1u << (rel & 31));
+            }
+            wave_sync();
+            // the last range starting at or before f: the highest start at or
+            // below this place, else the range running on from the previous step
+            const uint64_t sm = (static_cast<uint64_t>(starts[1]) << 32) | starts[0];
+            const uint64_t below = sm & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1));
+            const int o = below ? starter[63 - __builtin_clzll(below)] : carry;
+            carry = __builtin_amdgcn_readlane(o, kWave - 1);
             const double oar = __shfl(ar, o, kWave), oaz = __shfl(az, o, kWave), oLa = __shfl(La, o, kWave);
             const int at = __shfl(wstart, o, kWave) + (f - __shfl(P, o, kWave));
             bool pass = false;
