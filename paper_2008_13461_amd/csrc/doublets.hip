@@ -97,20 +97,43 @@ __global__ void k_hit_keys(HitsIn<T> in, int n_bins, float bin_scale, int32_t* _
   }
 }
 
+// Places every valid hit in its bin (arrival order within the bin, from the
+// ranks of k_hit_keys) and clears the per-hit cell counts.
 template <class T>
 __global__ void k_scatter(HitsIn<T> in, const int32_t* __restrict__ key, const int32_t* __restrict__ rank,
-                          const int32_t* __restrict__ bin_start, int32_t* __restrict__ sorted_hit,
-                          int32_t* __restrict__ skey, double* __restrict__ sX, double* __restrict__ sY,
-                          double* __restrict__ sZ, double* __restrict__ sR, int32_t* __restrict__ inner_count) {
+                          const int32_t* __restrict__ bin_start, int32_t* __restrict__ arrived,
+                          int32_t* __restrict__ skey, int32_t* __restrict__ inner_count) {
   for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < in.n_hits; h += gridDim.x * blockDim.x) {
     inner_count[h] = 0;
     const int k = key[h];
     if (k < 0) continue;
     const int pos = bin_start[k] + rank[h];
+    arrived[pos] = h;
+    skey[pos] = k;
+  }
+}
+
+// Orders each bin by hit index, so that the sorted order -- and with it the
+// order of the cells, links and rows -- does not depend on the order in
+// which the atomics of k_hit_keys were served: the hit at position p moves to
+// its bin's start plus the number of the bin's hits with a smaller index.
+// Then fills the sorted copies (in double) at the new position.
+template <class T>
+__global__ void k_bin_order(HitsIn<T> in, const int32_t* __restrict__ valid, const int32_t* __restrict__ bin_start,
+                            const int32_t* __restrict__ arrived, const int32_t* __restrict__ skey,
+                            int32_t* __restrict__ sorted_hit, double* __restrict__ sX, double* __restrict__ sY,
+                            double* __restrict__ sZ, double* __restrict__ sR) {
+  const int total = *valid;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
+    const int k = skey[p];
+    const int b0 = bin_start[k], b1 = bin_start[k + 1];
+    const int h = arrived[p];
+    int r = 0;
+    for (int q = b0; q < b1; ++q) r += arrived[q] < h ? 1 : 0;
+    const int pos = b0 + r;
     const double X = static_cast<double>(in.x[h]);
     const double Y = static_cast<double>(in.y[h]);
     sorted_hit[pos] = h;
-    skey[pos] = k;
     sX[pos] = X;
     sY[pos] = Y;
     sZ[pos] = static_cast<double>(in.z[h]);
@@ -439,8 +462,12 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   if (exclusive_scan(bin_start, nb, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   k_copy_total<<<1, 1, 0, s>>>(bin_start, static_cast<int>(nb), bins);
   PT_LAUNCH_CHECK();
-  k_scatter<T><<<grid_for(n, 256), 256, 0, s>>>(in, key, rank, bin_start, sorted_hit, skey, sX, sY, sZ, sR,
-                                               cells.inner_count);
+  // the hits in arrival order within their bins, then each bin ordered by
+  // hit index
+  int32_t* arrived = cnt;  // the per-hit counts are free until the count pass
+  k_scatter<T><<<grid_for(n, 256), 256, 0, s>>>(in, key, rank, bin_start, arrived, skey, cells.inner_count);
+  PT_LAUNCH_CHECK();
+  k_bin_order<T><<<grid_for(n, 256), 256, 0, s>>>(in, bins, bin_start, arrived, skey, sorted_hit, sX, sY, sZ, sR);
   PT_LAUNCH_CHECK();
 
   DoubletArgs a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, chunks, n_chunks, cells.cap, cells.inner,

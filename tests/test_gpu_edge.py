@@ -98,6 +98,11 @@ def test_capacity_overflow_is_flagged(which):
         assert int(pipe.links.count.item()) == n_links
     if which == "tuplets":
         assert int(pipe.tuplets.count_raw.item()) == n_raw
+        # rows come out in root order: the rows that fit are the first rows
+        # of the full run (the root whose rows straddle the capacity included)
+        cap = caps["tuplets_cap"]
+        assert np.array_equal(got["raw_hits"], full["raw_hits"][:cap])
+        assert np.array_equal(got["raw_n"], full["raw_n"][:cap])
 
 
 def test_permuted_hits_give_the_same_sets():
