@@ -23,7 +23,7 @@ namespace {
 constexpr int kMinN = 3;
 constexpr int kNBins = kMaxHits - kMinN + 1;  // N = 3..8
 constexpr int kBlock = 256;
-constexpr int kBwdBlocks = 512;
+constexpr int kBwdBlocks = 256;
 
 struct FitArgs {
   int32_t dtype;
