@@ -373,7 +373,8 @@ struct HitArgs {
   const int2* seg;           // segments: (first entry, entries)
   const InCell* ent;         // index entries
   int32_t* out_count;  // [cells_cap] links of each cell, zero on entry (scanned afterwards)
-  int32_t* spill;     // [cells_cap][kRow] per in-cell with links: its out-cells (at most kLocal)
+  int32_t* spill;     // per in-cell with links: its out-cells (at most kLocal), the first four
+                      // at [cell][4], the others at [cells_cap + cell][4]
   int32_t* ovf;       // in-cells with more than kLocal links
   int32_t* ovf_count;
   uint8_t* has_inner;  // set for every out-cell with a link (zero on entry)
@@ -785,10 +786,12 @@ __global__ void __launch_bounds__(WAVES * kWave)
       }
       if (n > 0 && n <= kLocal) {  // the links are sorted by k_link_emit
         static_assert(kRow == 8 && kLocal == 8, "a record is two 16-byte vectors");
-        int4* sp = reinterpret_cast<int4*>(a.spill + static_cast<int64_t>(cell) * kRow);
+        // two halves of 16 bytes per cell, so that the records of the cells
+        // with at most four links (nearly all) are dense
+        int4* sp = reinterpret_cast<int4*>(a.spill);
         const int4* fl = reinterpret_cast<const int4*>(L.found + lane * kLocal);
-        sp[0] = fl[0];  // places past n are never read
-        if (n > 4) sp[1] = fl[1];
+        sp[cell] = fl[0];  // places past n are never read
+        if (n > 4) sp[static_cast<int64_t>(a.cells_cap) + cell] = fl[1];
       }
       wave_sync();
     }
@@ -806,7 +809,7 @@ struct EmitArgs {
   int32_t cells_cap;
   const int32_t* out_start;  // first link of each cell (scanned counts)
   const int32_t* out_count;  // links of each cell
-  const int32_t* spill;      // per in-cell with 1..kLocal links: its out-cells
+  const int32_t* spill;      // per in-cell with 1..kLocal links: its out-cells (two halves)
   int32_t links_cap;
   int32_t* in_cell;
   int32_t* out_cell;
@@ -881,9 +884,9 @@ __global__ void __launch_bounds__(kEmitBlock) k_link_emit(EmitArgs a) {
   for (int q = 0; q < kCells; ++q) {
     r0[q] = r1[q] = make_int4(0, 0, 0, 0);
     if (cnt[q] > 0 && cnt[q] <= kLocal) {
-      const int4* sp = reinterpret_cast<const int4*>(a.spill + (c0 + q) * kRow);
-      r0[q] = sp[0];
-      if (cnt[q] > 4) r1[q] = sp[1];
+      const int4* sp = reinterpret_cast<const int4*>(a.spill);
+      r0[q] = sp[c0 + q];
+      if (cnt[q] > 4) r1[q] = sp[a.cells_cap + c0 + q];
       if (!VEC || c0 + kCells > n) pos[q] = a.out_start[c0 + q];
     }
   }
@@ -974,7 +977,7 @@ size_t ws_links(int n_hits, int cells_cap) {
   c.take<int32_t>(static_cast<size_t>(n_hits) + 1);     // segments per hit -> first segment
   c.take<int2>(cells_cap);                  // segments
   c.take<int32_t>(scan_tmp_elems(scan_n));
-  c.take<int32_t>(static_cast<size_t>(cells_cap) * kRow);  // records of the cells with links
+  c.take<int32_t>(static_cast<size_t>(cells_cap) * kRow);  // records of the cells with links (two halves)
   c.take<int32_t>(cells_cap);               // overflow list
   c.take<int32_t>(1);                       // overflow count
   return c.off + 256;
