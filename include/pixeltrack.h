@@ -31,8 +31,10 @@
  *    Cell, link and n-tuplet indices are positions in their output arrays.
  *  - Units: cm, GeV, tesla, radians.  kappa > 0 turns counter-clockwise seen
  *    from +z (a negative particle in a field along +z).
- *  - Order: doublets, links and n-tuplets come out in no particular order
- *    (they are sets); the fit writes track i for kept n-tuplet i.
+ *  - Order: doublets, links and n-tuplets are sets; they come out in an
+ *    order that depends only on the inputs and the configuration (the same
+ *    on every run), which is not part of this contract.  The fit writes
+ *    track i for kept n-tuplet i.
  */
 #ifndef PIXELTRACK_H
 #define PIXELTRACK_H
@@ -302,8 +304,8 @@ pt_err pt_fit_broken_line(const pt_hits* hits, const pt_config* cfg, const pt_nt
                           uint32_t* status, pt_workspace ws, pt_stream stream);
 
 /* Adjoint of pt_fit_broken_line (same tracks, same precision).  With the
- * upstream gradients g_params (device float [cap][5]) and g_chi2 (device
- * float [cap], may be NULL), adds
+ * upstream gradients g_params (device [cap][5]) and g_chi2 (device [cap], may
+ * be NULL), both double for PT_FIT_F64 and float otherwise, adds
  *   grad_hits[h]    += sum over tracks t containing h of J_t(h)^T (g_params[t], g_chi2[t])
  *   grad_offsets[m] += sum over hits h on module m of the same
  * where J_t(h) = d(kappa, phi0, cot, d0, z0, chi2)_t / d(x, y, z)_h of the
@@ -315,7 +317,7 @@ pt_err pt_fit_broken_line(const pt_hits* hits, const pt_config* cfg, const pt_nt
  * order of the additions is not fixed).  Tracks whose fit fails add nothing. */
 pt_err pt_fit_broken_line_bwd(const pt_hits* hits, const pt_config* cfg,
                               const pt_ntuplets* tuplets, const float* module_offsets,
-                              int32_t precision, const float* g_params, const float* g_chi2,
+                              int32_t precision, const void* g_params, const void* g_chi2,
                               void* grad_hits, double* grad_offsets, uint32_t* status,
                               pt_workspace ws, pt_stream stream);
 
@@ -338,7 +340,7 @@ pt_err pt_plan_create(const pt_config* cfg, int32_t n_hits_max, int32_t n_events
                       int32_t links_cap, int32_t tuplets_cap, int32_t precision, int32_t with_adjoint,
                       pt_plan* plan);
 pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links* links, pt_ntuplets* tuplets,
-                   pt_tracks* tracks, const float* module_offsets, const float* g_params, const float* g_chi2,
+                   pt_tracks* tracks, const float* module_offsets, const void* g_params, const void* g_chi2,
                    void* grad_hits, double* grad_offsets, uint32_t* status, pt_stream stream);
 void pt_plan_destroy(pt_plan plan);
 

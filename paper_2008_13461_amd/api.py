@@ -274,15 +274,16 @@ def fit_broken_line_bwd(hits: Hits, cfg: A.pt_config, tuplets: Tuplets, offsets:
                         precision: int, g_params: torch.Tensor, g_chi2: torch.Tensor | None,
                         grad_hits: torch.Tensor | None, grad_offsets: torch.Tensor | None, status: torch.Tensor,
                         ws: torch.Tensor, stream=None) -> None:
-    if g_params.dtype != torch.float32 or (g_chi2 is not None and g_chi2.dtype != torch.float32):
-        raise TypeError("upstream gradients must be float32")
     want = torch.float64 if precision == A.PT_FIT_F64 else torch.float32
+    if g_params.dtype != want or (g_chi2 is not None and g_chi2.dtype != want):
+        raise TypeError(f"upstream gradients must be {want} for this precision")
     if grad_hits is not None and grad_hits.dtype != want:
         raise TypeError(f"grad_hits must be {want} [n_hits, 3] for this precision")
     if grad_offsets is not None and grad_offsets.dtype != torch.float64:
         raise TypeError("grad_offsets must be float64 [n_modules, 3]")
     A.check(A.load().pt_fit_broken_line_bwd(ct.byref(hits.abi()), ct.byref(cfg), ct.byref(tuplets.abi()),
-                                            _p(offsets), precision, _p(g_params.contiguous()), _p(g_chi2),
+                                            _p(offsets), precision, _p(g_params.contiguous()),
+                                            _p(g_chi2.contiguous() if g_chi2 is not None else None),
                                             _p(grad_hits), _p(grad_offsets), _p(status), _ws(ws),
                                             _stream(stream)), "pt_fit_broken_line_bwd")
 

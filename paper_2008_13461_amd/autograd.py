@@ -48,9 +48,10 @@ class _Fit(torch.autograd.Function):
         tup = api.Tuplets.from_rows(tuplets, nhits)
         status = api.new_status(x.device)
         ws = api.new_workspace(api.workspace_size(cfg, hits.n_hits, 1, 0, 0, n), x.device)
-        gp = (g_params if g_params is not None else torch.zeros((n, 5), device=x.device)).float().contiguous()
-        gc = (g_chi2 if g_chi2 is not None else torch.zeros(n, device=x.device)).float().contiguous()
+        # cotangents in the fit's precision: double for the double fit
         gdt = torch.float64 if ctx.precision == A.PT_FIT_F64 else torch.float32
+        gp = (g_params if g_params is not None else torch.zeros((n, 5), device=x.device)).to(gdt).contiguous()
+        gc = (g_chi2 if g_chi2 is not None else torch.zeros(n, device=x.device)).to(gdt).contiguous()
         gh = torch.zeros((hits.n_hits, 3), dtype=gdt, device=x.device)
         off = offsets if ctx.has_offsets else None
         go = torch.zeros((cfg.n_modules, 3), dtype=torch.float64, device=x.device) if ctx.has_offsets else None

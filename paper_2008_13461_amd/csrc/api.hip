@@ -18,7 +18,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
 pt_err launch_fit(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets, int precision,
                   pt_tracks& out, uint32_t* status, pt_workspace ws, hipStream_t s);
 pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets,
-                      int precision, const float* g_params, const float* g_chi2, void* grad_hits,
+                      int precision, const void* g_params, const void* g_chi2, void* grad_hits,
                       double* grad_offsets, int n_max, uint32_t* status, pt_workspace ws, hipStream_t s);
 
 // The derived constants, with the expressions documented in pixeltrack.h.
@@ -201,8 +201,8 @@ pt_err pt_fit_broken_line(const pt_hits* hits, const pt_config* cfg, const pt_nt
 }
 
 pt_err pt_fit_broken_line_bwd(const pt_hits* hits, const pt_config* cfg, const pt_ntuplets* tuplets,
-                              const float* module_offsets, int32_t precision, const float* g_params,
-                              const float* g_chi2, void* grad_hits, double* grad_offsets, uint32_t* status,
+                              const float* module_offsets, int32_t precision, const void* g_params,
+                              const void* g_chi2, void* grad_hits, double* grad_offsets, uint32_t* status,
                               pt_workspace ws, pt_stream stream) {
   DevCfg d;
   if (!hits_ok(hits) || !cfg || !tuplets || !derive_config(*cfg, &d)) return PT_ERR_ARG;

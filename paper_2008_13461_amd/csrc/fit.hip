@@ -13,7 +13,9 @@
 // (fit_core.h).  Hit gradients are added with float atomics (hits can be
 // shared between tracks); module-offset gradients are accumulated per block in
 // LDS in double and written as one partial sum per block, then reduced across
-// blocks in a fixed order, so that they are reproducible bit for bit.
+// blocks in a fixed order (no global atomics on the table).  The order of the
+// additions within a block still depends on the schedule, so module sums
+// agree between runs to the rounding of double, not bit for bit.
 #include "fit_core.h"
 #include "pt_internal.h"
 
@@ -50,8 +52,8 @@ struct FitArgs {
   void* chi2;
   uint8_t* track_status;
   // adjoint
-  const float* g_params;
-  const float* g_chi2;
+  const void* g_params;       // GT (the type of grad_hits) [n][5]
+  const void* g_chi2;         // GT [n], may be null
   void* grad_hits;           // float, or double in the double-precision mode
   double* partials;          // [kBwdBlocks][n_modules * 3]
   uint32_t* status;
@@ -306,10 +308,10 @@ __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const Fit
   }
   if (f.status != fit::ST_OK) return;
   double g[6];
-  const float* gp = a.g_params + static_cast<int64_t>(i) * 5;
+  const GT* gp = static_cast<const GT*>(a.g_params) + static_cast<int64_t>(i) * 5;
 #pragma unroll
   for (int q = 0; q < 5; ++q) g[q] = double(gp[q]);
-  g[5] = a.g_chi2 ? double(a.g_chi2[i]) : 0.0;
+  g[5] = a.g_chi2 ? double(static_cast<const GT*>(a.g_chi2)[i]) : 0.0;
   S gP[N][3];
   fit::backward<N, S>(C, f, g, gP);
 #pragma unroll
@@ -412,18 +414,21 @@ int fit_grid(int n_max) { return grid_for(n_max, kBlock, 4096); }
 
 }  // namespace
 
-size_t ws_fit(int n_max, int n_modules) {
+// Workspace of the forward fit (with_partials = false) or of the adjoint.
+static size_t fit_scratch_bytes(int n_max, int n_modules, bool with_partials) {
   Carver c(nullptr);
   c.take<int32_t>(static_cast<size_t>(kNBins) * n_max);
   c.take<int32_t>(kNBins);
   c.take<int32_t>(n_max);
   c.take<int32_t>(1);
-  c.take<double>(static_cast<size_t>(kBwdBlocks) * n_modules * 3);
+  if (with_partials) c.take<double>(static_cast<size_t>(kBwdBlocks) * n_modules * 3);
   return c.off + 256;
 }
 
+size_t ws_fit(int n_max, int n_modules) { return fit_scratch_bytes(n_max, n_modules, true); }
+
 static FitArgs make_args(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets,
-                         int n_max, pt_workspace ws, uint32_t* status) {
+                         int n_max, pt_workspace ws, uint32_t* status, bool with_partials = true) {
   Carver c(ws.ptr);
   FitArgs a{};
   a.dtype = h.dtype;
@@ -444,7 +449,7 @@ static FitArgs make_args(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T
   a.bin_count = c.take<int32_t>(kNBins);
   a.redo = c.take<int32_t>(n_max);
   a.redo_count = c.take<int32_t>(1);
-  a.partials = c.take<double>(static_cast<size_t>(kBwdBlocks) * k.n_modules * 3);
+  a.partials = with_partials ? c.take<double>(static_cast<size_t>(kBwdBlocks) * k.n_modules * 3) : nullptr;
   a.status = status;
   return a;
 }
@@ -477,7 +482,7 @@ static pt_err run_fit(const DevCfg& k, FitArgs& a, bool fallback, hipStream_t s)
 pt_err launch_fit(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets, int precision,
                   pt_tracks& out, uint32_t* status, pt_workspace ws, hipStream_t s) {
   const int n_max = std::min(T.cap, out.cap);
-  FitArgs a = make_args(h, k, T, offsets, n_max, ws, status);
+  FitArgs a = make_args(h, k, T, offsets, n_max, ws, status, false);
   a.params = out.params;
   a.chi2 = out.chi2;
   a.track_status = out.status;
@@ -513,7 +518,7 @@ static pt_err run_grad(const DevCfg& k, FitArgs& a, bool fallback, double* grad_
 }
 
 pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets, int precision,
-                      const float* g_params, const float* g_chi2, void* grad_hits, double* grad_offsets,
+                      const void* g_params, const void* g_chi2, void* grad_hits, double* grad_offsets,
                       int n_max, uint32_t* status, pt_workspace ws, hipStream_t s) {
   FitArgs a = make_args(h, k, T, offsets, n_max, ws, status);
   a.g_params = g_params;

@@ -24,7 +24,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
 pt_err launch_fit(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets, int precision,
                   pt_tracks& out, uint32_t* status, pt_workspace ws, hipStream_t s);
 pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets,
-                      int precision, const float* g_params, const float* g_chi2, void* grad_hits,
+                      int precision, const void* g_params, const void* g_chi2, void* grad_hits,
                       double* grad_offsets, int n_max, uint32_t* status, pt_workspace ws, hipStream_t s);
 
 // ---------------------------------------------------------------------------
@@ -179,7 +179,7 @@ void pt_plan_destroy(pt_plan plan) {
 }
 
 static pt_err enqueue_step(Plan* p, const pt_hits* hits, pt_cells* cells, pt_links* links, pt_ntuplets* tuplets,
-                           pt_tracks* tracks, const float* offsets, const float* g_params, const float* g_chi2,
+                           pt_tracks* tracks, const float* offsets, const void* g_params, const void* g_chi2,
                            void* grad_hits, double* grad_offsets, uint32_t* status, hipStream_t s) {
   pt_workspace ws{p->ws, p->ws_bytes};
   pt_err e = launch_doublets(*hits, p->dev, *cells, status, ws, s);
@@ -193,7 +193,7 @@ static pt_err enqueue_step(Plan* p, const pt_hits* hits, pt_cells* cells, pt_lin
 }
 
 pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links* links, pt_ntuplets* tuplets,
-                   pt_tracks* tracks, const float* module_offsets, const float* g_params, const float* g_chi2,
+                   pt_tracks* tracks, const float* module_offsets, const void* g_params, const void* g_chi2,
                    void* grad_hits, double* grad_offsets, uint32_t* status, pt_stream stream) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p || !hits || !cells || !links || !tuplets || !tracks) return PT_ERR_ARG;

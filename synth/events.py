@@ -467,14 +467,17 @@ def cotangents(seed, n_tracks):
 
 
 def track_hits_ms(rng, trk, *, x_over_x0=0.015, highland=(0.0136, 0.038), disks=True,
-                  smear=True, bfield=3.8):
+                  smear=True, bfield=3.8, scatter_first=True):
     """Layer crossings of tracks that scatter in the material of every layer.
 
     Piecewise helices: at each crossing the 3D direction is deflected by two
     independent Gaussian angles of width theta0 (Highland, with the material
     x/X0 times the path length through the layer: 1/sin(theta) for a barrel
     cylinder, 1/|cos(theta)| for a disk) and the next crossing is found from
-    the deflected helix.  The momentum is unchanged (no energy loss).
+    the deflected helix.  The momentum is unchanged (no energy loss).  With
+    scatter_first=False the first crossing of each track deflects nothing, so
+    that the generating perigee parameters describe the track up to its
+    second hit.
     Returns (track index, layer, x, y, z) of all crossings ordered per track.
     """
     T = trk["kappa"].shape[0]
@@ -486,6 +489,7 @@ def track_hits_ms(rng, trk, *, x_over_x0=0.015, highland=(0.0136, 0.038), disks=
     phi0, d0, z0, s_cur = trk["phi0"].copy(), trk["d0"].copy(), trk["z0"].copy(), trk["s_v"].copy()
     crossed = np.zeros((T, C.N_LAYERS), bool)
     active = np.ones(T, bool)
+    n_crossed = np.zeros(T, np.int64)
     out_t, out_l, out_x, out_y, out_z = [], [], [], [], []
     for _ in range(C.N_LAYERS):
         idx = np.nonzero(active)[0]
@@ -512,6 +516,9 @@ def track_hits_ms(rng, trk, *, x_over_x0=0.015, highland=(0.0136, 0.038), disks=
         path = np.where(barrel, 1.0 / sin_t, 1.0 / np.maximum(np.abs(cos_t), 1e-6))
         X = x_over_x0 * path
         th0 = highland[0] / p[idx] * np.sqrt(X) * (1.0 + highland[1] * np.log(X))
+        if not scatter_first:
+            th0 = np.where(n_crossed[idx] == 0, 0.0, th0)
+        n_crossed[idx] += 1
         a1 = rng.normal(size=idx.size) * th0
         a2 = rng.normal(size=idx.size) * th0
         d = np.stack([sin_t * np.cos(phi), sin_t * np.sin(phi), cos_t], 1)
@@ -540,3 +547,40 @@ def track_hits_ms(rng, trk, *, x_over_x0=0.015, highland=(0.0136, 0.038), disks=
     if smear:
         x, y, z = _smear(rng, li, x, y, z, _SIGMAS)
     return ti, li, x, y, z
+
+
+def cylinder_tracks(seed, n_tracks, radii, dtype=np.float32, eta_max=1.0):
+    """Tracks crossing concentric cylinders at the given radii, hits in track
+    order: fit rows with any number of hits (3 to 8), all on barrel-like
+    surfaces (layer ids 0..3, the later cylinders labelled 3), smeared like
+    barrel hits.  Tracks that do not reach the last radius are dropped."""
+    rng = np.random.Generator(np.random.PCG64([seed, 7]))
+    radii = np.asarray(radii, np.float64)
+    n = len(radii)
+    out = []
+    have = 0
+    while have < n_tracks:
+        trk = draw_tracks(rng, 2 * n_tracks, pt="power", eta_max=eta_max)
+        S = np.stack([_barrel_s(trk["kappa"], trk["d0"], R) for R in radii], axis=1)
+        ok = np.all(np.isfinite(S), axis=1) & np.all(np.diff(S, axis=1) > 0, axis=1)
+        idx = np.nonzero(ok)[0][: n_tracks - have]
+        out.append(({k: v[idx] for k, v in trk.items()}, S[idx]))
+        have += len(idx)
+    sub = {k: np.concatenate([o[0][k] for o in out]) for k in out[0][0]}
+    S = np.concatenate([o[1] for o in out])
+    ti = np.repeat(np.arange(n_tracks), n)
+    s = S.reshape(-1)
+    li = np.tile(np.minimum(np.arange(n), 3), n_tracks).astype(np.uint8)
+    x, y = helix_xy(sub["kappa"][ti], sub["phi0"][ti], sub["d0"][ti], s)
+    z = sub["z0"][ti] + s * sub["cot"][ti]
+    r_nom = np.tile(radii, n_tracks)
+    rr = np.hypot(x, y)
+    x, y = x * r_nom / rr, y * r_nom / rr
+    x, y, z = _smear(rng, li, x, y, z, _SIGMAS)
+    x, y, z = x.astype(dtype), y.astype(dtype), z.astype(dtype)
+    mod = module_id(li, x.astype(np.float64), y.astype(np.float64), z.astype(np.float64))
+    tuplets = np.full((n_tracks, 8), -1, dtype=np.int32)
+    tuplets[:, :n] = np.arange(n_tracks * n, dtype=np.int32).reshape(n_tracks, n)
+    hits = Hits(x, y, z, li, mod, ti.astype(np.int32), np.array([0, x.shape[0]], dtype=np.int32), [])
+    params = np.stack([sub["kappa"], sub["phi0"], sub["cot"], sub["d0"], sub["z0"]], axis=1)
+    return TrackSet(hits, tuplets, np.full(n_tracks, n, np.uint8), params)

@@ -42,3 +42,14 @@ def tuplets_from_tracks(track_ids, n_tracks, min_hits=1):
         if t >= 0:
             out[t].append(h)
     return [o for o in out if len(o) >= min_hits]
+
+
+def sorted_keys(*cols):
+    """Rows of non-negative int columns (each < 2^21) packed into sorted int64
+    keys: a fast canonical form of a set of index tuples."""
+    key = np.zeros(np.asarray(cols[0]).shape, np.int64)
+    for c in cols:
+        c = np.asarray(c, np.int64)
+        assert c.size == 0 or (c.min() >= 0 and c.max() < (1 << 21))
+        key = (key << 21) | c
+    return np.sort(key)

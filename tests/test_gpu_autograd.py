@@ -43,7 +43,7 @@ def test_gradcheck_double():
         p, c2, _ = broken_line_fit(x_, y_, z_, layer, module, tup, nh, None, fc)
         return p, c2
 
-    assert torch.autograd.gradcheck(f, (x, y, z), eps=1e-6, atol=1e-4, rtol=1e-3)
+    assert torch.autograd.gradcheck(f, (x, y, z), eps=1e-6, atol=1e-6, rtol=1e-4)
 
 
 def test_float_gradients_match_oracle():

@@ -120,8 +120,11 @@ def test_permuted_hits_give_the_same_sets():
 
 
 def test_plan_graph_replays_match_eager():
-    """Several replays of the captured step, with eager work in between, each
-    checked against the eager calls."""
+    """Several replays of the captured step (module offsets, the adjoint with
+    hit and module gradients), with eager work in between, each checked
+    against the eager calls: the same rows in the same order, the same
+    parameters bit for bit, gradients equal up to the order of the atomic
+    additions."""
     _need_gpu()
     from paper_2008_13461_amd import _abi as A
     from paper_2008_13461_amd import api
@@ -131,40 +134,44 @@ def test_plan_graph_replays_match_eager():
     cfg = A.make_config(CFG)
     hits = api.Hits.from_host(h)
     off = torch.from_numpy(E.module_offsets()).cuda()
-    # the same cotangent for every row: row order comes from atomics, so a
-    # per-row cotangent would attach to different tracks in different runs
-    g1, c1 = E.cotangents(3, 1)
-    gp = torch.from_numpy(np.repeat(g1, caps["tuplets_cap"], axis=0)).cuda()
-    gc = torch.from_numpy(np.repeat(c1, caps["tuplets_cap"], axis=0)).cuda()
+    # rows come out in the same order on every run, so each row has its own
+    # cotangent
+    g_np, c_np = E.cotangents(3, caps["tuplets_cap"])
+    gp = torch.from_numpy(g_np).cuda()
+    gc = torch.from_numpy(c_np).cuda()
     # eager reference
     pipe = api.Pipeline(CFG, **caps)
     pipe.reconstruct(hits, offsets=off)
     gh_ref = torch.zeros((h.n_hits, 3), dtype=torch.float32, device="cuda")
-    pipe.backward(hits, gp, gc, gh_ref, None, offsets=off)
+    go_ref = torch.zeros((C.N_MODULES, 3), dtype=torch.float64, device="cuda")
+    pipe.backward(hits, gp, gc, gh_ref, go_ref, offsets=off)
     torch.cuda.synchronize()
-    ref_t = tuplet_set(*(t.cpu().numpy() for t in pipe.tuplets.kept_rows()))
     nk = int(pipe.tuplets.count.item())
-    ref_rows = pipe.tuplets.kept_rows()[0].cpu().numpy()
+    ref_rows, ref_n = (t.cpu().numpy() for t in pipe.tuplets.kept_rows())
     ref_p = pipe.tracks.params[:nk].cpu().numpy()
-    order_ref = np.lexsort(ref_rows.T[::-1])
+    ref_c = pipe.tracks.chi2[:nk].cpu().numpy()
     plan = api.Plan(cfg, precision=A.PT_FIT_F32_F64SOLVE, with_adjoint=True, **caps)
     cells = api.Cells.empty(caps["cells_cap"], h.n_hits)
     links = api.Links.empty(caps["links_cap"], caps["cells_cap"])
     tup = api.Tuplets.empty(caps["tuplets_cap"])
     tracks = api.Tracks.empty(caps["tuplets_cap"], A.PT_FIT_F32_F64SOLVE)
     status = api.new_status()
+    gh = torch.zeros((h.n_hits, 3), dtype=torch.float32, device="cuda")
+    go = torch.zeros((C.N_MODULES, 3), dtype=torch.float64, device="cuda")
     for rep in range(4):
-        gh = torch.zeros((h.n_hits, 3), dtype=torch.float32, device="cuda")
-        plan.run(hits, cells, links, tup, tracks, status, offsets=off, g_params=gp, g_chi2=gc, grad_hits=gh)
+        gh.zero_()
+        go.zero_()
+        plan.run(hits, cells, links, tup, tracks, status, offsets=off, g_params=gp, g_chi2=gc, grad_hits=gh,
+                 grad_offsets=go)
         torch.cuda.synchronize()
-        got_rows = tup.kept_rows()[0].cpu().numpy()
-        assert tuplet_set(got_rows, tup.kept_rows()[1].cpu().numpy()) == ref_t, rep
-        got_p = tracks.params[:nk].cpu().numpy()
-        order = np.lexsort(got_rows.T[::-1])
-        assert np.array_equal(got_rows[order], ref_rows[order_ref])
-        assert np.allclose(got_p[order], ref_p[order_ref], rtol=0, atol=0, equal_nan=True)
-        # hit gradients: same sums up to the order of float atomic additions
-        assert (torch.linalg.norm(gh - gh_ref) / torch.linalg.norm(gh_ref)).item() <= 1e-5
+        got_rows, got_n = (t.cpu().numpy() for t in tup.kept_rows())
+        assert np.array_equal(got_rows, ref_rows) and np.array_equal(got_n, ref_n), rep
+        assert np.array_equal(tracks.params[:nk].cpu().numpy(), ref_p, equal_nan=True), rep
+        assert np.array_equal(tracks.chi2[:nk].cpu().numpy(), ref_c, equal_nan=True), rep
+        # hit gradients: float sums in another order
+        assert (torch.linalg.norm(gh - gh_ref) / torch.linalg.norm(gh_ref)).item() <= 1e-5, rep
+        # module gradients: double sums in another order
+        assert (torch.abs(go - go_ref).max() / torch.abs(go_ref).max()).item() <= 1e-12, rep
         # eager work between replays
         pipe.reconstruct(hits, offsets=off)
         torch.cuda.synchronize()

@@ -36,9 +36,9 @@ def _run_fit(ts, precision, offsets, with_grad=False, g=None):
     out = dict(params=tracks.params.cpu().numpy().astype(np.float64), chi2=tracks.chi2.cpu().numpy().astype(np.float64),
                status=tracks.status.cpu().numpy(), flags=status.cpu().numpy())
     if with_grad:
-        gp = torch.from_numpy(g[0]).cuda()
-        gc = torch.from_numpy(g[1]).cuda()
         gdt = torch.float64 if precision == A.PT_FIT_F64 else torch.float32
+        gp = torch.from_numpy(g[0]).cuda().to(gdt)
+        gc = torch.from_numpy(g[1]).cuda().to(gdt)
         gh = torch.zeros((h.n_hits, 3), dtype=gdt, device="cuda")
         go = torch.zeros((C.N_MODULES, 3), dtype=torch.float64, device="cuda")
         api.fit_broken_line_bwd(hits, cfg, tup, off, precision, gp, gc, gh, go, status, ws)

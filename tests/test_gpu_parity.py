@@ -3,7 +3,8 @@
 Integer products (doublets, links, n-tuplets before and after duplicate
 removal) must be identical as sets; fits must agree within 1e-9 relative in
 double precision and 1e-4 relative in single precision (with the floors of
-tests/helpers.py for quantities that cross zero).
+tests/helpers.py for quantities that cross zero), chi2 within 1e-9 (double)
+and 1e-3 (single) of max(chi2, 1).
 """
 import numpy as np
 import pytest
@@ -58,7 +59,8 @@ def _compare_event(prod, h, e, cfg=CFG, fit_tol=None, precision_f64=False):
         err = param_rel_err(prod["params"][ksel], params)
         assert err.max() <= fit_tol, (err.max(axis=0), e)
         cerr = np.abs(prod["chi2"][ksel] - chi2) / np.maximum(np.abs(chi2), 1.0)
-        assert cerr.max() <= (fit_tol if precision_f64 else 2e-2)
+        # chi2 of the single-precision fit: within 1e-3 of max(chi2, 1)
+        assert cerr.max() <= (fit_tol if precision_f64 else 1e-3)
     return len(got_d), len(got_l), int(ksel.sum())
 
 
