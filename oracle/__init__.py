@@ -19,6 +19,10 @@ Parity status of each function (pins in tests/test_oracle_*.py):
                 no-scattering limit against textbook polynomial regression,
                 dense solve against numpy, chi2 statistics
   fit gradient  pinned: central finite differences, translation identities
+  fit covariance pinned: numpy inverses of the normal matrices, sample
+                covariance of repeated simulations of one track, pulls of a
+                population of tracks, symmetries
+  ambiguity     pinned: brute force over all pairs of tracks in Python
 """
 from __future__ import annotations
 
@@ -117,6 +121,12 @@ def lib():
         L.oracle_fit_debug.argtypes = [P, ct.c_int32] + [P] * 18
         L.oracle_fit_jacobian.restype = ct.c_int32
         L.oracle_fit_jacobian.argtypes = [P, ct.c_int32, P, P, P, P, P]
+        L.oracle_fit_cov.restype = None
+        L.oracle_fit_cov.argtypes = [P, ct.c_int64, P, P, P, P, P, P, P, P, P]
+        L.oracle_fit_cov_debug.restype = ct.c_int32
+        L.oracle_fit_cov_debug.argtypes = [P, ct.c_int32, P, P, P, P, P, P, P]
+        L.oracle_ambiguity.restype = ct.c_int64
+        L.oracle_ambiguity.argtypes = [ct.c_int64, P, P, P, P, P, P]
         L.oracle_fit_grad.restype = None
         L.oracle_fit_grad.argtypes = [P, ct.c_int64, P, P, P, P, P, P, P, P, P, P, P, P]
         _lib = L
@@ -252,6 +262,62 @@ def fit_jacobian(cfg, X, Y, Z, layers):
     if st != 0:
         raise ValueError(f"fit status {st}")
     return jac.reshape(6, n, 3)
+
+
+COV_INDEX = [(a, b) for a in range(5) for b in range(a, 5)]
+
+
+def cov_full(c15):
+    """[..., 15] upper triangles -> [..., 5, 5] symmetric matrices."""
+    c15 = np.asarray(c15)
+    out = np.empty(c15.shape[:-1] + (5, 5))
+    for q, (a, b) in enumerate(COV_INDEX):
+        out[..., a, b] = c15[..., q]
+        out[..., b, a] = c15[..., q]
+    return out
+
+
+def fit_cov(cfg, tuplets, nhits, x, y, z, layer, module=None, offsets=None):
+    """Covariance of every fit: [N, 15], the upper triangle of the 5x5
+    covariance of (kappa, phi0, cot_theta, d0, z0) row by row; NaN rows for
+    failed fits."""
+    tup = np.ascontiguousarray(tuplets, dtype=np.int32)
+    nh = np.ascontiguousarray(nhits, dtype=np.uint8)
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    layer = np.ascontiguousarray(layer, dtype=np.uint8)
+    mod = np.ascontiguousarray(module if module is not None else np.zeros(x.shape[0]), dtype=np.int16)
+    off = _f64(offsets).reshape(-1) if offsets is not None else None
+    cov = np.empty((tup.shape[0], 15), np.float64)
+    lib().oracle_fit_cov(ct.byref(_config(cfg)), tup.shape[0], _p(tup), _p(nh), _p(x), _p(y), _p(z), _p(layer),
+                         _p(mod), _p(off), _p(cov))
+    return cov
+
+
+def fit_cov_debug(cfg, X, Y, Z, layers):
+    """(jc [5, n+1], jl [5, n], cov [5, 5]) of one track given its hit coordinates."""
+    n = len(X)
+    X, Y, Z = _f64(X), _f64(Y), _f64(Z)
+    lay = np.ascontiguousarray(layers, dtype=np.int32)
+    jc = np.empty(5 * (n + 1))
+    jl = np.empty(5 * n)
+    cov = np.empty(25)
+    st = lib().oracle_fit_cov_debug(ct.byref(_config(cfg)), n, _p(X), _p(Y), _p(Z), _p(lay), _p(jc), _p(jl),
+                                    _p(cov))
+    if st != 0:
+        raise ValueError(f"fit status {st}")
+    return jc.reshape(5, n + 1), jl.reshape(5, n), cov.reshape(5, 5)
+
+
+def ambiguity(hits, cells, nhits, chi2, tip):
+    """Ambiguity resolution of section 3.5: bool keep [N] (see oracle.cpp)."""
+    h = np.ascontiguousarray(hits, dtype=np.int32)
+    c = np.ascontiguousarray(cells, dtype=np.int32)
+    nh = np.ascontiguousarray(nhits, dtype=np.uint8)
+    c2 = _f64(chi2)
+    tp = _f64(tip)
+    keep = np.empty(h.shape[0], np.uint8)
+    lib().oracle_ambiguity(h.shape[0], _p(h), _p(c), _p(nh), _p(c2), _p(tp), _p(keep))
+    return keep.astype(bool)
 
 
 def fit_grad(cfg, tuplets, nhits, x, y, z, layer, module, offsets, g_params, g_chi2, n_modules=1856):

@@ -33,6 +33,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <vector>
 
 namespace {
@@ -468,8 +469,57 @@ struct FitResult {
   // intermediate quantities, exported for the tests' independent checks
   std::vector<T> s, um, delta, wT, wZ, VZ, ucirc, vline;
   T kappa_pre, t_pre, p;
+  T tx, ty;  // direction of the pre-fit at P_0
   std::vector<T> A, b, N, q;
 };
+
+// 8. Perigee parameters from the fitted quantities at s = 0 (section 3.4:
+// the circle fit gives d0, p_T and phi, the line fit cot(theta) and the z
+// of the point of closest approach, combined here).
+//   u0, u1, dk   circle solution: offsets at hits 0 and 1, curvature correction
+//   v0, v1       line solution: z at hits 0 and 1
+//   kappa_pre, D0 (= s_1 - s_0), P_0 = (X0, Y0) and the pre-fit direction
+//   (tx, ty) at P_0 define the local frame.
+// The fitted point is Q = P_0 + u0 n (n the left normal), its direction psi
+// the pre-fit direction turned by atan(u'_0) with
+// u'_0 = (u1 - u0) / D0 - dk D0 / 2; the circle of curvature
+// kappa = kappa_pre + dk through Q with direction psi has the signed distance
+// d0 to the origin (U = kappa |Q|^2 + 2 Q x (cos psi, sin psi),
+// d0 = U / (1 + sqrt(1 + kappa U))) and the direction phi0 at its point of
+// closest approach; cot(theta) = (v1 - v0) / D0, and z0 extrapolates v0 back
+// along the arc ds from the point of closest approach to Q.
+template <class T>
+void perigee(T u0, T u1, T dk, T v0, T v1, T kappa_pre, T D0, T X0, T Y0, T tx, T ty, T out[5]) {
+  const T one = cst<T>(1.0), two = cst<T>(2.0);
+  const T nx = -ty, ny = tx;
+  const T kappa = kappa_pre + dk;
+  const T Qx = X0 + u0 * nx;
+  const T Qy = Y0 + u0 * ny;
+  const T du0 = (u1 - u0) / D0 - dk * D0 / two;
+  // direction psi = psi_pre + atan(du0): (tx, ty) rotated by atan(du0)
+  const T ca = one / sqrt(one + du0 * du0);
+  const T sa = du0 * ca;
+  const T cpsi = tx * ca - ty * sa;
+  const T spsi = ty * ca + tx * sa;
+  const T U = kappa * (Qx * Qx + Qy * Qy) + two * (-Qx * spsi + Qy * cpsi);
+  const T d0 = U / (one + sqrt(one + kappa * U));
+  // direction at the point of closest approach
+  const T hx = cpsi + kappa * Qy, hy = spsi - kappa * Qx;
+  const T phi0 = atan2(hy, hx);
+  const T hn = sqrt(hx * hx + hy * hy);
+  const T cph = hx / hn, sph = hy / hn;
+  const T at = Qx * cph + Qy * sph;
+  const T an = -Qx * sph + Qy * cph;
+  T ds = at;
+  if (val(kappa) != 0.0) ds = atan2(kappa * at, one + kappa * (d0 - an)) / kappa;
+  const T cot = (v1 - v0) / D0;
+  const T z0 = v0 - cot * ds;
+  out[0] = kappa;
+  out[1] = phi0;
+  out[2] = cot;
+  out[3] = d0;
+  out[4] = z0;
+}
 
 // The fit of one n-tuplet, hits P_k = (X_k, Y_k, Z_k), k = 0..n-1, inside out.
 //
@@ -535,6 +585,8 @@ FitResult<T> fit_track(const FitSettings& F, int n, const T* X, const T* Y, cons
     ty = vy / lv;
   }
   const T nx = -ty, ny = tx;
+  R.tx = tx;
+  R.ty = ty;
 
   // 2. arc lengths and offsets
   R.s.assign(n, zero);
@@ -677,35 +729,13 @@ FitResult<T> fit_track(const FitSettings& F, int n, const T* X, const T* Y, cons
   }
 
   // 8. perigee parameters
-  const T dk = xsol[n];
-  const T kappa = kappa_pre + dk;
-  const T Qx = X[0] + xsol[0] * nx;
-  const T Qy = Y[0] + xsol[0] * ny;
-  const T du0 = (xsol[1] - xsol[0]) / R.delta[0] - dk * R.delta[0] / two;
-  // direction psi = psi_pre + atan(du0): (tx, ty) rotated by atan(du0)
-  const T ca = one / sqrt(one + du0 * du0);
-  const T sa = du0 * ca;
-  const T cpsi = tx * ca - ty * sa;
-  const T spsi = ty * ca + tx * sa;
-  const T U = kappa * (Qx * Qx + Qy * Qy) + two * (-Qx * spsi + Qy * cpsi);
-  const T d0 = U / (one + sqrt(one + kappa * U));
-  // direction at the point of closest approach
-  const T hx = cpsi + kappa * Qy, hy = spsi - kappa * Qx;
-  const T phi0 = atan2(hy, hx);
-  const T hn = sqrt(hx * hx + hy * hy);
-  const T cph = hx / hn, sph = hy / hn;
-  const T at = Qx * cph + Qy * sph;
-  const T an = -Qx * sph + Qy * cph;
-  T ds = at;
-  if (val(kappa) != 0.0) ds = atan2(kappa * at, one + kappa * (d0 - an)) / kappa;
-  const T cot = (vsol[1] - vsol[0]) / R.delta[0];
-  const T z0 = vsol[0] - cot * ds;
-
-  R.kappa = kappa;
-  R.phi0 = phi0;
-  R.cot = cot;
-  R.d0 = d0;
-  R.z0 = z0;
+  T par[5];
+  perigee<T>(xsol[0], xsol[1], xsol[n], vsol[0], vsol[1], kappa_pre, R.delta[0], X[0], Y[0], tx, ty, par);
+  R.kappa = par[0];
+  R.phi0 = par[1];
+  R.cot = par[2];
+  R.d0 = par[3];
+  R.z0 = par[4];
   R.chi2 = chi2T + chi2Z;
   return R;
 }
@@ -726,6 +756,66 @@ void gather(int n, const int32_t* hit, const double* x, const double* y, const d
     }
     lay[k] = layer[h];
   }
+}
+
+// Covariance of the fitted (kappa, phi0, cot, d0, z0) (section 3.4: the
+// circle fit and the line fit each give their parameters with a covariance,
+// and the two are combined).  The broken-line solutions are linear in the
+// measurements with the kinks as zero-mean pseudo-measurements, so the
+// covariance of the circle unknowns (u_0..u_{n-1}, dk) is A^-1 and that of
+// the line unknowns (v_0..v_{n-1}) is N^-1, the inverses of the two normal
+// matrices; the two fits share no measurement and are independent.  Through
+// the perigee map of step 8, linearised at the solution (pre-fit held fixed):
+//   C = Jc A^-1 Jc^T + Jl N^-1 Jl^T,
+// Jc = d(params)/d(circle unknowns), Jl = d(params)/d(line unknowns).  The
+// map depends on the circle only through u_0, u_1 and dk and on the line only
+// through v_0 and v_1; those columns of Jc and Jl come from dual numbers
+// seeded on each, the others are zero.
+// jc [5][n+1], jl [5][n] and cov [5][5] are row-major.
+int fit_cov(const FitSettings& F, int n, const Real* X, const Real* Y, const Real* Z, const int* lay,
+            Real* jc, Real* jl, Real* cov) {
+  const FitResult<Real> R = fit_track<Real>(F, n, X, Y, Z, lay);
+  if (R.status != FIT_OK) return R.status;
+  const int m = n + 1;
+  // inverses column by column
+  std::vector<Real> Ainv(m * m), Ninv(n * n), e, col;
+  for (int j = 0; j < m; ++j) {
+    e.assign(m, 0.0L);
+    e[j] = 1.0L;
+    if (!gauss_solve(m, R.A, e, col)) return FIT_SINGULAR;
+    for (int i = 0; i < m; ++i) Ainv[i * m + j] = col[i];
+  }
+  for (int j = 0; j < n; ++j) {
+    e.assign(n, 0.0L);
+    e[j] = 1.0L;
+    if (!gauss_solve(n, R.N, e, col)) return FIT_SINGULAR;
+    for (int i = 0; i < n; ++i) Ninv[i * n + j] = col[i];
+  }
+  // Jacobians: one dual pass per unknown the perigee map reads
+  auto D = [](Real v, bool seed) { return Dual{v, seed ? 1.0L : 0.0L}; };
+  for (int i = 0; i < 5 * m; ++i) jc[i] = 0.0L;
+  for (int i = 0; i < 5 * n; ++i) jl[i] = 0.0L;
+  const int ids[5] = {0, 1, n, 0, 1};  // circle u0, u1, dk; line v0, v1
+  for (int q = 0; q < 5; ++q) {
+    Dual out[5];
+    perigee<Dual>(D(R.ucirc[0], q == 0), D(R.ucirc[1], q == 1), D(R.ucirc[n], q == 2), D(R.vline[0], q == 3),
+                  D(R.vline[1], q == 4), D(R.kappa_pre, false), D(R.delta[0], false), D(X[0], false),
+                  D(Y[0], false), D(R.tx, false), D(R.ty, false), out);
+    for (int o = 0; o < 5; ++o) {
+      if (q < 3) jc[o * m + ids[q]] = out[o].d;
+      else jl[o * n + ids[q]] = out[o].d;
+    }
+  }
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b) {
+      Real s = 0.0L;
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) s += jc[a * m + i] * Ainv[i * m + j] * jc[b * m + j];
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) s += jl[a * n + i] * Ninv[i * n + j] * jl[b * n + j];
+      cov[a * 5 + b] = s;
+    }
+  return FIT_OK;
 }
 
 }  // namespace
@@ -871,6 +961,113 @@ void oracle_fit_grad(const oracle_config* cfg, int64_t n_tracks, const int32_t* 
       if (grad_offsets) grad_offsets[3 * module[hit[k]] + c] += acc;
     }
   }
+}
+
+// Covariance of every fit: cov [n_tracks][15], the upper triangle of the
+// symmetric 5x5 covariance of (kappa, phi0, cot, d0, z0) row by row
+// ((0,0) (0,1) .. (0,4) (1,1) .. (4,4)); NaN for tracks whose fit fails.
+// Inputs as oracle_fit.  See fit_cov for the definition.
+void oracle_fit_cov(const oracle_config* cfg, int64_t n_tracks, const int32_t* tuplets, const uint8_t* nhits,
+                    const double* x, const double* y, const double* z, const uint8_t* layer,
+                    const int16_t* module, const double* offsets, double* cov_out) {
+  const FitSettings F = fit_settings(*cfg);
+  double X[kMaxHits], Y[kMaxHits], Z[kMaxHits];
+  int lay[kMaxHits];
+  Real jc[5 * (kMaxHits + 1)], jl[5 * kMaxHits], cov[25];
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    const int n = nhits[t];
+    double* o = cov_out + 15 * t;
+    gather(n, tuplets + t * kMaxHits, x, y, z, layer, module, offsets, X, Y, Z, lay);
+    Real XL[kMaxHits], YL[kMaxHits], ZL[kMaxHits];
+    for (int k = 0; k < n; ++k) {
+      XL[k] = X[k];
+      YL[k] = Y[k];
+      ZL[k] = Z[k];
+    }
+    const int st = fit_cov(F, n, XL, YL, ZL, lay, jc, jl, cov);
+    int q = 0;
+    for (int a = 0; a < 5; ++a)
+      for (int b = a; b < 5; ++b) o[q++] = st == FIT_OK ? static_cast<double>(cov[a * 5 + b]) : NAN;
+  }
+}
+
+// The pieces of one track's covariance, for the tests: jc [5][n+1], jl
+// [5][n], cov [5][5] (row-major).  Returns the fit status.
+int32_t oracle_fit_cov_debug(const oracle_config* cfg, int32_t n, const double* X, const double* Y,
+                             const double* Z, const int32_t* layer_k, double* jc, double* jl, double* cov) {
+  const FitSettings F = fit_settings(*cfg);
+  if (n < 3 || n > kMaxHits) return FIT_SINGULAR;
+  int lay[kMaxHits] = {};
+  Real XL[kMaxHits] = {}, YL[kMaxHits] = {}, ZL[kMaxHits] = {};
+  for (int k = 0; k < n; ++k) {
+    lay[k] = layer_k[k];
+    XL[k] = X[k];
+    YL[k] = Y[k];
+    ZL[k] = Z[k];
+  }
+  Real a[5 * (kMaxHits + 1)], b[5 * kMaxHits], c[25];
+  const int st = fit_cov(F, n, XL, YL, ZL, lay, a, b, c);
+  if (st != FIT_OK) return st;
+  for (int i = 0; i < 5 * (n + 1); ++i) jc[i] = static_cast<double>(a[i]);
+  for (int i = 0; i < 5 * n; ++i) jl[i] = static_cast<double>(b[i]);
+  for (int i = 0; i < 25; ++i) cov[i] = static_cast<double>(c[i]);
+  return st;
+}
+
+// Ambiguity resolution among fitted tracks (section 3.5).
+// Tracks: hit rows hits [n][8], cell rows cells [n][7] (the row's doublets,
+// inside -> out), nhits [n]; chi2 [n] and tip [n] (the transverse impact
+// parameter d0) of their fits.  A track takes part when its chi2 is finite.
+//   1. Tracks sharing a hit doublet (a cell) are ambiguous: a track is
+//      dropped when a track sharing one of its cells has a smaller chi2
+//      (equal chi2: both stay).
+//   2. Among the 3-hit tracks that survive step 1, tracks sharing a hit are
+//      ambiguous: a triplet is dropped when a triplet sharing one of its hits
+//      has a smaller |tip| (equal: both stay).
+// keep [n] receives 1 for the tracks that stay, 0 otherwise.  Returns the
+// number kept.
+int64_t oracle_ambiguity(int64_t n_tracks, const int32_t* hits, const int32_t* cells, const uint8_t* nhits,
+                         const double* chi2, const double* tip, uint8_t* keep) {
+  std::vector<uint8_t> cand(n_tracks), keep1(n_tracks, 0);
+  for (int64_t t = 0; t < n_tracks; ++t) cand[t] = std::isfinite(chi2[t]) ? 1 : 0;
+  // step 1: the smallest chi2 among the candidates through each cell
+  std::map<int32_t, double> best_cell;
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    if (!cand[t]) continue;
+    for (int k = 0; k + 1 < nhits[t]; ++k) {
+      const int32_t c = cells[t * (kMaxHits - 1) + k];
+      auto it = best_cell.find(c);
+      if (it == best_cell.end() || chi2[t] < it->second) best_cell[c] = chi2[t];
+    }
+  }
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    if (!cand[t]) continue;
+    bool ok = true;
+    for (int k = 0; k + 1 < nhits[t]; ++k)
+      if (best_cell[cells[t * (kMaxHits - 1) + k]] < chi2[t]) ok = false;
+    keep1[t] = ok ? 1 : 0;
+  }
+  // step 2: the smallest |tip| among the surviving triplets through each hit
+  std::map<int32_t, double> best_hit;
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    if (!keep1[t] || nhits[t] != 3) continue;
+    for (int k = 0; k < 3; ++k) {
+      const int32_t h = hits[t * kMaxHits + k];
+      const double a = std::fabs(tip[t]);
+      auto it = best_hit.find(h);
+      if (it == best_hit.end() || a < it->second) best_hit[h] = a;
+    }
+  }
+  int64_t kept = 0;
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    bool ok = keep1[t] != 0;
+    if (ok && nhits[t] == 3)
+      for (int k = 0; k < 3; ++k)
+        if (best_hit[hits[t * kMaxHits + k]] < std::fabs(tip[t])) ok = false;
+    keep[t] = ok ? 1 : 0;
+    kept += ok;
+  }
+  return kept;
 }
 
 int32_t oracle_abi_version(void) { return 1; }
