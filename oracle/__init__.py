@@ -23,6 +23,9 @@ Parity status of each function (pins in tests/test_oracle_*.py):
                 covariance of repeated simulations of one track, pulls of a
                 population of tracks, symmetries
   ambiguity     pinned: brute force over all pairs of tracks in Python
+  vertices      pinned: hand-built clusters with known answers (densities,
+                links, splits, ordering), symmetries (z shift, order of the
+                tracks), truth vertices of simulated events
 """
 from __future__ import annotations
 
@@ -127,6 +130,10 @@ def lib():
         L.oracle_fit_cov_debug.argtypes = [P, ct.c_int32, P, P, P, P, P, P, P]
         L.oracle_ambiguity.restype = ct.c_int64
         L.oracle_ambiguity.argtypes = [ct.c_int64, P, P, P, P, P, P]
+        L.oracle_vertices.restype = ct.c_int64
+        L.oracle_vertices.argtypes = [ct.c_int64, P, P, P, P, P, ct.c_int32, ct.c_double, ct.c_double,
+                                      ct.c_double, ct.c_double, ct.c_double, ct.c_double, ct.c_int32, ct.c_double,
+                                      ct.c_int64, P, P, P, P, P, P, P]
         L.oracle_fit_grad.restype = None
         L.oracle_fit_grad.argtypes = [P, ct.c_int64, P, P, P, P, P, P, P, P, P, P, P, P]
         _lib = L
@@ -318,6 +325,31 @@ def ambiguity(hits, cells, nhits, chi2, tip):
     keep = np.empty(h.shape[0], np.uint8)
     lib().oracle_ambiguity(h.shape[0], _p(h), _p(c), _p(nh), _p(c2), _p(tp), _p(keep))
     return keep.astype(bool)
+
+
+def vertices(cfg, z0, var_z0, kappa, nhits, use=None):
+    """Pixel vertices of one event (section 3.6; see oracle.cpp).
+
+    Returns dict: z, var, chi2, ndf, n_tracks, sum_pt2 per vertex (largest
+    sum_pt2 first) and track_vertex [N] (vertex index or -1)."""
+    z0, var = _f64(z0), _f64(var_z0)
+    kap = _f64(kappa)
+    nh = np.ascontiguousarray(nhits, dtype=np.uint8)
+    n = z0.shape[0]
+    u = np.ascontiguousarray(np.ones(n, bool) if use is None else use, dtype=np.uint8)
+    K = 0.299792458 * cfg["bfield"] / 100.0
+    cap = max(16, n)
+    out = {k: np.empty(cap, np.float64) for k in ("z", "var", "chi2", "sum_pt2")}
+    ndf = np.empty(cap, np.int32)
+    nt = np.empty(cap, np.int32)
+    tv = np.empty(n, np.int32)
+    nv = lib().oracle_vertices(n, _p(z0), _p(var), _p(kap), _p(nh), _p(u), cfg["vtx_min_hits"], cfg["vtx_pt_min"],
+                               cfg["vtx_err_max"], cfg["vtx_dz_cut"], cfg["vtx_chi2_max"], cfg["vtx_split_chi2_ndf"],
+                               cfg["vtx_pt_cap"], cfg["vtx_kmeans_iter"], K, cap, _p(out["z"]), _p(out["var"]),
+                               _p(out["chi2"]), _p(ndf), _p(nt), _p(out["sum_pt2"]), _p(tv))
+    res = {k: v[:nv] for k, v in out.items()}
+    res.update(ndf=ndf[:nv], n_tracks=nt[:nv], track_vertex=tv)
+    return res
 
 
 def fit_grad(cfg, tuplets, nhits, x, y, z, layer, module, offsets, g_params, g_chi2, n_modules=1856):

@@ -1070,6 +1070,177 @@ int64_t oracle_ambiguity(int64_t n_tracks, const int32_t* hits, const int32_t* c
   return kept;
 }
 
+// Pixel vertices of one event (section 3.6), from its fitted tracks.
+// Per track: z0, var_z0 (its variance, the (z0, z0) element of the fit
+// covariance), kappa, nhits and use (1 for tracks that survived ambiguity
+// resolution).  Settings: min_hits, pt_min, err_max (largest sigma(z0) for
+// which a density is computed), dz_cut, chi2_max, split_chi2_ndf, pt_cap,
+// kmeans_iter, K (p_T = K / |kappa|).
+//  1. Tracks take part when used, with at least min_hits hits, p_T > pt_min
+//     and a finite z0 with a positive finite variance.
+//  2. Density of track i (only when sigma(z0) <= err_max, else 0): the
+//     number of other taking-part tracks j with |z_i - z_j| < dz_cut and
+//     (z_i - z_j)^2 < chi2_max (var_i + var_j).
+//  3. Tracks are ranked by (density, index).  Each track links to the
+//     nearest (smallest |z_i - z_j|, then smallest j) higher-ranked track
+//     with |z_i - z_j| < dz_cut and (z_i - z_j)^2 <= chi2_max (var_i + var_j);
+//     links only climb in rank, so they form trees.
+//  4. The tracks of a tree whose root has density > 1 (a seed) form a vertex
+//     candidate; candidates with at least 2 tracks are vertices.
+//  5. Each vertex: members in order of (z0, index); weights w = 1 / var;
+//     z = sum w z0 / sum w, var = 1 / sum w, chi2 = sum w (z0 - z)^2,
+//     ndf = members - 1, sums taken in member order.
+//  6. A vertex with chi2 / ndf > split_chi2_ndf is split in two by 1-D
+//     k-means: centres at its smallest and largest z0; each member goes to
+//     the nearer centre (the first on a tie); centres move to the weighted
+//     means of their members (member order); repeated until no member moves
+//     or kmeans_iter rounds.  Each part with at least 2 members becomes a
+//     vertex (step 5); members of a part of one track are left out.
+//  7. Vertices are ordered by sum over members of min(p_T, pt_cap)^2,
+//     largest first (the first is the primary vertex); equal sums keep the
+//     order of their smallest-z member.
+// Outputs (capacity cap): vz, vvar, vchi2, vndf, vn, vsum; track_vertex [n]
+// (vertex position in that order, or -1).  Returns the number of vertices.
+int64_t oracle_vertices(int64_t n, const double* z0, const double* var_z0, const double* kappa,
+                        const uint8_t* nhits, const uint8_t* use, int32_t min_hits, double pt_min,
+                        double err_max, double dz_cut, double chi2_max, double split_chi2_ndf, double pt_cap,
+                        int32_t kmeans_iter, double K, int64_t cap, double* vz, double* vvar, double* vchi2,
+                        int32_t* vndf, int32_t* vn, double* vsum, int32_t* track_vertex) {
+  std::vector<double> pt(n);
+  std::vector<uint8_t> part(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    pt[i] = K / std::fabs(kappa[i]);
+    part[i] = use[i] && nhits[i] >= min_hits && pt[i] > pt_min && std::isfinite(z0[i]) &&
+              std::isfinite(var_z0[i]) && var_z0[i] > 0.0;
+    track_vertex[i] = -1;
+  }
+  // 2. densities
+  std::vector<int64_t> rho(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!part[i] || !(std::sqrt(var_z0[i]) <= err_max)) continue;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i || !part[j]) continue;
+      const double d = z0[i] - z0[j];
+      if (std::fabs(d) < dz_cut && d * d < chi2_max * (var_z0[i] + var_z0[j])) ++rho[i];
+    }
+  }
+  // 3. links to the nearest higher-ranked compatible track
+  auto higher = [&](int64_t j, int64_t i) { return rho[j] > rho[i] || (rho[j] == rho[i] && j > i); };
+  std::vector<int64_t> parent(n, -1);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!part[i]) continue;
+    double best = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (!part[j] || !higher(j, i)) continue;
+      const double d = z0[i] - z0[j];
+      if (!(std::fabs(d) < dz_cut && d * d <= chi2_max * (var_z0[i] + var_z0[j]))) continue;
+      if (parent[i] < 0 || std::fabs(d) < best) {  // j ascending: ties keep the smaller j
+        parent[i] = j;
+        best = std::fabs(d);
+      }
+    }
+  }
+  // 4. trees, seeds, candidates
+  std::map<int64_t, std::vector<int64_t>> trees;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!part[i]) continue;
+    int64_t r = i;
+    while (parent[r] >= 0) r = parent[r];
+    trees[r].push_back(i);
+  }
+  struct Vtx {
+    std::vector<int64_t> m;  // members in (z0, index) order
+    double z, var, chi2, sum;
+    int ndf;
+  };
+  auto by_z = [&](int64_t a, int64_t b) { return z0[a] < z0[b] || (z0[a] == z0[b] && a < b); };
+  auto fit = [&](Vtx& v) {
+    double W = 0.0, S = 0.0;
+    for (int64_t i : v.m) {
+      const double w = 1.0 / var_z0[i];
+      W = W + w;
+      S = S + w * z0[i];
+    }
+    v.z = S / W;
+    v.var = 1.0 / W;
+    double c = 0.0, s2 = 0.0;
+    for (int64_t i : v.m) {
+      const double d = z0[i] - v.z;
+      c = c + (d * d) / var_z0[i];
+      const double p = std::min(pt[i], pt_cap);
+      s2 = s2 + p * p;
+    }
+    v.chi2 = c;
+    v.sum = s2;
+    v.ndf = static_cast<int>(v.m.size()) - 1;
+  };
+  std::vector<Vtx> out;
+  for (auto& kv : trees) {
+    if (!(rho[kv.first] > 1) || kv.second.size() < 2) continue;
+    Vtx v;
+    v.m = kv.second;
+    std::sort(v.m.begin(), v.m.end(), by_z);
+    fit(v);
+    if (!(v.chi2 / v.ndf > split_chi2_ndf)) {
+      out.push_back(v);
+      continue;
+    }
+    // 6. two-means split
+    const size_t M = v.m.size();
+    double c1 = z0[v.m.front()], c2 = z0[v.m.back()];
+    std::vector<uint8_t> side(M, 0), prev(M, 2);
+    bool empty = false;
+    for (int it = 0; it < kmeans_iter; ++it) {
+      for (size_t q = 0; q < M; ++q) side[q] = std::fabs(z0[v.m[q]] - c1) <= std::fabs(z0[v.m[q]] - c2) ? 0 : 1;
+      if (side == prev) break;
+      prev = side;
+      double W1 = 0.0, S1 = 0.0, W2 = 0.0, S2 = 0.0;
+      for (size_t q = 0; q < M; ++q) {
+        const double w = 1.0 / var_z0[v.m[q]];
+        if (side[q] == 0) {
+          W1 = W1 + w;
+          S1 = S1 + w * z0[v.m[q]];
+        } else {
+          W2 = W2 + w;
+          S2 = S2 + w * z0[v.m[q]];
+        }
+      }
+      if (W1 == 0.0 || W2 == 0.0) {
+        empty = true;
+        break;
+      }
+      c1 = S1 / W1;
+      c2 = S2 / W2;
+    }
+    if (empty) {
+      out.push_back(v);
+      continue;
+    }
+    for (int p = 0; p < 2; ++p) {
+      Vtx h;
+      for (size_t q = 0; q < M; ++q)
+        if (side[q] == p) h.m.push_back(v.m[q]);
+      if (h.m.size() < 2) continue;
+      fit(h);
+      out.push_back(h);
+    }
+  }
+  // 7. order by the sum of p_T^2; ties by the smallest z0 of the members
+  std::stable_sort(out.begin(), out.end(), [&](const Vtx& a, const Vtx& b) { return by_z(a.m.front(), b.m.front()); });
+  std::stable_sort(out.begin(), out.end(), [](const Vtx& a, const Vtx& b) { return a.sum > b.sum; });
+  for (size_t k = 0; k < out.size(); ++k) {
+    for (int64_t i : out[k].m) track_vertex[i] = static_cast<int32_t>(k);
+    if (static_cast<int64_t>(k) >= cap) continue;
+    vz[k] = out[k].z;
+    vvar[k] = out[k].var;
+    vchi2[k] = out[k].chi2;
+    vndf[k] = out[k].ndf;
+    vn[k] = static_cast<int32_t>(out[k].m.size());
+    vsum[k] = out[k].sum;
+  }
+  return static_cast<int64_t>(out.size());
+}
+
 int32_t oracle_abi_version(void) { return 1; }
 
 }  // extern "C"

@@ -143,6 +143,15 @@ def default_config(**overrides) -> dict:
       sigma_r           disk radial resolution (cm)
       p_cap             momentum cap in the scattering estimate (GeV)
       n_modules         number of detector modules (alignment offsets)
+      vtx_min_hits      vertices: fewest hits of a track that is used (section 3.6)
+      vtx_pt_min        vertices: smallest p_T of a track that is used (GeV)
+      vtx_err_max       vertices: largest sigma(z0) of a track whose local density
+                        is computed (cm)
+      vtx_dz_cut        vertices: largest |dz0| of close-by tracks (cm)
+      vtx_chi2_max      vertices: largest chi2 compatibility of two tracks' z0
+      vtx_split_chi2_ndf vertices: chi2/ndf above which a vertex is split in two
+      vtx_pt_cap        vertices: p_T cap in the sum of p_T^2 that orders them (GeV)
+      vtx_kmeans_iter   vertices: most rounds of the two-means split
     """
     bfield = 3.8
     pt_min = 0.45
@@ -174,6 +183,14 @@ def default_config(**overrides) -> dict:
         "sigma_r": 20e-4,
         "p_cap": 1.0e4,
         "n_modules": N_MODULES,
+        "vtx_min_hits": 4,
+        "vtx_pt_min": 0.5,
+        "vtx_err_max": 0.1,
+        "vtx_dz_cut": 0.07,
+        "vtx_chi2_max": 9.0,
+        "vtx_split_chi2_ndf": 9.0,
+        "vtx_pt_cap": 75.0,
+        "vtx_kmeans_iter": 10,
     }
     for k, v in overrides.items():
         if k not in cfg:
