@@ -53,7 +53,8 @@ typedef enum {
   PT_ERR_ARG = 1,         /* invalid argument; nothing was enqueued */
   PT_ERR_DEVICE = 2,      /* a HIP runtime call or kernel launch failed */
   PT_ERR_UNSUPPORTED = 3, /* valid request that this build does not implement */
-  PT_ERR_WORKSPACE = 4    /* workspace smaller than pt_workspace_size() */
+  PT_ERR_WORKSPACE = 4,   /* workspace smaller than pt_workspace_size() */
+  PT_ERR_TOO_LARGE = 5    /* request beyond the fixed scratch of pt_fit_broken_line_noalloc */
 } pt_err;
 
 enum { PT_F32 = 0, PT_F64 = 1 };
@@ -320,6 +321,23 @@ pt_err pt_fit_broken_line_bwd(const pt_hits* hits, const pt_config* cfg,
                               int32_t precision, const void* g_params, const void* g_chi2,
                               void* grad_hits, double* grad_offsets, uint32_t* status,
                               pt_workspace ws, pt_stream stream);
+
+/* The forward fit of pt_fit_broken_line for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same arguments without a workspace.  Its
+ * scratch (the tracks binned by hit count and the list of tracks refitted in
+ * double) is a fixed device array inside the library, one per GPU, which it
+ * keeps until the process ends; the call allocates and frees nothing.
+ * Limit: min(tuplets->cap, tracks->cap) <= PT_NOALLOC_FIT_MAX_TRACKS, else
+ * PT_ERR_TOO_LARGE and nothing is enqueued.  All calls on one GPU share that
+ * array: calls that overlap in time on one GPU (on different streams, or
+ * from different threads) race and must be serialised by the caller.  The
+ * call clears what it needs at the start, so consecutive calls are
+ * independent.  Results equal those of pt_fit_broken_line. */
+#define PT_NOALLOC_FIT_MAX_TRACKS 262144
+pt_err pt_fit_broken_line_noalloc(const pt_hits* hits, const pt_config* cfg, const pt_ntuplets* tuplets,
+                                  const float* module_offsets, int32_t precision, pt_tracks* tracks,
+                                  uint32_t* status, pt_stream stream);
 
 /* ------------------------------------------------------------------------
  * Batched plans: one hipGraph per step.

@@ -18,7 +18,8 @@ PT_MAX_HITS = 8
 PT_STATUS_WORDS = 16
 PT_ABI_VERSION = 1
 
-PT_OK, PT_ERR_ARG, PT_ERR_DEVICE, PT_ERR_UNSUPPORTED, PT_ERR_WORKSPACE = range(5)
+PT_OK, PT_ERR_ARG, PT_ERR_DEVICE, PT_ERR_UNSUPPORTED, PT_ERR_WORKSPACE, PT_ERR_TOO_LARGE = range(6)
+PT_NOALLOC_FIT_MAX_TRACKS = 262144
 PT_F32, PT_F64 = 0, 1
 PT_FIT_F64, PT_FIT_F32, PT_FIT_F32_F64SOLVE = 0, 1, 2
 PT_CUT_PHIW, PT_CUT_ZW, PT_CUT_ZIP, PT_CUT_PT = 1, 2, 4, 8
@@ -153,6 +154,8 @@ SIGNATURES = {
                                       ct.c_int32, ct.POINTER(pt_tracks), P, pt_workspace, P]),
     "pt_fit_broken_line_bwd": (ct.c_int, [ct.POINTER(pt_hits), ct.POINTER(pt_config), ct.POINTER(pt_ntuplets),
                                           P, ct.c_int32, P, P, P, P, P, pt_workspace, P]),
+    "pt_fit_broken_line_noalloc": (ct.c_int, [ct.POINTER(pt_hits), ct.POINTER(pt_config), ct.POINTER(pt_ntuplets),
+                                              P, ct.c_int32, ct.POINTER(pt_tracks), P, P]),
     "pt_plan_create": (ct.c_int, [ct.POINTER(pt_config), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32,
                                   ct.c_int32, ct.c_int32, ct.POINTER(P)]),
     "pt_plan_run": (ct.c_int, [P, ct.POINTER(pt_hits), ct.POINTER(pt_cells), ct.POINTER(pt_links),

@@ -270,6 +270,18 @@ def fit_broken_line(hits: Hits, cfg: A.pt_config, tuplets: Tuplets, offsets: tor
     return tracks
 
 
+def fit_broken_line_noalloc(hits: Hits, cfg: A.pt_config, tuplets: Tuplets, offsets: torch.Tensor | None,
+                            precision: int, tracks: Tracks, status: torch.Tensor, stream=None) -> Tracks:
+    """pt_fit_broken_line without a workspace (the library's fixed scratch;
+    at most PT_NOALLOC_FIT_MAX_TRACKS tracks; calls on one GPU must not overlap)."""
+    if offsets is not None and (offsets.dtype != torch.float32 or not offsets.is_contiguous()):
+        raise TypeError("module offsets must be a contiguous float32 [n_modules, 3] tensor")
+    A.check(A.load().pt_fit_broken_line_noalloc(ct.byref(hits.abi()), ct.byref(cfg), ct.byref(tuplets.abi()),
+                                                _p(offsets), precision, ct.byref(tracks.abi()), _p(status),
+                                                _stream(stream)), "pt_fit_broken_line_noalloc")
+    return tracks
+
+
 def fit_broken_line_bwd(hits: Hits, cfg: A.pt_config, tuplets: Tuplets, offsets: torch.Tensor | None,
                         precision: int, g_params: torch.Tensor, g_chi2: torch.Tensor | None,
                         grad_hits: torch.Tensor | None, grad_offsets: torch.Tensor | None, status: torch.Tensor,

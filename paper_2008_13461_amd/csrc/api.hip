@@ -20,6 +20,8 @@ pt_err launch_fit(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const
 pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets,
                       int precision, const void* g_params, const void* g_chi2, void* grad_hits,
                       double* grad_offsets, int n_max, uint32_t* status, pt_workspace ws, hipStream_t s);
+pt_err launch_fit_noalloc(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets,
+                          int precision, pt_tracks& out, uint32_t* status, hipStream_t s);
 
 // The derived constants, with the expressions documented in pixeltrack.h.
 // Evaluated without contraction so that they are reproducible.
@@ -125,6 +127,7 @@ const char* pt_err_string(pt_err e) {
     case PT_ERR_DEVICE: return "HIP runtime or kernel launch failure";
     case PT_ERR_UNSUPPORTED: return "unsupported request";
     case PT_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case PT_ERR_TOO_LARGE: return "more tracks than the fixed scratch of the allocation-free fit holds";
   }
   return "unknown error";
 }
@@ -198,6 +201,22 @@ pt_err pt_fit_broken_line(const pt_hits* hits, const pt_config* cfg, const pt_nt
   if (!ws_ok(ws, ws_fit(n_max, d.n_modules))) return PT_ERR_WORKSPACE;
   return launch_fit(*hits, d, *tuplets, module_offsets, precision, *tracks, status, ws,
                     reinterpret_cast<hipStream_t>(stream));
+}
+
+pt_err pt_fit_broken_line_noalloc(const pt_hits* hits, const pt_config* cfg, const pt_ntuplets* tuplets,
+                                  const float* module_offsets, int32_t precision, pt_tracks* tracks,
+                                  uint32_t* status, pt_stream stream) {
+  DevCfg d;
+  if (!hits_ok(hits) || !cfg || !tuplets || !tracks || !derive_config(*cfg, &d)) return PT_ERR_ARG;
+  if (precision != PT_FIT_F64 && precision != PT_FIT_F32 && precision != PT_FIT_F32_F64SOLVE) return PT_ERR_ARG;
+  if (tuplets->cap < 0 || tracks->cap < 0 || !tuplets->count) return PT_ERR_ARG;
+  if (module_offsets && !hits->module) return PT_ERR_ARG;
+  const int n_max = std::min(tuplets->cap, tracks->cap);
+  if (n_max > 0 && (!tuplets->hits || !tuplets->n || !tracks->params || !tracks->chi2 || !tracks->status))
+    return PT_ERR_ARG;
+  if (n_max > PT_NOALLOC_FIT_MAX_TRACKS) return PT_ERR_TOO_LARGE;
+  return launch_fit_noalloc(*hits, d, *tuplets, module_offsets, precision, *tracks, status,
+                            reinterpret_cast<hipStream_t>(stream));
 }
 
 pt_err pt_fit_broken_line_bwd(const pt_hits* hits, const pt_config* cfg, const pt_ntuplets* tuplets,

@@ -16,6 +16,8 @@
 // blocks in a fixed order (no global atomics on the table).  The order of the
 // additions within a block still depends on the schedule, so module sums
 // agree between runs to the rounding of double, not bit for bit.
+#include <mutex>
+
 #include "fit_core.h"
 #include "pt_internal.h"
 
@@ -535,6 +537,60 @@ pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, c
   const bool fb = precision == PT_FIT_F32_F64SOLVE;
   return f64in ? run_grad<float, double, float>(k, a, fb, grad_offsets, s)
                : run_grad<float, float, float>(k, a, fb, grad_offsets, s);
+}
+
+// ---------------------------------------------------------------------------
+// The forward fit without a caller workspace, for callers that cannot
+// allocate (graph capture, tight serving loops).  Its scratch (track bins and
+// the double-refit list) is a file-scope device array of fixed size, one per
+// GPU, held until the process ends.  Calls on one GPU share it: calls that
+// overlap in time on one GPU race.  The counters it must start from zero are
+// cleared by fill kernels at the start of every call.
+
+constexpr size_t kStaticScratchBytes = 7340800;  // >= fit_scratch_bytes(PT_NOALLOC_FIT_MAX_TRACKS, -, false)
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this GPU's scratch array (looked up once per device,
+// with that device current).  Null on failure.
+static void* static_scratch(hipError_t* err) {
+  int dev = 0;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+pt_err launch_fit_noalloc(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets,
+                         int precision, pt_tracks& out, uint32_t* status, hipStream_t s) {
+  const int n_max = std::min(T.cap, out.cap);
+  if (n_max > PT_NOALLOC_FIT_MAX_TRACKS) return PT_ERR_TOO_LARGE;
+  static_assert(kStaticScratchBytes >= 6 * 4 * size_t(PT_NOALLOC_FIT_MAX_TRACKS) + 4 * size_t(PT_NOALLOC_FIT_MAX_TRACKS),
+                "scratch smaller than the forward fit needs");
+  if (fit_scratch_bytes(n_max, k.n_modules, false) > kStaticScratchBytes) return PT_ERR_TOO_LARGE;
+  hipError_t err = hipSuccess;
+  void* p = static_scratch(&err);
+  if (!p) return PT_ERR_DEVICE;
+  const bool was = g_no_timing;
+  g_no_timing = true;  // timing records create events: not here
+  const pt_err e = launch_fit(h, k, T, offsets, precision, out, status, pt_workspace{p, kStaticScratchBytes}, s);
+  g_no_timing = was;
+  return e;
 }
 
 }  // namespace pt

@@ -46,9 +46,10 @@ TimingState& timing() {
 }  // namespace
 
 thread_local bool g_capturing = false;
+thread_local bool g_no_timing = false;
 
 void* timing_begin(hipStream_t s) {
-  if (!timing().on || g_capturing) return nullptr;
+  if (!timing().on || g_capturing || g_no_timing) return nullptr;
   hipEvent_t* ev = new hipEvent_t[2];
   if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
     delete[] ev;

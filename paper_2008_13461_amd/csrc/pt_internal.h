@@ -104,6 +104,7 @@ inline int grid_for(int64_t n, int block, int max_blocks = 65536) {
 void* timing_begin(hipStream_t s);
 void timing_end(void* token, const char* name, hipStream_t s);
 extern thread_local bool g_capturing;
+extern thread_local bool g_no_timing;  // set by entry points that must not create events
 
 #define PT_LAUNCH_CHECK()                        \
   do {                                           \
