@@ -113,6 +113,12 @@ def lib():
         P = ct.c_void_p
         L.oracle_doublets.restype = ct.c_int64
         L.oracle_doublets.argtypes = [P, ct.c_int32, P, P, P, P, ct.c_int64, P, P, P]
+        L.oracle_doublets_binned.restype = ct.c_int64
+        L.oracle_doublets_binned.argtypes = [P, ct.c_int32, P, P, P, P, ct.c_int32, ct.c_int64, P, P, P]
+        L.oracle_chain_batch.restype = ct.c_int64
+        L.oracle_chain_batch.argtypes = [P, ct.c_int32, P, P, P, P, P, P, P, ct.c_int32, ct.c_int32, P]
+        L.oracle_fit_grad_batch.restype = None
+        L.oracle_fit_grad_batch.argtypes = [P, ct.c_int64, P, P, P, P, P, P, P, P, P, P, ct.c_int32, P, P, P]
         L.oracle_links.restype = ct.c_int64
         L.oracle_links.argtypes = [P, ct.c_int32, P, P, P, P, ct.c_int32, P, P, ct.c_int64, P, P]
         L.oracle_ntuplets.restype = ct.c_int64
@@ -164,6 +170,58 @@ def doublets(cfg, x, y, z, layer):
         if cnt <= cap:
             return inner[:cnt], outer[:cnt], pair[:cnt]
         cap = int(cnt)
+
+
+def doublets_binned(cfg, x, y, z, layer, n_bins=64):
+    """The doublets of `doublets`, found through azimuth bins (same set, other order)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    layer = np.ascontiguousarray(layer, dtype=np.uint8)
+    n = x.shape[0]
+    c = _config(cfg)
+    cap = max(1024, 16 * n)
+    while True:
+        inner = np.empty(cap, np.int32)
+        outer = np.empty(cap, np.int32)
+        pair = np.empty(cap, np.uint8)
+        cnt = lib().oracle_doublets_binned(ct.byref(c), n, _p(x), _p(y), _p(z), _p(layer), n_bins, cap,
+                                           _p(inner), _p(outer), _p(pair))
+        if cnt <= cap:
+            return inner[:cnt], outer[:cnt], pair[:cnt]
+        cap = int(cnt)
+
+
+def chain_batch(cfg, event_offsets, x, y, z, layer, module, offsets, n_threads=1, n_bins=64):
+    """Whole chain (binned doublets .. dual-number gradient) of every event,
+    events over n_threads OpenMP threads; returns tracks per event."""
+    off = np.ascontiguousarray(event_offsets, dtype=np.int32)
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    layer = np.ascontiguousarray(layer, dtype=np.uint8)
+    mod = np.ascontiguousarray(module, dtype=np.int16)
+    o = _f64(offsets).reshape(-1) if offsets is not None else None
+    tr = np.zeros(off.shape[0] - 1, np.int64)
+    lib().oracle_chain_batch(ct.byref(_config(cfg)), off.shape[0] - 1, _p(off), _p(x), _p(y), _p(z), _p(layer),
+                             _p(mod), _p(o), n_bins, n_threads, _p(tr))
+    return tr
+
+
+def fit_grad_batch(cfg, tuplets, nhits, x, y, z, layer, module, offsets, g_params, g_chi2, n_threads=1):
+    """Fit and dual-number gradient of given tracks over n_threads OpenMP
+    threads: (params [N, 5], chi2 [N], grad_hits [n_hits, 3])."""
+    tup = np.ascontiguousarray(tuplets, dtype=np.int32)
+    nh = np.ascontiguousarray(nhits, dtype=np.uint8)
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    layer = np.ascontiguousarray(layer, dtype=np.uint8)
+    mod = np.ascontiguousarray(module, dtype=np.int16)
+    o = _f64(offsets).reshape(-1) if offsets is not None else None
+    gp = _f64(g_params).reshape(-1)
+    gc = _f64(g_chi2)
+    n = tup.shape[0]
+    params = np.empty((n, 5))
+    chi2 = np.empty(n)
+    gh = np.zeros((x.shape[0], 3))
+    lib().oracle_fit_grad_batch(ct.byref(_config(cfg)), n, _p(tup), _p(nh), _p(x), _p(y), _p(z), _p(layer), _p(mod),
+                                _p(o), _p(gp), _p(gc), n_threads, _p(params), _p(chi2), _p(gh))
+    return params, chi2, gh
 
 
 def links(cfg, x, y, z, layer, cell_inner, cell_outer):

@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC]
+           "-fopenmp", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

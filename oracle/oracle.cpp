@@ -237,6 +237,52 @@ int64_t oracle_doublets(const oracle_config* cfg, int32_t n, const double* x, co
   return count;
 }
 
+// The same doublets found faster: the hits of each layer binned in azimuth
+// (n_bins bins of width w), and for each outer hit only the inner hits of
+// the bins within ceil(dphi / w) + 1 of its own bin are tested -- a pair
+// passing the PhiW cut differs in azimuth by less than dphi, and the extra
+// bin absorbs the rounding of atan2 -- with the same predicate as above.
+// Without the PhiW cut every bin is scanned.  The set equals the brute-force
+// set (in another order).
+int64_t oracle_doublets_binned(const oracle_config* cfg, int32_t n, const double* x, const double* y,
+                               const double* z, const uint8_t* layer, int32_t n_bins, int64_t cap,
+                               int32_t* inner, int32_t* outer, uint8_t* pair) {
+  const DoubletCuts k = doublet_cuts(*cfg);
+  if (n_bins < 1) n_bins = 1;
+  const double w = 2.0 * M_PI / n_bins;
+  auto bin_of = [&](int32_t h) {
+    int b = static_cast<int>(std::floor((std::atan2(y[h], x[h]) + M_PI) / w));
+    return std::min(std::max(b, 0), n_bins - 1);
+  };
+  std::vector<std::vector<std::vector<int32_t>>> bins(kLayers, std::vector<std::vector<int32_t>>(n_bins));
+  for (int32_t h = 0; h < n; ++h) bins[layer[h]][bin_of(h)].push_back(h);
+  int64_t count = 0;
+  for (int p = 0; p < cfg->n_pairs; ++p) {
+    int wb = n_bins;
+    if (cfg->cut_mask & CUT_PHIW) wb = static_cast<int>(std::ceil(cfg->pair_dphi[p] / w)) + 1;
+    const bool all = 2 * wb + 1 >= n_bins;
+    for (int bo = 0; bo < n_bins; ++bo) {
+      for (int32_t o : bins[cfg->pair_outer[p]][bo]) {
+        const int first = all ? 0 : bo - wb, last = all ? n_bins - 1 : bo + wb;
+        for (int bb = first; bb <= last; ++bb) {
+          const int b = ((bb % n_bins) + n_bins) % n_bins;
+          for (int32_t i : bins[cfg->pair_inner[p]][b]) {
+            if (doublet_passes(k, p, x[i], y[i], z[i], x[o], y[o], z[o])) {
+              if (count < cap) {
+                inner[count] = i;
+                outer[count] = o;
+                pair[count] = static_cast<uint8_t>(p);
+              }
+              ++count;
+            }
+          }
+        }
+      }
+    }
+  }
+  return count;
+}
+
 // Cell links of one event: for every cell c = (h1, h2) and every cell
 // c' = (h0, h1) ending on its inner hit, the link (c' -> c) when the triplet
 // passes the cuts.  Cells are given as (inner, outer) hit index arrays.
@@ -1239,6 +1285,100 @@ int64_t oracle_vertices(int64_t n, const double* z0, const double* var_z0, const
     vsum[k] = out[k].sum;
   }
   return static_cast<int64_t>(out.size());
+}
+
+// ---------------------------------------------------------------------------
+// Batches for timing the oracle as a CPU baseline (OpenMP over events or
+// tracks; n_threads = 1 runs them in order on the calling thread).
+
+// The whole chain of each event: binned doublets, links, n-tuplets with
+// duplicate removal, the fit and the dual-number gradient of every track
+// (unit cotangents, module offsets applied when given).  Events in parallel.
+// Returns the number of tracks; tracks [n_events] receives each event's.
+int64_t oracle_chain_batch(const oracle_config* cfg, int32_t n_events, const int32_t* event_offsets,
+                           const double* x, const double* y, const double* z, const uint8_t* layer,
+                           const int16_t* module, const double* offsets, int32_t n_bins, int32_t n_threads,
+                           int64_t* tracks) {
+  int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads) reduction(+ : total)
+  for (int32_t e = 0; e < n_events; ++e) {
+    const int32_t a = event_offsets[e], n = event_offsets[e + 1] - a;
+    std::vector<int32_t> ci, co;
+    std::vector<uint8_t> cp;
+    int64_t cap = 64 * static_cast<int64_t>(n) + 1024, nc = 0;
+    for (;;) {
+      ci.resize(cap);
+      co.resize(cap);
+      cp.resize(cap);
+      nc = oracle_doublets_binned(cfg, n, x + a, y + a, z + a, layer + a, n_bins, cap, ci.data(), co.data(),
+                                  cp.data());
+      if (nc <= cap) break;
+      cap = nc;
+    }
+    std::vector<int32_t> li, lo;
+    int64_t lcap = 4 * nc + 1024, nl = 0;
+    for (;;) {
+      li.resize(lcap);
+      lo.resize(lcap);
+      nl = oracle_links(cfg, n, x + a, y + a, z + a, layer + a, static_cast<int32_t>(nc), ci.data(), co.data(),
+                        lcap, li.data(), lo.data());
+      if (nl <= lcap) break;
+      lcap = nl;
+    }
+    int64_t tcap = nc + 256, nt = 0, n_raw = 0;
+    int32_t trunc = 0;
+    std::vector<int32_t> th, tc;
+    std::vector<uint8_t> tn;
+    for (;;) {
+      th.resize(tcap * kMaxHits);
+      tc.resize(tcap * (kMaxHits - 1));
+      tn.resize(tcap);
+      nt = oracle_ntuplets(cfg, n, layer + a, static_cast<int32_t>(nc), ci.data(), co.data(),
+                           static_cast<int32_t>(nl), li.data(), lo.data(), 1, tcap, th.data(), tc.data(), tn.data(),
+                           &n_raw, &trunc);
+      if (nt <= tcap) break;
+      tcap = nt;
+    }
+    std::vector<double> params(5 * nt + 5), chi2(nt + 1), gp(5 * nt + 5, 1.0), gc(nt + 1, 1.0), gh(3 * n + 3, 0.0);
+    std::vector<uint8_t> st(nt + 1);
+    oracle_fit(cfg, nt, th.data(), tn.data(), x + a, y + a, z + a, layer + a, module + a, offsets, params.data(),
+               chi2.data(), st.data());
+    oracle_fit_grad(cfg, nt, th.data(), tn.data(), x + a, y + a, z + a, layer + a, module + a, offsets, gp.data(),
+                    gc.data(), gh.data(), nullptr);
+    tracks[e] = nt;
+    total += nt;
+  }
+  return total;
+}
+
+// The fit and the dual-number gradient of n_tracks given tracks, tracks in
+// parallel: params [n][5], chi2 [n] and grad_hits [n_hits][3] (added into).
+void oracle_fit_grad_batch(const oracle_config* cfg, int64_t n_tracks, const int32_t* tuplets,
+                           const uint8_t* nhits, const double* x, const double* y, const double* z,
+                           const uint8_t* layer, const int16_t* module, const double* offsets,
+                           const double* g_params, const double* g_chi2, int32_t n_threads, double* params,
+                           double* chi2, double* grad_hits) {
+#pragma omp parallel for schedule(dynamic, 256) num_threads(n_threads)
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    uint8_t st = 0;
+    oracle_fit(cfg, 1, tuplets + t * kMaxHits, nhits + t, x, y, z, layer, module, offsets, params + 5 * t,
+               chi2 + t, &st);
+    const int n = nhits[t];
+    double X[kMaxHits], Y[kMaxHits], Z[kMaxHits], jac[6 * 3 * kMaxHits];
+    int lay[kMaxHits];
+    int32_t layk[kMaxHits];
+    gather(n, tuplets + t * kMaxHits, x, y, z, layer, module, offsets, X, Y, Z, lay);
+    for (int k = 0; k < n; ++k) layk[k] = lay[k];
+    if (oracle_fit_jacobian(cfg, n, X, Y, Z, layk, jac) != FIT_OK) continue;
+    for (int col = 0; col < 3 * n; ++col) {
+      double acc = 0.0;
+      for (int o = 0; o < 5; ++o) acc += jac[o * 3 * n + col] * g_params[5 * t + o];
+      acc += jac[5 * 3 * n + col] * (g_chi2 ? g_chi2[t] : 0.0);
+      const int64_t at = 3 * static_cast<int64_t>(tuplets[t * kMaxHits + col / 3]) + col % 3;
+#pragma omp atomic
+      grad_hits[at] += acc;
+    }
+  }
 }
 
 int32_t oracle_abi_version(void) { return 1; }

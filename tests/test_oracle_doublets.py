@@ -181,3 +181,25 @@ def test_empty_and_single_layer():
     assert len(O.doublets(CFG, x, y, z, np.array([0, 0], np.uint8))[0]) == 0
     e = np.zeros(0)
     assert len(O.doublets(CFG, e, e, e, np.zeros(0, np.uint8))[0]) == 0
+
+
+def test_binned_search_equals_the_brute_force():
+    """The oracle's azimuth-binned doublet search (used to time the oracle on
+    whole pileup-200 events) finds exactly the brute-force set: configs 1
+    and 2 with several bin counts, and 4 pileup-200 events."""
+    import concurrent.futures as cf
+
+    from tests.helpers import sorted_keys
+
+    def same(h, n_bins=64, cfg=CFG):
+        a = O.doublets(cfg, h.x, h.y, h.z, h.layer)
+        b = O.doublets_binned(cfg, h.x, h.y, h.z, h.layer, n_bins)
+        return len(a[0]) > 0 and np.array_equal(sorted_keys(a[0], a[1]), sorted_keys(b[0], b[1]))
+
+    for bins in (1, 7, 64, 512):
+        assert same(E.config1(), bins)
+        assert same(E.config2(), bins)
+    assert same(E.config2(), 64, C.default_config(cut_mask=C.CUT_ZW | C.CUT_ZIP | C.CUT_PT))
+    h = E.config5(n_events=4)
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        assert all(ex.map(lambda e: same(h.event(e)), range(4)))
