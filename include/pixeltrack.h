@@ -96,7 +96,8 @@ enum {
   PT_FLAG_BAD_HITS = 1u << 3,
   PT_FLAG_TRUNCATED = 1u << 4,
   PT_FLAG_FIT_BAD_ORDER = 1u << 5,
-  PT_FLAG_FIT_FAILED = 1u << 6
+  PT_FLAG_FIT_FAILED = 1u << 6,
+  PT_FLAG_VERTICES_OVERFLOW = 1u << 7
 };
 /* Per-track fit status bits (pt_tracks.status). */
 enum { PT_FIT_OK = 0, PT_FIT_ST_BAD_ORDER = 1, PT_FIT_ST_F64_SOLVE = 2, PT_FIT_ST_FAILED = 4 };
@@ -144,6 +145,15 @@ typedef struct {
   int32_t block_links;                /* threads per block of the link sweep (one wavefront per
                                          middle hit): 64, 128 or 256; other values mean 64 */
   double f64_solve_threshold;         /* see PT_FIT_F32_F64SOLVE; <= 0 means 1024 */
+  /* pixel vertices (section 3.6), see pt_find_vertices */
+  int32_t vtx_min_hits;               /* fewest hits of a track that is used */
+  int32_t vtx_kmeans_iter;            /* most rounds of the two-means split, >= 1 */
+  double vtx_pt_min;                  /* smallest p_T of a track that is used (GeV) */
+  double vtx_err_max;                 /* largest sigma(z0) of a track whose density is computed (cm) */
+  double vtx_dz_cut;                  /* largest |dz0| of close-by tracks (cm), > 0 */
+  double vtx_chi2_max;                /* largest (dz0)^2 / (var_i + var_j) of compatible tracks */
+  double vtx_split_chi2_ndf;          /* chi2/ndf above which a vertex is split in two */
+  double vtx_pt_cap;                  /* p_T cap in the sum of p_T^2 that orders the vertices (GeV) */
 } pt_config;
 
 /* Hits of n_events events.  Event e owns hits [event_offsets[e], event_offsets[e+1]). */
@@ -227,10 +237,13 @@ typedef struct {
                          PT_FIT_F64, float otherwise */
   void* chi2;         /* [cap] same type */
   uint8_t* status;    /* [cap] PT_FIT_ST_* bits */
+  void* cov;          /* [cap][15] or NULL (not computed): the covariance of the
+                         five parameters, same type, upper triangle row by row
+                         ((0,0) (0,1) .. (0,4) (1,1) .. (4,4)) */
 } pt_tracks;
 
 /* Version of this interface (the value of PT_ABI_VERSION). */
-#define PT_ABI_VERSION 1
+#define PT_ABI_VERSION 2
 int32_t pt_abi_version(void);
 const char* pt_err_string(pt_err e);
 
@@ -298,8 +311,15 @@ pt_err pt_find_ntuplets(const pt_hits* hits, const pt_config* cfg, const pt_cell
  * for offsets and the curvature correction, the S-Z broken-line solve; the
  * perigee (kappa, phi0, cot(theta), d0, z0) with respect to the origin and
  * chi2 = circle + line chi^2 at the optimum (2n - 5 degrees of freedom).
+ * When tracks->cov is not NULL it also writes the covariance of the five
+ * parameters (section 3.4: the circle and line fits give parameters with
+ * covariances, combined at the end): with the kinks as zero-mean
+ * pseudo-measurements the covariance of the circle unknowns (offsets,
+ * curvature correction) is the inverse of its normal matrix and that of the
+ * line unknowns the inverse of its own; propagated through the linearised
+ * perigee conversion (pre-fit held fixed), C = Jc Ac^-1 Jc^T + Jl Al^-1 Jl^T.
  * Hits must be ordered along the track; tracks that are not get NaN
- * parameters and PT_FIT_ST_BAD_ORDER. */
+ * parameters (and covariance) and PT_FIT_ST_BAD_ORDER. */
 pt_err pt_fit_broken_line(const pt_hits* hits, const pt_config* cfg, const pt_ntuplets* tuplets,
                           const float* module_offsets, int32_t precision, pt_tracks* tracks,
                           uint32_t* status, pt_workspace ws, pt_stream stream);
@@ -322,6 +342,67 @@ pt_err pt_fit_broken_line_bwd(const pt_hits* hits, const pt_config* cfg,
                               void* grad_hits, double* grad_offsets, uint32_t* status,
                               pt_workspace ws, pt_stream stream);
 
+/* Ambiguity resolution (section 3.5) among the fitted tracks of
+ * pt_fit_broken_line (same tuplets, precision and tracks; cells are the
+ * n-tuplets' cells, whose indices must lie below cells->cap).
+ *   1. Tracks sharing a hit doublet (a cell) are ambiguous: a track is
+ *      dropped when a track sharing one of its cells has a smaller chi2.
+ *   2. Among the 3-hit tracks that survive 1, tracks sharing a hit are
+ *      ambiguous: a triplet is dropped when a triplet sharing one of its
+ *      hits has a smaller |d0| (transverse impact parameter).
+ * Equal values keep both; tracks with a non-finite chi2 take no part and are
+ * dropped.  Values are compared in the fit's precision.  selected (device
+ * int32 [min(tuplets->cap, tracks->cap)]) receives the indices of the tracks
+ * that stay, in increasing order, and n_selected[0] their number. */
+pt_err pt_resolve_ambiguities(const pt_hits* hits, const pt_config* cfg, const pt_cells* cells,
+                              const pt_ntuplets* tuplets, int32_t precision, const pt_tracks* tracks,
+                              int32_t* selected, int32_t* n_selected, uint32_t* status, pt_workspace ws,
+                              pt_stream stream);
+
+/* Pixel vertices of each event (section 3.6). */
+typedef struct {
+  int32_t cap;           /* vertex capacity */
+  double* z;             /* [cap] weighted mean of the tracks' z0 (cm) */
+  double* var;           /* [cap] its variance */
+  double* chi2;          /* [cap] sum of (z0 - z)^2 / var_z0 over the tracks */
+  int32_t* ndf;          /* [cap] tracks - 1 */
+  int32_t* n_tracks;     /* [cap] */
+  double* sum_pt2;       /* [cap] sum of min(p_T, vtx_pt_cap)^2 over the tracks */
+  int32_t* event_first;  /* [n_events + 1]: event e's vertices are [event_first[e], event_first[e+1]) */
+  int32_t* count;        /* [1] vertices found (may exceed cap) */
+  int32_t* track_vertex; /* [min(tuplets->cap, tracks->cap)] vertex of each track, -1 for none */
+} pt_vertices;
+
+/* Pixel vertices (section 3.6) from the fitted tracks, which must carry
+ * their covariance (tracks->cov).  Tracks take part when selected (the
+ * output of pt_resolve_ambiguities; every track when selected is NULL), with
+ * at least vtx_min_hits hits, p_T = 0.299792458 B / 100 / |kappa| above
+ * vtx_pt_min and a finite z0 with a positive variance var = cov[14].  A
+ * track belongs to the event of its first hit.  Per event:
+ *   density of track i (0 unless sqrt(var_i) <= vtx_err_max): the number of
+ *     other tracks j with |z_i - z_j| < vtx_dz_cut and
+ *     (z_i - z_j)^2 < vtx_chi2_max (var_i + var_j);
+ *   each track links to the nearest track of higher rank (density, then
+ *     track index) with |z_i - z_j| < vtx_dz_cut and
+ *     (z_i - z_j)^2 <= vtx_chi2_max (var_i + var_j) (equal distances: the
+ *     smaller index); the links form trees;
+ *   a tree whose root has density > 1 and with at least 2 tracks is a
+ *     vertex: with members in (z0, track index) order, weights 1/var,
+ *     z = sum w z0 / sum w, var = 1 / sum w, chi2 = sum (z0 - z)^2 / var_z0,
+ *     ndf = members - 1;
+ *   a vertex with chi2/ndf > vtx_split_chi2_ndf is split by 1-D two-means:
+ *     centres at its smallest and largest z0, members to the nearer centre
+ *     (the first on a tie), centres to the weighted means, until no member
+ *     moves or vtx_kmeans_iter rounds; each part with at least 2 members is
+ *     a vertex (fitted as above), the members of a part of one are dropped;
+ *   vertices are ordered by sum_pt2, largest first (the primary vertex);
+ *     equal sums keep the order of their first member.
+ * All of it in double, sums in member order, without contraction.  Vertices
+ * beyond out->cap are counted but not written (PT_FLAG_VERTICES_OVERFLOW). */
+pt_err pt_find_vertices(const pt_hits* hits, const pt_config* cfg, const pt_ntuplets* tuplets, int32_t precision,
+                        const pt_tracks* tracks, const int32_t* selected, const int32_t* n_selected,
+                        pt_vertices* out, uint32_t* status, pt_workspace ws, pt_stream stream);
+
 /* The forward fit of pt_fit_broken_line for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation): the same arguments without a workspace.  Its
@@ -343,23 +424,30 @@ pt_err pt_fit_broken_line_noalloc(const pt_hits* hits, const pt_config* cfg, con
  * Batched plans: one hipGraph per step.
  *
  * A plan runs the whole path -- pt_build_doublets, pt_link_cells,
- * pt_find_ntuplets, pt_fit_broken_line and, when created with_adjoint,
- * pt_fit_broken_line_bwd -- over all events of a batch as one graph launch.
+ * pt_find_ntuplets, pt_fit_broken_line, then the optional stages chosen at
+ * creation: PT_STAGE_ADJOINT (pt_fit_broken_line_bwd), PT_STAGE_AMBIGUITY
+ * (pt_resolve_ambiguities), PT_STAGE_VERTICES (pt_find_vertices over the
+ * tracks the ambiguity stage selects, or over every track without it) -- over
+ * all events of a batch as one graph launch.
  * pt_plan_create allocates the plan's workspace (this and pt_plan_destroy are
  * the only calls that allocate or free device memory) and a private,
  * default-priority capture stream.  The first pt_plan_run, and every run whose
  * arguments (pointers, sizes, capacities) differ from the captured ones,
  * records the step into a graph; every run then launches the graph on
  * `stream`.  Arguments have the meaning of the individual calls; g_params is
- * required when with_adjoint is set.  A plan is not thread-safe.  Sizes above
- * the ones given at creation return PT_ERR_ARG. */
+ * required with PT_STAGE_ADJOINT, selected and n_selected with
+ * PT_STAGE_AMBIGUITY, vertices and tracks->cov with PT_STAGE_VERTICES (the
+ * fit writes the covariance whenever tracks->cov is set).  A plan is not
+ * thread-safe.  Sizes above the ones given at creation return PT_ERR_ARG. */
+enum { PT_STAGE_ADJOINT = 1, PT_STAGE_AMBIGUITY = 2, PT_STAGE_VERTICES = 4 };
 typedef struct pt_plan_s* pt_plan;
 pt_err pt_plan_create(const pt_config* cfg, int32_t n_hits_max, int32_t n_events_max, int32_t cells_cap,
-                      int32_t links_cap, int32_t tuplets_cap, int32_t precision, int32_t with_adjoint,
+                      int32_t links_cap, int32_t tuplets_cap, int32_t precision, int32_t stages,
                       pt_plan* plan);
 pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links* links, pt_ntuplets* tuplets,
                    pt_tracks* tracks, const float* module_offsets, const void* g_params, const void* g_chi2,
-                   void* grad_hits, double* grad_offsets, uint32_t* status, pt_stream stream);
+                   void* grad_hits, double* grad_offsets, int32_t* selected, int32_t* n_selected,
+                   pt_vertices* vertices, uint32_t* status, pt_stream stream);
 void pt_plan_destroy(pt_plan plan);
 
 /* Kernel timing (instrumentation).  While enabled, the individual calls (not
@@ -369,7 +457,7 @@ void pt_plan_destroy(pt_plan plan);
  * (the index of cells by outer hit), "link_segments" (placing the index segments), "links" (the
  * triplet sweep),
  * "link_emit" (placing the links), "root_count", "root_write", "dfs_count",
- * "dfs_write", "dedup" (several kernels), "fit_fwd", "fit_bwd".  pt_timing_read waits for the recorded events and
+ * "dfs_write", "dedup" (several kernels), "fit_fwd" and "fit_bwd" (every kernel of the fit and of its adjoint).  pt_timing_read waits for the recorded events and
  * returns the summed milliseconds and the number of launches since the last
  * reset (PT_ERR_ARG when the name has no record). */
 void pt_timing_enable(int32_t on);

@@ -16,7 +16,7 @@ PT_MAX_PAIRS = 32
 PT_N_LAYERS = 10
 PT_MAX_HITS = 8
 PT_STATUS_WORDS = 16
-PT_ABI_VERSION = 1
+PT_ABI_VERSION = 2
 
 PT_OK, PT_ERR_ARG, PT_ERR_DEVICE, PT_ERR_UNSUPPORTED, PT_ERR_WORKSPACE, PT_ERR_TOO_LARGE = range(6)
 PT_NOALLOC_FIT_MAX_TRACKS = 262144
@@ -32,8 +32,10 @@ PT_FLAG_BAD_HITS = 1 << 3
 PT_FLAG_TRUNCATED = 1 << 4
 PT_FLAG_FIT_BAD_ORDER = 1 << 5
 PT_FLAG_FIT_FAILED = 1 << 6
+PT_FLAG_VERTICES_OVERFLOW = 1 << 7
 PT_SEG_BLOCK = 32
 PT_FIT_OK, PT_FIT_ST_BAD_ORDER, PT_FIT_ST_F64_SOLVE, PT_FIT_ST_FAILED = 0, 1, 2, 4
+PT_STAGE_ADJOINT, PT_STAGE_AMBIGUITY, PT_STAGE_VERTICES = 1, 2, 4
 
 P = ct.c_void_p
 
@@ -71,6 +73,14 @@ class pt_config(ct.Structure):
         ("block_doublets", ct.c_int32),
         ("block_links", ct.c_int32),
         ("f64_solve_threshold", ct.c_double),
+        ("vtx_min_hits", ct.c_int32),
+        ("vtx_kmeans_iter", ct.c_int32),
+        ("vtx_pt_min", ct.c_double),
+        ("vtx_err_max", ct.c_double),
+        ("vtx_dz_cut", ct.c_double),
+        ("vtx_chi2_max", ct.c_double),
+        ("vtx_split_chi2_ndf", ct.c_double),
+        ("vtx_pt_cap", ct.c_double),
     ]
 
 
@@ -135,6 +145,22 @@ class pt_tracks(ct.Structure):
         ("params", P),
         ("chi2", P),
         ("status", P),
+        ("cov", P),
+    ]
+
+
+class pt_vertices(ct.Structure):
+    _fields_ = [
+        ("cap", ct.c_int32),
+        ("z", P),
+        ("var", P),
+        ("chi2", P),
+        ("ndf", P),
+        ("n_tracks", P),
+        ("sum_pt2", P),
+        ("event_first", P),
+        ("count", P),
+        ("track_vertex", P),
     ]
 
 
@@ -154,12 +180,18 @@ SIGNATURES = {
                                       ct.c_int32, ct.POINTER(pt_tracks), P, pt_workspace, P]),
     "pt_fit_broken_line_bwd": (ct.c_int, [ct.POINTER(pt_hits), ct.POINTER(pt_config), ct.POINTER(pt_ntuplets),
                                           P, ct.c_int32, P, P, P, P, P, pt_workspace, P]),
+    "pt_resolve_ambiguities": (ct.c_int, [ct.POINTER(pt_hits), ct.POINTER(pt_config), ct.POINTER(pt_cells),
+                                          ct.POINTER(pt_ntuplets), ct.c_int32, ct.POINTER(pt_tracks), P, P, P,
+                                          pt_workspace, P]),
+    "pt_find_vertices": (ct.c_int, [ct.POINTER(pt_hits), ct.POINTER(pt_config), ct.POINTER(pt_ntuplets), ct.c_int32,
+                                    ct.POINTER(pt_tracks), P, P, ct.POINTER(pt_vertices), P, pt_workspace, P]),
     "pt_fit_broken_line_noalloc": (ct.c_int, [ct.POINTER(pt_hits), ct.POINTER(pt_config), ct.POINTER(pt_ntuplets),
                                               P, ct.c_int32, ct.POINTER(pt_tracks), P, P]),
     "pt_plan_create": (ct.c_int, [ct.POINTER(pt_config), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32,
                                   ct.c_int32, ct.c_int32, ct.POINTER(P)]),
     "pt_plan_run": (ct.c_int, [P, ct.POINTER(pt_hits), ct.POINTER(pt_cells), ct.POINTER(pt_links),
-                               ct.POINTER(pt_ntuplets), ct.POINTER(pt_tracks), P, P, P, P, P, P, P]),
+                               ct.POINTER(pt_ntuplets), ct.POINTER(pt_tracks), P, P, P, P, P, P, P,
+                               ct.POINTER(pt_vertices), P, P]),
     "pt_plan_destroy": (None, [P]),
     "pt_timing_enable": (None, [ct.c_int32]),
     "pt_timing_reset": (None, []),
@@ -231,4 +263,7 @@ def make_config(cfg: dict, *, n_phi_bins: int = 0, block_doublets: int = 0, bloc
     c.block_doublets = block_doublets
     c.block_links = block_links
     c.f64_solve_threshold = f64_solve_threshold
+    for k in ("vtx_min_hits", "vtx_kmeans_iter", "vtx_pt_min", "vtx_err_max", "vtx_dz_cut", "vtx_chi2_max",
+              "vtx_split_chi2_ndf", "vtx_pt_cap"):
+        setattr(c, k, cfg[k])
     return c

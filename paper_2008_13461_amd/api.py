@@ -197,18 +197,49 @@ class Tracks:
     params: torch.Tensor      # [cap, 5]
     chi2: torch.Tensor        # [cap]
     status: torch.Tensor      # [cap] uint8
+    cov: torch.Tensor | None = None   # [cap, 15] upper triangles of the parameter covariance
 
     @classmethod
-    def empty(cls, cap: int, precision: int, device="cuda") -> "Tracks":
+    def empty(cls, cap: int, precision: int, device="cuda", with_cov: bool = False) -> "Tracks":
         dt = torch.float64 if precision == A.PT_FIT_F64 else torch.float32
         return cls(torch.empty((cap, 5), dtype=dt, device=device), torch.empty(cap, dtype=dt, device=device),
-                   torch.empty(cap, dtype=torch.uint8, device=device))
+                   torch.empty(cap, dtype=torch.uint8, device=device),
+                   torch.empty((cap, 15), dtype=dt, device=device) if with_cov else None)
 
     def abi(self) -> A.pt_tracks:
         t = A.pt_tracks()
         t.cap = int(self.params.shape[0])
         t.params, t.chi2, t.status = self.params.data_ptr(), self.chi2.data_ptr(), self.status.data_ptr()
+        t.cov = self.cov.data_ptr() if self.cov is not None else None
         return t
+
+
+@dataclass
+class Vertices:
+    z: torch.Tensor
+    var: torch.Tensor
+    chi2: torch.Tensor
+    ndf: torch.Tensor
+    n_tracks: torch.Tensor
+    sum_pt2: torch.Tensor
+    event_first: torch.Tensor    # [n_events + 1]
+    count: torch.Tensor
+    track_vertex: torch.Tensor   # [tracks cap]
+
+    @classmethod
+    def empty(cls, cap: int, n_events: int, tracks_cap: int, device="cuda") -> "Vertices":
+        f64 = dict(dtype=torch.float64, device=device)
+        i32 = dict(dtype=torch.int32, device=device)
+        return cls(torch.empty(cap, **f64), torch.empty(cap, **f64), torch.empty(cap, **f64), torch.empty(cap, **i32),
+                   torch.empty(cap, **i32), torch.empty(cap, **f64), torch.zeros(n_events + 1, **i32),
+                   torch.zeros(1, **i32), torch.empty(max(tracks_cap, 1), **i32))
+
+    def abi(self) -> A.pt_vertices:
+        v = A.pt_vertices()
+        v.cap = int(self.z.shape[0])
+        for name in ("z", "var", "chi2", "ndf", "n_tracks", "sum_pt2", "event_first", "count", "track_vertex"):
+            setattr(v, name, getattr(self, name).data_ptr())
+        return v
 
 
 def new_status(device="cuda") -> torch.Tensor:
@@ -268,6 +299,30 @@ def fit_broken_line(hits: Hits, cfg: A.pt_config, tuplets: Tuplets, offsets: tor
                                         _p(offsets), precision, ct.byref(tracks.abi()), _p(status), _ws(ws),
                                         _stream(stream)), "pt_fit_broken_line")
     return tracks
+
+
+def resolve_ambiguities(hits: Hits, cfg: A.pt_config, cells: Cells, tuplets: Tuplets, precision: int,
+                        tracks: Tracks, status: torch.Tensor, ws: torch.Tensor, stream=None):
+    """pt_resolve_ambiguities: (selected track indices [cap] int32, count [1])."""
+    n = min(tuplets.cap, int(tracks.params.shape[0]))
+    sel = torch.empty(max(n, 1), dtype=torch.int32, device=tracks.params.device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=tracks.params.device)
+    A.check(A.load().pt_resolve_ambiguities(ct.byref(hits.abi()), ct.byref(cfg), ct.byref(cells.abi()),
+                                            ct.byref(tuplets.abi()), precision, ct.byref(tracks.abi()), _p(sel),
+                                            _p(cnt), _p(status), _ws(ws), _stream(stream)), "pt_resolve_ambiguities")
+    return sel, cnt
+
+
+def find_vertices(hits: Hits, cfg: A.pt_config, tuplets: Tuplets, precision: int, tracks: Tracks,
+                  selected: torch.Tensor | None, n_selected: torch.Tensor | None, vertices: Vertices,
+                  status: torch.Tensor, ws: torch.Tensor, stream=None) -> Vertices:
+    """pt_find_vertices (tracks must carry their covariance)."""
+    if tracks.cov is None:
+        raise ValueError("pt_find_vertices needs the tracks' covariance (Tracks.empty(..., with_cov=True))")
+    A.check(A.load().pt_find_vertices(ct.byref(hits.abi()), ct.byref(cfg), ct.byref(tuplets.abi()), precision,
+                                      ct.byref(tracks.abi()), _p(selected), _p(n_selected), ct.byref(vertices.abi()),
+                                      _p(status), _ws(ws), _stream(stream)), "pt_find_vertices")
+    return vertices
 
 
 def fit_broken_line_noalloc(hits: Hits, cfg: A.pt_config, tuplets: Tuplets, offsets: torch.Tensor | None,
@@ -342,19 +397,25 @@ class Plan:
     """pt_plan: the whole step captured once into a hipGraph, replayed per call."""
 
     def __init__(self, cfg: A.pt_config, *, n_hits: int, n_events: int, cells_cap: int, links_cap: int,
-                 tuplets_cap: int, precision: int, with_adjoint: bool):
+                 tuplets_cap: int, precision: int, with_adjoint: bool = False, stages: int = 0):
+        """stages: PT_STAGE_* bits; with_adjoint adds PT_STAGE_ADJOINT."""
         self._h = ct.c_void_p()
+        stages |= A.PT_STAGE_ADJOINT if with_adjoint else 0
         A.check(A.load().pt_plan_create(ct.byref(cfg), n_hits, n_events, cells_cap, links_cap, tuplets_cap,
-                                        precision, int(with_adjoint), ct.byref(self._h)), "pt_plan_create")
+                                        precision, stages, ct.byref(self._h)), "pt_plan_create")
         self._keep = None
 
     def run(self, hits: Hits, cells: Cells, links: Links, tuplets: Tuplets, tracks: Tracks, status: torch.Tensor,
-            offsets=None, g_params=None, g_chi2=None, grad_hits=None, grad_offsets=None, stream=None) -> None:
+            offsets=None, g_params=None, g_chi2=None, grad_hits=None, grad_offsets=None, selected=None,
+            n_selected=None, vertices: "Vertices | None" = None, stream=None) -> None:
         # the structs are rebuilt per call; the plan re-captures only when their contents change
         args = (hits.abi(), cells.abi(), links.abi(), tuplets.abi(), tracks.abi())
-        self._keep = args
+        vabi = vertices.abi() if vertices is not None else None
+        self._keep = (args, vabi)
         A.check(A.load().pt_plan_run(self._h, *(ct.byref(a) for a in args), _p(offsets), _p(g_params), _p(g_chi2),
-                                     _p(grad_hits), _p(grad_offsets), _p(status), _stream(stream)), "pt_plan_run")
+                                     _p(grad_hits), _p(grad_offsets), _p(selected), _p(n_selected),
+                                     ct.byref(vabi) if vabi is not None else None, _p(status), _stream(stream)),
+                "pt_plan_run")
 
     def __del__(self):
         if getattr(self, "_h", None) and self._h.value:

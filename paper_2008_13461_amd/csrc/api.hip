@@ -22,6 +22,12 @@ pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, c
                       double* grad_offsets, int n_max, uint32_t* status, pt_workspace ws, hipStream_t s);
 pt_err launch_fit_noalloc(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets,
                           int precision, pt_tracks& out, uint32_t* status, hipStream_t s);
+pt_err launch_ambiguity(const pt_hits& h, const pt_cells& cells, const pt_ntuplets& T, int precision,
+                        const pt_tracks& tracks, int32_t* selected, int32_t* n_selected, pt_workspace ws,
+                        hipStream_t s);
+pt_err launch_vertices(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, int precision,
+                       const pt_tracks& tracks, const int32_t* selected, const int32_t* n_selected,
+                       pt_vertices& out, uint32_t* status, pt_workspace ws, hipStream_t s);
 
 // The derived constants, with the expressions documented in pixeltrack.h.
 // Evaluated without contraction so that they are reproducible.
@@ -93,6 +99,15 @@ bool derive_config(const pt_config& c, DevCfg* d) {
   d->f64_threshold = c.f64_solve_threshold > 0.0 ? c.f64_solve_threshold : 1024.0;
   d->n_modules = c.n_modules;
   d->block_doublets = c.block_doublets;
+  if (!(c.vtx_dz_cut > 0.0) || c.vtx_kmeans_iter < 1) return false;
+  d->vtx_min_hits = c.vtx_min_hits;
+  d->vtx_kmeans_iter = c.vtx_kmeans_iter;
+  d->vtx_pt_min = c.vtx_pt_min;
+  d->vtx_err_max = c.vtx_err_max;
+  d->vtx_dz_cut = c.vtx_dz_cut;
+  d->vtx_chi2_max = c.vtx_chi2_max;
+  d->vtx_split_chi2_ndf = c.vtx_split_chi2_ndf;
+  d->vtx_pt_cap = c.vtx_pt_cap;
   return true;
 }
 #pragma clang fp contract(on)
@@ -142,6 +157,8 @@ size_t pt_workspace_size(const pt_config* cfg, int32_t n_hits, int32_t n_events,
   s = std::max(s, ws_links(n_hits, cells_cap));
   s = std::max(s, ws_ntuplets(cells_cap, tuplets_cap));
   s = std::max(s, ws_fit(tuplets_cap, d.n_modules));
+  s = std::max(s, ws_ambiguity(n_hits, cells_cap, tuplets_cap));
+  s = std::max(s, ws_vertices(n_events, tuplets_cap));
   return s;
 }
 
@@ -201,6 +218,44 @@ pt_err pt_fit_broken_line(const pt_hits* hits, const pt_config* cfg, const pt_nt
   if (!ws_ok(ws, ws_fit(n_max, d.n_modules))) return PT_ERR_WORKSPACE;
   return launch_fit(*hits, d, *tuplets, module_offsets, precision, *tracks, status, ws,
                     reinterpret_cast<hipStream_t>(stream));
+}
+
+pt_err pt_resolve_ambiguities(const pt_hits* hits, const pt_config* cfg, const pt_cells* cells,
+                              const pt_ntuplets* tuplets, int32_t precision, const pt_tracks* tracks,
+                              int32_t* selected, int32_t* n_selected, uint32_t* status, pt_workspace ws,
+                              pt_stream stream) {
+  DevCfg d;
+  (void)status;
+  if (!hits_ok(hits) || !cfg || !cells || !tuplets || !tracks || !derive_config(*cfg, &d)) return PT_ERR_ARG;
+  if (precision != PT_FIT_F64 && precision != PT_FIT_F32 && precision != PT_FIT_F32_F64SOLVE) return PT_ERR_ARG;
+  if (cells->cap < 0 || tuplets->cap < 0 || tracks->cap < 0 || !tuplets->count || !n_selected) return PT_ERR_ARG;
+  const int n_max = std::min(tuplets->cap, tracks->cap);
+  if (n_max > 0 && (!tuplets->hits || !tuplets->cells || !tuplets->n || !tracks->params || !tracks->chi2 ||
+                    !selected))
+    return PT_ERR_ARG;
+  if (!ws_ok(ws, ws_ambiguity(hits->n_hits, cells->cap, n_max))) return PT_ERR_WORKSPACE;
+  return launch_ambiguity(*hits, *cells, *tuplets, precision, *tracks, selected, n_selected, ws,
+                          reinterpret_cast<hipStream_t>(stream));
+}
+
+pt_err pt_find_vertices(const pt_hits* hits, const pt_config* cfg, const pt_ntuplets* tuplets, int32_t precision,
+                        const pt_tracks* tracks, const int32_t* selected, const int32_t* n_selected,
+                        pt_vertices* out, uint32_t* status, pt_workspace ws, pt_stream stream) {
+  DevCfg d;
+  if (!hits_ok(hits) || !cfg || !tuplets || !tracks || !out || !derive_config(*cfg, &d)) return PT_ERR_ARG;
+  if (precision != PT_FIT_F64 && precision != PT_FIT_F32 && precision != PT_FIT_F32_F64SOLVE) return PT_ERR_ARG;
+  if (tuplets->cap < 0 || tracks->cap < 0 || !tuplets->count || out->cap < 0) return PT_ERR_ARG;
+  if ((selected == nullptr) != (n_selected == nullptr)) return PT_ERR_ARG;
+  if (!out->event_first || !out->count) return PT_ERR_ARG;
+  if (out->cap > 0 && (!out->z || !out->var || !out->chi2 || !out->ndf || !out->n_tracks || !out->sum_pt2))
+    return PT_ERR_ARG;
+  const int n_max = std::min(tuplets->cap, tracks->cap);
+  if (n_max > 0 && (!tuplets->hits || !tuplets->n || !tracks->params || !tracks->cov || !out->track_vertex))
+    return PT_ERR_ARG;
+  if (hits->n_events > 0 && !hits->event_offsets) return PT_ERR_ARG;
+  if (!ws_ok(ws, ws_vertices(hits->n_events, n_max))) return PT_ERR_WORKSPACE;
+  return launch_vertices(*hits, d, *tuplets, precision, *tracks, selected, n_selected, *out, status, ws,
+                         reinterpret_cast<hipStream_t>(stream));
 }
 
 pt_err pt_fit_broken_line_noalloc(const pt_hits* hits, const pt_config* cfg, const pt_ntuplets* tuplets,

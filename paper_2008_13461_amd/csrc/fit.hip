@@ -53,6 +53,7 @@ struct FitArgs {
   void* params;
   void* chi2;
   uint8_t* track_status;
+  void* cov;                 // [n_max][15] or null
   // adjoint
   const void* g_params;       // GT (the type of grad_hits) [n][5]
   const void* g_chi2;         // GT [n], may be null
@@ -119,6 +120,8 @@ __global__ void k_reject(FitArgs a) {
       OT* P = static_cast<OT*>(a.params) + static_cast<int64_t>(i) * 5;
       for (int q = 0; q < 5; ++q) P[q] = OT(NAN);
       static_cast<OT*>(a.chi2)[i] = OT(NAN);
+      if (a.cov)
+        for (int q = 0; q < 15; ++q) static_cast<OT*>(a.cov)[static_cast<int64_t>(i) * 15 + q] = OT(NAN);
       a.track_status[i] = fit::ST_FAILED;
       ++bad;
     }
@@ -180,7 +183,7 @@ __device__ inline bool load_track(const FitArgs& a, const uint8_t* layer_barrel,
 
 // Forward fit of the tracks in bin N (LIST = false) or on the double-refit
 // list (LIST = true, any N, dispatched at run time).
-template <int N, class S, class HT, class OT>
+template <int N, class S, class HT, class OT, bool COV>
 __device__ inline void fit_one(const DevCfg& k, const fit::Consts& C, const FitArgs& a, int i, bool fallback,
                                uint32_t& n_bad, uint32_t& n_fail, uint32_t& n_redo) {
   fit::State<N, S> f;
@@ -204,9 +207,18 @@ __device__ inline void fit_one(const DevCfg& k, const fit::Consts& C, const FitA
     P[3] = OT(f.d0);
     P[4] = OT(f.z0);
     static_cast<OT*>(a.chi2)[i] = OT(f.chi2);
+    if (COV) {
+      double cv[15];
+      fit::covariance<N, S>(f, cv);
+      OT* V = static_cast<OT*>(a.cov) + static_cast<int64_t>(i) * 15;
+#pragma unroll
+      for (int q = 0; q < 15; ++q) V[q] = OT(cv[q]);
+    }
   } else {
     for (int q = 0; q < 5; ++q) P[q] = OT(NAN);
     static_cast<OT*>(a.chi2)[i] = OT(NAN);
+    if (COV)
+      for (int q = 0; q < 15; ++q) static_cast<OT*>(a.cov)[static_cast<int64_t>(i) * 15 + q] = OT(NAN);
     if (st & fit::ST_BAD_ORDER) ++n_bad; else ++n_fail;
   }
   a.track_status[i] = static_cast<uint8_t>(st);
@@ -251,7 +263,7 @@ __device__ inline int bin_total(const FitArgs& a) {
 }
 
 // Forward fit of the tracks with NLO..NHI hits.
-template <int NLO, int NHI, class S, class HT, class OT>
+template <int NLO, int NHI, class S, class HT, class OT, bool COV>
 __global__ void __launch_bounds__(kBlock) k_fit(DevCfg k, FitArgs a, bool fallback) {
   const fit::Consts C = consts_of(k);
   const int m = bin_total<NLO, NHI>(a);
@@ -259,12 +271,12 @@ __global__ void __launch_bounds__(kBlock) k_fit(DevCfg k, FitArgs a, bool fallba
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
     int nh;
     const int i = bin_item<NLO, NHI>(a, j, nh);
-    if (NLO <= 3 && 3 <= NHI && nh == 3) fit_one<3, S, HT, OT>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
-    if (NLO <= 4 && 4 <= NHI && nh == 4) fit_one<4, S, HT, OT>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
-    if (NLO <= 5 && 5 <= NHI && nh == 5) fit_one<5, S, HT, OT>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
-    if (NLO <= 6 && 6 <= NHI && nh == 6) fit_one<6, S, HT, OT>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
-    if (NLO <= 7 && 7 <= NHI && nh == 7) fit_one<7, S, HT, OT>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
-    if (NLO <= 8 && 8 <= NHI && nh == 8) fit_one<8, S, HT, OT>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
+    if (NLO <= 3 && 3 <= NHI && nh == 3) fit_one<3, S, HT, OT, COV>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
+    if (NLO <= 4 && 4 <= NHI && nh == 4) fit_one<4, S, HT, OT, COV>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
+    if (NLO <= 5 && 5 <= NHI && nh == 5) fit_one<5, S, HT, OT, COV>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
+    if (NLO <= 6 && 6 <= NHI && nh == 6) fit_one<6, S, HT, OT, COV>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
+    if (NLO <= 7 && 7 <= NHI && nh == 7) fit_one<7, S, HT, OT, COV>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
+    if (NLO <= 8 && 8 <= NHI && nh == 8) fit_one<8, S, HT, OT, COV>(k, C, a, i, fallback, n_bad, n_fail, n_redo);
   }
   flush_counts<HT>(a, n_bad, n_fail, n_redo);
 }
@@ -279,12 +291,30 @@ __global__ void k_refit(DevCfg k, FitArgs a) {
     const int i = a.redo[j];
     const int nh = a.tup_n[track_row(a, i)];
     switch (nh) {
-      case 3: fit_one<3, double, HT, OT>(k, C, a, i, false, n_bad, n_fail, n_redo); break;
-      case 4: fit_one<4, double, HT, OT>(k, C, a, i, false, n_bad, n_fail, n_redo); break;
-      case 5: fit_one<5, double, HT, OT>(k, C, a, i, false, n_bad, n_fail, n_redo); break;
-      case 6: fit_one<6, double, HT, OT>(k, C, a, i, false, n_bad, n_fail, n_redo); break;
-      case 7: fit_one<7, double, HT, OT>(k, C, a, i, false, n_bad, n_fail, n_redo); break;
-      case 8: fit_one<8, double, HT, OT>(k, C, a, i, false, n_bad, n_fail, n_redo); break;
+      case 3:
+        if (a.cov) fit_one<3, double, HT, OT, true>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        else fit_one<3, double, HT, OT, false>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        break;
+      case 4:
+        if (a.cov) fit_one<4, double, HT, OT, true>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        else fit_one<4, double, HT, OT, false>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        break;
+      case 5:
+        if (a.cov) fit_one<5, double, HT, OT, true>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        else fit_one<5, double, HT, OT, false>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        break;
+      case 6:
+        if (a.cov) fit_one<6, double, HT, OT, true>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        else fit_one<6, double, HT, OT, false>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        break;
+      case 7:
+        if (a.cov) fit_one<7, double, HT, OT, true>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        else fit_one<7, double, HT, OT, false>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        break;
+      case 8:
+        if (a.cov) fit_one<8, double, HT, OT, true>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        else fit_one<8, double, HT, OT, false>(k, C, a, i, false, n_bad, n_fail, n_redo);
+        break;
       default: break;
     }
     a.track_status[i] |= fit::ST_F64;
@@ -468,11 +498,15 @@ template <class S, class HT, class OT>
 static pt_err run_fit(const DevCfg& k, FitArgs& a, bool fallback, hipStream_t s) {
   const int g = fit_grid(a.n_max);
   k_reject<OT><<<g, kBlock, 0, s>>>(a);
-  void* tok = timing_begin(s);
-  k_fit<4, 6, S, HT, OT><<<g, kBlock, 0, s>>>(k, a, fallback);
-  timing_end(tok, "fit_fwd", s);
-  k_fit<3, 3, S, HT, OT><<<g, kBlock, 0, s>>>(k, a, fallback);
-  k_fit<7, 8, S, HT, OT><<<g, kBlock, 0, s>>>(k, a, fallback);
+  if (a.cov) {
+    k_fit<4, 6, S, HT, OT, true><<<g, kBlock, 0, s>>>(k, a, fallback);
+    k_fit<3, 3, S, HT, OT, true><<<g, kBlock, 0, s>>>(k, a, fallback);
+    k_fit<7, 8, S, HT, OT, true><<<g, kBlock, 0, s>>>(k, a, fallback);
+  } else {
+    k_fit<4, 6, S, HT, OT, false><<<g, kBlock, 0, s>>>(k, a, fallback);
+    k_fit<3, 3, S, HT, OT, false><<<g, kBlock, 0, s>>>(k, a, fallback);
+    k_fit<7, 8, S, HT, OT, false><<<g, kBlock, 0, s>>>(k, a, fallback);
+  }
   PT_LAUNCH_CHECK();
   if (fallback) {
     k_refit<HT, OT><<<64, 64, 0, s>>>(k, a);
@@ -488,23 +522,27 @@ pt_err launch_fit(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const
   a.params = out.params;
   a.chi2 = out.chi2;
   a.track_status = out.status;
+  a.cov = out.cov;
+  // one timing region over every kernel of the forward fit
+  void* tok = timing_begin(s);
   pt_err e = prepare(a, s);
-  if (e != PT_OK) return e;
-  const bool f64in = h.dtype == PT_F64;
-  if (precision == PT_FIT_F64) {
-    return f64in ? run_fit<double, double, double>(k, a, false, s) : run_fit<double, float, double>(k, a, false, s);
+  if (e == PT_OK) {
+    const bool f64in = h.dtype == PT_F64;
+    const bool fb = precision == PT_FIT_F32_F64SOLVE;
+    if (precision == PT_FIT_F64)
+      e = f64in ? run_fit<double, double, double>(k, a, false, s) : run_fit<double, float, double>(k, a, false, s);
+    else
+      e = f64in ? run_fit<float, double, float>(k, a, fb, s) : run_fit<float, float, float>(k, a, fb, s);
   }
-  const bool fb = precision == PT_FIT_F32_F64SOLVE;
-  return f64in ? run_fit<float, double, float>(k, a, fb, s) : run_fit<float, float, float>(k, a, fb, s);
+  timing_end(tok, "fit_fwd", s);
+  return e;
 }
 
 template <class S, class HT, class GT>
 static pt_err run_grad(const DevCfg& k, FitArgs& a, bool fallback, double* grad_offsets, hipStream_t s) {
   const size_t lds = a.partials ? static_cast<size_t>(a.n_modules) * 3 * sizeof(double) : 0;
   const int nm3 = a.n_modules * 3;
-  void* tok = timing_begin(s);
   k_grad<4, 6, true, S, HT, GT><<<kBwdBlocks, kBlock, lds, s>>>(k, a, fallback);
-  timing_end(tok, "fit_bwd", s);
   k_grad<3, 3, false, S, HT, GT><<<kBwdBlocks, kBlock, lds, s>>>(k, a, fallback);
   k_grad<7, 8, false, S, HT, GT><<<kBwdBlocks, kBlock, lds, s>>>(k, a, fallback);
   PT_LAUNCH_CHECK();
@@ -527,16 +565,21 @@ pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, c
   a.g_chi2 = g_chi2;
   a.grad_hits = grad_hits;
   if (!grad_offsets) a.partials = nullptr;
+  // one timing region over every kernel of the adjoint
+  void* tok = timing_begin(s);
   pt_err e = prepare(a, s);
-  if (e != PT_OK) return e;
-  const bool f64in = h.dtype == PT_F64;
-  if (precision == PT_FIT_F64) {
-    return f64in ? run_grad<double, double, double>(k, a, false, grad_offsets, s)
-                 : run_grad<double, float, double>(k, a, false, grad_offsets, s);
+  if (e == PT_OK) {
+    const bool f64in = h.dtype == PT_F64;
+    const bool fb = precision == PT_FIT_F32_F64SOLVE;
+    if (precision == PT_FIT_F64)
+      e = f64in ? run_grad<double, double, double>(k, a, false, grad_offsets, s)
+                : run_grad<double, float, double>(k, a, false, grad_offsets, s);
+    else
+      e = f64in ? run_grad<float, double, float>(k, a, fb, grad_offsets, s)
+                : run_grad<float, float, float>(k, a, fb, grad_offsets, s);
   }
-  const bool fb = precision == PT_FIT_F32_F64SOLVE;
-  return f64in ? run_grad<float, double, float>(k, a, fb, grad_offsets, s)
-               : run_grad<float, float, float>(k, a, fb, grad_offsets, s);
+  timing_end(tok, "fit_bwd", s);
+  return e;
 }
 
 // ---------------------------------------------------------------------------

@@ -427,17 +427,22 @@ PT_HD inline void forward(const Consts& C, State<N, S>& f) {
     f.status = ST_FAILED;
 }
 
-// Reverse sweep.  g = d(loss)/d(kappa, phi0, cot, d0, z0, chi2).  On return
-// gP[k][c] = d(loss)/d(coordinate c of hit k).
+// Reverse sweep of the perigee conversion alone: with g = d(loss)/d(kappa,
+// phi0, cot, d0, z0), the derivatives of the loss with respect to what the
+// conversion reads -- the first hit, the fitted offsets u0, u1 and curvature
+// correction dk of the circle fit, the fitted deviations w0, w1 of the line
+// fit, the pre-fit slope t, spacing D0, tangent (tx, ty) and curvature kp.
+struct PerigeeBar {
+  double P0x, P0y, P0z, wl0, wl1, t, D0, u0, u1, dk, tx, ty, kp;
+};
+
 template <int N, class S>
-PT_HD inline void backward(const Consts& C, const State<N, S>& f, const double g[6], S gP[N][3]) {
-  constexpr int b = N / 2;
+PT_HD inline void perigee_vjp(const State<N, S>& f, const double g[5], PerigeeBar& o) {
   const double tx = double(f.tx), ty = double(f.ty);
   const double tn = sqrt(tx * tx + ty * ty);
   const double ex = tx / tn, ey = ty / tn;
   const double D0 = double(f.D[0]);
   const double u0 = double(f.xc[0]), u1 = double(f.xc[1]);
-  // ---------------- perigee (double)
   double kappa_b = g[0], phi0_b = g[1], cot_b = g[2], d0_b = g[3], z0_b = g[4];
   double P0x_b = 0, P0y_b = 0, P0z_b = 0, wl0_b = 0, wl1_b = 0, t_bd = 0, D0_b = 0;
   double Qx_b = 0, Qy_b = 0, cph_b = 0, sph_b = 0, ex_b = 0, ey_b = 0;
@@ -518,6 +523,99 @@ PT_HD inline void backward(const Consts& C, const State<N, S>& f, const double g
   // kappa = kp + dk
   double kp_bd = kappa_b;
   dk_b += kappa_b;
+
+  o.P0x = P0x_b;
+  o.P0y = P0y_b;
+  o.P0z = P0z_b;
+  o.wl0 = wl0_b;
+  o.wl1 = wl1_b;
+  o.t = t_bd;
+  o.D0 = D0_b;
+  o.u0 = xu0_b;
+  o.u1 = xu1_b;
+  o.dk = dk_b;
+  o.tx = tx_bd;
+  o.ty = ty_bd;
+  o.kp = kp_bd;
+}
+
+// Covariance of (kappa, phi0, cot, d0, z0), the upper triangle row by row in
+// cov[15].  The broken-line solutions are linear in the measurements, the
+// kinks being zero-mean pseudo-measurements, so the covariance of the circle
+// unknowns is the inverse of its normal matrix and that of the line unknowns
+// the inverse of its own; the two fits share no measurement.  The perigee
+// conversion reads the circle solution only through (u0, u1, dk) and the
+// line solution only through (w0, w1), so with Sc and Sl the inverses
+// restricted to those unknowns (columns from solves with the Cholesky
+// factors) and Jc, Jl the derivatives of the conversion (rows from
+// perigee_vjp with unit cotangents), C = Jc Sc Jc^T + Jl Sl Jl^T.  The pre-fit
+// is held fixed (it is the point the fit is linearised around).
+template <int N, class S>
+PT_HD inline void covariance(const State<N, S>& f, double cov[15]) {
+  double jc[5][3], jl[5][2];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    g[q] = 1.0;
+    PerigeeBar pb;
+    perigee_vjp<N, S>(f, g, pb);
+    jc[q][0] = pb.u0;
+    jc[q][1] = pb.u1;
+    jc[q][2] = pb.dk;
+    jl[q][0] = pb.wl0;
+    jl[q][1] = pb.wl1;
+  }
+  const int ic[3] = {0, 1, N};
+  double sc[3][3], sl[2][2];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    S e[N + 1];
+#pragma unroll
+    for (int i = 0; i <= N; ++i) e[i] = S(0);
+    e[ic[j]] = S(1);
+    f.circ.solve(e);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) sc[i][j] = double(e[ic[i]]);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    S e[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) e[i] = S(0);
+    e[j] = S(1);
+    f.line.solve(e);
+    sl[0][j] = double(e[0]);
+    sl[1][j] = double(e[1]);
+  }
+  int q = 0;
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+#pragma unroll
+    for (int b = a; b < 5; ++b) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s += jc[a][i] * 0.5 * (sc[i][j] + sc[j][i]) * jc[b][j];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) s += jl[a][i] * 0.5 * (sl[i][j] + sl[j][i]) * jl[b][j];
+      cov[q++] = s;
+    }
+  }
+}
+
+// Reverse sweep.  g = d(loss)/d(kappa, phi0, cot, d0, z0, chi2).  On return
+// gP[k][c] = d(loss)/d(coordinate c of hit k).
+template <int N, class S>
+PT_HD inline void backward(const Consts& C, const State<N, S>& f, const double g[6], S gP[N][3]) {
+  constexpr int b = N / 2;
+  PerigeeBar pb;
+  perigee_vjp<N, S>(f, g, pb);
+  const double P0x_b = pb.P0x, P0y_b = pb.P0y, P0z_b = pb.P0z, wl0_b = pb.wl0, wl1_b = pb.wl1;
+  const double t_bd = pb.t, D0_b = pb.D0, xu0_b = pb.u0, xu1_b = pb.u1, dk_b = pb.dk;
+  const double tx_bd = pb.tx, ty_bd = pb.ty, kp_bd = pb.kp;
 
   // ---------------- the two solves
   const S G2 = S(g[5]);

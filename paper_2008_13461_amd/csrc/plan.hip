@@ -26,6 +26,12 @@ pt_err launch_fit(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const
 pt_err launch_fit_bwd(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, const float* offsets,
                       int precision, const void* g_params, const void* g_chi2, void* grad_hits,
                       double* grad_offsets, int n_max, uint32_t* status, pt_workspace ws, hipStream_t s);
+pt_err launch_ambiguity(const pt_hits& h, const pt_cells& cells, const pt_ntuplets& T, int precision,
+                        const pt_tracks& tracks, int32_t* selected, int32_t* n_selected, pt_workspace ws,
+                        hipStream_t s);
+pt_err launch_vertices(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, int precision,
+                       const pt_tracks& tracks, const int32_t* selected, const int32_t* n_selected,
+                       pt_vertices& out, uint32_t* status, pt_workspace ws, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // kernel timing
@@ -85,7 +91,7 @@ void timing_end(void* tok, const char* name, hipStream_t s) {
 struct Plan {
   pt_config cfg;
   DevCfg dev;
-  int32_t n_hits_max, n_events_max, cells_cap, links_cap, tuplets_cap, precision, with_adjoint;
+  int32_t n_hits_max, n_events_max, cells_cap, links_cap, tuplets_cap, precision, stages;
   void* ws = nullptr;
   size_t ws_bytes = 0;
   hipStream_t cap_stream = nullptr;
@@ -139,11 +145,12 @@ int32_t pt_timing_read(const char* kernel, double* total_ms, int64_t* launches) 
 }
 
 pt_err pt_plan_create(const pt_config* cfg, int32_t n_hits_max, int32_t n_events_max, int32_t cells_cap,
-                      int32_t links_cap, int32_t tuplets_cap, int32_t precision, int32_t with_adjoint,
+                      int32_t links_cap, int32_t tuplets_cap, int32_t precision, int32_t stages,
                       pt_plan* out) {
   if (!cfg || !out || n_hits_max < 0 || n_events_max < 0 || cells_cap < 0 || links_cap < 0 || tuplets_cap < 0)
     return PT_ERR_ARG;
   if (precision != PT_FIT_F64 && precision != PT_FIT_F32 && precision != PT_FIT_F32_F64SOLVE) return PT_ERR_ARG;
+  if (stages & ~(PT_STAGE_ADJOINT | PT_STAGE_AMBIGUITY | PT_STAGE_VERTICES)) return PT_ERR_ARG;
   Plan* p = new Plan();
   p->cfg = *cfg;
   if (!derive_config(*cfg, &p->dev)) {
@@ -156,7 +163,7 @@ pt_err pt_plan_create(const pt_config* cfg, int32_t n_hits_max, int32_t n_events
   p->links_cap = links_cap;
   p->tuplets_cap = tuplets_cap;
   p->precision = precision;
-  p->with_adjoint = with_adjoint;
+  p->stages = stages;
   p->ws_bytes = pt_workspace_size(cfg, n_hits_max, n_events_max, cells_cap, links_cap, tuplets_cap);
   if (p->ws_bytes == 0 || hipMalloc(&p->ws, p->ws_bytes) != hipSuccess ||
       hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -181,27 +188,42 @@ void pt_plan_destroy(pt_plan plan) {
 
 static pt_err enqueue_step(Plan* p, const pt_hits* hits, pt_cells* cells, pt_links* links, pt_ntuplets* tuplets,
                            pt_tracks* tracks, const float* offsets, const void* g_params, const void* g_chi2,
-                           void* grad_hits, double* grad_offsets, uint32_t* status, hipStream_t s) {
+                           void* grad_hits, double* grad_offsets, int32_t* selected, int32_t* n_selected,
+                           pt_vertices* vertices, uint32_t* status, hipStream_t s) {
   pt_workspace ws{p->ws, p->ws_bytes};
   pt_err e = launch_doublets(*hits, p->dev, *cells, status, ws, s);
   if (e == PT_OK) e = launch_links(*hits, p->dev, *cells, *links, status, ws, s, p->cfg.block_links);
   if (e == PT_OK) e = launch_ntuplets(*hits, p->dev, *cells, *links, *tuplets, status, ws, s);
   if (e == PT_OK) e = launch_fit(*hits, p->dev, *tuplets, offsets, p->precision, *tracks, status, ws, s);
-  if (e == PT_OK && p->with_adjoint)
+  if (e == PT_OK && (p->stages & PT_STAGE_ADJOINT))
     e = launch_fit_bwd(*hits, p->dev, *tuplets, offsets, p->precision, g_params, g_chi2, grad_hits, grad_offsets,
                        std::min(tuplets->cap, tracks->cap), status, ws, s);
+  if (e == PT_OK && (p->stages & PT_STAGE_AMBIGUITY))
+    e = launch_ambiguity(*hits, *cells, *tuplets, p->precision, *tracks, selected, n_selected, ws, s);
+  if (e == PT_OK && (p->stages & PT_STAGE_VERTICES)) {
+    const bool sel = (p->stages & PT_STAGE_AMBIGUITY) != 0;
+    e = launch_vertices(*hits, p->dev, *tuplets, p->precision, *tracks, sel ? selected : nullptr,
+                        sel ? n_selected : nullptr, *vertices, status, ws, s);
+  }
   return e;
 }
 
 pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links* links, pt_ntuplets* tuplets,
                    pt_tracks* tracks, const float* module_offsets, const void* g_params, const void* g_chi2,
-                   void* grad_hits, double* grad_offsets, uint32_t* status, pt_stream stream) {
+                   void* grad_hits, double* grad_offsets, int32_t* selected, int32_t* n_selected,
+                   pt_vertices* vertices, uint32_t* status, pt_stream stream) {
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p || !hits || !cells || !links || !tuplets || !tracks) return PT_ERR_ARG;
   if (hits->n_hits > p->n_hits_max || hits->n_events > p->n_events_max || cells->cap > p->cells_cap ||
       links->cap > p->links_cap || tuplets->cap > p->tuplets_cap || tracks->cap < tuplets->cap)
     return PT_ERR_ARG;
-  if (p->with_adjoint && !g_params) return PT_ERR_ARG;
+  if ((p->stages & PT_STAGE_ADJOINT) && !g_params) return PT_ERR_ARG;
+  if ((p->stages & PT_STAGE_AMBIGUITY) && (!selected || !n_selected || !tuplets->cells)) return PT_ERR_ARG;
+  if ((p->stages & PT_STAGE_VERTICES) &&
+      (!vertices || !tracks->cov || !vertices->event_first || !vertices->count || !vertices->track_vertex ||
+       (vertices->cap > 0 && (!vertices->z || !vertices->var || !vertices->chi2 || !vertices->ndf ||
+                              !vertices->n_tracks || !vertices->sum_pt2))))
+    return PT_ERR_ARG;
   if ((module_offsets || grad_offsets) && !hits->module) return PT_ERR_ARG;
   // everything the captured graph depends on
   std::vector<uint8_t> key;
@@ -214,8 +236,9 @@ pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links*
   add(links, sizeof(*links));
   add(tuplets, sizeof(*tuplets));
   add(tracks, sizeof(*tracks));
-  const void* ptrs[] = {module_offsets, g_params, g_chi2, grad_hits, grad_offsets, status};
+  const void* ptrs[] = {module_offsets, g_params, g_chi2, grad_hits, grad_offsets, selected, n_selected, status};
   add(ptrs, sizeof(ptrs));
+  if (vertices) add(vertices, sizeof(*vertices));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!p->exec || key != p->key) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -225,7 +248,7 @@ pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links*
     if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PT_ERR_DEVICE;
     g_capturing = true;
     pt_err e = enqueue_step(p, hits, cells, links, tuplets, tracks, module_offsets, g_params, g_chi2, grad_hits,
-                            grad_offsets, status, p->cap_stream);
+                            grad_offsets, selected, n_selected, vertices, status, p->cap_stream);
     g_capturing = false;
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);

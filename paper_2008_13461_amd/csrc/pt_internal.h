@@ -50,6 +50,9 @@ struct DevCfg {
   double f64_threshold;
   int32_t n_modules;
   int32_t block_doublets;
+  // vertices
+  int32_t vtx_min_hits, vtx_kmeans_iter;
+  double vtx_pt_min, vtx_err_max, vtx_dz_cut, vtx_chi2_max, vtx_split_chi2_ndf, vtx_pt_cap;
 };
 
 bool derive_config(const pt_config& c, DevCfg* d);
@@ -74,6 +77,8 @@ size_t ws_doublets(int n_hits, int n_events, int n_bins);
 size_t ws_links(int n_hits, int cells_cap);
 size_t ws_ntuplets(int cells_cap, int tuplets_cap);
 size_t ws_fit(int n_max, int n_modules);
+size_t ws_ambiguity(int n_hits, int cells_cap, int n_max);
+size_t ws_vertices(int n_events, int n_max);
 
 // Device-wide exclusive scan of n int32 values in place; data[n] receives the
 // total.  tmp must hold scan_tmp_elems(n) int32.

@@ -1,0 +1,608 @@
+// Pixel vertices (paper section 3.6): clusters of the fitted tracks in z0.
+//
+// Tracks take part when they were selected by the ambiguity resolution, have
+// at least vtx_min_hits hits, p_T above vtx_pt_min and a finite z0 with a
+// positive variance (the (z0, z0) element of their covariance).  Per event:
+//   * the local density of a track (computed only when its sigma(z0) is at
+//     most vtx_err_max): the other tracks within vtx_dz_cut in z0 whose
+//     compatibility (dz)^2 / (var_i + var_j) is below vtx_chi2_max;
+//   * each track links to the nearest track of higher rank (density, then
+//     track index) within the same window with compatibility at most
+//     vtx_chi2_max; links climb in rank, so they form trees;
+//   * a tree whose root has density > 1 (a seed) and at least 2 tracks is a
+//     vertex: weighted mean of z0 (weights 1/var), its variance and chi2;
+//   * a vertex with chi2/ndf > vtx_split_chi2_ndf is split in two by 1-D
+//     two-means (centres from its extreme members, at most vtx_kmeans_iter
+//     rounds); parts of one track are dropped;
+//   * the event's vertices are ordered by the sum of min(p_T, vtx_pt_cap)^2
+//     of their tracks, largest (the primary) first.
+// All sums run over a vertex's members in the order of (z0, track index),
+// sequentially in one thread, in double without contraction, so that the
+// result is reproducible and the decisions of the split are exact.
+//
+// GPU layout: the tracks of each event are gathered into a contiguous list
+// (count, scan, scatter), then one work-group per event sorts its list by
+// (z0, track index) -- a bitonic sort in LDS, or in global scratch for
+// events with more tracks than the LDS holds -- so that every window in z0
+// is a contiguous range of the sorted list.  Densities and links are one
+// thread per track over its window; the trees are resolved by pointer
+// jumping; one thread per tree fits (and splits) it; the vertices are
+// sorted by their key and written after a scan over events.
+#include <algorithm>
+
+#include "pt_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace pt {
+namespace {
+
+constexpr int kBlock = 1024;
+constexpr int kLdsSort = 4096;  // entries sorted in LDS (12 bytes each)
+
+struct VtxArgs {
+  // tracks
+  const int32_t* hits;   // rows [cap][kMaxHits]
+  const uint8_t* n;
+  const int32_t* kept;
+  const int32_t* count;
+  int32_t n_max;
+  const void* params;    // [n_max][5]
+  const void* cov;       // [n_max][15]
+  int32_t dbl;
+  const int32_t* selected;    // may be null: every track
+  const int32_t* n_selected;
+  // events
+  const int32_t* event_offsets;
+  int32_t n_events;
+  int32_t n_hits;
+  // settings
+  int32_t min_hits, kmeans_iter;
+  double pt_min, err_max, dz_cut, chi2_max, split, pt_cap, K;
+  // scratch, [n_max] unless noted
+  uint8_t* use;
+  int32_t* ev_of;        // event of each track, -1 when it takes no part
+  int32_t* ev_count;     // [n_events + 1], scanned in place into the starts
+  int32_t* ev_cursor;    // [n_events]
+  int32_t* list;         // tracks grouped by event
+  uint64_t* skey;        // [2 n_max] sort keys (padded per event)
+  int32_t* sval;         // [2 n_max]
+  double* sz;            // sorted z0
+  double* sv;            // sorted variance
+  int32_t* sidx;         // sorted track index
+  int32_t* rho;
+  int32_t* parent;
+  int32_t* root;
+  int32_t* tsize;        // tree size, per root position
+  int32_t* tlo;          // first member position, per root
+  int32_t* thi;          // last member position, per root
+  uint8_t* side;
+  // per event vertex records (at the event's list offset, at most one per track)
+  double* rz;
+  double* rvar;
+  double* rchi2;
+  double* rsum;
+  int32_t* rndf;
+  int32_t* rn;
+  int32_t* rfirst;       // first member position (identifies the record)
+  int32_t* rroot;        // tree root position
+  int32_t* rpart;        // 0 whole, 1 / 2 the parts of a split
+  int32_t* rslot;        // per position: record slot of the record whose first member it is
+  int32_t* vlocal;       // per position: rank of the track's vertex in its event, -1
+  int32_t* ev_nvtx;      // [n_events + 1], scanned into the first vertex of each event
+  // outputs
+  double *oz, *ovar, *ochi2, *osum;
+  int32_t *ondf, *on;
+  int32_t* event_first;  // [n_events + 1]
+  int32_t* n_vertices;   // [1]
+  int32_t* track_vertex; // [n_max]
+  int32_t cap;
+  uint32_t* status;
+};
+
+__device__ inline int n_tracks(const VtxArgs& a) { return min(*a.count, a.n_max); }
+
+__device__ inline double val(const void* p, int64_t i, int dbl) {
+  return dbl ? static_cast<const double*>(p)[i] : double(static_cast<const float*>(p)[i]);
+}
+
+// Key whose unsigned order is the numeric order of the double.
+__device__ inline uint64_t order_key(double v) {
+  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
+  return (b >> 63) ? ~b : (b | (uint64_t(1) << 63));
+}
+
+// ---------------------------------------------------------------------------
+// tracks -> events
+
+__global__ void k_vtx_clear(VtxArgs a) {
+  const int n = a.n_max;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    a.use[i] = a.selected ? 0 : 1;
+    a.track_vertex[i] = -1;
+  }
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e <= a.n_events; e += gridDim.x * blockDim.x) {
+    a.ev_count[e] = 0;
+    a.ev_nvtx[e] = 0;
+    if (e < a.n_events) a.ev_cursor[e] = 0;
+  }
+}
+
+__global__ void k_vtx_mark(VtxArgs a) {
+  const int m = min(*a.n_selected, a.n_max);
+  const int n = n_tracks(a);
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+    const int i = a.selected[j];
+    if (i >= 0 && i < n) a.use[i] = 1;
+  }
+}
+
+__global__ void k_vtx_events(VtxArgs a) {
+  const int n = n_tracks(a);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int e = -1;
+    const int row = a.kept ? a.kept[i] : i;
+    const int nh = a.n[row];
+    const double kap = val(a.params, static_cast<int64_t>(i) * 5 + 0, a.dbl);
+    const double z = val(a.params, static_cast<int64_t>(i) * 5 + 4, a.dbl);
+    const double v = val(a.cov, static_cast<int64_t>(i) * 15 + 14, a.dbl);
+    const double pt = a.K / fabs(kap);
+    const int h0 = a.hits[static_cast<int64_t>(row) * kMaxHits];
+    if (a.use[i] && nh >= a.min_hits && pt > a.pt_min && isfinite(z) && isfinite(v) && v > 0.0 && h0 >= 0 &&
+        h0 < a.n_hits) {
+      // the event owning the first hit: the last e with event_offsets[e] <= h0
+      int lo = 0, hi = a.n_events - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.event_offsets[mid] <= h0) lo = mid; else hi = mid - 1;
+      }
+      if (a.n_events > 0 && a.event_offsets[lo] <= h0 && h0 < a.event_offsets[lo + 1]) e = lo;
+    }
+    a.ev_of[i] = e;
+    if (e >= 0) atomicAdd(a.ev_count + e, 1);
+  }
+}
+
+__global__ void k_vtx_scatter(VtxArgs a) {
+  const int n = n_tracks(a);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int e = a.ev_of[i];
+    if (e >= 0) a.list[a.ev_count[e] + atomicAdd(a.ev_cursor + e, 1)] = i;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one work-group per event
+
+// Ascending bitonic sort of (key, val) pairs, P a power of two, by the whole
+// block; key and val may point to LDS or to global memory.
+__device__ void bitonic(uint64_t* key, int32_t* v, int P) {
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < P / 2; t += blockDim.x) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const uint64_t kl = key[lo], kh = key[hi];
+        const int32_t vl = v[lo], vh = v[hi];
+        const bool gt = kl > kh || (kl == kh && vl > vh);
+        if (gt == asc) {
+          key[lo] = kh;
+          key[hi] = kl;
+          v[lo] = vh;
+          v[hi] = vl;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ inline int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Sorts the n pairs at (key, v) (room for the padding to a power of two
+// given), in LDS when they fit.
+__device__ void sort_pairs(uint64_t* key, int32_t* v, int n, uint64_t* lkey, int32_t* lval) {
+  const int P = pow2_at_least(max(n, 2));
+  for (int k = n + threadIdx.x; k < P; k += blockDim.x) {
+    key[k] = ~uint64_t(0);
+    v[k] = 0x7fffffff;
+  }
+  __syncthreads();
+  if (P <= kLdsSort) {
+    for (int k = threadIdx.x; k < P; k += blockDim.x) {
+      lkey[k] = key[k];
+      lval[k] = v[k];
+    }
+    __syncthreads();
+    bitonic(lkey, lval, P);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      key[k] = lkey[k];
+      v[k] = lval[k];
+    }
+  } else {
+    bitonic(key, v, P);
+  }
+  __syncthreads();
+}
+
+// Fit of the members of tree r (positions lo..hi whose root is r, and, for
+// part p > 0, whose side is p - 1), in position order.
+struct VFit {
+  double z, var, chi2, sum;
+  int n, first;
+};
+
+__device__ inline VFit fit_members(const VtxArgs& a, int64_t b, int r, int lo, int hi, int part) {
+  VFit f;
+  double W = 0.0, S = 0.0;
+  f.n = 0;
+  f.first = -1;
+  for (int q = lo; q <= hi; ++q) {
+    if (a.root[b + q] != r || (part > 0 && a.side[b + q] != part - 1)) continue;
+    const double w = 1.0 / a.sv[b + q];
+    W = W + w;
+    S = S + w * a.sz[b + q];
+    if (f.first < 0) f.first = q;
+    ++f.n;
+  }
+  f.z = S / W;
+  f.var = 1.0 / W;
+  double c = 0.0, s2 = 0.0;
+  for (int q = lo; q <= hi; ++q) {
+    if (a.root[b + q] != r || (part > 0 && a.side[b + q] != part - 1)) continue;
+    const double d = a.sz[b + q] - f.z;
+    c = c + (d * d) / a.sv[b + q];
+    const int i = a.sidx[b + q];
+    const double pt = a.K / fabs(val(a.params, static_cast<int64_t>(i) * 5 + 0, a.dbl));
+    const double p = pt < a.pt_cap ? pt : a.pt_cap;
+    s2 = s2 + p * p;
+  }
+  f.chi2 = c;
+  f.sum = s2;
+  return f;
+}
+
+__device__ inline void put_record(const VtxArgs& a, int64_t slot, const VFit& f, int r, int part) {
+  a.rz[slot] = f.z;
+  a.rvar[slot] = f.var;
+  a.rchi2[slot] = f.chi2;
+  a.rsum[slot] = f.sum;
+  a.rndf[slot] = f.n - 1;
+  a.rn[slot] = f.n;
+  a.rfirst[slot] = f.first;
+  a.rroot[slot] = r;
+  a.rpart[slot] = part;
+}
+
+__global__ void __launch_bounds__(kBlock) k_vtx_event_cluster(VtxArgs a) {
+  __shared__ uint64_t lkey[kLdsSort];
+  __shared__ int32_t lval[kLdsSort];
+  __shared__ int s_changed;
+  __shared__ int s_nrec;
+  const int e = blockIdx.x;
+  const int64_t b = a.ev_count[e];             // the event's first list entry
+  const int n = a.ev_count[e + 1] - a.ev_count[e];
+  if (n == 0) return;
+  uint64_t* key = a.skey + 2 * b;
+  int32_t* sv = a.sval + 2 * b;
+  // ---- sort the event's tracks by (z0, track index)
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int i = a.list[b + k];
+    key[k] = order_key(val(a.params, static_cast<int64_t>(i) * 5 + 4, a.dbl));
+    sv[k] = i;
+  }
+  __syncthreads();
+  sort_pairs(key, sv, n, lkey, lval);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int i = sv[k];
+    a.sidx[b + k] = i;
+    a.sz[b + k] = val(a.params, static_cast<int64_t>(i) * 5 + 4, a.dbl);
+    a.sv[b + k] = val(a.cov, static_cast<int64_t>(i) * 15 + 14, a.dbl);
+    a.tsize[b + k] = 0;
+    a.tlo[b + k] = 0x7fffffff;
+    a.thi[b + k] = -1;
+    a.rslot[b + k] = -1;
+    a.vlocal[b + k] = -1;
+  }
+  __syncthreads();
+  const double* z = a.sz + b;
+  const double* v = a.sv + b;
+  // ---- densities
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    int c = 0;
+    if (sqrt(v[k]) <= a.err_max) {
+      for (int j = k - 1; j >= 0; --j) {
+        const double d = z[k] - z[j];
+        if (!(fabs(d) < a.dz_cut)) break;
+        if (d * d < a.chi2_max * (v[k] + v[j])) ++c;
+      }
+      for (int j = k + 1; j < n; ++j) {
+        const double d = z[k] - z[j];
+        if (!(fabs(d) < a.dz_cut)) break;
+        if (d * d < a.chi2_max * (v[k] + v[j])) ++c;
+      }
+    }
+    a.rho[b + k] = c;
+  }
+  __syncthreads();
+  // ---- links to the nearest higher-ranked compatible track
+  const int32_t* rho = a.rho + b;
+  const int32_t* idx = a.sidx + b;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    int best = -1;
+    double bd = 0.0;
+    for (int dir = -1; dir <= 1; dir += 2) {
+      for (int j = k + dir; j >= 0 && j < n; j += dir) {
+        const double d = z[k] - z[j];
+        if (!(fabs(d) < a.dz_cut)) break;
+        const bool higher = rho[j] > rho[k] || (rho[j] == rho[k] && idx[j] > idx[k]);
+        if (!higher || !(d * d <= a.chi2_max * (v[k] + v[j]))) continue;
+        const double ad = fabs(d);
+        if (best < 0 || ad < bd || (ad == bd && idx[j] < idx[best])) {
+          best = j;
+          bd = ad;
+        }
+      }
+    }
+    a.parent[b + k] = best;
+    a.root[b + k] = best < 0 ? k : best;
+  }
+  __syncthreads();
+  // ---- roots by pointer jumping
+  int32_t* root = a.root + b;
+  for (;;) {
+    if (threadIdx.x == 0) s_changed = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      const int r = root[k];
+      const int rr = root[r];
+      if (rr != r) {
+        root[k] = rr;
+        s_changed = 1;
+      }
+    }
+    __syncthreads();
+    const int again = s_changed;
+    __syncthreads();
+    if (!again) break;
+  }
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int r = root[k];
+    atomicAdd(a.tsize + b + r, 1);
+    atomicMin(a.tlo + b + r, k);
+    atomicMax(a.thi + b + r, k);
+  }
+  if (threadIdx.x == 0) s_nrec = 0;
+  __syncthreads();
+  // ---- one thread per candidate tree: fit, split, records
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    if (root[r] != r || !(rho[r] > 1) || a.tsize[b + r] < 2) continue;
+    const int lo = a.tlo[b + r], hi = a.thi[b + r];
+    const VFit f = fit_members(a, b, r, lo, hi, 0);
+    if (!(f.chi2 / (f.n - 1) > a.split)) {
+      const int slot = atomicAdd(&s_nrec, 1);
+      put_record(a, b + slot, f, r, 0);
+      continue;
+    }
+    // two-means from the extreme members
+    double c1 = z[lo], c2 = z[hi];
+    bool empty = false, first_round = true;
+    for (int it = 0; it < a.kmeans_iter; ++it) {
+      bool moved = first_round;
+      double W1 = 0.0, S1 = 0.0, W2 = 0.0, S2 = 0.0;
+      for (int q = lo; q <= hi; ++q) {
+        if (root[q] != r) continue;
+        const uint8_t s = fabs(z[q] - c1) <= fabs(z[q] - c2) ? 0 : 1;
+        if (!first_round && s != a.side[b + q]) moved = true;
+        a.side[b + q] = s;
+        const double w = 1.0 / v[q];
+        if (s == 0) {
+          W1 = W1 + w;
+          S1 = S1 + w * z[q];
+        } else {
+          W2 = W2 + w;
+          S2 = S2 + w * z[q];
+        }
+      }
+      first_round = false;
+      if (!moved) break;
+      if (W1 == 0.0 || W2 == 0.0) {
+        empty = true;
+        break;
+      }
+      c1 = S1 / W1;
+      c2 = S2 / W2;
+    }
+    if (empty) {
+      const int slot = atomicAdd(&s_nrec, 1);
+      put_record(a, b + slot, f, r, 0);
+      continue;
+    }
+    for (int p = 1; p <= 2; ++p) {
+      const VFit g = fit_members(a, b, r, lo, hi, p);
+      if (g.n < 2) continue;
+      const int slot = atomicAdd(&s_nrec, 1);
+      put_record(a, b + slot, g, r, p);
+    }
+  }
+  __syncthreads();
+  // ---- order the records: sum of p_T^2 descending, then first member
+  const int nr = s_nrec;
+  for (int k = threadIdx.x; k < nr; k += blockDim.x) {
+    key[k] = ~order_key(a.rsum[b + k]);
+    sv[k] = a.rfirst[b + k];
+    a.rslot[b + a.rfirst[b + k]] = k;
+  }
+  __syncthreads();
+  if (nr > 0) sort_pairs(key, sv, nr, lkey, lval);
+  // ---- each record's members learn their vertex's rank
+  for (int k = threadIdx.x; k < nr; k += blockDim.x) {
+    const int slot = a.rslot[b + sv[k]];
+    const int r = a.rroot[b + slot], part = a.rpart[b + slot];
+    for (int q = a.tlo[b + r]; q <= a.thi[b + r]; ++q)
+      if (root[q] == r && (part == 0 || a.side[b + q] == part - 1)) a.vlocal[b + q] = k;
+  }
+  if (threadIdx.x == 0) a.ev_nvtx[e] = nr;
+}
+
+// Writes event e's ordered vertices at event_first[e] and the tracks' vertex
+// indices.
+__global__ void __launch_bounds__(kBlock) k_vtx_write(VtxArgs a) {
+  const int e = blockIdx.x;
+  const int64_t b = a.ev_count[e];
+  const int n = a.ev_count[e + 1] - a.ev_count[e];
+  const int nr = a.event_first[e + 1] - a.event_first[e];
+  const int base = a.event_first[e];
+  const int32_t* sv = a.sval + 2 * b;
+  uint32_t over = 0;
+  for (int k = threadIdx.x; k < nr; k += blockDim.x) {
+    const int64_t slot = b + a.rslot[b + sv[k]];
+    const int at = base + k;
+    if (at >= a.cap) {
+      ++over;
+      continue;
+    }
+    a.oz[at] = a.rz[slot];
+    a.ovar[at] = a.rvar[slot];
+    a.ochi2[at] = a.rchi2[slot];
+    a.osum[at] = a.rsum[slot];
+    a.ondf[at] = a.rndf[slot];
+    a.on[at] = a.rn[slot];
+  }
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int l = a.vlocal[b + k];
+    if (l >= 0) a.track_vertex[a.sidx[b + k]] = base + l;
+  }
+  if (over) status_flag(a.status, PT_FLAG_VERTICES_OVERFLOW);
+}
+
+// event_first from the scanned vertex counts, and the total.
+__global__ void k_vtx_event_first(VtxArgs a) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e <= a.n_events; e += gridDim.x * blockDim.x) {
+    a.event_first[e] = a.ev_nvtx[e];
+    if (e == a.n_events) *a.n_vertices = a.ev_nvtx[e];
+  }
+}
+
+}  // namespace
+
+size_t ws_vertices(int n_events, int n_max) {
+  Carver c(nullptr);
+  const size_t n = static_cast<size_t>(n_max) + 1, E = static_cast<size_t>(n_events) + 1;
+  c.take<uint8_t>(n);        // use
+  c.take<int32_t>(n);        // ev_of
+  c.take<int32_t>(E);        // ev_count
+  c.take<int32_t>(E);        // ev_cursor
+  c.take<int32_t>(n);        // list
+  c.take<uint64_t>(2 * n);   // skey
+  c.take<int32_t>(2 * n);    // sval
+  c.take<double>(n);         // sz
+  c.take<double>(n);         // sv
+  for (int q = 0; q < 6; ++q) c.take<int32_t>(n);  // sidx rho parent root tsize tlo
+  c.take<int32_t>(n);        // thi
+  c.take<uint8_t>(n);        // side
+  for (int q = 0; q < 4; ++q) c.take<double>(n);   // rz rvar rchi2 rsum
+  for (int q = 0; q < 7; ++q) c.take<int32_t>(n);  // rndf rn rfirst rroot rpart rslot vlocal
+  c.take<int32_t>(E);        // ev_nvtx
+  c.take<int32_t>(scan_tmp_elems(static_cast<int64_t>(E)));
+  return c.off + 256;
+}
+
+pt_err launch_vertices(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, int precision,
+                       const pt_tracks& tracks, const int32_t* selected, const int32_t* n_selected,
+                       pt_vertices& out, uint32_t* status, pt_workspace ws, hipStream_t s) {
+  const int n_max = std::min(T.cap, tracks.cap);
+  const size_t n = static_cast<size_t>(n_max) + 1, E = static_cast<size_t>(h.n_events) + 1;
+  Carver c(ws.ptr);
+  VtxArgs a{};
+  a.hits = T.hits;
+  a.n = T.n;
+  a.kept = T.kept;
+  a.count = T.count;
+  a.n_max = n_max;
+  a.params = tracks.params;
+  a.cov = tracks.cov;
+  a.dbl = precision == PT_FIT_F64 ? 1 : 0;
+  a.selected = selected;
+  a.n_selected = n_selected;
+  a.event_offsets = h.event_offsets;
+  a.n_events = h.n_events;
+  a.n_hits = h.n_hits;
+  a.min_hits = k.vtx_min_hits;
+  a.kmeans_iter = k.vtx_kmeans_iter;
+  a.pt_min = k.vtx_pt_min;
+  a.err_max = k.vtx_err_max;
+  a.dz_cut = k.vtx_dz_cut;
+  a.chi2_max = k.vtx_chi2_max;
+  a.split = k.vtx_split_chi2_ndf;
+  a.pt_cap = k.vtx_pt_cap;
+  a.K = k.K;
+  a.use = c.take<uint8_t>(n);
+  a.ev_of = c.take<int32_t>(n);
+  a.ev_count = c.take<int32_t>(E);
+  a.ev_cursor = c.take<int32_t>(E);
+  a.list = c.take<int32_t>(n);
+  a.skey = c.take<uint64_t>(2 * n);
+  a.sval = c.take<int32_t>(2 * n);
+  a.sz = c.take<double>(n);
+  a.sv = c.take<double>(n);
+  a.sidx = c.take<int32_t>(n);
+  a.rho = c.take<int32_t>(n);
+  a.parent = c.take<int32_t>(n);
+  a.root = c.take<int32_t>(n);
+  a.tsize = c.take<int32_t>(n);
+  a.tlo = c.take<int32_t>(n);
+  a.thi = c.take<int32_t>(n);
+  a.side = c.take<uint8_t>(n);
+  a.rz = c.take<double>(n);
+  a.rvar = c.take<double>(n);
+  a.rchi2 = c.take<double>(n);
+  a.rsum = c.take<double>(n);
+  a.rndf = c.take<int32_t>(n);
+  a.rn = c.take<int32_t>(n);
+  a.rfirst = c.take<int32_t>(n);
+  a.rroot = c.take<int32_t>(n);
+  a.rpart = c.take<int32_t>(n);
+  a.rslot = c.take<int32_t>(n);
+  a.vlocal = c.take<int32_t>(n);
+  a.ev_nvtx = c.take<int32_t>(E);
+  int32_t* tmp = c.take<int32_t>(scan_tmp_elems(static_cast<int64_t>(E)));
+  a.oz = out.z;
+  a.ovar = out.var;
+  a.ochi2 = out.chi2;
+  a.osum = out.sum_pt2;
+  a.ondf = out.ndf;
+  a.on = out.n_tracks;
+  a.event_first = out.event_first;
+  a.n_vertices = out.count;
+  a.track_vertex = out.track_vertex;
+  a.cap = out.cap;
+  a.status = status;
+  const int g = grid_for(std::max<int64_t>(n_max, h.n_events + 1), 256, 8192);
+  k_vtx_clear<<<g, 256, 0, s>>>(a);
+  if (selected) k_vtx_mark<<<g, 256, 0, s>>>(a);
+  k_vtx_events<<<g, 256, 0, s>>>(a);
+  PT_LAUNCH_CHECK();
+  if (exclusive_scan(a.ev_count, h.n_events, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  k_vtx_scatter<<<g, 256, 0, s>>>(a);
+  PT_LAUNCH_CHECK();
+  if (h.n_events > 0) {
+    k_vtx_event_cluster<<<h.n_events, kBlock, 0, s>>>(a);
+    PT_LAUNCH_CHECK();
+  }
+  if (exclusive_scan(a.ev_nvtx, h.n_events, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  k_vtx_event_first<<<grid_for(h.n_events + 1, 256), 256, 0, s>>>(a);
+  PT_LAUNCH_CHECK();
+  if (h.n_events > 0) {
+    k_vtx_write<<<h.n_events, kBlock, 0, s>>>(a);
+    PT_LAUNCH_CHECK();
+  }
+  return PT_OK;
+}
+
+}  // namespace pt

@@ -37,13 +37,15 @@ def test_abi_version():
 _STRUCTS = {
     "pt_config": ["bfield", "n_pairs", "pair_inner", "pair_dphi", "pt_min", "cut_mask", "ca_rmax_other",
                   "root_always_mask", "min_hits", "layer_barrel", "x_over_x0", "p_cap", "n_modules", "n_phi_bins",
-                  "block_links", "f64_solve_threshold"],
+                  "block_links", "f64_solve_threshold", "vtx_min_hits", "vtx_kmeans_iter", "vtx_pt_min",
+                  "vtx_pt_cap"],
     "pt_hits": ["n_hits", "n_events", "event_offsets", "dtype", "x", "layer", "module"],
     "pt_workspace": ["ptr", "bytes"],
     "pt_cells": ["cap", "inner", "pair", "count", "inner_first", "inner_count", "seg"],
     "pt_links": ["cap", "in_cell", "count", "out_start", "out_count", "has_inner"],
     "pt_ntuplets": ["cap", "hits", "n", "count_raw", "kept", "count"],
-    "pt_tracks": ["cap", "params", "chi2", "status"],
+    "pt_tracks": ["cap", "params", "chi2", "status", "cov"],
+    "pt_vertices": ["cap", "z", "var", "chi2", "ndf", "n_tracks", "sum_pt2", "event_first", "count", "track_vertex"],
 }
 
 

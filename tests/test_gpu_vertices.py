@@ -1,0 +1,113 @@
+"""GPU parity of the pixel vertices (paper section 3.6) against the oracle.
+
+The oracle is given the GPU's own fitted z0, variance and curvature (the
+decisions are taken on the same values on both sides, in double without
+contraction, with sums in the same order), so the vertices, their members
+and their order must be identical, and the vertex values equal to 1e-12.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from synth import config as C
+from synth import events as E
+
+pytestmark = pytest.mark.gpu
+
+CFG = C.default_config()
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run(h, use_selection=True, cfg_d=CFG):
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from tests.gpu_helpers import caps_for
+    caps = caps_for(h.n_hits, h.n_events)
+    pipe = api.Pipeline(cfg_d, **caps)
+    pipe.tracks = api.Tracks.empty(caps["tuplets_cap"], pipe.precision, with_cov=True)
+    hits = api.Hits.from_host(h)
+    pipe.reconstruct(hits)
+    sel, nsel = api.resolve_ambiguities(hits, pipe.cfg, pipe.cells, pipe.tuplets, pipe.precision, pipe.tracks,
+                                        pipe.status, pipe.ws)
+    vtx = api.Vertices.empty(caps["tuplets_cap"], h.n_events, caps["tuplets_cap"])
+    if use_selection:
+        api.find_vertices(hits, pipe.cfg, pipe.tuplets, pipe.precision, pipe.tracks, sel, nsel, vtx, pipe.status,
+                          pipe.ws)
+    else:
+        api.find_vertices(hits, pipe.cfg, pipe.tuplets, pipe.precision, pipe.tracks, None, None, vtx, pipe.status,
+                          pipe.ws)
+    torch.cuda.synchronize()
+    assert pipe.flags() & A.PT_FLAG_VERTICES_OVERFLOW == 0
+    nk = int(pipe.tuplets.count.item())
+    rows = pipe.tuplets.kept[:nk].long()
+    trk = dict(hits=pipe.tuplets.hits[rows].cpu().numpy(), n=pipe.tuplets.n[rows].cpu().numpy(),
+               params=pipe.tracks.params[:nk].cpu().numpy().astype(np.float64),
+               cov=pipe.tracks.cov[:nk].cpu().numpy().astype(np.float64))
+    use = np.zeros(nk, bool)
+    if use_selection:
+        use[sel[: int(nsel.item())].cpu().numpy()] = True
+    else:
+        use[:] = True
+    nv = int(vtx.count.item())
+    got = {k: getattr(vtx, k)[:nv].cpu().numpy() for k in ("z", "var", "chi2", "ndf", "n_tracks", "sum_pt2")}
+    got["event_first"] = vtx.event_first.cpu().numpy()
+    got["track_vertex"] = vtx.track_vertex[:nk].cpu().numpy()
+    return trk, use, got
+
+
+def _compare(h, trk, use, got, cfg_d=CFG):
+    ev = np.searchsorted(h.event_offsets, trk["hits"][:, 0], side="right") - 1
+    n_total = 0
+    for e in range(h.n_events):
+        t = np.nonzero(ev == e)[0]
+        ref = O.vertices(cfg_d, trk["params"][t, 4], trk["cov"][t, 14], trk["params"][t, 0], trk["n"][t], use[t])
+        a, b = got["event_first"][e], got["event_first"][e + 1]
+        assert b - a == len(ref["z"]), (e, b - a, len(ref["z"]))
+        for k in ("ndf", "n_tracks"):
+            assert np.array_equal(got[k][a:b], ref[k]), (e, k)
+        for k in ("z", "var", "chi2", "sum_pt2"):
+            assert np.allclose(got[k][a:b], ref[k], rtol=1e-12, atol=0), (e, k)
+        tv = got["track_vertex"][t]
+        want = np.where(ref["track_vertex"] >= 0, ref["track_vertex"] + a, -1)
+        assert np.array_equal(tv, want), e
+        n_total += b - a
+    return n_total
+
+
+def test_vertices_of_a_pileup_50_event():
+    _need_gpu()
+    h = E.config2()
+    trk, use, got = _run(h)
+    nv = _compare(h, trk, use, got)
+    assert nv > 20
+    assert np.all(np.diff(got["sum_pt2"]) <= 0)
+
+
+def test_vertices_of_a_batch_with_every_track():
+    """Eight pileup-200 events and two empty ones, every fitted track used:
+    several thousand tracks per event, sorted in global memory."""
+    _need_gpu()
+    b = E.config5(n_events=8)
+    a = int(b.event_offsets[4])
+    off = np.array(list(b.event_offsets[:5]) + [a] + list(b.event_offsets[5:]) + [b.n_hits], np.int32)
+    h = E.Hits(b.x, b.y, b.z, b.layer, b.module, b.track, off)
+    trk, use, got = _run(h, use_selection=False)
+    counts = np.bincount(np.searchsorted(h.event_offsets, trk["hits"][:, 0], side="right") - 1,
+                         minlength=h.n_events)
+    assert counts.max() > 4096
+    assert got["event_first"][5] == got["event_first"][4] and got["event_first"][10] == got["event_first"][9]
+    nv = _compare(h, trk, use, got)
+    assert nv > 100
+
+
+def test_vertices_of_a_pileup_200_batch_after_ambiguity_resolution():
+    _need_gpu()
+    h = E.config5(n_events=4)
+    trk, use, got = _run(h)
+    assert _compare(h, trk, use, got) > 100
