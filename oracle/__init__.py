@@ -113,6 +113,8 @@ def lib():
         P = ct.c_void_p
         L.oracle_doublets.restype = ct.c_int64
         L.oracle_doublets.argtypes = [P, ct.c_int32, P, P, P, P, ct.c_int64, P, P, P]
+        L.oracle_fishbone.restype = ct.c_int64
+        L.oracle_fishbone.argtypes = [ct.c_double, ct.c_int32, P, P, P, ct.c_int32, P, P, P]
         L.oracle_doublets_binned.restype = ct.c_int64
         L.oracle_doublets_binned.argtypes = [P, ct.c_int32, P, P, P, P, ct.c_int32, ct.c_int64, P, P, P]
         L.oracle_chain_batch.restype = ct.c_int64
@@ -222,6 +224,18 @@ def fit_grad_batch(cfg, tuplets, nhits, x, y, z, layer, module, offsets, g_param
     lib().oracle_fit_grad_batch(ct.byref(_config(cfg)), n, _p(tup), _p(nh), _p(x), _p(y), _p(z), _p(layer), _p(mod),
                                 _p(o), _p(gp), _p(gc), n_threads, _p(params), _p(chi2), _p(gh))
     return params, chi2, gh
+
+
+def fishbone(cfg, x, y, z, cell_inner, cell_outer):
+    """Fishbone of section 3.3 (see oracle.cpp): bool keep [n_cells] of the
+    doublets that stay; theta from cfg["fishbone_theta"]."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    ci = np.ascontiguousarray(cell_inner, dtype=np.int32)
+    co = np.ascontiguousarray(cell_outer, dtype=np.int32)
+    keep = np.empty(ci.shape[0], np.uint8)
+    th = float(cfg["fishbone_theta"])
+    lib().oracle_fishbone(th * th, x.shape[0], _p(x), _p(y), _p(z), ci.shape[0], _p(ci), _p(co), _p(keep))
+    return keep.astype(bool)
 
 
 def links(cfg, x, y, z, layer, cell_inner, cell_outer):
@@ -429,8 +443,12 @@ def fit_grad(cfg, tuplets, nhits, x, y, z, layer, module, offsets, g_params, g_c
 
 
 def reconstruct_event(cfg, x, y, z, layer, dedup=True):
-    """Doublets -> links -> n-tuplets of one event (dict of every product)."""
+    """Doublets (then the Fishbone when cfg["fishbone_theta"] > 0) -> links ->
+    n-tuplets of one event (dict of every product)."""
     ci, co, cp = doublets(cfg, x, y, z, layer)
+    if cfg.get("fishbone_theta", 0.0) > 0.0:
+        keep = fishbone(cfg, x, y, z, ci, co)
+        ci, co, cp = ci[keep], co[keep], cp[keep]
     li, lo = links(cfg, x, y, z, layer, ci, co)
     nt = ntuplets(cfg, layer, ci, co, li, lo, dedup=dedup)
     return {"cell_inner": ci, "cell_outer": co, "cell_pair": cp, "link_in": li, "link_out": lo, **nt}

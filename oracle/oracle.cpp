@@ -283,6 +283,43 @@ int64_t oracle_doublets_binned(const oracle_config* cfg, int32_t n, const double
   return count;
 }
 
+// Fishbone (section 3.3): among the doublets that share their outer hit, a
+// doublet is dropped when another one is aligned with it and shorter.  For
+// c = (a, h) and c' = (b, h), with u = P_h - P_a and v = P_h - P_b in double:
+//   w = u x v = (uy vz - uz vy, uz vx - ux vz, ux vy - uy vx),
+//   W2 = (wx wx + wy wy) + wz wz, U2 = (ux ux + uy uy) + uz uz, V2 likewise;
+//   aligned iff W2 <= theta2 (U2 V2) (the sine of the angle between the two
+//   doublets is at most theta), and c is dropped iff such a c' has V2 < U2.
+// keep [n_cells] receives 1 for the doublets that stay.  Returns how many.
+int64_t oracle_fishbone(double theta2, int32_t n, const double* x, const double* y, const double* z,
+                        int32_t n_cells, const int32_t* cell_inner, const int32_t* cell_outer, uint8_t* keep) {
+  std::vector<std::vector<int32_t>> ending_at(n);
+  for (int32_t c = 0; c < n_cells; ++c) ending_at[cell_outer[c]].push_back(c);
+  int64_t kept = 0;
+  for (int32_t c = 0; c < n_cells; ++c) {
+    const int32_t a = cell_inner[c], h = cell_outer[c];
+    const double ux = x[h] - x[a], uy = y[h] - y[a], uz = z[h] - z[a];
+    const double U2 = (ux * ux + uy * uy) + uz * uz;
+    bool stay = true;
+    for (int32_t d : ending_at[h]) {
+      if (d == c) continue;
+      const int32_t b = cell_inner[d];
+      const double vx = x[h] - x[b], vy = y[h] - y[b], vz = z[h] - z[b];
+      const double V2 = (vx * vx + vy * vy) + vz * vz;
+      if (!(V2 < U2)) continue;
+      const double wx = uy * vz - uz * vy, wy = uz * vx - ux * vz, wz = ux * vy - uy * vx;
+      const double W2 = (wx * wx + wy * wy) + wz * wz;
+      if (W2 <= theta2 * (U2 * V2)) {
+        stay = false;
+        break;
+      }
+    }
+    keep[c] = stay ? 1 : 0;
+    kept += stay;
+  }
+  return kept;
+}
+
 // Cell links of one event: for every cell c = (h1, h2) and every cell
 // c' = (h0, h1) ending on its inner hit, the link (c' -> c) when the triplet
 // passes the cuts.  Cells are given as (inner, outer) hit index arrays.

@@ -152,6 +152,9 @@ def default_config(**overrides) -> dict:
       vtx_split_chi2_ndf vertices: chi2/ndf above which a vertex is split in two
       vtx_pt_cap        vertices: p_T cap in the sum of p_T^2 that orders them (GeV)
       vtx_kmeans_iter   vertices: most rounds of the two-means split
+      fishbone_theta    Fishbone (section 3.3): largest sine of the angle between
+                        two doublets sharing their outer hit for which the longer
+                        one is dropped; 0 turns the Fishbone off
     """
     bfield = 3.8
     pt_min = 0.45
@@ -191,6 +194,7 @@ def default_config(**overrides) -> dict:
         "vtx_split_chi2_ndf": 9.0,
         "vtx_pt_cap": 75.0,
         "vtx_kmeans_iter": 10,
+        "fishbone_theta": 0.0,
     }
     for k, v in overrides.items():
         if k not in cfg:

@@ -229,9 +229,17 @@ def draw_tracks(rng, n, *, pt="power", eta_max=2.5, z_sigma=3.5, xy_sigma=1.5e-3
             "pt": pts, "eta": eta, "q": q, "vx": vx, "vy": vy, "vz": vz}
 
 
-def track_hits(rng, trk, *, disks=True, eff=1.0, smear=True):
+OVERLAP_DR = 0.35   # barrel: radial offset of an overlapping ladder (cm)
+OVERLAP_DZ = 0.5    # disks: offset in |z| of an overlapping blade (cm)
+
+
+def track_hits(rng, trk, *, disks=True, eff=1.0, smear=True, overlap=0.0):
     """Layer crossings of each track, ordered by arc length.
 
+    overlap: probability that a crossing also leaves a second hit on the same
+    layer, as where modules overlap (section 3.1 and the Fishbone of section
+    3.3): a barrel ladder OVERLAP_DR further out, a disk blade OVERLAP_DZ
+    further from z = 0.
     Returns (track index, layer, x, y, z, s) arrays over all kept crossings.
     """
     S = _crossings(trk["kappa"], trk["phi0"], trk["d0"], trk["cot"], trk["z0"], trk["s_v"], disks)
@@ -239,13 +247,34 @@ def track_hits(rng, trk, *, disks=True, eff=1.0, smear=True):
         S = np.where(rng.uniform(size=S.shape) < eff, S, np.nan)
     ti, li = np.nonzero(np.isfinite(S))
     s = S[ti, li]
+    r_nom = np.array(C.BARREL_R + (0,) * 6)[li]
+    if overlap > 0.0:
+        pick = rng.uniform(size=ti.shape[0]) < overlap
+        t2, l2 = ti[pick], li[pick]
+        bar2 = l2 < 4
+        s2 = np.full(t2.shape[0], np.nan)
+        rb = np.array(C.BARREL_R + (0,) * 6)[l2] + OVERLAP_DR
+        sb = _barrel_s(trk["kappa"][t2], trk["d0"][t2], np.where(bar2, rb, 1.0))
+        zb = trk["z0"][t2] + sb * trk["cot"][t2]
+        s2 = np.where(bar2 & (np.abs(zb) <= C.BARREL_HALF_Z), sb, s2)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            zd = np.array([0.0] * 4 + [C.disk_z(l) for l in range(4, 10)])[l2]
+            sd = (zd + OVERLAP_DZ * np.sign(zd) - trk["z0"][t2]) / trk["cot"][t2]
+            xd, yd = helix_xy(trk["kappa"][t2], trk["phi0"][t2], trk["d0"][t2], np.where(np.isfinite(sd), sd, 0.0))
+            rd = np.hypot(xd, yd)
+            okd = ~bar2 & np.isfinite(sd) & (sd > s[pick]) & (rd >= C.DISK_RMIN) & (rd <= C.DISK_RMAX)
+        s2 = np.where(okd, sd, s2)
+        keep2 = np.isfinite(s2)
+        ti = np.concatenate([ti, t2[keep2]])
+        li = np.concatenate([li, l2[keep2]])
+        s = np.concatenate([s, s2[keep2]])
+        r_nom = np.concatenate([r_nom, np.where(bar2, rb, 0.0)[keep2]])
     order = np.lexsort((s, ti))
-    ti, li, s = ti[order], li[order], s[order]
+    ti, li, s, r_nom = ti[order], li[order], s[order], r_nom[order]
     x, y = helix_xy(trk["kappa"][ti], trk["phi0"][ti], trk["d0"][ti], s)
     z = trk["z0"][ti] + s * trk["cot"][ti]
     bar = li < 4
     # put barrel hits exactly on their cylinder before smearing
-    r_nom = np.array(C.BARREL_R + (0,) * 6)[li]
     rr = np.hypot(x, y)
     x = np.where(bar, x * r_nom / np.where(bar, rr, 1.0), x)
     y = np.where(bar, y * r_nom / np.where(bar, rr, 1.0), y)
@@ -260,7 +289,7 @@ def _truth_dict(trk):
 
 def make_event(rng, *, n_vertices=50, tracks_per_vertex=30.0, pt="power", eta_max=2.5,
                disks=True, eff=0.99, noise_frac=0.10, dtype=np.float32, fixed_tracks=None,
-               xy_sigma=1.5e-3, shuffle=True):
+               xy_sigma=1.5e-3, shuffle=True, overlap=0.0):
     """One event: n_vertices vertices with Poisson(tracks_per_vertex) tracks each."""
     if fixed_tracks is not None:
         counts = np.array([fixed_tracks] * n_vertices)
@@ -270,7 +299,7 @@ def make_event(rng, *, n_vertices=50, tracks_per_vertex=30.0, pt="power", eta_ma
     vz = np.repeat(vz_each, counts)
     n = int(counts.sum())
     trk = draw_tracks(rng, n, pt=pt, eta_max=eta_max, vertex_z=vz, xy_sigma=xy_sigma)
-    ti, li, x, y, z, _ = track_hits(rng, trk, disks=disks, eff=eff)
+    ti, li, x, y, z, _ = track_hits(rng, trk, disks=disks, eff=eff, overlap=overlap)
     n_noise = int(round(noise_frac * ti.shape[0]))
     if n_noise:
         nl, nx, ny, nz = _noise(rng, n_noise, disks)
@@ -332,6 +361,21 @@ def config3(seed=3, n_events=256):
     """Uneven batch: pileup uniform in [20, 200] per event."""
     return make_batch(seed, n_events, pileup=(20, 200), tracks_per_vertex=30.0, eff=0.99,
                       noise_frac=0.10)
+
+
+def overlap_event(seed=6, n_vertices=50, overlap=0.25):
+    """A PU50-like event in the overlap-geometry variant: a quarter of the
+    layer crossings leave a second hit on the same layer (overlapping
+    modules), the situation the Fishbone of section 3.3 resolves."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return make_event(rng, n_vertices=n_vertices, tracks_per_vertex=30.0, eff=0.99, noise_frac=0.10,
+                      overlap=overlap)
+
+
+def overlap_batch(seed=6, n_events=64, pileup=50, overlap=0.25):
+    """Events of the overlap-geometry variant, batched."""
+    return make_batch(seed, n_events, pileup=pileup, tracks_per_vertex=30.0, eff=0.99, noise_frac=0.10,
+                      overlap=overlap)
 
 
 def config5(seed=5, n_events=64):
