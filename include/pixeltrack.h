@@ -21,7 +21,11 @@
  *    re-entrant on distinct streams with distinct workspaces.  The plain
  *    calls do not use hipMemsetAsync, so they may be captured in a graph.
  *  - Errors: argument errors return PT_ERR_ARG synchronously and enqueue
- *    nothing.  A failed kernel launch returns PT_ERR_DEVICE.  Conditions that
+ *    nothing.  A failed kernel launch or HIP runtime call returns
+ *    PT_ERR_DEVICE; pt_last_device_error names the HIP error.  Every call
+ *    clears the calling thread's HIP error state (hipGetLastError) before it
+ *    launches, so an error left there by other code on the thread is neither
+ *    reported by the call nor kept for the caller.  Conditions that
  *    are only known on the device (capacity overflow, non-finite hits, layer
  *    ids out of range, truncated searches, fit failures) set bits and
  *    counters in the caller's pt_status block; outputs are then truncated
@@ -154,6 +158,8 @@ typedef struct {
   double vtx_chi2_max;                /* largest (dz0)^2 / (var_i + var_j) of compatible tracks */
   double vtx_split_chi2_ndf;          /* chi2/ndf above which a vertex is split in two */
   double vtx_pt_cap;                  /* p_T cap in the sum of p_T^2 that orders the vertices (GeV) */
+  /* Fishbone (section 3.3), see pt_build_doublets; 0 = off */
+  double fishbone_theta;              /* largest sine of the angle between two aligned doublets */
 } pt_config;
 
 /* Hits of n_events events.  Event e owns hits [event_offsets[e], event_offsets[e+1]). */
@@ -246,6 +252,10 @@ typedef struct {
 #define PT_ABI_VERSION 2
 int32_t pt_abi_version(void);
 const char* pt_err_string(pt_err e);
+/* The HIP error behind the calling thread's last PT_ERR_DEVICE, as
+ * "hipErrorName: description" (a thread-local buffer, valid until the thread's
+ * next call of this function); "" when no call on this thread has failed so. */
+const char* pt_last_device_error(void);
 
 /* Bytes of workspace the calls below need for these sizes.  0 on invalid arguments. */
 size_t pt_workspace_size(const pt_config* cfg, int32_t n_hits, int32_t n_events,
@@ -263,6 +273,14 @@ size_t pt_workspace_size(const pt_config* cfg, int32_t n_hits, int32_t n_events,
  * without contraction.  Candidate inner hits come from azimuth bins around
  * the outer hit (the binned window of Table 1), widened by one bin so that the
  * result equals the all-pairs definition.
+ * With fishbone_theta > 0 the Fishbone of section 3.3 follows: of two
+ * doublets c = (a, h) and c' = (b, h) sharing their outer hit, with
+ * u = P_h - P_a, v = P_h - P_b in double, w = u x v = (uy vz - uz vy,
+ * uz vx - ux vz, ux vy - uy vx), W2 = (wx wx + wy wy) + wz wz and
+ * U2, V2 the squared lengths in the same order, c is dropped when
+ * W2 <= fishbone_theta^2 (U2 V2) and V2 < U2 (a shorter aligned doublet
+ * exists).  The remaining cells keep their order, grouped by inner hit; when
+ * the cells overflowed their capacity the Fishbone is not applied.
  * Requires a workspace of pt_workspace_size(cfg, hits->n_hits, hits->n_events, ...). */
 pt_err pt_build_doublets(const pt_hits* hits, const pt_config* cfg, pt_cells* cells,
                          uint32_t* status, pt_workspace ws, pt_stream stream);
@@ -453,11 +471,13 @@ void pt_plan_destroy(pt_plan plan);
 /* Kernel timing (instrumentation).  While enabled, the individual calls (not
  * graph launches) record a pair of HIP events around their main kernels on
  * their stream, one kernel each unless noted: "doublets_count",
- * "doublets_write" (which also writes the cells' R-Z segments), "cell_index"
- * (the index of cells by outer hit), "link_segments" (placing the index segments), "links" (the
- * triplet sweep),
- * "link_emit" (placing the links), "root_count", "root_write", "dfs_count",
- * "dfs_write", "dedup" (several kernels), "fit_fwd" and "fit_bwd" (every kernel of the fit and of its adjoint).  pt_timing_read waits for the recorded events and
+ * "doublets_write" (which also writes the cells' R-Z segments), "fishbone"
+ * (every kernel of the Fishbone, when it is on), "cell_index" (the index of
+ * cells by outer hit), "link_segments" (placing the index segments), "links"
+ * (the triplet sweep), "link_emit" (placing the links), "root_count",
+ * "root_write", "dfs_count", "dfs_write", "dedup" (several kernels),
+ * "fit_fwd" and "fit_bwd" (every kernel of the fit and of its adjoint).
+ * pt_timing_read waits for the recorded events and
  * returns the summed milliseconds and the number of launches since the last
  * reset (PT_ERR_ARG when the name has no record). */
 void pt_timing_enable(int32_t on);

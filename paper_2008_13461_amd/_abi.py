@@ -81,6 +81,7 @@ class pt_config(ct.Structure):
         ("vtx_chi2_max", ct.c_double),
         ("vtx_split_chi2_ndf", ct.c_double),
         ("vtx_pt_cap", ct.c_double),
+        ("fishbone_theta", ct.c_double),
     ]
 
 
@@ -168,6 +169,7 @@ class pt_vertices(ct.Structure):
 SIGNATURES = {
     "pt_abi_version": (ct.c_int32, []),
     "pt_err_string": (ct.c_char_p, [ct.c_int]),
+    "pt_last_device_error": (ct.c_char_p, []),
     "pt_workspace_size": (ct.c_size_t, [ct.POINTER(pt_config), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32,
                                         ct.c_int32]),
     "pt_build_doublets": (ct.c_int, [ct.POINTER(pt_hits), ct.POINTER(pt_config), ct.POINTER(pt_cells), P,
@@ -210,6 +212,12 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        # torch ships its own HIP runtime: load it before the library so that
+        # the process holds one runtime (the library binds to the one loaded)
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise LibraryMissing(f"{path} is not built: run `python -m paper_2008_13461_amd.build` "
                              "(or __graft_entry__.build())")
@@ -227,6 +235,8 @@ def load(path: str = LIB_PATH):
 def check(err: int, what: str) -> None:
     if err != PT_OK:
         msg = load().pt_err_string(err).decode()
+        if err == PT_ERR_DEVICE:
+            msg += f" [{load().pt_last_device_error().decode()}]"
         raise RuntimeError(f"{what} failed: {msg} (code {err})")
 
 
@@ -264,6 +274,6 @@ def make_config(cfg: dict, *, n_phi_bins: int = 0, block_doublets: int = 0, bloc
     c.block_links = block_links
     c.f64_solve_threshold = f64_solve_threshold
     for k in ("vtx_min_hits", "vtx_kmeans_iter", "vtx_pt_min", "vtx_err_max", "vtx_dz_cut", "vtx_chi2_max",
-              "vtx_split_chi2_ndf", "vtx_pt_cap"):
+              "vtx_split_chi2_ndf", "vtx_pt_cap", "fishbone_theta"):
         setattr(c, k, cfg[k])
     return c

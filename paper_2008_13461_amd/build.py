@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpixeltrack.so")
-SOURCES = ["api.hip", "util.hip", "doublets.hip", "links.hip", "ntuplets.hip", "fit.hip", "ambiguity.hip",
-           "vertices.hip", "plan.hip"]
+SOURCES = ["api.hip", "util.hip", "doublets.hip", "fishbone.hip", "links.hip", "ntuplets.hip", "fit.hip",
+           "ambiguity.hip", "vertices.hip", "plan.hip"]
 ARCH = os.environ.get("PT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

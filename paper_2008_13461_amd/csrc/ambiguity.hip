@@ -181,7 +181,7 @@ pt_err launch_ambiguity(const pt_hits& h, const pt_cells& cells, const pt_ntuple
   k_amb_chi2_rule<<<g, kBlock, 0, s>>>(a);
   k_amb_tip_rule<<<g, kBlock, 0, s>>>(a);
   PT_LAUNCH_CHECK();
-  if (exclusive_scan_to(a.flag, a.pos, n_max, a.count, n_selected, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan_to(a.flag, a.pos, n_max, a.count, n_selected, tmp, s));
   k_amb_list<<<g, kBlock, 0, s>>>(a, selected);
   PT_LAUNCH_CHECK();
   return PT_OK;

@@ -3,6 +3,7 @@
 // to the kernels of each step.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "pt_internal.h"
@@ -108,6 +109,8 @@ bool derive_config(const pt_config& c, DevCfg* d) {
   d->vtx_chi2_max = c.vtx_chi2_max;
   d->vtx_split_chi2_ndf = c.vtx_split_chi2_ndf;
   d->vtx_pt_cap = c.vtx_pt_cap;
+  if (!(c.fishbone_theta >= 0.0)) return false;
+  d->fishbone_theta2 = c.fishbone_theta * c.fishbone_theta;
   return true;
 }
 #pragma clang fp contract(on)
@@ -126,7 +129,16 @@ bool ws_ok(const pt_workspace& ws, size_t need) {
   return need == 0 || (ws.ptr && ws.bytes >= need && (reinterpret_cast<uintptr_t>(ws.ptr) & 255) == 0);
 }
 
+thread_local hipError_t g_last_device_error = hipSuccess;
+thread_local char g_last_device_text[256];
+
 }  // namespace
+
+pt_err device_error(hipError_t e) {
+  g_last_device_error = e;
+  return PT_ERR_DEVICE;
+}
+
 }  // namespace pt
 
 using namespace pt;
@@ -147,6 +159,13 @@ const char* pt_err_string(pt_err e) {
   return "unknown error";
 }
 
+const char* pt_last_device_error(void) {
+  if (g_last_device_error == hipSuccess) return "";
+  std::snprintf(g_last_device_text, sizeof(g_last_device_text), "%s: %s", hipGetErrorName(g_last_device_error),
+                hipGetErrorString(g_last_device_error));
+  return g_last_device_text;
+}
+
 size_t pt_workspace_size(const pt_config* cfg, int32_t n_hits, int32_t n_events, int32_t cells_cap,
                          int32_t links_cap, int32_t tuplets_cap) {
   (void)links_cap;
@@ -154,6 +173,7 @@ size_t pt_workspace_size(const pt_config* cfg, int32_t n_hits, int32_t n_events,
   DevCfg d;
   if (!derive_config(*cfg, &d)) return 0;
   size_t s = ws_doublets(n_hits, n_events, d.n_bins);
+  if (d.fishbone_theta2 > 0.0) s = std::max(s, ws_fishbone(n_hits, cells_cap));
   s = std::max(s, ws_links(n_hits, cells_cap));
   s = std::max(s, ws_ntuplets(cells_cap, tuplets_cap));
   s = std::max(s, ws_fit(tuplets_cap, d.n_modules));
@@ -170,7 +190,10 @@ pt_err pt_build_doublets(const pt_hits* hits, const pt_config* cfg, pt_cells* ce
     return PT_ERR_ARG;
   if (cells->cap > 0 && (!cells->inner || !cells->outer || !cells->pair || !cells->seg))
     return PT_ERR_ARG;
-  if (!ws_ok(ws, ws_doublets(hits->n_hits, hits->n_events, d.n_bins))) return PT_ERR_WORKSPACE;
+  size_t need = ws_doublets(hits->n_hits, hits->n_events, d.n_bins);
+  if (d.fishbone_theta2 > 0.0) need = std::max(need, ws_fishbone(hits->n_hits, cells->cap));
+  if (!ws_ok(ws, need)) return PT_ERR_WORKSPACE;
+  clear_stale_error();
   return launch_doublets(*hits, d, *cells, status, ws, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -185,6 +208,7 @@ pt_err pt_link_cells(const pt_hits* hits, const pt_config* cfg, const pt_cells* 
   if (hits->n_hits > 0 && (!cells->inner_first || !cells->inner_count)) return PT_ERR_ARG;
   if (links->cap > 0 && (!links->in_cell || !links->out_cell)) return PT_ERR_ARG;
   if (!ws_ok(ws, ws_links(hits->n_hits, cells->cap))) return PT_ERR_WORKSPACE;
+  clear_stale_error();
   return launch_links(*hits, d, *cells, *links, status, ws, reinterpret_cast<hipStream_t>(stream),
                       cfg->block_links);
 }
@@ -201,6 +225,7 @@ pt_err pt_find_ntuplets(const pt_hits* hits, const pt_config* cfg, const pt_cell
     return PT_ERR_ARG;
   if (links->cap > 0 && !links->out_cell) return PT_ERR_ARG;
   if (!ws_ok(ws, ws_ntuplets(cells->cap, tuplets->cap))) return PT_ERR_WORKSPACE;
+  clear_stale_error();
   return launch_ntuplets(*hits, d, *cells, *links, *tuplets, status, ws, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -216,6 +241,7 @@ pt_err pt_fit_broken_line(const pt_hits* hits, const pt_config* cfg, const pt_nt
   if (n_max > 0 && (!tuplets->hits || !tuplets->n || !tracks->params || !tracks->chi2 || !tracks->status))
     return PT_ERR_ARG;
   if (!ws_ok(ws, ws_fit(n_max, d.n_modules))) return PT_ERR_WORKSPACE;
+  clear_stale_error();
   return launch_fit(*hits, d, *tuplets, module_offsets, precision, *tracks, status, ws,
                     reinterpret_cast<hipStream_t>(stream));
 }
@@ -234,6 +260,7 @@ pt_err pt_resolve_ambiguities(const pt_hits* hits, const pt_config* cfg, const p
                     !selected))
     return PT_ERR_ARG;
   if (!ws_ok(ws, ws_ambiguity(hits->n_hits, cells->cap, n_max))) return PT_ERR_WORKSPACE;
+  clear_stale_error();
   return launch_ambiguity(*hits, *cells, *tuplets, precision, *tracks, selected, n_selected, ws,
                           reinterpret_cast<hipStream_t>(stream));
 }
@@ -254,6 +281,7 @@ pt_err pt_find_vertices(const pt_hits* hits, const pt_config* cfg, const pt_ntup
     return PT_ERR_ARG;
   if (hits->n_events > 0 && !hits->event_offsets) return PT_ERR_ARG;
   if (!ws_ok(ws, ws_vertices(hits->n_events, n_max))) return PT_ERR_WORKSPACE;
+  clear_stale_error();
   return launch_vertices(*hits, d, *tuplets, precision, *tracks, selected, n_selected, *out, status, ws,
                          reinterpret_cast<hipStream_t>(stream));
 }
@@ -270,6 +298,7 @@ pt_err pt_fit_broken_line_noalloc(const pt_hits* hits, const pt_config* cfg, con
   if (n_max > 0 && (!tuplets->hits || !tuplets->n || !tracks->params || !tracks->chi2 || !tracks->status))
     return PT_ERR_ARG;
   if (n_max > PT_NOALLOC_FIT_MAX_TRACKS) return PT_ERR_TOO_LARGE;
+  clear_stale_error();
   return launch_fit_noalloc(*hits, d, *tuplets, module_offsets, precision, *tracks, status,
                             reinterpret_cast<hipStream_t>(stream));
 }
@@ -286,6 +315,7 @@ pt_err pt_fit_broken_line_bwd(const pt_hits* hits, const pt_config* cfg, const p
   const int n_max = tuplets->cap;
   if (n_max > 0 && (!tuplets->hits || !tuplets->n || !g_params)) return PT_ERR_ARG;
   if (!ws_ok(ws, ws_fit(n_max, d.n_modules))) return PT_ERR_WORKSPACE;
+  clear_stale_error();
   return launch_fit_bwd(*hits, d, *tuplets, module_offsets, precision, g_params, g_chi2, grad_hits, grad_offsets,
                         n_max, status, ws, reinterpret_cast<hipStream_t>(stream));
 }

@@ -20,6 +20,8 @@
 
 namespace pt {
 
+pt_err launch_fishbone(const pt_hits& h, const DevCfg& k, pt_cells& cells, void* ws_base, hipStream_t s);
+
 // The cut predicates of Table 1, as documented in pixeltrack.h (tdphi is
 // tan_dphi of the pair, loaded once per pair by the caller).
 __device__ __forceinline__ bool doublet_pass(const DevCfg& k, double tdphi, double Xi, double Yi, double Zi,
@@ -456,10 +458,10 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
 
   HitsIn<T> in{n, h.n_events, h.event_offsets, static_cast<const T*>(h.x), static_cast<const T*>(h.y),
                static_cast<const T*>(h.z), h.layer};
-  if (fill_i32(bins, 0, nb + 2, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(fill_i32(bins, 0, nb + 2, s));
   k_hit_keys<T><<<grid_for(n, 256), 256, 0, s>>>(in, B, k.bin_scale, key, rank, bin_start, status);
   PT_LAUNCH_CHECK();
-  if (exclusive_scan(bin_start, nb, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan(bin_start, nb, tmp, s));
   k_copy_total<<<1, 1, 0, s>>>(bin_start, static_cast<int>(nb), bins);
   PT_LAUNCH_CHECK();
   // the hits in arrival order within their bins, then each bin ordered by
@@ -479,13 +481,15 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   launch_doublets<false>(k, a, n, block, s);
   timing_end(tok, "doublets_count", s);
   PT_LAUNCH_CHECK();
-  if (exclusive_scan(cnt, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan(cnt, n, tmp, s));
   tok = timing_begin(s);
   launch_doublets<true>(k, a, n, kWriteBlock, s);
   timing_end(tok, "doublets_write", s);
   PT_LAUNCH_CHECK();
   k_finish_cells<<<1, 1, 0, s>>>(cnt + n, cells.cap, cells.count, status);
   PT_LAUNCH_CHECK();
+  // the Fishbone reuses the workspace from its start (the sorted hits are dead)
+  if (k.fishbone_theta2 > 0.0) return launch_fishbone(h, k, cells, ws.ptr, s);
   return PT_OK;
 }
 

@@ -487,8 +487,8 @@ static FitArgs make_args(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T
 }
 
 static pt_err prepare(FitArgs& a, hipStream_t s) {
-  if (fill_i32(a.bin_count, 0, kNBins, s) != hipSuccess) return PT_ERR_DEVICE;
-  if (fill_i32(a.redo_count, 0, 1, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(fill_i32(a.bin_count, 0, kNBins, s));
+  PT_HIP_CHECK(fill_i32(a.redo_count, 0, 1, s));
   k_bin<<<fit_grid(a.n_max), kBlock, 0, s>>>(a);
   PT_LAUNCH_CHECK();
   return PT_OK;
@@ -628,7 +628,7 @@ pt_err launch_fit_noalloc(const pt_hits& h, const DevCfg& k, const pt_ntuplets& 
   if (fit_scratch_bytes(n_max, k.n_modules, false) > kStaticScratchBytes) return PT_ERR_TOO_LARGE;
   hipError_t err = hipSuccess;
   void* p = static_scratch(&err);
-  if (!p) return PT_ERR_DEVICE;
+  if (!p) return device_error(err);
   const bool was = g_no_timing;
   g_no_timing = true;  // timing records create events: not here
   const pt_err e = launch_fit(h, k, T, offsets, precision, out, status, pt_workspace{p, kStaticScratchBytes}, s);

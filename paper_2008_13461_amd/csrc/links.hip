@@ -1010,8 +1010,8 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   const T* y = static_cast<const T*>(h.y);
   const T* z = static_cast<const T*>(h.z);
 
-  if (fill_i32(ovf_count, 0, 1, s) != hipSuccess) return PT_ERR_DEVICE;
-  if (fill_i32(seg_first, 0, static_cast<int64_t>(n) + 1, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(fill_i32(ovf_count, 0, 1, s));
+  PT_HIP_CHECK(fill_i32(seg_first, 0, static_cast<int64_t>(n) + 1, s));
   if (n > 0) {
     k_hit_table<T><<<grid_for(n, 256), 256, 0, s>>>(n, x, y, z, hx);
     PT_LAUNCH_CHECK();
@@ -1022,7 +1022,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   k_cell_index<<<static_cast<unsigned>(chunks), kIndexBlock, 0, s>>>(g);
   timing_end(tok, "cell_index", s);
   PT_LAUNCH_CHECK();
-  if (exclusive_scan(seg_first, n, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan(seg_first, n, tmp, s));
   tok = timing_begin(s);
   k_seg_scatter<<<static_cast<unsigned>(chunks), kScatterBlock, 0, s>>>(cells.count, cells.cap, grp, n_grp, seg_first, seg);
   timing_end(tok, "link_segments", s);
@@ -1042,8 +1042,7 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   }
   timing_end(tok, "links", s);
   // first link of each cell, and the number of links
-  if (exclusive_scan_to(L.out_count, L.out_start, cells.cap, cells.count, L.count, tmp, s) != hipSuccess)
-    return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan_to(L.out_count, L.out_start, cells.cap, cells.count, L.count, tmp, s));
   tok = timing_begin(s);
   EmitArgs e{cells.count, cells.cap, L.out_start, L.out_count, spill, L.cap, L.in_cell, L.out_cell};
   if (reinterpret_cast<uintptr_t>(L.out_count) % 16 == 0 && reinterpret_cast<uintptr_t>(L.out_start) % 16 == 0)

@@ -489,7 +489,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
     k_root_count<false><<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(k, a, chunk_roots, root_bits);
   timing_end(tok, "root_count", s);
   PT_LAUNCH_CHECK();
-  if (exclusive_scan(chunk_roots, chunks, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan(chunk_roots, chunks, tmp, s));
   tok = timing_begin(s);
   k_mask_write<<<static_cast<unsigned>(chunks), kWave, 0, s>>>(cells.count, cells.cap, root_bits, chunk_roots, roots);
   timing_end(tok, "root_write", s);
@@ -498,11 +498,11 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   k_dfs<true><<<grid_for(cells.cap, 256, 65536), 256, 0, s>>>(k, a, paths, nullptr, nullptr);
   timing_end(tok, "dfs_count", s);
   PT_LAUNCH_CHECK();
-  if (exclusive_scan_dev(paths, cells.cap, n_roots, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan_dev(paths, cells.cap, n_roots, tmp, s));
   tok = timing_begin(s);
   k_prod_count<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(a, paths, chunk_prod, root_bits);
   PT_LAUNCH_CHECK();
-  if (exclusive_scan(chunk_prod, chunks, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan(chunk_prod, chunks, tmp, s));
   k_mask_write<<<static_cast<unsigned>(chunks), kWave, 0, s>>>(n_roots, cells.cap, root_bits, chunk_prod, prod);
   PT_LAUNCH_CHECK();
   k_dfs<false><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths, prod, chunk_prod + chunks);
@@ -521,7 +521,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   const int64_t row_chunks = std::max<int64_t>(1, (static_cast<int64_t>(T.cap) + kRootChunk - 1) / kRootChunk);
   k_keep_count<<<static_cast<unsigned>(row_chunks), kBlock, 0, s>>>(a, chunk_roots);
   PT_LAUNCH_CHECK();
-  if (exclusive_scan(chunk_roots, row_chunks, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan(chunk_roots, row_chunks, tmp, s));
   k_keep_write<<<static_cast<unsigned>(row_chunks), kBlock, 0, s>>>(a, chunk_roots);
   PT_LAUNCH_CHECK();
   k_copy_total<<<1, 1, 0, s>>>(chunk_roots + row_chunks, T.count);

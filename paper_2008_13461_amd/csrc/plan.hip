@@ -134,9 +134,9 @@ int32_t pt_timing_read(const char* kernel, double* total_ms, int64_t* launches) 
   }
   double sum = 0.0;
   for (auto& r : it->second) {
-    if (hipEventSynchronize(r.b) != hipSuccess) return PT_ERR_DEVICE;
+    PT_HIP_CHECK(hipEventSynchronize(r.b));
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return PT_ERR_DEVICE;
+    PT_HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
     sum += ms;
   }
   if (total_ms) *total_ms = sum;
@@ -165,11 +165,16 @@ pt_err pt_plan_create(const pt_config* cfg, int32_t n_hits_max, int32_t n_events
   p->precision = precision;
   p->stages = stages;
   p->ws_bytes = pt_workspace_size(cfg, n_hits_max, n_events_max, cells_cap, links_cap, tuplets_cap);
-  if (p->ws_bytes == 0 || hipMalloc(&p->ws, p->ws_bytes) != hipSuccess ||
-      hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+  if (p->ws_bytes == 0) {
+    delete p;
+    return PT_ERR_ARG;
+  }
+  hipError_t he = hipMalloc(&p->ws, p->ws_bytes);
+  if (he == hipSuccess) he = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  if (he != hipSuccess) {
     if (p->ws) (void)hipFree(p->ws);
     delete p;
-    return PT_ERR_DEVICE;
+    return device_error(he);
   }
   *out = reinterpret_cast<pt_plan>(p);
   return PT_OK;
@@ -240,12 +245,13 @@ pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links*
   add(ptrs, sizeof(ptrs));
   if (vertices) add(vertices, sizeof(*vertices));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  clear_stale_error();
   if (!p->exec || key != p->key) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     p->exec = nullptr;
     p->graph = nullptr;
-    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PT_ERR_DEVICE;
+    PT_HIP_CHECK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     g_capturing = true;
     pt_err e = enqueue_step(p, hits, cells, links, tuplets, tracks, module_offsets, g_params, g_chi2, grad_hits,
                             grad_offsets, selected, n_selected, vertices, status, p->cap_stream);
@@ -256,12 +262,13 @@ pt_err pt_plan_run(pt_plan plan, const pt_hits* hits, pt_cells* cells, pt_links*
       if (g) (void)hipGraphDestroy(g);
       return e;
     }
-    if (ce != hipSuccess || !g) return PT_ERR_DEVICE;
+    if (ce != hipSuccess || !g) return device_error(ce != hipSuccess ? ce : hipErrorStreamCaptureInvalidated);
     p->graph = g;
-    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) return PT_ERR_DEVICE;
+    PT_HIP_CHECK(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
     p->key = key;
   }
-  return hipGraphLaunch(p->exec, s) == hipSuccess ? PT_OK : PT_ERR_DEVICE;
+  PT_HIP_CHECK(hipGraphLaunch(p->exec, s));
+  return PT_OK;
 }
 
 }  // extern "C"

@@ -53,6 +53,8 @@ struct DevCfg {
   // vertices
   int32_t vtx_min_hits, vtx_kmeans_iter;
   double vtx_pt_min, vtx_err_max, vtx_dz_cut, vtx_chi2_max, vtx_split_chi2_ndf, vtx_pt_cap;
+  // Fishbone (0: off)
+  double fishbone_theta2;
 };
 
 bool derive_config(const pt_config& c, DevCfg* d);
@@ -78,6 +80,7 @@ size_t ws_links(int n_hits, int cells_cap);
 size_t ws_ntuplets(int cells_cap, int tuplets_cap);
 size_t ws_fit(int n_max, int n_modules);
 size_t ws_ambiguity(int n_hits, int cells_cap, int n_max);
+size_t ws_fishbone(int n_hits, int cells_cap);
 size_t ws_vertices(int n_events, int n_max);
 
 // Device-wide exclusive scan of n int32 values in place; data[n] receives the
@@ -111,10 +114,20 @@ void timing_end(void* token, const char* name, hipStream_t s);
 extern thread_local bool g_capturing;
 extern thread_local bool g_no_timing;  // set by entry points that must not create events
 
-#define PT_LAUNCH_CHECK()                        \
-  do {                                           \
-    if (hipGetLastError() != hipSuccess) return PT_ERR_DEVICE; \
+// Device errors: the HIP error behind a PT_ERR_DEVICE is kept per host thread
+// (pt_last_device_error).  Entry points clear the thread's HIP error state
+// before they launch, so that an error another caller left there (an event
+// query's hipErrorNotReady, say) is not taken for one of theirs.
+pt_err device_error(hipError_t e);
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
+#define PT_HIP_CHECK(expr)                                   \
+  do {                                                       \
+    const hipError_t pt_e_ = (expr);                         \
+    if (pt_e_ != hipSuccess) return ::pt::device_error(pt_e_); \
   } while (0)
+
+#define PT_LAUNCH_CHECK() PT_HIP_CHECK(hipGetLastError())
 
 // ---------------------------------------------------------------------------
 // device helpers

@@ -588,14 +588,14 @@ pt_err launch_vertices(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, 
   if (selected) k_vtx_mark<<<g, 256, 0, s>>>(a);
   k_vtx_events<<<g, 256, 0, s>>>(a);
   PT_LAUNCH_CHECK();
-  if (exclusive_scan(a.ev_count, h.n_events, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan(a.ev_count, h.n_events, tmp, s));
   k_vtx_scatter<<<g, 256, 0, s>>>(a);
   PT_LAUNCH_CHECK();
   if (h.n_events > 0) {
     k_vtx_event_cluster<<<h.n_events, kBlock, 0, s>>>(a);
     PT_LAUNCH_CHECK();
   }
-  if (exclusive_scan(a.ev_nvtx, h.n_events, tmp, s) != hipSuccess) return PT_ERR_DEVICE;
+  PT_HIP_CHECK(exclusive_scan(a.ev_nvtx, h.n_events, tmp, s));
   k_vtx_event_first<<<grid_for(h.n_events + 1, 256), 256, 0, s>>>(a);
   PT_LAUNCH_CHECK();
   if (h.n_events > 0) {

@@ -38,7 +38,7 @@ _STRUCTS = {
     "pt_config": ["bfield", "n_pairs", "pair_inner", "pair_dphi", "pt_min", "cut_mask", "ca_rmax_other",
                   "root_always_mask", "min_hits", "layer_barrel", "x_over_x0", "p_cap", "n_modules", "n_phi_bins",
                   "block_links", "f64_solve_threshold", "vtx_min_hits", "vtx_kmeans_iter", "vtx_pt_min",
-                  "vtx_pt_cap"],
+                  "vtx_pt_cap", "fishbone_theta"],
     "pt_hits": ["n_hits", "n_events", "event_offsets", "dtype", "x", "layer", "module"],
     "pt_workspace": ["ptr", "bytes"],
     "pt_cells": ["cap", "inner", "pair", "count", "inner_first", "inner_count", "seg"],
@@ -106,6 +106,8 @@ def test_argument_errors_are_synchronous():
     assert L.pt_fit_broken_line(ct.byref(hits), ct.byref(cfg), ct.byref(t), None, 9, ct.byref(tr), None, ws,
                                 None) == A.PT_ERR_ARG
     assert L.pt_err_string(A.PT_ERR_WORKSPACE).decode().startswith("workspace")
+    # argument errors leave no device error behind
+    assert L.pt_last_device_error() == b""
 
 
 def test_python_package_fails_loudly_without_library(tmp_path):
