@@ -194,11 +194,112 @@ def chain_workload(args):
     n_pairs, n_examined = link_pair_counts(pipe_b.cells, h.n_hits, cfg_d)
     counts = dict(hits=h.n_hits, doublets=n_cells, links=n_links, ntuplets=n_raw, tracks=n_trk,
                   link_candidates=n_pairs, link_examined=n_examined)
+    table2 = table2_counters(pipe_b, cfg_d, h.n_events)
     del pipe_b, pipe, plan
     torch.cuda.empty_cache()
-    mixed = mixed_pileup(args, cfg_d, perf) if args.mixed_events else None
+    workflows = {name: full_chain(args, cfg, perf, h, hits, name) for name, cfg in
+                 (("quadruplets", cfg_d), ("triplets", C.default_config(min_hits=3)))}
+    mixed = mixed_pileup(args, cfg_d) if args.mixed_events else None
     return dict(t_batched=t_batched, t_per_event=t_per_event, t_h2d=t_h2d, kernels_ms=kern, counts=counts,
-                n_events=h.n_events, hits_np=h, cfg_d=cfg_d, perf=perf, mixed=mixed)
+                n_events=h.n_events, hits_np=h, cfg_d=cfg_d, perf=perf, mixed=mixed, table2=table2,
+                workflows=workflows)
+
+
+def table2_counters(pipe, cfg_d, n_events):
+    """Per-event counters in the shape of the paper's Table 2 (doublets,
+    n-tuplets and tracks per event, the fraction of doublets without any
+    link), plus roots, n-tuplets by hit count and the fit's fallback and
+    failure counts, from the products of one eager pass."""
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    n_cells = min(int(pipe.cells.count.item()), pipe.cells.cap)
+    out_count = pipe.links.out_count[:n_cells]
+    has_inner = pipe.links.has_inner[:n_cells]
+    unconn = ((out_count == 0) & (has_inner == 0)).sum().item()
+    inner_layer = torch.tensor([p[0] for p in cfg_d["pairs"]], device="cuda")[pipe.cells.pair[:n_cells].long()]
+    always = torch.zeros(10, dtype=torch.bool, device="cuda")
+    always[cfg_d["root_always"]] = True
+    if_free = torch.zeros(10, dtype=torch.bool, device="cuda")
+    if_free[cfg_d["root_if_free"]] = True
+    roots = (always[inner_layer] | (if_free[inner_layer] & (has_inner == 0))).sum().item()
+    raw_n = pipe.tuplets.raw()[1].long().cpu().numpy()
+    kept_n = pipe.tuplets.kept_rows()[1].long().cpu().numpy()
+    st = pipe.status.cpu().numpy()
+    return dict(doublets_per_event=n_cells / n_events, unconn_fraction=unconn / max(n_cells, 1),
+                roots_per_event=roots / n_events, ntuplets_per_event=len(raw_n) / n_events,
+                tracks_per_event=len(kept_n) / n_events,
+                ntuplets_by_hits={int(k): int(v) for k, v in zip(*np.unique(raw_n, return_counts=True))},
+                tracks_by_hits={int(k): int(v) for k, v in zip(*np.unique(kept_n, return_counts=True))},
+                fit_f64_refits=int(st[A.PT_ST_FIT_F64]), fit_failed=int(st[A.PT_ST_FIT_FAILED]),
+                truncated_searches=int(st[A.PT_ST_TRUNCATED]))
+
+
+def full_chain(args, cfg_d, perf, h, hits, name):
+    """The whole workflow of the paper's throughput measurement minus local
+    reconstruction, as one graph per step: doublets .. fit with covariance,
+    ambiguity resolution and pixel vertices (no adjoint), on the same batch;
+    plus the eager time of the ambiguity and vertex stages alone."""
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+
+    cp = caps(h.n_hits, h.n_events)
+    if cfg_d["min_hits"] == 3:   # triplets: about 18 rows per hit at pileup 200
+        cp["tuplets_cap"] = 24 * h.n_hits
+    cfg = A.make_config(cfg_d, **perf)
+    cells = api.Cells.empty(cp["cells_cap"], h.n_hits)
+    links = api.Links.empty(cp["links_cap"], cp["cells_cap"])
+    tup = api.Tuplets.empty(cp["tuplets_cap"])
+    tracks = api.Tracks.empty(cp["tuplets_cap"], A.PT_FIT_F32_F64SOLVE, with_cov=True)
+    status = api.new_status()
+    sel = torch.empty(cp["tuplets_cap"], dtype=torch.int32, device="cuda")
+    nsel = torch.zeros(1, dtype=torch.int32, device="cuda")
+    vtx = api.Vertices.empty(cp["tuplets_cap"], h.n_events, cp["tuplets_cap"])
+    plan = api.Plan(cfg, precision=A.PT_FIT_F32_F64SOLVE, stages=A.PT_STAGE_AMBIGUITY | A.PT_STAGE_VERTICES, **cp)
+
+    def step():
+        plan.run(hits, cells, links, tup, tracks, status, selected=sel, n_selected=nsel, vertices=vtx)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    flags = int(status[A.PT_ST_FLAGS].item()) & 0xFFFFFFFF
+    if flags & (A.PT_FLAG_CELLS_OVERFLOW | A.PT_FLAG_LINKS_OVERFLOW | A.PT_FLAG_TUPLETS_OVERFLOW |
+                A.PT_FLAG_VERTICES_OVERFLOW):
+        raise RuntimeError(f"capacity overflow in the {name} workflow (flags {flags:#x})")
+    steps = max(3, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    # the two stages alone, eagerly, timed with events on the current stream
+    ws = api.new_workspace(api.workspace_size(cfg, h.n_hits, h.n_events, cp["cells_cap"], cp["links_cap"],
+                                              cp["tuplets_cap"]))
+    stage_ms = {}
+    for stage in ("ambiguity", "vertices"):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            if stage == "ambiguity":
+                api.resolve_ambiguities(hits, cfg, cells, tup, A.PT_FIT_F32_F64SOLVE, tracks, status, ws)
+            else:
+                api.find_vertices(hits, cfg, tup, A.PT_FIT_F32_F64SOLVE, tracks, sel, nsel, vtx, status, ws)
+        b.record()
+        b.synchronize()
+        stage_ms[stage] = a.elapsed_time(b) / steps
+    nv = int(vtx.count.item())
+    out = dict(events_per_s=h.n_events / t, ms_per_step=t * 1e3, min_hits=cfg_d["min_hits"],
+               tracks=int(tup.count.item()), selected_tracks=int(nsel.item()), vertices=nv,
+               vertices_per_event=nv / h.n_events, stage_ms=stage_ms,
+               workload=f"{h.n_events} events at pileup 200: doublets, links, n-tuplets (min {cfg_d['min_hits']} "
+                        "hits), dedup, fit with covariance, ambiguity resolution, pixel vertices; one hipGraph")
+    log(f"{name} workflow: {t * 1e3:.3f} ms per step, {nv} vertices, stages {stage_ms}")
+    del plan, cells, links, tup, tracks, vtx, ws
+    torch.cuda.empty_cache()
+    return out
 
 
 def link_pair_counts(cells, n_hits, cfg_d):
@@ -248,8 +349,10 @@ def link_pair_counts(cells, n_hits, cfg_d):
     return pairs, int(examined.sum().item())
 
 
-def mixed_pileup(args, cfg_d, perf):
-    """256 events with pileup uniform in 20..200 in one batch (graph replays)."""
+def mixed_pileup(args, cfg_d):
+    """256 events with pileup uniform in 20..200: the batched form (one graph
+    per step, settings tuned for this batch) and the per-event form (the same
+    calls event by event on one stream, no graph), forward path."""
     import torch
 
     from paper_2008_13461_amd import _abi as A
@@ -259,12 +362,13 @@ def mixed_pileup(args, cfg_d, perf):
     h = E.config3(n_events=args.mixed_events)
     cp = caps(h.n_hits, h.n_events)
     hits = api.Hits.from_host(h)
+    perf = settings(args, cfg_d, hits, cp)
     cells = api.Cells.empty(cp["cells_cap"], h.n_hits)
     links = api.Links.empty(cp["links_cap"], cp["cells_cap"])
     tup = api.Tuplets.empty(cp["tuplets_cap"])
     tracks = api.Tracks.empty(cp["tuplets_cap"], A.PT_FIT_F32_F64SOLVE)
     status = api.new_status()
-    plan = api.Plan(A.make_config(cfg_d, **perf), precision=A.PT_FIT_F32_F64SOLVE, with_adjoint=False, **cp)
+    plan = api.Plan(A.make_config(cfg_d, **perf), precision=A.PT_FIT_F32_F64SOLVE, **cp)
 
     def step():
         plan.run(hits, cells, links, tup, tracks, status)
@@ -281,11 +385,37 @@ def mixed_pileup(args, cfg_d, perf):
         step()
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / steps
-    out = dict(events=h.n_events, hits=h.n_hits, doublets=int(cells.count.item()), tracks=int(tup.count.item()),
-               ms_per_step=t * 1e3, events_per_s=h.n_events / t,
-               workload=f"{h.n_events} events, pileup uniform in 20..200, forward path (no adjoint), one hipGraph")
-    log(f"mixed pileup: {h.n_events} events, {h.n_hits} hits, {t * 1e3:.3f} ms per step")
-    del plan, cells, links, tup, tracks, hits
+    n_trk = int(tup.count.item())
+    n_dbl = int(cells.count.item())
+    del plan, cells, links, tup, tracks
+    torch.cuda.empty_cache()
+    # per-event form
+    ev_hits = []
+    for e in range(h.n_events):
+        a, b = int(h.event_offsets[e]), int(h.event_offsets[e + 1])
+        ev_hits.append(api.Hits(hits.x[a:b], hits.y[a:b], hits.z[a:b], hits.layer[a:b], hits.module[a:b],
+                                torch.tensor([0, b - a], dtype=torch.int32, device="cuda")))
+    pipe = api.Pipeline(cfg_d, precision=A.PT_FIT_F32_F64SOLVE, **perf, **caps(max(x.n_hits for x in ev_hits), 1))
+
+    def per_event_pass():
+        for eh in ev_hits:
+            pipe.reconstruct(eh)
+
+    per_event_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, steps // 2)):
+        per_event_pass()
+    torch.cuda.synchronize()
+    t_pe = (time.perf_counter() - t0) / max(1, steps // 2)
+    out = dict(events=h.n_events, hits=h.n_hits, doublets=n_dbl, tracks=n_trk, tuned=perf,
+               ms_per_step=t * 1e3, events_per_s=h.n_events / t, per_event_ms=t_pe * 1e3,
+               per_event_events_per_s=h.n_events / t_pe, batched_over_per_event=t_pe / t,
+               workload=f"{h.n_events} events, pileup uniform in 20..200, forward path (no adjoint); batched: one "
+                        "hipGraph per step; per-event: the same calls event by event, no graph")
+    log(f"mixed pileup: {h.n_events} events, {h.n_hits} hits, {t * 1e3:.3f} ms batched, {t_pe * 1e3:.3f} ms "
+        "per-event")
+    del pipe, hits, ev_hits
     torch.cuda.empty_cache()
     return out
 
@@ -335,9 +465,84 @@ def fit_workload(args):
     fwd_ms, nf = api.timing_read("fit_fwd")
     bwd_ms, nb = api.timing_read("fit_bwd")
     api.timing_reset()
+    # forward + adjoint captured as one graph (torch's capture of the library's
+    # kernels on the capture stream), replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / steps
+    del graph
     nh = ts.nhits.astype(np.int64)
-    return dict(t_step=t_step, fwd_ms=fwd_ms / max(nf, 1), bwd_ms=bwd_ms / max(nb, 1), n_tracks=n,
-                n_hits_total=int(nh.sum()), mean_n=float(nh.mean()), nhits=nh)
+    out = dict(t_step=t_step, t_graph=t_graph, fwd_ms=fwd_ms / max(nf, 1), bwd_ms=bwd_ms / max(nb, 1), n_tracks=n,
+               n_hits_total=int(nh.sum()), mean_n=float(nh.mean()), nhits=nh)
+    del tup, tracks, ws, gh, hits
+    torch.cuda.empty_cache()
+    if args.fit_tiles > 1:
+        out["asymptote"] = fit_asymptote(args, ts)
+    return out
+
+
+def fit_asymptote(args, ts):
+    """Forward + adjoint on fit_tiles copies of the fit workload side by side
+    (each copy's rows point at its own copy of the hits), eagerly."""
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from synth import config as C
+    from synth import events as E
+
+    k = args.fit_tiles
+    h = ts.hits
+    n_h = h.n_hits
+    big = E.Hits(np.tile(h.x, k), np.tile(h.y, k), np.tile(h.z, k), np.tile(h.layer, k), np.tile(h.module, k),
+                 np.zeros(0, np.int32), np.array([0, k * n_h], np.int32))
+    rows = np.concatenate([np.where(ts.tuplets >= 0, ts.tuplets + c * n_h, -1) for c in range(k)]).astype(np.int32)
+    nhits = np.tile(ts.nhits, k)
+    n = rows.shape[0]
+    cfg = A.make_config(C.default_config())
+    hits = api.Hits.from_host(big)
+    tup = api.Tuplets.from_rows(torch.from_numpy(rows).cuda(), torch.from_numpy(nhits).cuda())
+    tracks = api.Tracks.empty(n, A.PT_FIT_F32_F64SOLVE)
+    status = api.new_status()
+    ws = api.new_workspace(api.workspace_size(cfg, big.n_hits, 1, 0, 0, n))
+    off = torch.from_numpy(E.module_offsets()).cuda()
+    gp, gc = (torch.from_numpy(a).cuda() for a in E.cotangents(4, n))
+    gh = torch.zeros((big.n_hits, 3), dtype=torch.float32, device="cuda")
+    go = torch.zeros((C.N_MODULES, 3), dtype=torch.float64, device="cuda")
+
+    def step():
+        api.fit_broken_line(hits, cfg, tup, off, A.PT_FIT_F32_F64SOLVE, tracks, status, ws)
+        api.fit_broken_line_bwd(hits, cfg, tup, off, A.PT_FIT_F32_F64SOLVE, gp, gc, gh, go, status, ws)
+
+    step()
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    nh = nhits.astype(np.int64)
+    nbytes = float((19 * nh + 26).sum() + (31 * nh + 25).sum())
+    out = dict(tracks=n, ms_fwd_bwd_step=t * 1e3, tracks_per_s=n / t, achieved_gbs=nbytes / t / 1e9,
+               frac=nbytes / t / 1e9 / HBM_PEAK_GBS,
+               workload=f"{k} copies of the fit workload side by side ({n} tracks), forward + adjoint, eager calls")
+    log(f"fit asymptote: {n} tracks, {t * 1e3:.3f} ms per forward + adjoint")
+    del tup, tracks, ws, gh, hits
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_model():
@@ -425,6 +630,26 @@ def traffic_record(name):
     return None
 
 
+def fit_counter_record():
+    """Counters of the fit workload's kernels from profiles/fit_config4_counters.txt
+    (its 'fit_counters' line), or None when the fit sources changed since."""
+    import hashlib
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "fit_config4_counters.txt")
+    if not os.path.exists(path):
+        return None
+    csrc = os.path.join(here, "paper_2008_13461_amd", "csrc")
+    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                  for f in ("fit.hip", "fit_core.h"))).hexdigest()
+    for line in open(path):
+        if line.startswith("fit_counters "):
+            f = dict(kv.split("=", 1) for kv in line.split()[1:])
+            if f.get("sha256") == sha:
+                return {"traffic_bytes": float(f["traffic_bytes"]), "valu_issue_frac": float(f["valu_issue_frac"])}
+    return None
+
+
 def roofline(kern, cnt):
     """Roofline object of the dominant timed kernel of the step."""
     if not kern:
@@ -476,6 +701,41 @@ def settings(args, cfg_d, hits, cp):
     return perf
 
 
+def profile_fit_run(args):
+    """Two eager forward + adjoint passes over the fit workload, then two
+    copies of 1 GiB (the calibration of the traffic counters)."""
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from synth import config as C
+    from synth import events as E
+
+    ts = E.config4(n_tracks=args.fit_tracks)
+    cfg = A.make_config(C.default_config())
+    hits = api.Hits.from_host(ts.hits)
+    n = len(ts.nhits)
+    tup = api.Tuplets.from_rows(torch.from_numpy(ts.tuplets).cuda(), torch.from_numpy(ts.nhits).cuda())
+    tracks = api.Tracks.empty(n, A.PT_FIT_F32_F64SOLVE)
+    status = api.new_status()
+    ws = api.new_workspace(api.workspace_size(cfg, ts.hits.n_hits, 1, 0, 0, n))
+    off = torch.from_numpy(E.module_offsets()).cuda()
+    gp, gc = (torch.from_numpy(a).cuda() for a in E.cotangents(4, n))
+    gh = torch.zeros((ts.hits.n_hits, 3), dtype=torch.float32, device="cuda")
+    go = torch.zeros((C.N_MODULES, 3), dtype=torch.float64, device="cuda")
+    for rep in range(2):
+        api.fit_broken_line(hits, cfg, tup, off, A.PT_FIT_F32_F64SOLVE, tracks, status, ws)
+        api.fit_broken_line_bwd(hits, cfg, tup, off, A.PT_FIT_F32_F64SOLVE, gp, gc, gh, go, status, ws)
+        torch.cuda.synchronize()
+        log(f"fit profile pass {rep}")
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("profile copies done (2^30 bytes read and written each)")
+
+
 def profile_run(args):
     """Two eager passes of the batched step (with the settings the bench
     tunes), then two copies of 1 GiB: the copy
@@ -518,6 +778,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events", type=int, default=64)
     ap.add_argument("--fit-tracks", type=int, default=1_000_000)
+    ap.add_argument("--fit-tiles", type=int, default=8,
+                    help="copies of the fit workload for the large-batch figure (1: skip)")
     ap.add_argument("--bins", type=int, default=0, help="azimuth bins per layer (0: autotuned)")
     ap.add_argument("--block-doublets", type=int, default=0, help="doublet kernel block size (0: autotuned)")
     ap.add_argument("--block-links", type=int, default=0, help="link sweep block size (0: autotuned)")
@@ -525,6 +787,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-events", type=int, default=256,
                     help="events of the mixed-pileup batch also reported (0: skip)")
+    ap.add_argument("--profile-fit", action="store_true",
+                    help="only two eager passes of the fit workload (forward + adjoint) and two 1 GiB copies, for "
+                         "profiler counter runs; prints no JSON")
     ap.add_argument("--profile", action="store_true",
                     help="only two eager passes of the batched step (reconstruction + adjoint) and two 1 GiB "
                          "copies, for profiler counter runs; prints no JSON")
@@ -544,6 +809,9 @@ def main():
     if args.profile:
         profile_run(args)
         return
+    if args.profile_fit:
+        profile_fit_run(args)
+        return
     chain = chain_workload(args)
     fit = fit_workload(args)
 
@@ -560,14 +828,23 @@ def main():
     bwd_bytes = float((31 * nh + 25).sum())
     fit_ms = fit["fwd_ms"] + fit["bwd_ms"]
     fit_gbs = (fwd_bytes + bwd_bytes) / (fit_ms * 1e-3) / 1e9
+    fit_counters = fit_counter_record()
     fit_obj = {
         "workload": f"{fit['n_tracks']} tracks (50% 4-hit, 30% 5-hit, 20% 6-hit), module offsets, f32 with f64 refit",
-        "tracks_per_s": fit["n_tracks"] / fit["t_step"],
-        "ms_fwd_bwd_step": fit["t_step"] * 1e3,
-        "kernel_ms": {"fit_fwd": fit["fwd_ms"], "fit_bwd": fit["bwd_ms"]},
+        "tracks_per_s": fit["n_tracks"] / fit["t_graph"],
+        "ms_fwd_bwd_step": fit["t_graph"] * 1e3,
+        "ms_fwd_bwd_step_eager": fit["t_step"] * 1e3,
+        "region_ms": {"fit_fwd": fit["fwd_ms"], "fit_bwd": fit["bwd_ms"]},
         "roofline": {"bound": "hbm", "achieved": fit_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": fit_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_track": (fwd_bytes + bwd_bytes) / fit["n_tracks"]},
+                     "frac": fit_gbs / HBM_PEAK_GBS,
+                     "traffic": fit_counters.get("traffic_bytes") if fit_counters else None,
+                     "valu_issue_frac": fit_counters.get("valu_issue_frac") if fit_counters else None,
+                     "bytes_per_track": (fwd_bytes + bwd_bytes) / fit["n_tracks"],
+                     "note": "algorithmic bytes (19n+26 forward, 31n+25 adjoint per track of n float hits) over "
+                             "the timing regions of every fit and adjoint kernel; traffic and the VALU issue "
+                             "fraction from the committed rocprofv3 counters of the same kernels, when they "
+                             "match the current sources"},
+        "asymptote": fit.get("asymptote"),
     }
 
     roof = roofline(kern, cnt)
@@ -597,6 +874,8 @@ def main():
         "kernel_ms": kern,
         "roofline": roof,
         "fit": fit_obj,
+        "workflows": chain["workflows"],
+        "table2_per_event": chain["table2"],
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, chain)

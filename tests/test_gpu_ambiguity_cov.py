@@ -66,7 +66,11 @@ def test_covariance_equals_the_oracle(precision_name, tol):
 def _chain(h, cfg_d, min_hits=4):
     from tests.gpu_helpers import caps_for, run_chain
     cfg = dict(cfg_d, min_hits=min_hits)
-    pipe, hits = run_chain(h, cfg, caps=caps_for(h.n_hits, h.n_events))
+    caps = caps_for(h.n_hits, h.n_events)
+    if min_hits == 3:      # the triplet workflow has more rows than hits
+        caps["tuplets_cap"] = 4 * max(h.n_hits, 256)
+    pipe, hits = run_chain(h, cfg, caps=caps)
+    assert pipe.flags() == 0
     return pipe, hits, cfg
 
 
