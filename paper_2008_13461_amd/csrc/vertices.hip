@@ -24,10 +24,11 @@
 // (count, scan, scatter), then one work-group per event sorts its list by
 // (z0, track index) -- a bitonic sort in LDS, or in global scratch for
 // events with more tracks than the LDS holds -- so that every window in z0
-// is a contiguous range of the sorted list.  Densities and links are one
-// thread per track over its window; the trees are resolved by pointer
-// jumping; one thread per tree fits (and splits) it; the vertices are
-// sorted by their key and written after a scan over events.
+// is a contiguous range of the sorted list.  Everything after the sort is
+// flat over the sorted positions of all events at once: densities and
+// links one thread per position over its window, roots by following the
+// links, one thread per tree for its fit (and split).  A second work-group
+// per event orders its vertices by their key, and the writes are flat again.
 #include <algorithm>
 
 #include "pt_internal.h"
@@ -38,7 +39,7 @@ namespace pt {
 namespace {
 
 constexpr int kBlock = 1024;
-constexpr int kLdsSort = 4096;  // entries sorted in LDS (12 bytes each)
+constexpr int kLdsSort = 8192;  // entries sorted in LDS (12 bytes each: 96 KB)
 
 struct VtxArgs {
   // tracks
@@ -70,6 +71,7 @@ struct VtxArgs {
   double* sz;            // sorted z0
   double* sv;            // sorted variance
   int32_t* sidx;         // sorted track index
+  int32_t* pev;          // event of each sorted position
   int32_t* rho;
   int32_t* parent;
   int32_t* root;
@@ -85,11 +87,13 @@ struct VtxArgs {
   int32_t* rndf;
   int32_t* rn;
   int32_t* rfirst;       // first member position (identifies the record)
-  int32_t* rroot;        // tree root position
-  int32_t* rpart;        // 0 whole, 1 / 2 the parts of a split
-  int32_t* rslot;        // per position: record slot of the record whose first member it is
+  int32_t* rslot;        // per position: event-local slot of the record whose first member it is
+  int32_t* rrank;        // per record slot: rank of the vertex in its event
+  int32_t* rec0;         // per root position: record slot of the whole tree, -1
+  int32_t* rec1;         // per root position: record slots of the two parts of a split tree, -1
+  int32_t* rec2;
   int32_t* vlocal;       // per position: rank of the track's vertex in its event, -1
-  int32_t* ev_nvtx;      // [n_events + 1], scanned into the first vertex of each event
+  int32_t* ev_nvtx;      // [n_events + 1] records per event, scanned into the first vertex of each event
   // outputs
   double *oz, *ovar, *ochi2, *osum;
   int32_t *ondf, *on;
@@ -114,6 +118,27 @@ __device__ inline uint64_t order_key(double v) {
 
 // ---------------------------------------------------------------------------
 // tracks -> events
+
+// Adds the active lanes with key e >= 0 to cnt[e], one atomic per distinct
+// key in the wavefront (tracks come grouped by event, so mostly one), and
+// returns each lane's slot (the old count plus its rank among the lanes of
+// its key), -1 for e < 0.  Called by every active lane of the wavefront.
+__device__ inline int wave_add(int32_t* cnt, int e) {
+  const int lane = __lane_id();
+  int slot = -1;
+  uint64_t todo = __ballot(e >= 0);
+  while (todo) {  // wave-uniform
+    const int leader = __builtin_ctzll(todo);
+    const int e0 = __shfl(e, leader);
+    const uint64_t grp = __ballot(e == e0) & todo;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cnt + e0, __popcll(grp));
+    base = __shfl(base, leader);
+    if ((grp >> lane) & 1) slot = base + __popcll(grp & ((uint64_t(1) << lane) - 1));
+    todo &= ~grp;
+  }
+  return slot;
+}
 
 __global__ void k_vtx_clear(VtxArgs a) {
   const int n = a.n_max;
@@ -159,7 +184,7 @@ __global__ void k_vtx_events(VtxArgs a) {
       if (a.n_events > 0 && a.event_offsets[lo] <= h0 && h0 < a.event_offsets[lo + 1]) e = lo;
     }
     a.ev_of[i] = e;
-    if (e >= 0) atomicAdd(a.ev_count + e, 1);
+    wave_add(a.ev_count, e);
   }
 }
 
@@ -167,7 +192,8 @@ __global__ void k_vtx_scatter(VtxArgs a) {
   const int n = n_tracks(a);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int e = a.ev_of[i];
-    if (e >= 0) a.list[a.ev_count[e] + atomicAdd(a.ev_cursor + e, 1)] = i;
+    const int slot = wave_add(a.ev_cursor, e);
+    if (e >= 0) a.list[a.ev_count[e] + slot] = i;
   }
 }
 
@@ -237,16 +263,16 @@ struct VFit {
   int n, first;
 };
 
-__device__ inline VFit fit_members(const VtxArgs& a, int64_t b, int r, int lo, int hi, int part) {
+__device__ inline VFit fit_members(const VtxArgs& a, int r, int lo, int hi, int part) {
   VFit f;
   double W = 0.0, S = 0.0;
   f.n = 0;
   f.first = -1;
   for (int q = lo; q <= hi; ++q) {
-    if (a.root[b + q] != r || (part > 0 && a.side[b + q] != part - 1)) continue;
-    const double w = 1.0 / a.sv[b + q];
+    if (a.root[q] != r || (part > 0 && a.side[q] != part - 1)) continue;
+    const double w = 1.0 / a.sv[q];
     W = W + w;
-    S = S + w * a.sz[b + q];
+    S = S + w * a.sz[q];
     if (f.first < 0) f.first = q;
     ++f.n;
   }
@@ -254,10 +280,10 @@ __device__ inline VFit fit_members(const VtxArgs& a, int64_t b, int r, int lo, i
   f.var = 1.0 / W;
   double c = 0.0, s2 = 0.0;
   for (int q = lo; q <= hi; ++q) {
-    if (a.root[b + q] != r || (part > 0 && a.side[b + q] != part - 1)) continue;
-    const double d = a.sz[b + q] - f.z;
-    c = c + (d * d) / a.sv[b + q];
-    const int i = a.sidx[b + q];
+    if (a.root[q] != r || (part > 0 && a.side[q] != part - 1)) continue;
+    const double d = a.sz[q] - f.z;
+    c = c + (d * d) / a.sv[q];
+    const int i = a.sidx[q];
     const double pt = a.K / fabs(val(a.params, static_cast<int64_t>(i) * 5 + 0, a.dbl));
     const double p = pt < a.pt_cap ? pt : a.pt_cap;
     s2 = s2 + p * p;
@@ -267,7 +293,7 @@ __device__ inline VFit fit_members(const VtxArgs& a, int64_t b, int r, int lo, i
   return f;
 }
 
-__device__ inline void put_record(const VtxArgs& a, int64_t slot, const VFit& f, int r, int part) {
+__device__ inline void put_record(const VtxArgs& a, int64_t slot, const VFit& f) {
   a.rz[slot] = f.z;
   a.rvar[slot] = f.var;
   a.rchi2[slot] = f.chi2;
@@ -275,22 +301,18 @@ __device__ inline void put_record(const VtxArgs& a, int64_t slot, const VFit& f,
   a.rndf[slot] = f.n - 1;
   a.rn[slot] = f.n;
   a.rfirst[slot] = f.first;
-  a.rroot[slot] = r;
-  a.rpart[slot] = part;
 }
 
-__global__ void __launch_bounds__(kBlock) k_vtx_event_cluster(VtxArgs a) {
+// ---- one work-group per event: sort its tracks by (z0, track index)
+__global__ void __launch_bounds__(kBlock) k_vtx_sort(VtxArgs a) {
   __shared__ uint64_t lkey[kLdsSort];
   __shared__ int32_t lval[kLdsSort];
-  __shared__ int s_changed;
-  __shared__ int s_nrec;
   const int e = blockIdx.x;
   const int64_t b = a.ev_count[e];             // the event's first list entry
   const int n = a.ev_count[e + 1] - a.ev_count[e];
   if (n == 0) return;
   uint64_t* key = a.skey + 2 * b;
   int32_t* sv = a.sval + 2 * b;
-  // ---- sort the event's tracks by (z0, track index)
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
     const int i = a.list[b + k];
     key[k] = order_key(val(a.params, static_cast<int64_t>(i) * 5 + 4, a.dbl));
@@ -300,93 +322,112 @@ __global__ void __launch_bounds__(kBlock) k_vtx_event_cluster(VtxArgs a) {
   sort_pairs(key, sv, n, lkey, lval);
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
     const int i = sv[k];
-    a.sidx[b + k] = i;
-    a.sz[b + k] = val(a.params, static_cast<int64_t>(i) * 5 + 4, a.dbl);
-    a.sv[b + k] = val(a.cov, static_cast<int64_t>(i) * 15 + 14, a.dbl);
-    a.tsize[b + k] = 0;
-    a.tlo[b + k] = 0x7fffffff;
-    a.thi[b + k] = -1;
-    a.rslot[b + k] = -1;
-    a.vlocal[b + k] = -1;
+    const int64_t p = b + k;
+    a.sidx[p] = i;
+    a.sz[p] = val(a.params, static_cast<int64_t>(i) * 5 + 4, a.dbl);
+    a.sv[p] = val(a.cov, static_cast<int64_t>(i) * 15 + 14, a.dbl);
+    a.pev[p] = e;
+    a.tsize[p] = 0;
+    a.tlo[p] = 0x7fffffff;
+    a.thi[p] = -1;
+    a.rec0[p] = -1;
+    a.rec1[p] = -1;
+    a.rec2[p] = -1;
   }
-  __syncthreads();
-  const double* z = a.sz + b;
-  const double* v = a.sv + b;
-  // ---- densities
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+}
+
+// ---- flat over the sorted positions of every event
+
+__device__ inline int positions(const VtxArgs& a) { return a.ev_count[a.n_events]; }
+
+__global__ void k_vtx_density(VtxArgs a) {
+  const int total = positions(a);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
+    const int e = a.pev[p];
+    const int lo = a.ev_count[e], hi = a.ev_count[e + 1];
+    const double zk = a.sz[p], vk = a.sv[p];
     int c = 0;
-    if (sqrt(v[k]) <= a.err_max) {
-      for (int j = k - 1; j >= 0; --j) {
-        const double d = z[k] - z[j];
+    if (sqrt(vk) <= a.err_max) {
+      for (int j = p - 1; j >= lo; --j) {
+        const double d = zk - a.sz[j];
         if (!(fabs(d) < a.dz_cut)) break;
-        if (d * d < a.chi2_max * (v[k] + v[j])) ++c;
+        if (d * d < a.chi2_max * (vk + a.sv[j])) ++c;
       }
-      for (int j = k + 1; j < n; ++j) {
-        const double d = z[k] - z[j];
+      for (int j = p + 1; j < hi; ++j) {
+        const double d = zk - a.sz[j];
         if (!(fabs(d) < a.dz_cut)) break;
-        if (d * d < a.chi2_max * (v[k] + v[j])) ++c;
+        if (d * d < a.chi2_max * (vk + a.sv[j])) ++c;
       }
     }
-    a.rho[b + k] = c;
+    a.rho[p] = c;
   }
-  __syncthreads();
-  // ---- links to the nearest higher-ranked compatible track
-  const int32_t* rho = a.rho + b;
-  const int32_t* idx = a.sidx + b;
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    int best = -1;
+}
+
+// Link to the nearest higher-ranked compatible track (-1: none).
+__global__ void k_vtx_parent(VtxArgs a) {
+  const int total = positions(a);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
+    const int e = a.pev[p];
+    const int lo = a.ev_count[e], hi = a.ev_count[e + 1];
+    const double zk = a.sz[p], vk = a.sv[p];
+    const int rk = a.rho[p], ik = a.sidx[p];
+    int best = -1, ib = 0;
     double bd = 0.0;
     for (int dir = -1; dir <= 1; dir += 2) {
-      for (int j = k + dir; j >= 0 && j < n; j += dir) {
-        const double d = z[k] - z[j];
+      for (int j = p + dir; j >= lo && j < hi; j += dir) {
+        const double d = zk - a.sz[j];
         if (!(fabs(d) < a.dz_cut)) break;
-        const bool higher = rho[j] > rho[k] || (rho[j] == rho[k] && idx[j] > idx[k]);
-        if (!higher || !(d * d <= a.chi2_max * (v[k] + v[j]))) continue;
+        const int rj = a.rho[j], ij = a.sidx[j];
+        const bool higher = rj > rk || (rj == rk && ij > ik);
+        if (!higher || !(d * d <= a.chi2_max * (vk + a.sv[j]))) continue;
         const double ad = fabs(d);
-        if (best < 0 || ad < bd || (ad == bd && idx[j] < idx[best])) {
+        if (best < 0 || ad < bd || (ad == bd && ij < ib)) {
           best = j;
           bd = ad;
+          ib = ij;
         }
       }
     }
-    a.parent[b + k] = best;
-    a.root[b + k] = best < 0 ? k : best;
+    a.parent[p] = best;
   }
-  __syncthreads();
-  // ---- roots by pointer jumping
-  int32_t* root = a.root + b;
-  for (;;) {
-    if (threadIdx.x == 0) s_changed = 0;
-    __syncthreads();
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-      const int r = root[k];
-      const int rr = root[r];
-      if (rr != r) {
-        root[k] = rr;
-        s_changed = 1;
-      }
+}
+
+// Root of each position's tree (links climb in rank, so the walk ends), and
+// each tree's size and range of positions.
+__global__ void k_vtx_root(VtxArgs a) {
+  const int total = positions(a);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
+    const int e = a.pev[p];
+    const int steps = a.ev_count[e + 1] - a.ev_count[e];
+    int r = p;
+    for (int s = 0; s < steps; ++s) {
+      const int q = a.parent[r];
+      if (q < 0) break;
+      r = q;
     }
-    __syncthreads();
-    const int again = s_changed;
-    __syncthreads();
-    if (!again) break;
+    a.root[p] = r;
+    atomicAdd(a.tsize + r, 1);
+    atomicMin(a.tlo + r, p);
+    atomicMax(a.thi + r, p);
   }
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const int r = root[k];
-    atomicAdd(a.tsize + b + r, 1);
-    atomicMin(a.tlo + b + r, k);
-    atomicMax(a.thi + b + r, k);
-  }
-  if (threadIdx.x == 0) s_nrec = 0;
-  __syncthreads();
-  // ---- one thread per candidate tree: fit, split, records
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
-    if (root[r] != r || !(rho[r] > 1) || a.tsize[b + r] < 2) continue;
-    const int lo = a.tlo[b + r], hi = a.thi[b + r];
-    const VFit f = fit_members(a, b, r, lo, hi, 0);
+}
+
+// One thread per tree: fit, split, records (in the event's record slots).
+__global__ void k_vtx_trees(VtxArgs a) {
+  const int total = positions(a);
+  const double* z = a.sz;
+  const double* v = a.sv;
+  const int32_t* root = a.root;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < total; r += gridDim.x * blockDim.x) {
+    if (root[r] != r || !(a.rho[r] > 1) || a.tsize[r] < 2) continue;
+    const int e = a.pev[r];
+    const int64_t eb = a.ev_count[e];
+    const int lo = a.tlo[r], hi = a.thi[r];
+    const VFit f = fit_members(a, r, lo, hi, 0);
     if (!(f.chi2 / (f.n - 1) > a.split)) {
-      const int slot = atomicAdd(&s_nrec, 1);
-      put_record(a, b + slot, f, r, 0);
+      const int64_t slot = eb + atomicAdd(a.ev_nvtx + e, 1);
+      put_record(a, slot, f);
+      a.rec0[r] = static_cast<int32_t>(slot);
       continue;
     }
     // two-means from the extreme members
@@ -398,8 +439,8 @@ __global__ void __launch_bounds__(kBlock) k_vtx_event_cluster(VtxArgs a) {
       for (int q = lo; q <= hi; ++q) {
         if (root[q] != r) continue;
         const uint8_t s = fabs(z[q] - c1) <= fabs(z[q] - c2) ? 0 : 1;
-        if (!first_round && s != a.side[b + q]) moved = true;
-        a.side[b + q] = s;
+        if (!first_round && s != a.side[q]) moved = true;
+        a.side[q] = s;
         const double w = 1.0 / v[q];
         if (s == 0) {
           W1 = W1 + w;
@@ -419,64 +460,80 @@ __global__ void __launch_bounds__(kBlock) k_vtx_event_cluster(VtxArgs a) {
       c2 = S2 / W2;
     }
     if (empty) {
-      const int slot = atomicAdd(&s_nrec, 1);
-      put_record(a, b + slot, f, r, 0);
+      const int64_t slot = eb + atomicAdd(a.ev_nvtx + e, 1);
+      put_record(a, slot, f);
+      a.rec0[r] = static_cast<int32_t>(slot);
       continue;
     }
-    for (int p = 1; p <= 2; ++p) {
-      const VFit g = fit_members(a, b, r, lo, hi, p);
+    for (int part = 1; part <= 2; ++part) {
+      const VFit g = fit_members(a, r, lo, hi, part);
       if (g.n < 2) continue;
-      const int slot = atomicAdd(&s_nrec, 1);
-      put_record(a, b + slot, g, r, p);
+      const int64_t slot = eb + atomicAdd(a.ev_nvtx + e, 1);
+      put_record(a, slot, g);
+      (part == 1 ? a.rec1 : a.rec2)[r] = static_cast<int32_t>(slot);
     }
   }
-  __syncthreads();
-  // ---- order the records: sum of p_T^2 descending, then first member
-  const int nr = s_nrec;
+}
+
+// ---- one work-group per event: its records by sum of p_T^2 (descending),
+// then first member
+__global__ void __launch_bounds__(kBlock) k_vtx_order(VtxArgs a) {
+  __shared__ uint64_t lkey[kLdsSort];
+  __shared__ int32_t lval[kLdsSort];
+  const int e = blockIdx.x;
+  const int64_t b = a.ev_count[e];
+  const int nr = a.ev_nvtx[e];
+  if (nr == 0) return;
+  uint64_t* key = a.skey + 2 * b;
+  int32_t* sv = a.sval + 2 * b;
   for (int k = threadIdx.x; k < nr; k += blockDim.x) {
     key[k] = ~order_key(a.rsum[b + k]);
     sv[k] = a.rfirst[b + k];
-    a.rslot[b + a.rfirst[b + k]] = k;
+    a.rslot[a.rfirst[b + k]] = k;
   }
   __syncthreads();
-  if (nr > 0) sort_pairs(key, sv, nr, lkey, lval);
-  // ---- each record's members learn their vertex's rank
-  for (int k = threadIdx.x; k < nr; k += blockDim.x) {
-    const int slot = a.rslot[b + sv[k]];
-    const int r = a.rroot[b + slot], part = a.rpart[b + slot];
-    for (int q = a.tlo[b + r]; q <= a.thi[b + r]; ++q)
-      if (root[q] == r && (part == 0 || a.side[b + q] == part - 1)) a.vlocal[b + q] = k;
-  }
-  if (threadIdx.x == 0) a.ev_nvtx[e] = nr;
+  sort_pairs(key, sv, nr, lkey, lval);
+  for (int k = threadIdx.x; k < nr; k += blockDim.x) a.rrank[b + a.rslot[sv[k]]] = k;
 }
 
-// Writes event e's ordered vertices at event_first[e] and the tracks' vertex
-// indices.
-__global__ void __launch_bounds__(kBlock) k_vtx_write(VtxArgs a) {
-  const int e = blockIdx.x;
-  const int64_t b = a.ev_count[e];
-  const int n = a.ev_count[e + 1] - a.ev_count[e];
-  const int nr = a.event_first[e + 1] - a.event_first[e];
-  const int base = a.event_first[e];
-  const int32_t* sv = a.sval + 2 * b;
-  uint32_t over = 0;
-  for (int k = threadIdx.x; k < nr; k += blockDim.x) {
-    const int64_t slot = b + a.rslot[b + sv[k]];
-    const int at = base + k;
-    if (at >= a.cap) {
-      ++over;
-      continue;
+// Each track's vertex rank in its event (-1: none).
+__global__ void k_vtx_members(VtxArgs a) {
+  const int total = positions(a);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
+    const int r = a.root[p];
+    int slot = a.rec0[r];
+    if (slot < 0) {
+      const int s1 = a.rec1[r], s2 = a.rec2[r];
+      if (s1 >= 0 || s2 >= 0) slot = a.side[p] == 0 ? s1 : s2;   // a split tree
     }
-    a.oz[at] = a.rz[slot];
-    a.ovar[at] = a.rvar[slot];
-    a.ochi2[at] = a.rchi2[slot];
-    a.osum[at] = a.rsum[slot];
-    a.ondf[at] = a.rndf[slot];
-    a.on[at] = a.rn[slot];
+    a.vlocal[p] = slot >= 0 ? a.rrank[slot] : -1;
   }
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const int l = a.vlocal[b + k];
-    if (l >= 0) a.track_vertex[a.sidx[b + k]] = base + l;
+}
+
+// Writes each event's ordered vertices at event_first[e] and the tracks'
+// vertex indices.
+__global__ void k_vtx_write(VtxArgs a) {
+  const int total = positions(a);
+  uint32_t over = 0;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
+    const int e = a.pev[p];
+    const int base = a.event_first[e];
+    const int nr = a.event_first[e + 1] - base;
+    if (p - a.ev_count[e] < nr) {   // a record slot
+      const int at = base + a.rrank[p];
+      if (at >= a.cap) {
+        ++over;
+      } else {
+        a.oz[at] = a.rz[p];
+        a.ovar[at] = a.rvar[p];
+        a.ochi2[at] = a.rchi2[p];
+        a.osum[at] = a.rsum[p];
+        a.ondf[at] = a.rndf[p];
+        a.on[at] = a.rn[p];
+      }
+    }
+    const int l = a.vlocal[p];
+    if (l >= 0) a.track_vertex[a.sidx[p]] = base + l;
   }
   if (over) status_flag(a.status, PT_FLAG_VERTICES_OVERFLOW);
 }
@@ -507,7 +564,8 @@ size_t ws_vertices(int n_events, int n_max) {
   c.take<int32_t>(n);        // thi
   c.take<uint8_t>(n);        // side
   for (int q = 0; q < 4; ++q) c.take<double>(n);   // rz rvar rchi2 rsum
-  for (int q = 0; q < 7; ++q) c.take<int32_t>(n);  // rndf rn rfirst rroot rpart rslot vlocal
+  for (int q = 0; q < 5; ++q) c.take<int32_t>(n);  // rndf rn rfirst rslot vlocal
+  for (int q = 0; q < 5; ++q) c.take<int32_t>(n);  // pev rrank rec0 rec1 rec2
   c.take<int32_t>(E);        // ev_nvtx
   c.take<int32_t>(scan_tmp_elems(static_cast<int64_t>(E)));
   return c.off + 256;
@@ -566,10 +624,13 @@ pt_err launch_vertices(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, 
   a.rndf = c.take<int32_t>(n);
   a.rn = c.take<int32_t>(n);
   a.rfirst = c.take<int32_t>(n);
-  a.rroot = c.take<int32_t>(n);
-  a.rpart = c.take<int32_t>(n);
   a.rslot = c.take<int32_t>(n);
   a.vlocal = c.take<int32_t>(n);
+  a.pev = c.take<int32_t>(n);
+  a.rrank = c.take<int32_t>(n);
+  a.rec0 = c.take<int32_t>(n);
+  a.rec1 = c.take<int32_t>(n);
+  a.rec2 = c.take<int32_t>(n);
   a.ev_nvtx = c.take<int32_t>(E);
   int32_t* tmp = c.take<int32_t>(scan_tmp_elems(static_cast<int64_t>(E)));
   a.oz = out.z;
@@ -591,17 +652,26 @@ pt_err launch_vertices(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T, 
   PT_HIP_CHECK(exclusive_scan(a.ev_count, h.n_events, tmp, s));
   k_vtx_scatter<<<g, 256, 0, s>>>(a);
   PT_LAUNCH_CHECK();
+  const int gp = grid_for(n_max, 256, 16384);   // flat over the sorted positions
   if (h.n_events > 0) {
-    k_vtx_event_cluster<<<h.n_events, kBlock, 0, s>>>(a);
+    k_vtx_sort<<<h.n_events, kBlock, 0, s>>>(a);
     PT_LAUNCH_CHECK();
   }
-  PT_HIP_CHECK(exclusive_scan(a.ev_nvtx, h.n_events, tmp, s));
-  k_vtx_event_first<<<grid_for(h.n_events + 1, 256), 256, 0, s>>>(a);
+  k_vtx_density<<<gp, 256, 0, s>>>(a);
+  k_vtx_parent<<<gp, 256, 0, s>>>(a);
+  k_vtx_root<<<gp, 256, 0, s>>>(a);
+  k_vtx_trees<<<gp, 256, 0, s>>>(a);
   PT_LAUNCH_CHECK();
   if (h.n_events > 0) {
-    k_vtx_write<<<h.n_events, kBlock, 0, s>>>(a);
+    k_vtx_order<<<h.n_events, kBlock, 0, s>>>(a);
     PT_LAUNCH_CHECK();
   }
+  k_vtx_members<<<gp, 256, 0, s>>>(a);
+  PT_LAUNCH_CHECK();
+  PT_HIP_CHECK(exclusive_scan(a.ev_nvtx, h.n_events, tmp, s));
+  k_vtx_event_first<<<grid_for(h.n_events + 1, 256), 256, 0, s>>>(a);
+  k_vtx_write<<<gp, 256, 0, s>>>(a);
+  PT_LAUNCH_CHECK();
   return PT_OK;
 }
 

@@ -90,24 +90,33 @@ def test_vertices_of_a_pileup_50_event():
 
 
 def test_vertices_of_a_batch_with_every_track():
-    """Eight pileup-200 events and two empty ones, every fitted track used:
-    several thousand tracks per event, sorted in global memory."""
+    """Eight pileup-200 events and two empty ones, every fitted track used and
+    no p_T cut: over 8192 tracks in an event (sorted in global memory)."""
     _need_gpu()
+    cfg_d = C.default_config(vtx_pt_min=0.0)
     b = E.config5(n_events=8)
     a = int(b.event_offsets[4])
     off = np.array(list(b.event_offsets[:5]) + [a] + list(b.event_offsets[5:]) + [b.n_hits], np.int32)
     h = E.Hits(b.x, b.y, b.z, b.layer, b.module, b.track, off)
-    trk, use, got = _run(h, use_selection=False)
-    counts = np.bincount(np.searchsorted(h.event_offsets, trk["hits"][:, 0], side="right") - 1,
-                         minlength=h.n_events)
-    assert counts.max() > 4096
+    trk, use, got = _run(h, use_selection=False, cfg_d=cfg_d)
+    ev = np.searchsorted(h.event_offsets, trk["hits"][:, 0], side="right") - 1
+    ok = (trk["n"] >= 4) & np.isfinite(trk["params"][:, 4]) & (trk["cov"][:, 14] > 0)
+    counts = np.bincount(ev[ok], minlength=h.n_events)
+    assert counts.max() > 8192
     assert got["event_first"][5] == got["event_first"][4] and got["event_first"][10] == got["event_first"][9]
-    nv = _compare(h, trk, use, got)
+    nv = _compare(h, trk, use, got, cfg_d=cfg_d)
     assert nv > 100
 
 
+
 def test_vertices_of_a_pileup_200_batch_after_ambiguity_resolution():
+    """The tracks left by the ambiguity resolution: a few thousand per event,
+    sorted in LDS."""
     _need_gpu()
     h = E.config5(n_events=4)
     trk, use, got = _run(h)
+    ev = np.searchsorted(h.event_offsets, trk["hits"][:, 0], side="right") - 1
+    K = 0.299792458 * CFG["bfield"] / 100.0
+    ok = use & (trk["n"] >= 4) & (K / np.abs(trk["params"][:, 0]) > CFG["vtx_pt_min"]) & (trk["cov"][:, 14] > 0)
+    assert 1000 < np.bincount(ev[ok], minlength=h.n_events).max() <= 8192
     assert _compare(h, trk, use, got) > 100
