@@ -257,38 +257,66 @@ __device__ void sort_pairs(uint64_t* key, int32_t* v, int n, uint64_t* lkey, int
 }
 
 // Fit of the members of tree r (positions lo..hi whose root is r, and, for
-// part p > 0, whose side is p - 1), in position order.
+// part p > 0, whose side is p - 1) by one wavefront: lanes scan 64
+// consecutive positions at a time and the sums run over the members in
+// position order (each member's term taken from its lane in turn), the same
+// additions in the same order as one thread walking the members.
 struct VFit {
   double z, var, chi2, sum;
   int n, first;
 };
 
-__device__ inline VFit fit_members(const VtxArgs& a, int r, int lo, int hi, int part) {
+__device__ inline bool member(const VtxArgs& a, int q, int hi, int r, int part) {
+  return q <= hi && a.root[q] == r && (part == 0 || a.side[q] == part - 1);
+}
+
+__device__ inline VFit wave_fit(const VtxArgs& a, int r, int lo, int hi, int part, int lane) {
   VFit f;
-  double W = 0.0, S = 0.0;
   f.n = 0;
   f.first = -1;
-  for (int q = lo; q <= hi; ++q) {
-    if (a.root[q] != r || (part > 0 && a.side[q] != part - 1)) continue;
-    const double w = 1.0 / a.sv[q];
-    W = W + w;
-    S = S + w * a.sz[q];
-    if (f.first < 0) f.first = q;
-    ++f.n;
+  double W = 0.0, S = 0.0;
+  for (int c = lo; c <= hi; c += kWave) {
+    const int q = c + lane;
+    const bool m = member(a, q, hi, r, part);
+    double w = 0.0, wz = 0.0;
+    if (m) {
+      w = 1.0 / a.sv[q];
+      wz = w * a.sz[q];
+    }
+    uint64_t bits = __ballot(m);
+    if (bits && f.first < 0) f.first = c + __builtin_ctzll(bits);
+    f.n += __popcll(bits);
+    while (bits) {
+      const int l = __builtin_ctzll(bits);
+      bits &= bits - 1;
+      W = W + __shfl(w, l);
+      S = S + __shfl(wz, l);
+    }
   }
   f.z = S / W;
   f.var = 1.0 / W;
-  double c = 0.0, s2 = 0.0;
-  for (int q = lo; q <= hi; ++q) {
-    if (a.root[q] != r || (part > 0 && a.side[q] != part - 1)) continue;
-    const double d = a.sz[q] - f.z;
-    c = c + (d * d) / a.sv[q];
-    const int i = a.sidx[q];
-    const double pt = a.K / fabs(val(a.params, static_cast<int64_t>(i) * 5 + 0, a.dbl));
-    const double p = pt < a.pt_cap ? pt : a.pt_cap;
-    s2 = s2 + p * p;
+  double c2 = 0.0, s2 = 0.0;
+  for (int c = lo; c <= hi; c += kWave) {
+    const int q = c + lane;
+    const bool m = member(a, q, hi, r, part);
+    double tc = 0.0, tp = 0.0;
+    if (m) {
+      const double d = a.sz[q] - f.z;
+      tc = (d * d) / a.sv[q];
+      const int i = a.sidx[q];
+      const double pt = a.K / fabs(val(a.params, static_cast<int64_t>(i) * 5 + 0, a.dbl));
+      const double p = pt < a.pt_cap ? pt : a.pt_cap;
+      tp = p * p;
+    }
+    uint64_t bits = __ballot(m);
+    while (bits) {
+      const int l = __builtin_ctzll(bits);
+      bits &= bits - 1;
+      c2 = c2 + __shfl(tc, l);
+      s2 = s2 + __shfl(tp, l);
+    }
   }
-  f.chi2 = c;
+  f.chi2 = c2;
   f.sum = s2;
   return f;
 }
@@ -412,65 +440,93 @@ __global__ void k_vtx_root(VtxArgs a) {
   }
 }
 
-// One thread per tree: fit, split, records (in the event's record slots).
-__global__ void k_vtx_trees(VtxArgs a) {
-  const int total = positions(a);
+// One wavefront per tree (the trees rooted in each run of 64 positions in
+// turn): fit, split, records (in the event's record slots, taken by lane 0).
+__device__ inline void record(const VtxArgs& a, int e, int64_t eb, const VFit& f, int32_t* rec, int r, int lane) {
+  if (lane == 0) {
+    const int64_t slot = eb + atomicAdd(a.ev_nvtx + e, 1);
+    put_record(a, slot, f);
+    rec[r] = static_cast<int32_t>(slot);
+  }
+}
+
+__device__ inline void wave_tree(const VtxArgs& a, int r, int lane) {
   const double* z = a.sz;
   const double* v = a.sv;
-  const int32_t* root = a.root;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < total; r += gridDim.x * blockDim.x) {
-    if (root[r] != r || !(a.rho[r] > 1) || a.tsize[r] < 2) continue;
-    const int e = a.pev[r];
-    const int64_t eb = a.ev_count[e];
-    const int lo = a.tlo[r], hi = a.thi[r];
-    const VFit f = fit_members(a, r, lo, hi, 0);
-    if (!(f.chi2 / (f.n - 1) > a.split)) {
-      const int64_t slot = eb + atomicAdd(a.ev_nvtx + e, 1);
-      put_record(a, slot, f);
-      a.rec0[r] = static_cast<int32_t>(slot);
-      continue;
-    }
-    // two-means from the extreme members
-    double c1 = z[lo], c2 = z[hi];
-    bool empty = false, first_round = true;
-    for (int it = 0; it < a.kmeans_iter; ++it) {
-      bool moved = first_round;
-      double W1 = 0.0, S1 = 0.0, W2 = 0.0, S2 = 0.0;
-      for (int q = lo; q <= hi; ++q) {
-        if (root[q] != r) continue;
-        const uint8_t s = fabs(z[q] - c1) <= fabs(z[q] - c2) ? 0 : 1;
-        if (!first_round && s != a.side[q]) moved = true;
-        a.side[q] = s;
-        const double w = 1.0 / v[q];
-        if (s == 0) {
-          W1 = W1 + w;
-          S1 = S1 + w * z[q];
-        } else {
-          W2 = W2 + w;
-          S2 = S2 + w * z[q];
-        }
+  const int e = a.pev[r];
+  const int64_t eb = a.ev_count[e];
+  const int lo = a.tlo[r], hi = a.thi[r];
+  const VFit f = wave_fit(a, r, lo, hi, 0, lane);
+  if (!(f.chi2 / (f.n - 1) > a.split)) {
+    record(a, e, eb, f, a.rec0, r, lane);
+    return;
+  }
+  // two-means from the extreme members
+  double c1 = z[lo], c2 = z[hi];
+  bool empty = false, first_round = true;
+  for (int it = 0; it < a.kmeans_iter; ++it) {
+    bool moved = first_round;
+    double W1 = 0.0, S1 = 0.0, W2 = 0.0, S2 = 0.0;
+    for (int c = lo; c <= hi; c += kWave) {
+      const int q = c + lane;
+      const bool m = member(a, q, hi, r, 0);
+      uint8_t sd = 0;
+      bool mv = false;
+      double w = 0.0, wz = 0.0;
+      if (m) {
+        sd = fabs(z[q] - c1) <= fabs(z[q] - c2) ? 0 : 1;
+        mv = !first_round && sd != a.side[q];
+        a.side[q] = sd;
+        w = 1.0 / v[q];
+        wz = w * z[q];
       }
-      first_round = false;
-      if (!moved) break;
-      if (W1 == 0.0 || W2 == 0.0) {
-        empty = true;
-        break;
+      if (__ballot(mv)) moved = true;
+      uint64_t b0 = __ballot(m && sd == 0), b1 = __ballot(m && sd == 1);
+      while (b0) {
+        const int l = __builtin_ctzll(b0);
+        b0 &= b0 - 1;
+        W1 = W1 + __shfl(w, l);
+        S1 = S1 + __shfl(wz, l);
       }
-      c1 = S1 / W1;
-      c2 = S2 / W2;
+      while (b1) {
+        const int l = __builtin_ctzll(b1);
+        b1 &= b1 - 1;
+        W2 = W2 + __shfl(w, l);
+        S2 = S2 + __shfl(wz, l);
+      }
     }
-    if (empty) {
-      const int64_t slot = eb + atomicAdd(a.ev_nvtx + e, 1);
-      put_record(a, slot, f);
-      a.rec0[r] = static_cast<int32_t>(slot);
-      continue;
+    first_round = false;
+    if (!moved) break;
+    if (W1 == 0.0 || W2 == 0.0) {
+      empty = true;
+      break;
     }
-    for (int part = 1; part <= 2; ++part) {
-      const VFit g = fit_members(a, r, lo, hi, part);
-      if (g.n < 2) continue;
-      const int64_t slot = eb + atomicAdd(a.ev_nvtx + e, 1);
-      put_record(a, slot, g);
-      (part == 1 ? a.rec1 : a.rec2)[r] = static_cast<int32_t>(slot);
+    c1 = S1 / W1;
+    c2 = S2 / W2;
+  }
+  if (empty) {
+    record(a, e, eb, f, a.rec0, r, lane);
+    return;
+  }
+  for (int part = 1; part <= 2; ++part) {
+    const VFit g = wave_fit(a, r, lo, hi, part, lane);
+    if (g.n >= 2) record(a, e, eb, g, part == 1 ? a.rec1 : a.rec2, r, lane);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_vtx_trees(VtxArgs a) {
+  const int total = positions(a);
+  const int lane = __lane_id();
+  const int w = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int nw = static_cast<int>(gridDim.x * blockDim.x / kWave);
+  for (int base = w * kWave; base < total; base += nw * kWave) {
+    const int p = base + lane;
+    const bool cand = p < total && a.root[p] == p && a.rho[p] > 1 && a.tsize[p] >= 2;
+    uint64_t todo = __ballot(cand);
+    while (todo) {
+      const int r = base + __builtin_ctzll(todo);
+      todo &= todo - 1;
+      wave_tree(a, r, lane);
     }
   }
 }
