@@ -200,9 +200,73 @@ def chain_workload(args):
     workflows = {name: full_chain(args, cfg, perf, h, hits, name) for name, cfg in
                  (("quadruplets", cfg_d), ("triplets", C.default_config(min_hits=3)))}
     mixed = mixed_pileup(args, cfg_d) if args.mixed_events else None
+    fishbone = fishbone_workload(args, perf)
     return dict(t_batched=t_batched, t_per_event=t_per_event, t_h2d=t_h2d, kernels_ms=kern, counts=counts,
                 n_events=h.n_events, hits_np=h, cfg_d=cfg_d, perf=perf, mixed=mixed, table2=table2,
-                workflows=workflows)
+                workflows=workflows, fishbone=fishbone)
+
+
+def fishbone_workload(args, perf):
+    """The overlap geometry (a quarter of the layer crossings leave a second
+    hit on an overlapping module) at pileup 200: the forward path (doublets ..
+    fit) as one graph per step with the Fishbone off and on, and the
+    Fishbone's own kernels timed eagerly."""
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from synth import config as C
+    from synth import events as E
+
+    h = E.overlap_batch(n_events=args.events, pileup=200)
+    hits = api.Hits.from_host(h)
+    cp = caps(h.n_hits, h.n_events)
+    out = {"events": h.n_events, "hits": h.n_hits,
+           "workload": f"{h.n_events} events at pileup 200 in the overlap geometry (second hits on overlapping "
+                       "ladders and blades for a quarter of the layer crossings), forward path doublets .. fit, "
+                       "one hipGraph per step"}
+    for name, theta in (("off", 0.0), ("on", 0.01)):
+        cfg = A.make_config(C.default_config(fishbone_theta=theta), **perf)
+        cells = api.Cells.empty(cp["cells_cap"], h.n_hits)
+        links = api.Links.empty(cp["links_cap"], cp["cells_cap"])
+        tup = api.Tuplets.empty(cp["tuplets_cap"])
+        tracks = api.Tracks.empty(cp["tuplets_cap"], A.PT_FIT_F32_F64SOLVE)
+        status = api.new_status()
+        plan = api.Plan(cfg, precision=A.PT_FIT_F32_F64SOLVE, **cp)
+        for _ in range(max(args.warmup, 1)):
+            plan.run(hits, cells, links, tup, tracks, status)
+        torch.cuda.synchronize()
+        flags = int(status[A.PT_ST_FLAGS].item()) & 0xFFFFFFFF
+        if flags & (A.PT_FLAG_CELLS_OVERFLOW | A.PT_FLAG_LINKS_OVERFLOW | A.PT_FLAG_TUPLETS_OVERFLOW):
+            raise RuntimeError(f"capacity overflow in the overlap batch (flags {flags:#x})")
+        steps = max(3, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.run(hits, cells, links, tup, tracks, status)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        rec = dict(events_per_s=h.n_events / t, ms_per_step=t * 1e3, doublets=int(cells.count.item()),
+                   links=int(links.count.item()), tracks=int(tup.count.item()))
+        del plan
+        if theta > 0.0:
+            ws = api.new_workspace(api.workspace_size(cfg, h.n_hits, h.n_events, cp["cells_cap"], cp["links_cap"],
+                                                      cp["tuplets_cap"]))
+            api.timing_reset()
+            api.timing_enable(True)
+            for _ in range(steps):
+                api.build_doublets(hits, cfg, cells, status, ws)
+            torch.cuda.synchronize()
+            api.timing_enable(False)
+            ms, n = api.timing_read("fishbone")
+            api.timing_reset()
+            rec["fishbone_ms"] = ms / max(n, 1)
+            del ws
+        out[name] = rec
+        log(f"overlap batch, Fishbone {name}: {t * 1e3:.3f} ms per step, {rec['doublets']} doublets, "
+            f"{rec['tracks']} tracks")
+        del cells, links, tup, tracks
+        torch.cuda.empty_cache()
+    return out
 
 
 def table2_counters(pipe, cfg_d, n_events):
@@ -389,6 +453,26 @@ def mixed_pileup(args, cfg_d):
     n_dbl = int(cells.count.item())
     del plan, cells, links, tup, tracks
     torch.cuda.empty_cache()
+    # kernel times of the eager batched calls: per doublet, against the
+    # uniform PU200 batch, they show whether uneven events leave the flat
+    # all-event kernels idle in a tail
+    pipe_b = api.Pipeline(cfg_d, precision=A.PT_FIT_F32_F64SOLVE, **perf, **cp)
+    pipe_b.reconstruct(hits)
+    torch.cuda.synchronize()
+    api.timing_reset()
+    api.timing_enable(True)
+    for _ in range(steps):
+        pipe_b.reconstruct(hits)
+    torch.cuda.synchronize()
+    api.timing_enable(False)
+    kern = {}
+    for name in TIMED:
+        ms, n = api.timing_read(name)
+        if n:
+            kern[name] = ms / n
+    api.timing_reset()
+    del pipe_b
+    torch.cuda.empty_cache()
     # per-event form
     ev_hits = []
     for e in range(h.n_events):
@@ -409,6 +493,7 @@ def mixed_pileup(args, cfg_d):
     torch.cuda.synchronize()
     t_pe = (time.perf_counter() - t0) / max(1, steps // 2)
     out = dict(events=h.n_events, hits=h.n_hits, doublets=n_dbl, tracks=n_trk, tuned=perf,
+               kernel_ms=kern, kernel_ns_per_doublet={k: v * 1e6 / n_dbl for k, v in kern.items()},
                ms_per_step=t * 1e3, events_per_s=h.n_events / t, per_event_ms=t_pe * 1e3,
                per_event_events_per_s=h.n_events / t_pe, batched_over_per_event=t_pe / t,
                workload=f"{h.n_events} events, pileup uniform in 20..200, forward path (no adjoint); batched: one "
@@ -431,7 +516,7 @@ def fit_workload(args):
     t0 = time.time()
     ts = E.config4(n_tracks=args.fit_tracks)
     log(f"generated {len(ts.nhits)} tracks in {time.time() - t0:.1f}s")
-    cfg = A.make_config(C.default_config())
+    cfg = A.make_config(C.default_config(exclusive_hits=1))
     hits = api.Hits.from_host(ts.hits)
     n = len(ts.nhits)
     tup = api.Tuplets.from_rows(torch.from_numpy(ts.tuplets).cuda(), torch.from_numpy(ts.nhits).cuda())
@@ -511,7 +596,7 @@ def fit_asymptote(args, ts):
     rows = np.concatenate([np.where(ts.tuplets >= 0, ts.tuplets + c * n_h, -1) for c in range(k)]).astype(np.int32)
     nhits = np.tile(ts.nhits, k)
     n = rows.shape[0]
-    cfg = A.make_config(C.default_config())
+    cfg = A.make_config(C.default_config(exclusive_hits=1))
     hits = api.Hits.from_host(big)
     tup = api.Tuplets.from_rows(torch.from_numpy(rows).cuda(), torch.from_numpy(nhits).cuda())
     tracks = api.Tracks.empty(n, A.PT_FIT_F32_F64SOLVE)
@@ -712,7 +797,7 @@ def profile_fit_run(args):
     from synth import events as E
 
     ts = E.config4(n_tracks=args.fit_tracks)
-    cfg = A.make_config(C.default_config())
+    cfg = A.make_config(C.default_config(exclusive_hits=1))
     hits = api.Hits.from_host(ts.hits)
     n = len(ts.nhits)
     tup = api.Tuplets.from_rows(torch.from_numpy(ts.tuplets).cuda(), torch.from_numpy(ts.nhits).cuda())
@@ -734,6 +819,42 @@ def profile_fit_run(args):
         dst.copy_(src)
     torch.cuda.synchronize()
     log("profile copies done (2^30 bytes read and written each)")
+
+
+def profile_workflows_run(args):
+    """Two eager passes of each workflow on the PU200 batch (reconstruction,
+    fit with covariance, ambiguity resolution, vertices), with the bench's
+    fixed settings, for kernel traces of the stages after the fit."""
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from synth import config as C
+    from synth import events as E
+
+    h = E.config5(n_events=args.events)
+    hits = api.Hits.from_host(h)
+    perf = dict(n_phi_bins=args.bins or 512, block_doublets=args.block_doublets or 64,
+                block_links=args.block_links or 64)
+    for min_hits in (4, 3):
+        cfg_d = C.default_config(min_hits=min_hits)
+        cp = caps(h.n_hits, h.n_events)
+        if min_hits == 3:
+            cp["tuplets_cap"] = 24 * h.n_hits
+        pipe = api.Pipeline(cfg_d, precision=A.PT_FIT_F32_F64SOLVE, **perf, **cp)
+        pipe.tracks = api.Tracks.empty(cp["tuplets_cap"], pipe.precision, with_cov=True)
+        sel = torch.empty(cp["tuplets_cap"], dtype=torch.int32, device="cuda")
+        vtx = api.Vertices.empty(cp["tuplets_cap"], h.n_events, cp["tuplets_cap"])
+        for rep in range(2):
+            pipe.reconstruct(hits)
+            sel, nsel = api.resolve_ambiguities(hits, pipe.cfg, pipe.cells, pipe.tuplets, pipe.precision,
+                                                pipe.tracks, pipe.status, pipe.ws)
+            api.find_vertices(hits, pipe.cfg, pipe.tuplets, pipe.precision, pipe.tracks, sel, nsel, vtx,
+                              pipe.status, pipe.ws)
+            torch.cuda.synchronize()
+            log(f"workflow min_hits={min_hits} pass {rep}: flags {pipe.flags()}, {int(vtx.count.item())} vertices")
+        del pipe, vtx, sel
+        torch.cuda.empty_cache()
 
 
 def profile_run(args):
@@ -790,6 +911,9 @@ def main():
     ap.add_argument("--profile-fit", action="store_true",
                     help="only two eager passes of the fit workload (forward + adjoint) and two 1 GiB copies, for "
                          "profiler counter runs; prints no JSON")
+    ap.add_argument("--profile-workflows", action="store_true",
+                    help="only two eager passes of each workflow (quadruplets, triplets) with ambiguity resolution "
+                         "and vertices, for kernel traces; prints no JSON")
     ap.add_argument("--profile", action="store_true",
                     help="only two eager passes of the batched step (reconstruction + adjoint) and two 1 GiB "
                          "copies, for profiler counter runs; prints no JSON")
@@ -811,6 +935,9 @@ def main():
         return
     if args.profile_fit:
         profile_fit_run(args)
+        return
+    if args.profile_workflows:
+        profile_workflows_run(args)
         return
     chain = chain_workload(args)
     fit = fit_workload(args)
@@ -872,9 +999,11 @@ def main():
         "tracks_per_s": cnt["tracks"] / chain["t_batched"],
         "counts_per_batch": cnt,
         "kernel_ms": kern,
+        "kernel_ns_per_doublet": {k: v * 1e6 / cnt["doublets"] for k, v in kern.items()},
         "roofline": roof,
         "fit": fit_obj,
         "workflows": chain["workflows"],
+        "fishbone": chain["fishbone"],
         "table2_per_event": chain["table2"],
     }
     if not args.no_cpu_baseline:

@@ -160,6 +160,11 @@ typedef struct {
   double vtx_pt_cap;                  /* p_T cap in the sum of p_T^2 that orders the vertices (GeV) */
   /* Fishbone (section 3.3), see pt_build_doublets; 0 = off */
   double fishbone_theta;              /* largest sine of the angle between two aligned doublets */
+  /* 1: no hit belongs to two of the n-tuplets given to pt_fit_broken_line_bwd
+   * (nor twice to one), so the adjoint may add into grad_hits with plain loads
+   * and stores instead of atomic additions (the same sums); results are
+   * undefined when hits are shared.  0: atomic additions. */
+  int32_t exclusive_hits;
 } pt_config;
 
 /* Hits of n_events events.  Event e owns hits [event_offsets[e], event_offsets[e+1]). */

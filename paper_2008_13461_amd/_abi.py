@@ -82,6 +82,7 @@ class pt_config(ct.Structure):
         ("vtx_split_chi2_ndf", ct.c_double),
         ("vtx_pt_cap", ct.c_double),
         ("fishbone_theta", ct.c_double),
+        ("exclusive_hits", ct.c_int32),
     ]
 
 
@@ -274,6 +275,6 @@ def make_config(cfg: dict, *, n_phi_bins: int = 0, block_doublets: int = 0, bloc
     c.block_links = block_links
     c.f64_solve_threshold = f64_solve_threshold
     for k in ("vtx_min_hits", "vtx_kmeans_iter", "vtx_pt_min", "vtx_err_max", "vtx_dz_cut", "vtx_chi2_max",
-              "vtx_split_chi2_ndf", "vtx_pt_cap", "fishbone_theta"):
+              "vtx_split_chi2_ndf", "vtx_pt_cap", "fishbone_theta", "exclusive_hits"):
         setattr(c, k, cfg[k])
     return c

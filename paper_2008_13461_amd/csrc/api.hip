@@ -111,6 +111,8 @@ bool derive_config(const pt_config& c, DevCfg* d) {
   d->vtx_pt_cap = c.vtx_pt_cap;
   if (!(c.fishbone_theta >= 0.0)) return false;
   d->fishbone_theta2 = c.fishbone_theta * c.fishbone_theta;
+  if (c.exclusive_hits != 0 && c.exclusive_hits != 1) return false;
+  d->exclusive_hits = c.exclusive_hits;
   return true;
 }
 #pragma clang fp contract(on)

@@ -28,6 +28,7 @@ constexpr int kMinN = 3;
 constexpr int kNBins = kMaxHits - kMinN + 1;  // N = 3..8
 constexpr int kBlock = 256;
 constexpr int kBwdBlocks = 256;
+constexpr int kRefitBlock = 64;
 
 struct FitArgs {
   int32_t dtype;
@@ -79,32 +80,71 @@ __host__ __device__ fit::Consts consts_of(const DevCfg& k) {
 __device__ inline int track_row(const FitArgs& a, int i) { return a.kept ? a.kept[i] : i; }
 __device__ inline int n_tracks(const FitArgs& a) { return min(*a.count, a.n_max); }
 
-// Bin tracks by hit count (one atomic per block and bin).
+// Bin tracks by hit count.  Each block owns a contiguous range of tracks:
+// it counts its tracks per bin (ballots), takes its base in each bin with
+// one atomic per bin, then walks its range again placing the tracks (ranks
+// within a wavefront from ballots, per-wave offsets in LDS).  The grid is
+// capped (kBinBlocks) so that few atomics meet on each bin counter.
+constexpr int kBinBlocks = 1024;
+
+__device__ inline int track_bin(const FitArgs& a, int i, int n) {
+  if (i >= n) return -1;
+  const int nh = a.tup_n[track_row(a, i)];
+  return nh >= kMinN && nh <= kMaxHits ? nh - kMinN : -1;
+}
+
 __global__ void __launch_bounds__(kBlock) k_bin(FitArgs a) {
-  __shared__ int32_t s_cnt[kNBins];
-  __shared__ int32_t s_base[kNBins];
+  constexpr int kWaves = kBlock / kWave;
+  __shared__ int32_t s_cnt[kWaves][kNBins];
+  __shared__ int32_t s_run[kNBins];
   const int n = n_tracks(a);
-  const int stride = gridDim.x * kBlock;
-  const int rounds = (n + stride - 1) / stride;
-  for (int r = 0; r < rounds; ++r) {
-    if (threadIdx.x < kNBins) s_cnt[threadIdx.x] = 0;
+  const int lane = __lane_id();
+  const int w = static_cast<int>(threadIdx.x) / kWave;
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  const int per = ((n + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+  const int lo = blockIdx.x * per, hi = min(n, lo + per);
+  // pass 1: counts of the block's range
+  int cnt[kNBins];
+#pragma unroll
+  for (int b = 0; b < kNBins; ++b) cnt[b] = 0;
+  for (int i0 = lo; i0 < hi; i0 += kBlock) {
+    const int bin = track_bin(a, i0 + threadIdx.x, hi);
+#pragma unroll
+    for (int b = 0; b < kNBins; ++b) cnt[b] += __popcll(__ballot(bin == b));
+  }
+  if (lane == 0)
+    for (int b = 0; b < kNBins; ++b) s_cnt[w][b] = cnt[b];
+  __syncthreads();
+  if (threadIdx.x < kNBins) {
+    const int b = threadIdx.x;
+    int c = 0;
+    for (int q = 0; q < kWaves; ++q) c += s_cnt[q][b];
+    s_run[b] = c ? atomicAdd(a.bin_count + b, c) : 0;
+  }
+  __syncthreads();
+  // pass 2: place the tracks in order of the range
+  for (int i0 = lo; i0 < hi; i0 += kBlock) {
+    const int i = i0 + threadIdx.x;
+    const int bin = track_bin(a, i, hi);
+    int rank = 0;
+#pragma unroll
+    for (int b = 0; b < kNBins; ++b) {
+      const uint64_t m = __ballot(bin == b);
+      if (bin == b) rank = __popcll(m & below);
+      if (lane == 0) s_cnt[w][b] = __popcll(m);
+    }
     __syncthreads();
-    const int i = r * stride + blockIdx.x * kBlock + threadIdx.x;
-    int bin = -1, rank = 0;
-    if (i < n) {
-      const int nh = a.tup_n[track_row(a, i)];
-      if (nh >= kMinN && nh <= kMaxHits) {
-        bin = nh - kMinN;
-        rank = atomicAdd(s_cnt + bin, 1);
-      }
+    if (bin >= 0) {
+      int off = s_run[bin];
+      for (int q = 0; q < w; ++q) off += s_cnt[q][bin];
+      a.bins[static_cast<int64_t>(bin) * a.n_max + off + rank] = i;
     }
     __syncthreads();
     if (threadIdx.x < kNBins) {
-      const int c = s_cnt[threadIdx.x];
-      s_base[threadIdx.x] = c ? atomicAdd(a.bin_count + threadIdx.x, c) : 0;
+      int c = 0;
+      for (int q = 0; q < kWaves; ++q) c += s_cnt[q][threadIdx.x];
+      s_run[threadIdx.x] += c;
     }
-    __syncthreads();
-    if (bin >= 0) a.bins[static_cast<int64_t>(bin) * a.n_max + s_base[bin] + rank] = i;
     __syncthreads();
   }
 }
@@ -283,7 +323,7 @@ __global__ void __launch_bounds__(kBlock) k_fit(DevCfg k, FitArgs a, bool fallba
 
 // Double-precision refit of the listed tracks; outputs in OT.
 template <class HT, class OT>
-__global__ void k_refit(DevCfg k, FitArgs a) {
+__global__ void __launch_bounds__(kRefitBlock) k_refit(DevCfg k, FitArgs a) {
   const fit::Consts C = consts_of(k);
   const int m = *a.redo_count;
   uint32_t n_bad = 0, n_fail = 0, n_redo = 0;
@@ -350,9 +390,15 @@ __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const Fit
   for (int kk = 0; kk < N; ++kk) {
     if (a.grad_hits) {
       GT* gh = static_cast<GT*>(a.grad_hits) + static_cast<int64_t>(hit[kk]) * 3;
-      unsafeAtomicAdd(gh + 0, GT(gP[kk][0]));
-      unsafeAtomicAdd(gh + 1, GT(gP[kk][1]));
-      unsafeAtomicAdd(gh + 2, GT(gP[kk][2]));
+      if (k.exclusive_hits) {  // the row is this track's alone
+        gh[0] += GT(gP[kk][0]);
+        gh[1] += GT(gP[kk][1]);
+        gh[2] += GT(gP[kk][2]);
+      } else {
+        unsafeAtomicAdd(gh + 0, GT(gP[kk][0]));
+        unsafeAtomicAdd(gh + 1, GT(gP[kk][1]));
+        unsafeAtomicAdd(gh + 2, GT(gP[kk][2]));
+      }
     }
     if (lds_mod) {
       double* lm = lds_mod + 3 * mod[kk];
@@ -432,13 +478,27 @@ __global__ void __launch_bounds__(kBlock) k_regrad(DevCfg k, FitArgs a) {
   if (nm3) lds_flush<false>(lds_mod, nm3, any, a.partials + static_cast<int64_t>(blockIdx.x) * nm3);
 }
 
-// grad_offsets[q] += sum over blocks of partials[b][q], in block order.
-__global__ void k_reduce_modules(const double* __restrict__ partials, int nm3, int nblocks,
-                                 double* __restrict__ out) {
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nm3; q += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partials[static_cast<int64_t>(b) * nm3 + q];
-    out[q] += s;
+// grad_offsets[q] += sum over blocks of partials[b][q]: each of the
+// kRedWaves wavefronts of a block sums the rows b = w, w + kRedWaves, ... of
+// 64 consecutive q in order, and the wavefronts' sums are added in order
+// (a fixed order, the same on every run).
+constexpr int kRedWaves = 16;
+
+__global__ void __launch_bounds__(kRedWaves * kWave) k_reduce_modules(const double* __restrict__ partials, int nm3,
+                                                                      int nblocks, double* __restrict__ out) {
+  __shared__ double s_part[kRedWaves][kWave];
+  const int lane = __lane_id();
+  const int w = static_cast<int>(threadIdx.x) / kWave;
+  const int q = blockIdx.x * kWave + lane;
+  double s = 0.0;
+  if (q < nm3)
+    for (int b = w; b < nblocks; b += kRedWaves) s += partials[static_cast<int64_t>(b) * nm3 + q];
+  s_part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && q < nm3) {
+    double t = 0.0;
+    for (int v = 0; v < kRedWaves; ++v) t += s_part[v][lane];
+    out[q] += t;
   }
 }
 
@@ -489,7 +549,7 @@ static FitArgs make_args(const pt_hits& h, const DevCfg& k, const pt_ntuplets& T
 static pt_err prepare(FitArgs& a, hipStream_t s) {
   PT_HIP_CHECK(fill_i32(a.bin_count, 0, kNBins, s));
   PT_HIP_CHECK(fill_i32(a.redo_count, 0, 1, s));
-  k_bin<<<fit_grid(a.n_max), kBlock, 0, s>>>(a);
+  k_bin<<<std::min(fit_grid(a.n_max), kBinBlocks), kBlock, 0, s>>>(a);
   PT_LAUNCH_CHECK();
   return PT_OK;
 }
@@ -509,7 +569,8 @@ static pt_err run_fit(const DevCfg& k, FitArgs& a, bool fallback, hipStream_t s)
   }
   PT_LAUNCH_CHECK();
   if (fallback) {
-    k_refit<HT, OT><<<64, 64, 0, s>>>(k, a);
+    // one thread per refitted track (a few percent of the tracks)
+    k_refit<HT, OT><<<grid_for(a.n_max / 16 + 1, kRefitBlock, 1024), kRefitBlock, 0, s>>>(k, a);
     PT_LAUNCH_CHECK();
   }
   return PT_OK;
@@ -551,7 +612,8 @@ static pt_err run_grad(const DevCfg& k, FitArgs& a, bool fallback, double* grad_
     PT_LAUNCH_CHECK();
   }
   if (a.partials) {
-    k_reduce_modules<<<grid_for(nm3, 256), 256, 0, s>>>(a.partials, nm3, kBwdBlocks, grad_offsets);
+    k_reduce_modules<<<(nm3 + kWave - 1) / kWave, kRedWaves * kWave, 0, s>>>(a.partials, nm3, kBwdBlocks,
+                                                                         grad_offsets);
     PT_LAUNCH_CHECK();
   }
   return PT_OK;

@@ -164,7 +164,7 @@ static_assert((kIndexChunk & (kIndexChunk - 1)) == 0, "hash table size must be a
 // segment of its outer hit's in-cell list: the hit's segment count is taken
 // with one global atomic per group, and the segment itself is placed by
 // k_seg_scatter once the counts are scanned.  has_inner and the link counts
-// are cleared here.
+// are cleared here (when given).
 //
 // Every global load and atomic of the block is issued before its first
 // global store: on this architecture one counter tracks loads and stores
@@ -290,13 +290,15 @@ __global__ void __launch_bounds__(kIndexBlock) k_cell_index(IndexArgs a) {
     e.h0b = s_h0b[loc];
     a.ent[base + i] = e;
   }
+  if (a.has_inner) {
 #pragma unroll
-  for (int u = 0; u < kIndexItems; ++u) {
-    const int loc = u * kIndexBlock + threadIdx.x;
-    if (loc >= m) break;
-    const int c = static_cast<int>(base) + loc;
-    a.has_inner[c] = 0;
-    a.out_count[c] = 0;
+    for (int u = 0; u < kIndexItems; ++u) {
+      const int loc = u * kIndexBlock + threadIdx.x;
+      if (loc >= m) break;
+      const int c = static_cast<int>(base) + loc;
+      a.has_inner[c] = 0;
+      a.out_count[c] = 0;
+    }
   }
 }
 
@@ -965,6 +967,55 @@ __global__ void k_finish_links(const int32_t* count, int32_t cap, uint32_t* stat
 }
 
 }  // namespace
+
+// The index of the stored cells by outer hit alone (for the Fishbone), in
+// the workspace from its start; returns the bytes it takes.
+static size_t carve_outer_index(Carver& c, int n_hits, int cells_cap, OuterIndex* out, InCell** ent, int4** grp,
+                                int32_t** n_grp, int32_t** tmp) {
+  const int64_t scan_n = std::max<int64_t>(n_hits, cells_cap);
+  const int64_t chunks = std::max<int64_t>(1, (static_cast<int64_t>(cells_cap) + kIndexChunk - 1) / kIndexChunk);
+  InCell* e = c.take<InCell>(cells_cap);
+  int4* g = c.take<int4>(cells_cap);
+  int32_t* ng = c.take<int32_t>(chunks);
+  int32_t* sf = c.take<int32_t>(static_cast<size_t>(n_hits) + 1);
+  int2* sg = c.take<int2>(cells_cap);
+  int32_t* t = c.take<int32_t>(scan_tmp_elems(scan_n));
+  if (out) {
+    out->ent = reinterpret_cast<const int2*>(e);
+    out->seg = sg;
+    out->seg_first = sf;
+    *ent = e;
+    *grp = g;
+    *n_grp = ng;
+    *tmp = t;
+  }
+  return c.off;
+}
+
+size_t ws_outer_index(int n_hits, int cells_cap) {
+  Carver c(nullptr);
+  return carve_outer_index(c, n_hits, cells_cap, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+pt_err build_outer_index(const pt_hits& h, const pt_cells& cells, Carver& c, OuterIndex& out, hipStream_t s) {
+  const int n = h.n_hits;
+  const int64_t chunks = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kIndexChunk - 1) / kIndexChunk);
+  InCell* ent = nullptr;
+  int4* grp = nullptr;
+  int32_t *n_grp = nullptr, *tmp = nullptr;
+  carve_outer_index(c, n, cells.cap, &out, &ent, &grp, &n_grp, &tmp);
+  int32_t* seg_first = const_cast<int32_t*>(out.seg_first);
+  PT_HIP_CHECK(fill_i32(seg_first, 0, static_cast<int64_t>(n) + 1, s));
+  IndexArgs g{cells.count, cells.cap, cells.inner, cells.outer, h.layer, ent, grp, n_grp, seg_first, nullptr,
+              nullptr};
+  k_cell_index<<<static_cast<unsigned>(chunks), kIndexBlock, 0, s>>>(g);
+  PT_LAUNCH_CHECK();
+  PT_HIP_CHECK(exclusive_scan(seg_first, n, tmp, s));
+  k_seg_scatter<<<static_cast<unsigned>(chunks), kScatterBlock, 0, s>>>(cells.count, cells.cap, grp, n_grp, seg_first,
+                                                                       const_cast<int2*>(out.seg));
+  PT_LAUNCH_CHECK();
+  return PT_OK;
+}
 
 size_t ws_links(int n_hits, int cells_cap) {
   const int64_t scan_n = std::max<int64_t>(n_hits, cells_cap);

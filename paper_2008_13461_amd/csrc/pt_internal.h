@@ -55,6 +55,8 @@ struct DevCfg {
   double vtx_pt_min, vtx_err_max, vtx_dz_cut, vtx_chi2_max, vtx_split_chi2_ndf, vtx_pt_cap;
   // Fishbone (0: off)
   double fishbone_theta2;
+  // adjoint: grad_hits rows are written by one track each
+  int32_t exclusive_hits;
 };
 
 bool derive_config(const pt_config& c, DevCfg* d);
@@ -81,6 +83,18 @@ size_t ws_ntuplets(int cells_cap, int tuplets_cap);
 size_t ws_fit(int n_max, int n_modules);
 size_t ws_ambiguity(int n_hits, int cells_cap, int n_max);
 size_t ws_fishbone(int n_hits, int cells_cap);
+
+// The index of the stored cells by outer hit (links.hip): hit h's cells are
+// the entries ent[f .. f + k) (cell, inner hit with bit 31 set when on
+// BPix1) of its segments (f, k) = seg[seg_first[h] .. seg_first[h + 1]).
+// The cells must not have overflowed their capacity.
+struct OuterIndex {
+  const int2* ent;
+  const int2* seg;
+  const int32_t* seg_first;
+};
+size_t ws_outer_index(int n_hits, int cells_cap);
+pt_err build_outer_index(const pt_hits& h, const pt_cells& cells, Carver& c, OuterIndex& out, hipStream_t s);
 size_t ws_vertices(int n_events, int n_max);
 
 // Device-wide exclusive scan of n int32 values in place; data[n] receives the
@@ -146,6 +160,22 @@ __device__ inline uint32_t wave_status_add(uint32_t* st, int word, uint32_t v) {
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
   if (__lane_id() == 0) status_add(st, word, v);
+  return v;
+}
+
+// Sum and inclusive prefix sum over the wavefront; all lanes must call them.
+__device__ inline int wave_sum(int v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+__device__ inline int wave_incl_scan(int v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
   return v;
 }
 

@@ -155,6 +155,9 @@ def default_config(**overrides) -> dict:
       fishbone_theta    Fishbone (section 3.3): largest sine of the angle between
                         two doublets sharing their outer hit for which the longer
                         one is dropped; 0 turns the Fishbone off
+      exclusive_hits    1 when no hit belongs to two of the tracks given to the
+                        adjoint (the fit workload), so that it may add into the
+                        hit gradients without atomics; 0 otherwise
     """
     bfield = 3.8
     pt_min = 0.45
@@ -195,6 +198,7 @@ def default_config(**overrides) -> dict:
         "vtx_pt_cap": 75.0,
         "vtx_kmeans_iter": 10,
         "fishbone_theta": 0.0,
+        "exclusive_hits": 0,
     }
     for k, v in overrides.items():
         if k not in cfg:

@@ -38,7 +38,7 @@ _STRUCTS = {
     "pt_config": ["bfield", "n_pairs", "pair_inner", "pair_dphi", "pt_min", "cut_mask", "ca_rmax_other",
                   "root_always_mask", "min_hits", "layer_barrel", "x_over_x0", "p_cap", "n_modules", "n_phi_bins",
                   "block_links", "f64_solve_threshold", "vtx_min_hits", "vtx_kmeans_iter", "vtx_pt_min",
-                  "vtx_pt_cap", "fishbone_theta"],
+                  "vtx_pt_cap", "fishbone_theta", "exclusive_hits"],
     "pt_hits": ["n_hits", "n_events", "event_offsets", "dtype", "x", "layer", "module"],
     "pt_workspace": ["ptr", "bytes"],
     "pt_cells": ["cap", "inner", "pair", "count", "inner_first", "inner_count", "seg"],

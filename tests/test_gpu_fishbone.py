@@ -132,3 +132,39 @@ def test_fishbone_in_a_plan_replays_equal_the_eager_chain():
         ref.reconstruct(hits)           # eager work between the replays
         torch.cuda.synchronize()
     del plan
+
+
+def test_fishbone_of_outer_hits_with_many_cells():
+    """BPix2 hits reached from 3600, 600 and 200 BPix1 hits (pairs 1 µm apart
+    in z, and neighbours within the cut angle): more cells than a work-group
+    stages (all pairs from global memory), more than a wavefront stages (one
+    work-group for the hit) and fewer (one wavefront); against the oracle."""
+    _need_gpu()
+    from tests.gpu_helpers import run_chain
+    rng = np.random.default_rng(7)
+    xs, ys, zs, ls = [], [], [], []
+    for phi_o, npair in ((0.0, 300), (1.0, 100), (2.0, 1800)):
+        xs.append(6.8 * np.cos(phi_o))
+        ys.append(6.8 * np.sin(phi_o))
+        zs.append(0.3)
+        ls.append(1)
+        for _ in range(npair):
+            z, dphi = rng.uniform(-4, 4), rng.uniform(-0.005, 0.005)
+            for dz in (0.0, 1e-4):
+                xs.append(2.9 * np.cos(phi_o + dphi))
+                ys.append(2.9 * np.sin(phi_o + dphi))
+                zs.append(z + dz)
+                ls.append(0)
+    n = len(xs)
+    h = E.Hits(np.array(xs, np.float32), np.array(ys, np.float32), np.array(zs, np.float32),
+               np.array(ls, np.uint8), np.zeros(n, np.int16), np.full(n, -1, np.int32),
+               np.array([0, n], np.int32))
+    ri, ro, _ = O.doublets(FB, h.x, h.y, h.z, h.layer)
+    per_hit = np.bincount(ro)
+    assert per_hit.max() > 3072 and np.any((per_hit > 512) & (per_hit <= 3072))
+    keep = O.fishbone(FB, h.x, h.y, h.z, ri, ro)
+    assert 0 < keep.sum() < len(keep) // 2
+    pipe, _ = run_chain(h, FB)
+    ci, co, _ = (t.cpu().numpy() for t in pipe.cells.valid())
+    assert doublet_set(ci, co) == doublet_set(ri[keep], ro[keep])
+    _inner_index_ok(pipe, h.n_hits)

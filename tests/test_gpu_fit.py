@@ -20,10 +20,10 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _run_fit(ts, precision, offsets, with_grad=False, g=None):
+def _run_fit(ts, precision, offsets, with_grad=False, g=None, cfg_d=CFG):
     from paper_2008_13461_amd import _abi as A
     from paper_2008_13461_amd import api
-    cfg = A.make_config(CFG)
+    cfg = A.make_config(cfg_d)
     h = ts.hits
     hits = api.Hits.from_host(h)
     n = ts.nhits.shape[0]
@@ -105,6 +105,22 @@ def test_adjoint_against_dual_numbers(precision_name, tol):
     assert worst <= tol
     scale = np.abs(go_ref).max()
     assert np.abs(got["grad_offsets"] - go_ref).max() <= tol * scale
+
+
+@pytest.mark.parametrize("precision_name", ["PT_FIT_F64", "PT_FIT_F32_F64SOLVE"])
+def test_adjoint_with_exclusive_hits_equals_the_atomic_one(tracks200k, precision_name):
+    """exclusive_hits = 1 (plain additions into grad_hits, for tracks that
+    share no hit, as here) gives the atomic additions' gradients bit for bit."""
+    _need_gpu()
+    from paper_2008_13461_amd import _abi as A
+    precision = getattr(A, precision_name)
+    ts, off = tracks200k
+    g = E.cotangents(4, len(ts.nhits))
+    a = _run_fit(ts, precision, off, with_grad=True, g=g)
+    b = _run_fit(ts, precision, off, with_grad=True, g=g, cfg_d=C.default_config(exclusive_hits=1))
+    assert np.array_equal(a["grad_hits"], b["grad_hits"])
+    assert np.array_equal(a["params"], b["params"])
+    assert np.allclose(a["grad_offsets"], b["grad_offsets"], rtol=1e-12, atol=1e-12 * np.abs(a["grad_offsets"]).max())
 
 
 def test_bad_and_short_tracks():
