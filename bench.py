@@ -821,6 +821,31 @@ def profile_fit_run(args):
     log("profile copies done (2^30 bytes read and written each)")
 
 
+def profile_fishbone_run(args):
+    """Two eager doublet passes with the Fishbone on the PU200 batch of the
+    overlap geometry, for kernel traces of the Fishbone."""
+    import torch
+
+    from paper_2008_13461_amd import _abi as A
+    from paper_2008_13461_amd import api
+    from synth import config as C
+    from synth import events as E
+
+    h = E.overlap_batch(n_events=args.events, pileup=200)
+    hits = api.Hits.from_host(h)
+    cp = caps(h.n_hits, h.n_events)
+    cfg = A.make_config(C.default_config(fishbone_theta=0.01), n_phi_bins=args.bins or 512,
+                        block_doublets=args.block_doublets or 64, block_links=args.block_links or 64)
+    cells = api.Cells.empty(cp["cells_cap"], h.n_hits)
+    status = api.new_status()
+    ws = api.new_workspace(api.workspace_size(cfg, h.n_hits, h.n_events, cp["cells_cap"], cp["links_cap"],
+                                              cp["tuplets_cap"]))
+    for rep in range(2):
+        api.build_doublets(hits, cfg, cells, status, ws)
+        torch.cuda.synchronize()
+        log(f"Fishbone pass {rep}: {int(cells.count.item())} doublets kept, flags {int(status[0].item())}")
+
+
 def profile_workflows_run(args):
     """Two eager passes of each workflow on the PU200 batch (reconstruction,
     fit with covariance, ambiguity resolution, vertices), with the bench's
@@ -911,6 +936,9 @@ def main():
     ap.add_argument("--profile-fit", action="store_true",
                     help="only two eager passes of the fit workload (forward + adjoint) and two 1 GiB copies, for "
                          "profiler counter runs; prints no JSON")
+    ap.add_argument("--profile-fishbone", action="store_true",
+                    help="only two eager doublet passes with the Fishbone on the overlap-geometry PU200 batch, for "
+                         "kernel traces; prints no JSON")
     ap.add_argument("--profile-workflows", action="store_true",
                     help="only two eager passes of each workflow (quadruplets, triplets) with ambiguity resolution "
                          "and vertices, for kernel traces; prints no JSON")
@@ -938,6 +966,9 @@ def main():
         return
     if args.profile_workflows:
         profile_workflows_run(args)
+        return
+    if args.profile_fishbone:
+        profile_fishbone_run(args)
         return
     chain = chain_workload(args)
     fit = fit_workload(args)

@@ -31,7 +31,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kCap = 512;      // cells per outer hit staged in LDS
+constexpr int kCapSmall = 256;  // cells per outer hit staged in LDS by the first kernel
+constexpr int kCap = 512;       // by the second (the hits with more than kCapSmall)
 constexpr int kNB = 128;       // most key buckets
 constexpr int32_t kHitMask = 0x7fffffff;
 
@@ -44,6 +45,7 @@ struct FbArgs {
   double theta2;
   int32_t nb;             // key buckets: each at least the cut angle wide
   float kwin;             // key window: asin(theta) with a margin, 2 when theta >= 1
+  float phwin;            // azimuth window of vectors at least kS0 transverse, > pi: none
   const int32_t* count;   // cells found
   int32_t cap;
   int32_t* inner;
@@ -55,6 +57,8 @@ struct FbArgs {
   OuterIndex idx;
   // workspace
   int32_t* keep;          // [cap + 1] flags, then positions
+  int32_t* mid;           // [n_hits] outer hits with more than kCapSmall cells
+  int32_t* n_mid;
   int32_t* big;           // [n_hits] outer hits with more than kCap cells
   int32_t* n_big;
   int32_t* t_inner;       // [cap] compacted copies
@@ -80,6 +84,25 @@ __device__ inline float polar_key(double ux, double uy, double uz) {
   const float t = sqrtf(float(ux * ux + uy * uy));
   const float l = t + fabsf(float(uz));
   return l > 0.f ? float(uz) / l : 0.f;
+}
+
+// Azimuth of a vector whose transverse part is at least kS0 of its length,
+// else kNoPhi.  Two such vectors at an angle a <= kS0 have transverse parts
+// at most a apart, hence azimuths at most asin(a / kS0) apart (for nearly
+// opposite vectors, pi minus that).
+constexpr float kS0 = 0.2f;
+constexpr float kNoPhi = 10.f;
+__device__ inline float azimuth(double ux, double uy, double uz) {
+  const float t2 = float(ux * ux + uy * uy), l2 = t2 + float(uz * uz);
+  return t2 >= (kS0 * kS0) * l2 ? atan2f(float(uy), float(ux)) : kNoPhi;
+}
+
+// Whether two azimuths allow an angle within the cut (opp: nearly opposite).
+__device__ inline bool phi_ok(float pi, float pj, float win, bool opp) {
+  if (pi == kNoPhi || pj == kNoPhi) return true;
+  float d = fabsf(pi - pj);
+  if (d > 3.14159265f) d = 6.28318531f - d;
+  return (opp ? 3.14159265f - d : d) <= win;
 }
 
 // Bucket of a key in [-1, 1] among nb buckets of width 2 / nb.
@@ -114,19 +137,26 @@ __global__ void k_fb_flags(FbArgs<T> a) {
 }
 
 // One wavefront per outer hit.
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_fb_kill(FbArgs<T> a) {
-  __shared__ int32_t s_bin[kWaves][kNB + 1];   // cells per key bucket, then first position
-  __shared__ int32_t s_bk[kWaves][kCap];       // per staged cell: bucket | rank in it << 16
-  __shared__ int32_t s_val[kWaves][kCap];      // staged cells in bucket order
-  __shared__ int32_t s_cell[kWaves][kCap];
-  __shared__ T s_x[kWaves][kCap];            // the inner hit's coordinates
-  __shared__ T s_y[kWaves][kCap];
-  __shared__ T s_z[kWaves][kCap];
+// CAP cells per wavefront, WAVES wavefronts per block.  Every outer hit (one
+// wavefront each) when LISTED is false, else the hits listed in a.mid (a
+// persistent grid); hits with more than CAP cells are listed for the next
+// kernel (a.mid, then a.big).
+template <class T, int CAP, int WAVES, bool LISTED>
+__global__ void __launch_bounds__(WAVES * kWave) k_fb_kill(FbArgs<T> a) {
+  __shared__ int32_t s_bin[WAVES][kNB + 1];   // cells per key bucket, then first position
+  __shared__ int32_t s_bk[WAVES][CAP];        // per staged cell: bucket | rank in it << 16
+  __shared__ int32_t s_val[WAVES][CAP];       // staged cells in bucket order
+  __shared__ int32_t s_cell[WAVES][CAP];
+  __shared__ float s_phi[WAVES][CAP];
+  __shared__ T s_x[WAVES][CAP];               // the inner hit's coordinates
+  __shared__ T s_y[WAVES][CAP];
+  __shared__ T s_z[WAVES][CAP];
   const int w = static_cast<int>(threadIdx.x) / kWave;
-  const int h = blockIdx.x * kWaves + w;
   const int lane = __lane_id();
-  if (h >= a.n_hits || stored(a) == 0) return;
+  if (stored(a) == 0) return;
+  const int n_items = LISTED ? *a.n_mid : a.n_hits;
+  for (int item = blockIdx.x * WAVES + w; item < n_items; item += LISTED ? gridDim.x * WAVES : n_items) {
+  const int h = LISTED ? a.mid[item] : item;
   const int sb = a.idx.seg_first[h], se = a.idx.seg_first[h + 1];
   // the hit's cells: segment descriptors 64 at a time, then their entries
   // 64 at a time (each lane finds its entry's segment among the 64)
@@ -135,12 +165,21 @@ __global__ void __launch_bounds__(kBlock) k_fb_kill(FbArgs<T> a) {
     const int n = s0 + lane < se ? a.idx.seg[s0 + lane].y : 0;
     m += wave_sum(n);
   }
-  if (m < 2) return;
+  if (m < 2) continue;
   const double Xh = double(a.x[h]), Yh = double(a.y[h]), Zh = double(a.z[h]);
-  if (m > kCap) {  // more cells than a wavefront stages: listed for k_fb_kill_big
-    if (lane == 0) a.big[atomicAdd(a.n_big, 1)] = h;
-    return;
+  if (m > CAP) {  // more cells than this kernel stages: listed for the next
+    if (lane == 0) {
+      if (LISTED) a.big[atomicAdd(a.n_big, 1)] = h;
+      else a.mid[atomicAdd(a.n_mid, 1)] = h;
+    }
+    continue;
   }
+  const float win = a.kwin;
+  const double rh = sqrt(Xh * Xh + Yh * Yh);
+  const double nx = rh > 0.0 ? Xh / rh : 0.0, ny = rh > 0.0 ? Yh / rh : 0.0;
+  const float zs = Zh < 0.0 ? -1.f : 1.f;
+  float rmin = 2.f, zmin = 2.f;  // smallest radial and z-side keys of the lane's cells
+  wave_sync();  // the previous hit's LDS is no longer read
   for (int b = lane; b <= a.nb; b += kWave) s_bin[w][b] = 0;
   wave_sync();
   int at = 0;
@@ -167,11 +206,25 @@ __global__ void __launch_bounds__(kBlock) k_fb_kill(FbArgs<T> a) {
       s_x[w][at + f] = hx;
       s_y[w][at + f] = hy;
       s_z[w][at + f] = hz;
-      const int b = bucket(polar_key(Xh - double(hx), Yh - double(hy), Zh - double(hz)), a.nb);
+      const double ux = Xh - double(hx), uy = Yh - double(hy), uz = Zh - double(hz);
+      s_phi[w][at + f] = azimuth(ux, uy, uz);
+      const float kz = polar_key(ux, uy, uz);
+      const int b = bucket(kz, a.nb);
       s_bk[w][at + f] = b | (atomicAdd(&s_bin[w][b], 1) << 16);
+      // key of the vector about the outer hit's transverse direction
+      const double ur = ux * nx + uy * ny;
+      const double ox = ux - ur * nx, oy = uy - ur * ny;
+      const float lr = sqrtf(float(ox * ox + oy * oy + uz * uz)) + fabsf(float(ur));
+      rmin = fminf(rmin, lr > 0.f ? float(ur) / lr : 0.f);
+      zmin = fminf(zmin, kz * zs);
     }
     at += tot;
   }
+  // nearly opposite partners are possible only when neither family of keys
+  // stays above the cut angle for every cell of the hit (two nearly opposite
+  // vectors cannot both point away from the beam line, or both along the
+  // outer hit's side of z, by more than the cut angle)
+  const bool mirror = wave_min(rmin) <= win && wave_min(zmin) <= win;
   wave_sync();
   // counting sort by bucket: first positions (a scan over the buckets), then
   // each staged cell at its bucket's first position plus its rank
@@ -193,27 +246,29 @@ __global__ void __launch_bounds__(kBlock) k_fb_kill(FbArgs<T> a) {
   }
   wave_sync();
   // each cell against the cells of its bucket and the two next to it, and of
-  // the buckets around its negated key (nearly opposite vectors); the exact
-  // test from the staged coordinates
+  // the buckets around its negated key (nearly opposite vectors); the
+  // azimuth test first, the exact test from the staged coordinates last
+  const float phw = a.phwin;
   for (int i = lane; i < m; i += kWave) {
     const double ux = Xh - double(s_x[w][i]), uy = Yh - double(s_y[w][i]), uz = Zh - double(s_z[w][i]);
     const double U2 = (ux * ux + uy * uy) + uz * uz;
     bool killed = false;
     const int nb = a.nb;
     const float ki = polar_key(ux, uy, uz);  // the staged key, recomputed
-    const int b = bucket(ki, nb), bn = bucket(-ki, nb);
-    for (int pass = 0; pass < 2 && !killed; ++pass) {
-      const int c = pass == 0 ? b : bn;
+    const float pi = s_phi[w][i];
+    for (int pass = 0; pass < (mirror ? 2 : 1) && !killed; ++pass) {
+      const int c = bucket(pass == 0 ? ki : -ki, nb);
       const int q0 = s_bin[w][max(c - 1, 0)], q1 = s_bin[w][min(c + 2, nb)];
       for (int q = q0; q < q1 && !killed; ++q) {
         const int j = s_val[w][q];
-        if (j == i) continue;
+        if (j == i || !phi_ok(pi, s_phi[w][j], phw, pass == 1)) continue;
         const double vx = Xh - double(s_x[w][j]), vy = Yh - double(s_y[w][j]), vz = Zh - double(s_z[w][j]);
         const double V2 = (vx * vx + vy * vy) + vz * vz;
         killed = kills(ux, uy, uz, U2, vx, vy, vz, V2, a.theta2);
       }
     }
     if (killed) a.keep[s_cell[w][i]] = 0;
+  }
   }
 }
 
@@ -361,6 +416,8 @@ __global__ void k_fb_set_count(FbArgs<T> a, int32_t* count) {
 template <class T>
 void carve_rest(Carver& c, FbArgs<T>* a, int cap, int n_hits, int32_t** tmp) {
   a->keep = c.take<int32_t>(static_cast<size_t>(cap) + 1);
+  a->mid = c.take<int32_t>(static_cast<size_t>(n_hits));
+  a->n_mid = c.take<int32_t>(1);
   a->big = c.take<int32_t>(static_cast<size_t>(n_hits));
   a->n_big = c.take<int32_t>(1);
   a->t_inner = c.take<int32_t>(static_cast<size_t>(cap));
@@ -390,6 +447,7 @@ pt_err run_fishbone(const pt_hits& h, const DevCfg& k, pt_cells& cells, void* ws
     const double win = th >= 1.0 ? 2.0 : std::asin(th) + 1e-5;
     a.nb = static_cast<int32_t>(std::min<double>(kNB, std::max(1.0, std::floor(2.0 / (win * 1.01)))));
     a.kwin = static_cast<float>(win * 1.001);
+    a.phwin = win < 0.9 * kS0 ? static_cast<float>(std::asin(win / kS0) * 1.01 + 1e-5) : 4.f;
   }
   a.count = cells.count;
   a.cap = cap;
@@ -406,8 +464,10 @@ pt_err run_fishbone(const pt_hits& h, const DevCfg& k, pt_cells& cells, void* ws
   const int gc = grid_for(cap, kBlock);
   const int gh = grid_for(n_hits + 1, kBlock);
   PT_HIP_CHECK(fill_i32(a.n_big, 0, 1, s));
+  PT_HIP_CHECK(fill_i32(a.n_mid, 0, 1, s));
   k_fb_flags<T><<<gc, kBlock, 0, s>>>(a);
-  k_fb_kill<T><<<static_cast<unsigned>((n_hits + kWaves - 1) / kWaves), kBlock, 0, s>>>(a);
+  k_fb_kill<T, kCapSmall, kWaves, false><<<static_cast<unsigned>((n_hits + kWaves - 1) / kWaves), kBlock, 0, s>>>(a);
+  k_fb_kill<T, kCap, 2, true><<<1024, 2 * kWave, 0, s>>>(a);
   k_fb_kill_big<T><<<256, kBigBlock, 0, s>>>(a);
   PT_LAUNCH_CHECK();
   PT_HIP_CHECK(exclusive_scan_dev(a.keep, cap, cells.count, tmp, s));

@@ -169,6 +169,11 @@ __device__ inline int wave_sum(int v) {
   for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
   return v;
 }
+__device__ inline float wave_min(float v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, kWave));
+  return v;
+}
 __device__ inline int wave_incl_scan(int v) {
   const int lane = __lane_id();
 #pragma unroll
