@@ -33,7 +33,7 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kCapSmall = 256;  // cells per outer hit staged in LDS by the first kernel
 constexpr int kCap = 512;       // by the second (the hits with more than kCapSmall)
-constexpr int kNB = 128;       // most key buckets
+constexpr int kNB = 256;       // most key buckets
 constexpr int32_t kHitMask = 0x7fffffff;
 
 template <class T>
