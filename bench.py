@@ -50,15 +50,14 @@ KERNEL_SYMBOL = {"doublets_count": "k_doublets<false>", "doublets_write": "k_dou
 #    (A = ar bz - az br: 2 mul + 1 sub; A A; La Lb; theta2 (La Lb); compare)
 #  cell_index: per cell read inner, outer (8 B), write the 8-byte index
 #    entry, and clear out_count and has_inner (5 B)
-#  doublets_write: per cell write inner, outer, pair and the R-Z segment
-#    dr, dz, ls (9 + 24 B)
+#  doublets_write: per cell write inner, outer and pair (9 B)
 LINK_OPS_PER_CANDIDATE = 7.0
 LINK_BYTES_PER_CANDIDATE = 12.0
 LINK_BYTES_PER_LINK = 8.0
 LINK_BUCKETS_MAX = 128  # direction buckets of the windowed link search, at most
 LINK_WIN_CAP = 224      # out-cells of a hit it stages (copies included)
 CELL_INDEX_BYTES_PER_CELL = 21.0
-DOUBLET_BYTES_PER_CELL = 33.0
+DOUBLET_BYTES_PER_CELL = 9.0
 HBM_PEAK_GBS = 8000.0
 
 
@@ -191,7 +190,7 @@ def chain_workload(args):
     api.timing_reset()
     # cell pairs sharing a hit, and those the link search examines (for the
     # link kernel's work accounting)
-    n_pairs, n_examined = link_pair_counts(pipe_b.cells, h.n_hits, cfg_d)
+    n_pairs, n_examined = link_pair_counts(pipe_b.cells, h, cfg_d)
     counts = dict(hits=h.n_hits, doublets=n_cells, links=n_links, ntuplets=n_raw, tracks=n_trk,
                   link_candidates=n_pairs, link_examined=n_examined)
     table2 = table2_counters(pipe_b, cfg_d, h.n_events)
@@ -366,21 +365,23 @@ def full_chain(args, cfg_d, perf, h, hits, name):
     return out
 
 
-def link_pair_counts(cells, n_hits, cfg_d):
+def link_pair_counts(cells, h, cfg_d):
     """(pairs, examined): the in-cell/out-cell pairs that share a middle hit,
     and how many of them the link search tests.  The search bins a hit's
     out-cells by the direction key of their R-Z segment (B buckets) and tests
     each in-cell against its own and the neighbouring buckets; a hit whose
     out-cells (with the copies of the two end buckets) exceed WIN_CAP, or one
-    with a keyless out-cell, has every pair tested.  Recomputed here with the
-    same float operations, for reporting only."""
+    with a keyless out-cell, has every pair tested.  Recomputed here from the
+    hits (h.x, h.y, h.z) with the same operations, for reporting only."""
     import math
 
+    import numpy as np
     import torch
 
     ci, co, _ = cells.valid()
     ci, co = ci.long(), co.long()
     n = ci.numel()
+    n_hits = h.n_hits
     nb = torch.zeros(n_hits, dtype=torch.int64, device=ci.device)
     nb.index_add_(0, ci, torch.ones_like(ci))
     pairs = int(nb[co].sum().item())
@@ -391,9 +392,10 @@ def link_pair_counts(cells, n_hits, cfg_d):
         B = min(b, LINK_BUCKETS_MAX) if b >= 4 else 0
     if B == 0 or n == 0:
         return pairs, pairs
-    c = torch.arange(n, device=ci.device)
-    at = (c // 32) * 96 + c % 32
-    dr, dz = cells.seg[at], cells.seg[at + 32]
+    x, y = (np.asarray(a, np.float64) for a in (h.x, h.y))
+    r = torch.from_numpy(np.sqrt(x * x + y * y)).to(ci.device)
+    z = torch.from_numpy(np.asarray(h.z, np.float64)).to(ci.device)
+    dr, dz = r[co] - r[ci], z[co] - z[ci]
     flip = dr < 0
     r = torch.where(flip, -dr, dr).float()
     z = torch.where(flip, -dz, dz).float()
@@ -694,39 +696,44 @@ def cpu_baseline(args, chain):
                            f"(a reference, not an optimised CPU adjoint): 10000 tracks on 1 thread, 60000 on {cores}")
 
 
-def traffic_record(name):
-    """HBM bytes per launch of a kernel from the committed counter summary
-    (profiles/pu200_step_counters.txt), or None when the kernel's source file
-    has changed since the counters were taken."""
+def source_sha(*files):
+    """SHA-256 of kernel sources (under paper_2008_13461_amd/csrc) together
+    with the internal header every kernel includes."""
     import hashlib
 
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2008_13461_amd", "csrc")
+    return hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                   for f in files + ("pt_internal.h",))).hexdigest()
+
+
+def traffic_record(name):
+    """(HBM bytes per launch, VALU issue fraction or None) of a kernel from
+    the committed counter summary (profiles/pu200_step_counters.txt), or None
+    when its sources have changed since the counters were taken."""
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "pu200_step_counters.txt")
     src = KERNEL_SOURCE.get(name)
     if src is None or not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(os.path.join(here, "paper_2008_13461_amd", "csrc", src), "rb").read()).hexdigest()
+    sha = source_sha(src)
     for line in open(path):
         if not line.startswith("traffic "):
             continue
         f = dict(kv.split("=", 1) for kv in line.split()[1:])
         if f.get("kernel") == name and f.get("sha256") == sha:
-            return float(f["fetch_bytes"]) + float(f["write_bytes"])
+            issue = float(f["valu_issue_frac"]) if "valu_issue_frac" in f else None
+            return float(f["fetch_bytes"]) + float(f["write_bytes"]), issue
     return None
 
 
 def fit_counter_record():
     """Counters of the fit workload's kernels from profiles/fit_config4_counters.txt
     (its 'fit_counters' line), or None when the fit sources changed since."""
-    import hashlib
-
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "fit_config4_counters.txt")
     if not os.path.exists(path):
         return None
-    csrc = os.path.join(here, "paper_2008_13461_amd", "csrc")
-    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                  for f in ("fit.hip", "fit_core.h"))).hexdigest()
+    sha = source_sha("fit.hip", "fit_core.h")
     for line in open(path):
         if line.startswith("fit_counters "):
             f = dict(kv.split("=", 1) for kv in line.split()[1:])
@@ -754,14 +761,19 @@ def roofline(kern, cnt):
                     note="12 B per examined candidate pair + 8 B per link, over the kernel time; alu: 7 fp64 VALU "
                          "ops per examined pair against 256 CU x 4 SIMD x 16 lanes x 2.4 GHz (no FMA: contraction "
                          "is off); all_pairs_rate_tops counts every pair sharing a hit, most of which the direction "
-                         "buckets skip.  The kernel is bound by the latency of its dependent gathers per hit.")
+                         "buckets skip.  Neither bound is reached: the kernel is limited by VALU instruction "
+                         "issue (valu_issue_frac, from the committed SQ counters), the fixed work of each "
+                         "hit's windowed search (staging, keys, scans, dealing pairs to lanes, beam-spot "
+                         "batches) rather than its R-Z tests.")
     else:
         per_cell = {"cell_index": CELL_INDEX_BYTES_PER_CELL, "doublets_write": DOUBLET_BYTES_PER_CELL}.get(name)
         achieved = per_cell * cnt["doublets"] / sec / 1e9 if per_cell else None
         roof.update(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS if achieved else None)
     t = traffic_record(name)
-    roof["traffic"] = t
+    roof["traffic"] = t[0] if t else None
+    if t and t[1] is not None:
+        roof["valu_issue_frac"] = t[1]
     roof["traffic_unit"] = "bytes per launch (FETCH_SIZE and WRITE_SIZE, copy-calibrated)"
     return roof
 

@@ -191,17 +191,7 @@ typedef struct {
  * cap; only min(count, cap) entries are written (PT_FLAG_CELLS_OVERFLOW set).
  * The cells whose inner hit is h are [inner_first[h], inner_first[h] +
  * inner_count[h]) (clipped to cap): pt_build_doublets writes them grouped by
- * inner hit, and pt_link_cells relies on this index.  pt_build_doublets also
- * writes each cell's R-Z segment, which pt_link_cells reads for the
- * alignment test of section 3.2: with R = sqrt(x x + y y) and z of a hit in
- * double, dr = R_outer - R_inner, dz = z_outer - z_inner, and
- * ls = dr dr + dz dz, negated when the outer hit lies on an end-cap layer
- * (layer_barrel[layer] == 0), whose theta cut then applies.  seg holds them
- * in blocks of PT_SEG_BLOCK cells: cell c's dr is seg[b * 3 PT_SEG_BLOCK + i]
- * with b = c / PT_SEG_BLOCK and i = c % PT_SEG_BLOCK, its dz PT_SEG_BLOCK and
- * its ls 2 PT_SEG_BLOCK doubles further. */
-#define PT_SEG_BLOCK 32
-#define PT_SEG_DOUBLES(cap) (3 * (((cap) + PT_SEG_BLOCK - 1) / PT_SEG_BLOCK) * PT_SEG_BLOCK)
+ * inner hit, and pt_link_cells relies on this index. */
 typedef struct {
   int32_t cap;
   int32_t* inner;       /* [cap] inner hit index */
@@ -210,7 +200,6 @@ typedef struct {
   int32_t* count;       /* [1] */
   int32_t* inner_first; /* [n_hits] */
   int32_t* inner_count; /* [n_hits] */
-  double* seg;          /* [PT_SEG_DOUBLES(cap)] R-Z segments */
 } pt_cells;
 
 /* Cell links c_in -> c_out: c_out starts on the outer hit of c_in.  The links
@@ -476,15 +465,14 @@ void pt_plan_destroy(pt_plan plan);
 /* Kernel timing (instrumentation).  While enabled, the individual calls (not
  * graph launches) record a pair of HIP events around their main kernels on
  * their stream, one kernel each unless noted: "doublets_count",
- * "doublets_write" (which also writes the cells' R-Z segments), "fishbone"
- * (every kernel of the Fishbone, when it is on), "cell_index" (the index of
- * cells by outer hit), "link_segments" (placing the index segments), "links"
- * (the triplet sweep), "link_emit" (placing the links), "root_count",
- * "root_write", "dfs_count", "dfs_write", "dedup" (several kernels),
- * "fit_fwd" and "fit_bwd" (every kernel of the fit and of its adjoint).
- * pt_timing_read waits for the recorded events and
- * returns the summed milliseconds and the number of launches since the last
- * reset (PT_ERR_ARG when the name has no record). */
+ * "doublets_write", "fishbone" (every kernel of the Fishbone, when it is
+ * on), "cell_index" (the index of cells by outer hit), "link_segments"
+ * (placing the index segments), "links" (the triplet sweep), "link_emit"
+ * (placing the links), "root_count", "root_write", "dfs_count",
+ * "dfs_write", "dedup" (several kernels), "fit_fwd" and "fit_bwd" (every
+ * kernel of the fit and of its adjoint).  pt_timing_read waits for the
+ * recorded events and returns the summed milliseconds and the number of
+ * launches since the last reset (PT_ERR_ARG when the name has no record). */
 void pt_timing_enable(int32_t on);
 void pt_timing_reset(void);
 int32_t pt_timing_read(const char* kernel, double* total_ms, int64_t* launches);

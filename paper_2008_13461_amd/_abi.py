@@ -33,7 +33,6 @@ PT_FLAG_TRUNCATED = 1 << 4
 PT_FLAG_FIT_BAD_ORDER = 1 << 5
 PT_FLAG_FIT_FAILED = 1 << 6
 PT_FLAG_VERTICES_OVERFLOW = 1 << 7
-PT_SEG_BLOCK = 32
 PT_FIT_OK, PT_FIT_ST_BAD_ORDER, PT_FIT_ST_F64_SOLVE, PT_FIT_ST_FAILED = 0, 1, 2, 4
 PT_STAGE_ADJOINT, PT_STAGE_AMBIGUITY, PT_STAGE_VERTICES = 1, 2, 4
 
@@ -113,7 +112,6 @@ class pt_cells(ct.Structure):
         ("count", P),
         ("inner_first", P),
         ("inner_count", P),
-        ("seg", P),
     ]
 
 

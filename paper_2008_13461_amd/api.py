@@ -82,7 +82,6 @@ class Cells:
     count: torch.Tensor
     inner_first: torch.Tensor
     inner_count: torch.Tensor
-    seg: torch.Tensor             # float64 R-Z segments of the cells, blocked (see pixeltrack.h)
 
     @property
     def cap(self) -> int:
@@ -91,10 +90,8 @@ class Cells:
     @classmethod
     def empty(cls, cap: int, n_hits: int, device="cuda") -> "Cells":
         i32 = dict(dtype=torch.int32, device=device)
-        seg_doubles = 3 * ((cap + A.PT_SEG_BLOCK - 1) // A.PT_SEG_BLOCK) * A.PT_SEG_BLOCK
         return cls(torch.empty(cap, **i32), torch.empty(cap, **i32), torch.empty(cap, dtype=torch.uint8, device=device),
-                   torch.zeros(1, **i32), torch.empty(max(n_hits, 1), **i32), torch.empty(max(n_hits, 1), **i32),
-                   torch.empty(max(seg_doubles, 1), dtype=torch.float64, device=device))
+                   torch.zeros(1, **i32), torch.empty(max(n_hits, 1), **i32), torch.empty(max(n_hits, 1), **i32))
 
     def abi(self) -> A.pt_cells:
         c = A.pt_cells()
@@ -102,7 +99,6 @@ class Cells:
         c.inner, c.outer, c.pair = self.inner.data_ptr(), self.outer.data_ptr(), self.pair.data_ptr()
         c.count = self.count.data_ptr()
         c.inner_first, c.inner_count = self.inner_first.data_ptr(), self.inner_count.data_ptr()
-        c.seg = self.seg.data_ptr()
         return c
 
     def valid(self):

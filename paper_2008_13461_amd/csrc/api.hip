@@ -85,6 +85,8 @@ bool derive_config(const pt_config& c, DevCfg* d) {
   d->rmax_bpix1 = c.ca_rmax_bpix1;
   d->rmax_other = c.ca_rmax_other;
   for (int l = 0; l < kLayers; ++l) d->layer_barrel[l] = c.layer_barrel[l] ? 1 : 0;
+  for (int p = 0; p < c.n_pairs; ++p)
+    if (!d->layer_barrel[d->pair_outer[p]]) d->endcap_pairs |= 1u << p;
   d->root_always_mask = c.root_always_mask;
   d->root_if_free_mask = c.root_if_free_mask;
   d->min_hits = c.min_hits;
@@ -190,8 +192,7 @@ pt_err pt_build_doublets(const pt_hits* hits, const pt_config* cfg, pt_cells* ce
   if (!hits_ok(hits) || !cfg || !cells || !derive_config(*cfg, &d)) return PT_ERR_ARG;
   if (cells->cap < 0 || !cells->count || (hits->n_hits > 0 && (!cells->inner_first || !cells->inner_count)))
     return PT_ERR_ARG;
-  if (cells->cap > 0 && (!cells->inner || !cells->outer || !cells->pair || !cells->seg))
-    return PT_ERR_ARG;
+  if (cells->cap > 0 && (!cells->inner || !cells->outer || !cells->pair)) return PT_ERR_ARG;
   size_t need = ws_doublets(hits->n_hits, hits->n_events, d.n_bins);
   if (d.fishbone_theta2 > 0.0) need = std::max(need, ws_fishbone(hits->n_hits, cells->cap));
   if (!ws_ok(ws, need)) return PT_ERR_WORKSPACE;
@@ -204,7 +205,7 @@ pt_err pt_link_cells(const pt_hits* hits, const pt_config* cfg, const pt_cells* 
   DevCfg d;
   if (!hits_ok(hits) || !cfg || !cells || !links || !derive_config(*cfg, &d)) return PT_ERR_ARG;
   if (cells->cap < 0 || links->cap < 0 || !cells->count || !links->count) return PT_ERR_ARG;
-  if (cells->cap > 0 && (!cells->inner || !cells->outer || !cells->seg ||
+  if (cells->cap > 0 && (!cells->inner || !cells->outer || !cells->pair ||
                          !links->out_start || !links->out_count || !links->has_inner))
     return PT_ERR_ARG;
   if (hits->n_hits > 0 && (!cells->inner_first || !cells->inner_count)) return PT_ERR_ARG;

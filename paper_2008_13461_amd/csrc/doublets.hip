@@ -162,7 +162,6 @@ struct DoubletArgs {
   uint8_t* pair;
   int32_t* inner_first;
   int32_t* inner_count;
-  double* seg;             // R-Z segments of the cells, blocked (write pass)
 };
 
 // The azimuth-bin ranges of the outer layer of pair p scanned for an inner
@@ -206,23 +205,19 @@ __device__ inline void window_ranges(const DevCfg& k, const int32_t* bin_start, 
 // for a store's acknowledgement (one counter tracks both on this GPU).
 constexpr int kStage = 256;
 // Groups of candidates with a passing one that the count pass keeps for the
-// write pass, per inner hit: (ballot of the group, first outer hit, pair |
-// kEndcapBit) in one 16-byte record.  A hit with more such groups is tested
-// again by the write pass.
+// write pass, per inner hit: (ballot of the group, first outer hit, pair) in
+// one 16-byte record.  A hit with more such groups is tested again by the
+// write pass.
 constexpr int kMaskChunks = 64;
 static_assert(kMaskChunks == kWave, "one kept group per lane");
 // Threads per block of the write pass, whatever the count pass takes: four
 // single-wavefront hits per block measured fastest for the stores.
 constexpr int kWriteBlock = 256;
-constexpr int kEndcapBit = 0x80;  // in a staged pair: the pair's outer layer is an end-cap
-static_assert(kMaxPairs <= kEndcapBit, "pair indices leave the top bit free");
 
 template <bool WRITE, int WAVES>
 __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArgs a) {
   __shared__ int32_t s_out[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   __shared__ uint8_t s_pair[WRITE ? WAVES : 1][WRITE ? kStage : 1];
-  __shared__ double s_R[WRITE ? WAVES : 1][WRITE ? kStage : 1];  // R and z of the staged outer hits
-  __shared__ double s_Z[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   __shared__ int4 s_chunk[WRITE ? WAVES : 1][WRITE ? kMaskChunks : 1];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = __lane_id();
@@ -250,24 +245,16 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   int pos = first;  // uniform: next cell position (write pass) or count
   const int hit_i = WRITE ? a.sorted_hit[j] : 0;
   int staged = 0;                   // uniform: staged cells, to be written from pos on
-  // stores the staged cells (outer hit, pair, outer R and z) with their R-Z
-  // segment, consecutive positions on consecutive lanes
+  // stores the staged cells (outer hit, pair), consecutive positions on
+  // consecutive lanes
   auto flush = [&]() {
     wave_sync();
     for (int i = lane; i < staged; i += kWave) {
       const int w = pos + i;
       if (w < a.cap) {
-        const int p = s_pair[wave][i];  // pair | kEndcapBit when the outer layer is an end-cap
-        const double dr = s_R[wave][i] - Ri;
-        const double dz = s_Z[wave][i] - Zi;
-        const double L = dr * dr + dz * dz;
         a.inner[w] = hit_i;
         a.outer[w] = s_out[wave][i];
-        a.pair[w] = static_cast<uint8_t>(p & ~kEndcapBit);
-        double* g = a.seg + seg_at(w);
-        g[0] = dr;
-        g[PT_SEG_BLOCK] = dz;
-        g[2 * PT_SEG_BLOCK] = (p & kEndcapBit) ? -L : L;
+        a.pair[w] = s_pair[wave][i];
       }
     }
     wave_sync();
@@ -286,23 +273,18 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
       constexpr int kGroupBatch = 4;
       for (int t0 = 0; t0 < nst; t0 += kGroupBatch) {
         uint64_t m[kGroupBatch];
-        int pe[kGroupBatch], hit[kGroupBatch];
-        double Ro[kGroupBatch], Zo[kGroupBatch];
+        int pr[kGroupBatch], hit[kGroupBatch];
 #pragma unroll
         for (int u = 0; u < kGroupBatch; ++u) {
           m[u] = 0;
-          pe[u] = 0;
+          pr[u] = 0;
           if (t0 + u < nst) {  // uniform
             const int4 d = s_chunk[wave][t0 + u];
             m[u] = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.y))) << 32) |
                    static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.x));
-            pe[u] = __builtin_amdgcn_readfirstlane(d.w);
+            pr[u] = __builtin_amdgcn_readfirstlane(d.w);
             const int o = __builtin_amdgcn_readfirstlane(d.z) + lane;
-            if ((m[u] >> lane) & 1u) {
-              hit[u] = a.sorted_hit[o];
-              Ro[u] = a.sR[o];
-              Zo[u] = a.sZ[o];
-            }
+            if ((m[u] >> lane) & 1u) hit[u] = a.sorted_hit[o];
           }
         }
 #pragma unroll
@@ -311,9 +293,7 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
           if ((m[u] >> lane) & 1u) {
             const int at = staged + lane_prefix(m[u]);
             s_out[wave][at] = hit[u];
-            s_pair[wave][at] = static_cast<uint8_t>(pe[u]);
-            s_R[wave][at] = Ro[u];
-            s_Z[wave][at] = Zo[u];
+            s_pair[wave][at] = static_cast<uint8_t>(pr[u]);
           }
           staged += __popcll(m[u]);
         }
@@ -335,7 +315,6 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
     if (k.cut_mask & PT_CUT_ZW) {
       if (!(k.zlo[p] <= Zi && Zi <= k.zhi[p])) continue;
     }
-    const int pe = p | (k.layer_barrel[k.pair_outer[p]] ? 0 : kEndcapBit);  // and the outer hits' class
     const double tdphi = k.tan_dphi[p];
     int ra[2], rb[2];
     window_ranges(k, a.bin_start, p, e, b, ra[0], rb[0], ra[1], rb[1]);
@@ -349,16 +328,14 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
           if (pass) {
             const int at = staged + lane_prefix(m);
             s_out[wave][at] = a.sorted_hit[o];
-            s_pair[wave][at] = static_cast<uint8_t>(pe);
-            s_R[wave][at] = a.sR[o];
-            s_Z[wave][at] = a.sZ[o];
+            s_pair[wave][at] = static_cast<uint8_t>(p);
           }
           staged += __popcll(m);
         } else {
           if (m) {
             if (lane == kept)
               rec = make_int4(static_cast<int>(static_cast<uint32_t>(m)), static_cast<int>(static_cast<uint32_t>(m >> 32)),
-                              o0, pe);
+                              o0, p);
             ++kept;
           }
           pos += __popcll(m);
@@ -473,7 +450,7 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   PT_LAUNCH_CHECK();
 
   DoubletArgs a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, chunks, n_chunks, cells.cap, cells.inner,
-                cells.outer, cells.pair, cells.inner_first, cells.inner_count, cells.seg};
+                cells.outer, cells.pair, cells.inner_first, cells.inner_count};
   // bin_start[-1] holds the number of valid hits (sorted positions).
   const int block = (k.block_doublets == 64 || k.block_doublets == 128 || k.block_doublets == 512)
                         ? k.block_doublets : 256;

@@ -51,7 +51,6 @@ struct FbArgs {
   int32_t* inner;
   int32_t* outer;
   uint8_t* pair;
-  double* seg;
   int32_t* inner_first;
   int32_t* inner_count;
   OuterIndex idx;
@@ -64,7 +63,6 @@ struct FbArgs {
   int32_t* t_inner;       // [cap] compacted copies
   int32_t* t_outer;
   uint8_t* t_pair;
-  double* t_seg;          // [PT_SEG_DOUBLES(cap)]
 };
 
 // Cells the Fishbone works on: every stored cell, or none when the cells
@@ -372,10 +370,6 @@ __global__ void k_fb_scatter(FbArgs<T> a) {
     a.t_inner[p] = a.inner[c];
     a.t_outer[p] = a.outer[c];
     a.t_pair[p] = a.pair[c];
-    const int64_t from = seg_at(c), to = seg_at(p);
-    a.t_seg[to] = a.seg[from];
-    a.t_seg[to + PT_SEG_BLOCK] = a.seg[from + PT_SEG_BLOCK];
-    a.t_seg[to + 2 * PT_SEG_BLOCK] = a.seg[from + 2 * PT_SEG_BLOCK];
   }
 }
 
@@ -390,10 +384,6 @@ __global__ void k_fb_copy_back(FbArgs<T> a) {
     a.inner[p] = a.t_inner[p];
     a.outer[p] = a.t_outer[p];
     a.pair[p] = a.t_pair[p];
-    const int64_t at = seg_at(p);
-    a.seg[at] = a.t_seg[at];
-    a.seg[at + PT_SEG_BLOCK] = a.t_seg[at + PT_SEG_BLOCK];
-    a.seg[at + 2 * PT_SEG_BLOCK] = a.t_seg[at + 2 * PT_SEG_BLOCK];
   }
   for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < a.n_hits; h += gridDim.x * blockDim.x) {
     const int cnt = a.inner_count[h];
@@ -423,7 +413,6 @@ void carve_rest(Carver& c, FbArgs<T>* a, int cap, int n_hits, int32_t** tmp) {
   a->t_inner = c.take<int32_t>(static_cast<size_t>(cap));
   a->t_outer = c.take<int32_t>(static_cast<size_t>(cap));
   a->t_pair = c.take<uint8_t>(static_cast<size_t>(cap));
-  a->t_seg = c.take<double>(PT_SEG_DOUBLES(static_cast<size_t>(cap)));
   *tmp = c.take<int32_t>(scan_tmp_elems(std::max(cap, n_hits) + 1));
 }
 
@@ -454,7 +443,6 @@ pt_err run_fishbone(const pt_hits& h, const DevCfg& k, pt_cells& cells, void* ws
   a.inner = cells.inner;
   a.outer = cells.outer;
   a.pair = cells.pair;
-  a.seg = cells.seg;
   a.inner_first = cells.inner_first;
   a.inner_count = cells.inner_count;
   const pt_err e = build_outer_index(h, cells, c, a.idx, s);

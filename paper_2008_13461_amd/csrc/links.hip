@@ -7,9 +7,10 @@
 // step is organised around that test:
 //
 //  1. k_hit_table: (X, Y, Z, R) of every hit in double, one 32-byte entry.
-//     Each cell's R-Z segment (dr, dz) and its squared length, signed by the
-//     barrel/end-cap class of its outer hit (the class of h2 selects theta),
-//     come with the cells from the doublet step.
+//     Each cell's R-Z segment (dr, dz) is rebuilt from it with the
+//     operations of the doublet step, and the class (barrel or end-cap) of
+//     the out-cell's outer hit h2, which selects theta, comes from the cell's
+//     layer pair.
 //  2. k_cell_index: each chunk of cells is grouped by outer hit in an LDS
 //     hash table and written to the index grouped that way.
 //  3. exclusive scan of the per-hit segment counts, then k_seg_scatter:
@@ -68,14 +69,9 @@ __device__ __forceinline__ bool rz_pass(double ar, double az, double La, double 
   return A * A <= theta2 * (La * Lb);
 }
 
-// Class of an out-cell's outer hit from the sign of its signed squared
-// length (negative: end-cap).  Called with wave-uniform values; the empty asm
-// keeps the test a 32-bit scalar compare of the high word instead of a 64-bit
-// vector compare.
-__device__ __forceinline__ bool endcap_outer(double Ls) {
-  int hi = __double2hiint(Ls);
-  asm volatile("" : "+s"(hi));
-  return hi < 0;
+// Class of a cell's outer hit from its layer pair: true for an end-cap layer.
+__device__ __forceinline__ bool endcap_outer(const DevCfg& k, int pair) {
+  return (k.endcap_pairs >> pair) & 1u;
 }
 
 // Direction key of an R-Z segment, in [-1, 1]: the diamond angle
@@ -369,6 +365,7 @@ struct HitArgs {
   const int32_t* cell_count;
   int32_t cells_cap;
   const int32_t* outer;
+  const uint8_t* pair;
   const int32_t* inner_first;
   const int32_t* inner_count;
   const int32_t* seg_first;  // [n_hits + 1] first segment of each hit's in-cell list
@@ -420,12 +417,13 @@ __device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a,
 }
 
 // Stages the hit's nb out-cells (from cb on) for the windowed search, sorted
-// by bucket into wdr / wdz / wj, and the bucket starts into bst.  Returns
-// false (wave-uniform) when an out-cell has no key or the list with its
-// copies does not fit; the hit is then swept pair by pair.
+// by bucket into wdr / wdz / wj, and the bucket starts into bst; (R1, Z1)
+// is the middle hit.  Returns false (wave-uniform) when an out-cell has no
+// key or the list with its copies does not fit; the hit is then swept pair
+// by pair.
 template <class T>
-__device__ bool stage_window(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L, const double* __restrict__ seg,
-                             int cb, int nb) {
+__device__ bool stage_window(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L, int cb, int nb, double R1,
+                             double Z1) {
   const int lane = __lane_id();
   const int B = k.rz_buckets;
   int32_t* hist = L.queue;  // bucket counts (the queue is empty between passes)
@@ -443,11 +441,10 @@ __device__ bool stage_window(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L
     sdr[r] = sdz[r] = 0.0;
     send[r] = false;
     if (j < nb) {
-      const double* g = seg + seg_at(cb + j);
       const double4 P2 = a.hx[a.outer[cb + j]];
-      sdr[r] = g[0];
-      sdz[r] = g[PT_SEG_BLOCK];
-      send[r] = __builtin_signbit(g[2 * PT_SEG_BLOCK]);
+      sdr[r] = P2.w - R1;  // as the doublet step computes dr and dz
+      sdz[r] = P2.z - Z1;
+      send[r] = endcap_outer(k, a.pair[cb + j]);
       const float key = rz_key(sdr[r], sdz[r]);
       bad |= !(key == key);
       const int b = key == key ? rz_bucket(key, B) : 0;
@@ -500,7 +497,7 @@ __device__ bool stage_window(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L
 // One wavefront per middle hit; WAVES independent wavefronts per block.
 template <class T, int WAVES>
 __global__ void __launch_bounds__(WAVES * kWave)
-    k_link_hits(DevCfg k, HitArgs<T> a, const double* __restrict__ seg) {
+    k_link_hits(DevCfg k, HitArgs<T> a) {
   __shared__ WaveLds<T> lds[WAVES];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const int lane = __lane_id();
@@ -515,7 +512,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
   const int nb = min(cb + a.inner_count[h1], n_cells) - cb;
   if (a.inner_count[h1] <= 0 || nb <= 0) return;  // no out-cells: no links (counts are zero)
   const double4 P1 = a.hx[h1];
-  const double X1 = P1.x, Y1 = P1.y;
+  const double X1 = P1.x, Y1 = P1.y, Z1 = P1.z, R1 = P1.w;
   const double th2b = k.theta2_barrel, th2e = k.theta2_endcap;
   const int nh = min(nb, kHinBits);  // out-cells whose has_inner bit is kept in LDS
   for (int w = lane; w < (nh + 31) / 32; w += kWave) L.hin[w] = 0;
@@ -523,7 +520,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
   int2 seg0 = make_int2(0, 0);
   if (lane < min(kSegWin, se - sb)) seg0 = a.seg[sb + lane];
   // the out-cells by direction bucket, when the search can be windowed
-  const bool win = k.rz_buckets > 0 && nb <= kWinCap && stage_window(k, a, L, seg, cb, nb);
+  const bool win = k.rz_buckets > 0 && nb <= kWinCap && stage_window(k, a, L, cb, nb, R1, Z1);
 
   for (int sw = sb; sw < se; sw += kSegWin) {
     // a window of the hit's segments and the prefix of their sizes
@@ -574,8 +571,8 @@ __global__ void __launch_bounds__(WAVES * kWave)
         r = L.sfirst[sg] + (idx - L.spre[sg]);
         const InCell e = a.ent[r];
         const double4 P0 = a.hx[e.h0b & ~kBpix1Bit];
-        ar = P1.w - P0.w;  // as the doublet step computes dr
-        az = P1.z - P0.z;
+        ar = R1 - P0.w;  // as the doublet step computes dr
+        az = Z1 - P0.z;
         La = ar * ar + az * az;
         cell = e.cell;
         X0 = P0.x;
@@ -688,12 +685,11 @@ __global__ void __launch_bounds__(WAVES * kWave)
             const bool valid = j < ns;
             double br = 0.0, bz = 0.0, Lb = 0.0, theta2 = 0.0;
             if (valid) {
-              const double* g = seg + seg_at(cs + j);
-              const double Ls = g[2 * PT_SEG_BLOCK];
-              br = g[0];
-              bz = g[PT_SEG_BLOCK];
-              Lb = fabs(Ls);
-              theta2 = __builtin_signbit(Ls) ? th2e : th2b;  // end-cap outer hit: negative
+              const double4 P2 = a.hx[a.outer[cs + j]];
+              br = P2.w - R1;
+              bz = P2.z - Z1;
+              Lb = br * br + bz * bz;
+              theta2 = endcap_outer(k, a.pair[cs + j]) ? th2e : th2b;
             }
             for (int i = 0; i < m; ++i) {
               const bool pass =
@@ -709,56 +705,42 @@ __global__ void __launch_bounds__(WAVES * kWave)
           wave_sync();
           continue;
         }
-        // one out-cell at a time (the head before the first group boundary and
-        // the tail)
-        auto single = [&](int j) {
-          const double* g = seg + seg_at(cs + j);
-          const double Ls = g[2 * PT_SEG_BLOCK];
-          const double theta2 = endcap_outer(Ls) ? th2e : th2b;
-          const bool pass = rz_pass(ar, az, La, g[0], g[PT_SEG_BLOCK], fabs(Ls), theta2);
-          const uint64_t mk = __ballot(pass);
-          if (mk) append(j, lane, pass, mk);
+        // One out-cell at a time, wave-uniform, its segment rebuilt from the
+        // hit table; the loads of the next kUnroll out-cells are issued before
+        // the tests of the current ones.
+        auto load_out = [&](int j, double& br, double& bz, bool& ec) {
+          const double4 P2 = a.hx[a.outer[cs + j]];
+          br = P2.w - R1;
+          bz = P2.z - Z1;
+          ec = endcap_outer(k, a.pair[cs + j]);
         };
-        // groups of kUnroll out-cells start on multiples of kUnroll, so that a
-        // group's fields are contiguous in its segment block
-        const int head = min(ns, (kUnroll - (cs % kUnroll)) % kUnroll);
-        int j = 0;
-        for (; j < head; ++j) single(j);
-        // the loads of the next group are issued before the tests of this one
-        double pdr[kUnroll], pdz[kUnroll], pLs[kUnroll];
-        if (j + kUnroll <= ns) {
-          const double* g = seg + seg_at(cs + j);
+        double pbr[kUnroll], pbz[kUnroll];
+        bool pec[kUnroll];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            pdr[u] = g[u];
-            pdz[u] = g[PT_SEG_BLOCK + u];
-            pLs[u] = g[2 * PT_SEG_BLOCK + u];
-          }
+        for (int u = 0; u < kUnroll; ++u) {
+          pbr[u] = pbz[u] = 0.0;
+          pec[u] = false;
+          if (u < ns) load_out(u, pbr[u], pbz[u], pec[u]);
         }
-        for (; j + kUnroll <= ns; j += kUnroll) {
-          double cdr[kUnroll], cdz[kUnroll], cLs[kUnroll];
+        for (int j = 0; j < ns; j += kUnroll) {
+          double cbr[kUnroll], cbz[kUnroll];
+          bool cec[kUnroll];
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
-            cdr[u] = pdr[u];
-            cdz[u] = pdz[u];
-            cLs[u] = pLs[u];
+            cbr[u] = pbr[u];
+            cbz[u] = pbz[u];
+            cec[u] = pec[u];
           }
-          if (j + 2 * kUnroll <= ns) {
-            const double* g = seg + seg_at(cs + j + kUnroll);
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-              pdr[u] = g[u];
-              pdz[u] = g[PT_SEG_BLOCK + u];
-              pLs[u] = g[2 * PT_SEG_BLOCK + u];
-            }
-          }
+          for (int u = 0; u < kUnroll; ++u)
+            if (j + kUnroll + u < ns) load_out(j + kUnroll + u, pbr[u], pbz[u], pec[u]);
           bool pass[kUnroll];
           uint64_t mk[kUnroll];
           uint64_t any = 0;
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
-            const double theta2 = endcap_outer(cLs[u]) ? th2e : th2b;
-            pass[u] = rz_pass(ar, az, La, cdr[u], cdz[u], fabs(cLs[u]), theta2);
+            pass[u] = j + u < ns &&
+                      rz_pass(ar, az, La, cbr[u], cbz[u], cbr[u] * cbr[u] + cbz[u] * cbz[u], cec[u] ? th2e : th2b);
             mk[u] = __ballot(pass[u]);
             any |= mk[u];
           }
@@ -768,7 +750,6 @@ __global__ void __launch_bounds__(WAVES * kWave)
               if (mk[u]) append(j + u, lane, pass[u], mk[u]);
           }
         }
-        for (; j < ns; ++j) single(j);
         if (qn > 0) {
           wave_sync();
           beam_batch(k, a, L, qn, cs, jb, X1, Y1, X0, Y0, bpix1, win);
@@ -907,7 +888,7 @@ constexpr int kOvfStage = 256;
 template <class T>
 __global__ void __launch_bounds__(kOvfWaves * kWave)
     k_links_overflow(DevCfg k, HitArgs<T> a, const int32_t* __restrict__ inner, const uint8_t* __restrict__ layer,
-                     const double* __restrict__ seg, const int32_t* __restrict__ out_start, int32_t links_cap,
+                     const int32_t* __restrict__ out_start, int32_t links_cap,
                      int32_t* __restrict__ in_cell, int32_t* __restrict__ out_cell) {
   __shared__ int32_t s_link[kOvfWaves][kOvfStage];
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
@@ -918,9 +899,9 @@ __global__ void __launch_bounds__(kOvfWaves * kWave)
     const int cp = a.ovf[i];
     const int h0 = inner[cp];
     const int h1 = a.outer[cp];
-    const double* gp = seg + seg_at(cp);
-    const double ar = gp[0], az = gp[PT_SEG_BLOCK], La = fabs(gp[2 * PT_SEG_BLOCK]);
     const double4 P0 = a.hx[h0], P1 = a.hx[h1];
+    const double ar = P1.w - P0.w, az = P1.z - P0.z;  // as the doublet step computes dr and dz
+    const double La = ar * ar + az * az;
     const double X0 = P0.x, Y0 = P0.y, X1 = P1.x, Y1 = P1.y;
     const double rmax = layer[h0] == 0 ? k.rmax_bpix1 : k.rmax_other;
     const int first = a.inner_first[h1];
@@ -944,14 +925,10 @@ __global__ void __launch_bounds__(kOvfWaves * kWave)
       const int c = c0 + lane;
       bool pass = false;
       if (c < last) {
-        const double* g = seg + seg_at(c);
-        const double Ls = g[2 * PT_SEG_BLOCK];
-        const double theta2 = __builtin_signbit(Ls) ? k.theta2_endcap : k.theta2_barrel;
-        pass = rz_pass(ar, az, La, g[0], g[PT_SEG_BLOCK], fabs(Ls), theta2);
-        if (pass) {
-          const double4 P2 = a.hx[a.outer[c]];
-          pass = beam_pass(X0, Y0, X1, Y1, P2.x, P2.y, rmax);
-        }
+        const double4 P2 = a.hx[a.outer[c]];
+        const double br = P2.w - P1.w, bz = P2.z - P1.z;
+        const double theta2 = endcap_outer(k, a.pair[c]) ? k.theta2_endcap : k.theta2_barrel;
+        pass = rz_pass(ar, az, La, br, bz, br * br + bz * bz, theta2) && beam_pass(X0, Y0, X1, Y1, P2.x, P2.y, rmax);
       }
       const uint64_t mk = __ballot(pass);
       if (staged + kWave > kOvfStage) flush();
@@ -1035,9 +1012,9 @@ size_t ws_links(int n_hits, int cells_cap) {
 }
 
 template <class T, int WAVES>
-static void launch_hits(const DevCfg& k, const HitArgs<T>& a, const double* seg, hipStream_t s) {
+static void launch_hits(const DevCfg& k, const HitArgs<T>& a, hipStream_t s) {
   const int64_t blocks = (static_cast<int64_t>(a.n_hits) + WAVES - 1) / WAVES;
-  k_link_hits<T, WAVES><<<static_cast<unsigned>(blocks < 1 ? 1 : blocks), WAVES * kWave, 0, s>>>(k, a, seg);
+  k_link_hits<T, WAVES><<<static_cast<unsigned>(blocks < 1 ? 1 : blocks), WAVES * kWave, 0, s>>>(k, a);
 }
 
 template <class T>
@@ -1079,16 +1056,16 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
   timing_end(tok, "link_segments", s);
   PT_LAUNCH_CHECK();
 
-  HitArgs<T> a{n, hx, cells.count, cells.cap, cells.outer, cells.inner_first, cells.inner_count, seg_first, seg,
-               ent, L.out_count, spill, ovf, ovf_count, L.has_inner};
+  HitArgs<T> a{n, hx, cells.count, cells.cap, cells.outer, cells.pair, cells.inner_first, cells.inner_count,
+               seg_first, seg, ent, L.out_count, spill, ovf, ovf_count, L.has_inner};
   tok = timing_begin(s);
   if (n > 0) {
     if (block == 128)
-      launch_hits<T, 2>(k, a, cells.seg, s);
+      launch_hits<T, 2>(k, a, s);
     else if (block == 256)
-      launch_hits<T, 4>(k, a, cells.seg, s);
+      launch_hits<T, 4>(k, a, s);
     else
-      launch_hits<T, 1>(k, a, cells.seg, s);
+      launch_hits<T, 1>(k, a, s);
     PT_LAUNCH_CHECK();
   }
   timing_end(tok, "links", s);
@@ -1104,8 +1081,8 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
                          kEmitBlock, 0, s>>>(e);
   timing_end(tok, "link_emit", s);
   PT_LAUNCH_CHECK();
-  k_links_overflow<T><<<1024, kOvfWaves * kWave, 0, s>>>(k, a, cells.inner, h.layer, cells.seg, L.out_start, L.cap,
-                                                         L.in_cell, L.out_cell);
+  k_links_overflow<T><<<1024, kOvfWaves * kWave, 0, s>>>(k, a, cells.inner, h.layer, L.out_start, L.cap, L.in_cell,
+                                                         L.out_cell);
   PT_LAUNCH_CHECK();
   k_finish_links<<<1, 1, 0, s>>>(L.count, L.cap, status);
   PT_LAUNCH_CHECK();

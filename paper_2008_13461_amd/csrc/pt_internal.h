@@ -37,6 +37,7 @@ struct DevCfg {
   int32_t n_inner_pairs[kLayers];
   // links
   double theta2_barrel, theta2_endcap;
+  uint32_t endcap_pairs;  // bit p set when the outer layer of pair p is an end-cap layer
   int32_t rz_buckets;  // direction buckets of the windowed R-Z search (0: every pair is tested)
   double rmax_bpix1, rmax_other;
   uint8_t layer_barrel[kLayers];
@@ -188,14 +189,6 @@ __device__ inline int wave_incl_scan(int v) {
 __device__ inline int lane_prefix(uint64_t mask) {
   return static_cast<int>(__builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
                                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u)));
-}
-
-// Index of cell c's dr in the cells' R-Z segment array (dz and ls follow at
-// +PT_SEG_BLOCK and +2 PT_SEG_BLOCK): blocks of PT_SEG_BLOCK cells hold the
-// three fields one after the other, so that the three streams a reader takes
-// at the same cells fall on different memory channels.
-__host__ __device__ inline int64_t seg_at(int64_t c) {
-  return (c / PT_SEG_BLOCK) * (3 * PT_SEG_BLOCK) + c % PT_SEG_BLOCK;
 }
 
 // Work-group dispatch places consecutive work-group ids on different XCDs

@@ -41,7 +41,7 @@ _STRUCTS = {
                   "vtx_pt_cap", "fishbone_theta", "exclusive_hits"],
     "pt_hits": ["n_hits", "n_events", "event_offsets", "dtype", "x", "layer", "module"],
     "pt_workspace": ["ptr", "bytes"],
-    "pt_cells": ["cap", "inner", "pair", "count", "inner_first", "inner_count", "seg"],
+    "pt_cells": ["cap", "inner", "pair", "count", "inner_first", "inner_count"],
     "pt_links": ["cap", "in_cell", "count", "out_start", "out_count", "has_inner"],
     "pt_ntuplets": ["cap", "hits", "n", "count_raw", "kept", "count"],
     "pt_tracks": ["cap", "params", "chi2", "status", "cov"],

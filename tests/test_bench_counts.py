@@ -19,22 +19,13 @@ from synth import events as E
 
 
 class _Cells:
-    """The two members of the library's cell container that the count reads."""
+    """The member of the library's cell container that the count reads."""
 
-    def __init__(self, ci, co, seg):
-        self._ci, self._co, self.seg = torch.from_numpy(ci), torch.from_numpy(co), torch.from_numpy(seg)
+    def __init__(self, ci, co):
+        self._ci, self._co = torch.from_numpy(ci), torch.from_numpy(co)
 
     def valid(self):
         return self._ci, self._co, None
-
-
-def _blocked_segments(dr, dz):
-    n = dr.shape[0]
-    seg = np.zeros(3 * ((n + 31) // 32) * 32)
-    c = np.arange(n)
-    at = (c // 32) * 96 + c % 32
-    seg[at], seg[at + 32], seg[at + 64] = dr, dz, dr * dr + dz * dz
-    return seg
 
 
 @pytest.mark.parametrize("theta", [None, 0.2])
@@ -45,7 +36,7 @@ def test_examined_pairs_cover_every_passing_pair(theta):
     x, y, z = (np.asarray(a, np.float64) for a in (h.x, h.y, h.z))
     r = np.sqrt(x * x + y * y)
     dr, dz = r[co] - r[ci], z[co] - z[ci]
-    pairs, examined = bench.link_pair_counts(_Cells(ci, co, _blocked_segments(dr, dz)), h.n_hits, cfg)
+    pairs, examined = bench.link_pair_counts(_Cells(ci, co), h, cfg)
     # every (in-cell, out-cell) pair meeting on a hit, and those passing the R-Z cut
     order = np.argsort(ci, kind="stable")
     first = np.searchsorted(ci[order], np.arange(h.n_hits + 1))

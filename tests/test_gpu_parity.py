@@ -161,29 +161,18 @@ def test_cut_set_without_zip():
     assert tuplet_set(prod["kept_hits"], prod["kept_n"]) == tuplet_set(ref["hits"], ref["n"])
 
 
-def test_cell_segments_match_their_definition():
-    """pt_cells.seg: each cell's R-Z segment (section 3.2's alignment test
-    reads it), bit for bit as pixeltrack.h defines it from the hits in
-    double: dr = R_outer - R_inner, dz = z_outer - z_inner, ls = dr dr + dz dz,
-    negated for an outer hit on an end-cap layer; blocks of PT_SEG_BLOCK."""
+def test_cell_pairs_match_their_hits():
+    """Each cell's layer pair has the layers of its two hits: the link step
+    takes the barrel or end-cap class of an out-cell's outer hit, which
+    selects its theta cut, from the pair's outer layer."""
     _need_gpu()
-    from paper_2008_13461_amd import _abi as A
     from tests.gpu_helpers import run_chain
     h = E.config2()
     pipe, _ = run_chain(h, CFG)
-    n = min(int(pipe.cells.count.item()), pipe.cells.cap)
-    ci = pipe.cells.inner[:n].cpu().numpy()
-    co = pipe.cells.outer[:n].cpu().numpy()
-    seg = pipe.cells.seg.cpu().numpy()
-    B = A.PT_SEG_BLOCK
-    c = np.arange(n)
-    at = (c // B) * (3 * B) + c % B
-    x, y, z = (np.asarray(v, np.float64) for v in (h.x, h.y, h.z))
-    R = np.sqrt(x * x + y * y)
-    dr = R[co] - R[ci]
-    dz = z[co] - z[ci]
-    L = dr * dr + dz * dz
-    barrel = np.asarray(CFG["layer_barrel"], bool)[h.layer[co]]
-    assert np.array_equal(seg[at], dr)
-    assert np.array_equal(seg[at + B], dz)
-    assert np.array_equal(seg[at + 2 * B], np.where(barrel, L, -L))
+    ci, co, cp = (t.cpu().numpy().astype(np.int64) for t in pipe.cells.valid())
+    assert len(ci) > 0
+    pairs = np.asarray(CFG["pairs"])
+    assert np.array_equal(pairs[cp, 0], h.layer[ci])
+    assert np.array_equal(pairs[cp, 1], h.layer[co])
+    barrel = np.asarray(CFG["layer_barrel"], bool)
+    assert barrel[h.layer[co]].any() and (~barrel[h.layer[co]]).any()  # both classes of outer hit
