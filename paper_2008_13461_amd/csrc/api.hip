@@ -43,6 +43,9 @@ bool derive_config(const pt_config& c, DevCfg* d) {
   if (B < 4 || B > 65536) return false;
   d->n_pairs = c.n_pairs;
   d->n_bins = B;
+  d->bin_shift = -1;
+  for (int sh = 0; sh < 31; ++sh)
+    if ((1 << sh) == B) d->bin_shift = sh;
   d->bin_scale = static_cast<float>(B / (2.0 * M_PI));
   d->cut_mask = c.cut_mask;
   d->z0_max = c.z0_max;

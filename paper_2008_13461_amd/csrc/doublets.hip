@@ -23,11 +23,29 @@ namespace pt {
 pt_err launch_fishbone(const pt_hits& h, const DevCfg& k, pt_cells& cells, void* ws_base, hipStream_t s);
 
 // The cut predicates of Table 1, as documented in pixeltrack.h (tdphi is
-// tan_dphi of the pair, loaded once per pair by the caller).
+// tan_dphi of the pair, loaded once per pair by the caller).  ALL: PhiW,
+// ZIP and PT are all on, and the three are evaluated without branches (a
+// divergent early exit costs scalar instructions to mask lanes, and a whole
+// wavefront of candidates rarely fails together); the same comparisons of
+// the same values, so the same decisions.
+constexpr uint32_t kCutsAll = PT_CUT_PHIW | PT_CUT_ZIP | PT_CUT_PT;
+template <bool ALL>
 __device__ __forceinline__ bool doublet_pass(const DevCfg& k, double tdphi, double Xi, double Yi, double Zi,
                                              double Ri, double Xo, double Yo, double Zo, double Ro) {
   const double D = Xi * Xo + Yi * Yo;
   const double C = Xi * Yo - Yi * Xo;
+  if (ALL) {
+    const double dR = Ro - Ri;
+    const double R2i = Xi * Xi + Yi * Yi;
+    const double R2o = Xo * Xo + Yo * Yo;
+    const double dx = Xo - Xi;
+    const double dy = Yo - Yi;
+    const double L2 = dx * dx + dy * dy;
+    const bool phiw = D > 0.0 && fabs(C) <= tdphi * D;
+    const bool zip = dR > 0.0 && fabs(Zi * Ro - Zo * Ri) <= k.z0_max * dR;
+    const bool pt = (4.0 * C) * C <= (k.kappa_max2 * (R2i * R2o)) * L2;
+    return static_cast<int>(phiw) & static_cast<int>(zip) & static_cast<int>(pt);
+  }
   if (k.cut_mask & PT_CUT_PHIW) {
     if (!(D > 0.0 && fabs(C) <= tdphi * D)) return false;
   }
@@ -214,7 +232,7 @@ static_assert(kMaskChunks == kWave, "one kept group per lane");
 // single-wavefront hits per block measured fastest for the stores.
 constexpr int kWriteBlock = 256;
 
-template <bool WRITE, int WAVES>
+template <bool WRITE, int WAVES, bool ALL>
 __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArgs a) {
   __shared__ int32_t s_out[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   __shared__ uint8_t s_pair[WRITE ? WAVES : 1][WRITE ? kStage : 1];
@@ -235,8 +253,9 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   }
   const int B = k.n_bins;
   const int key = a.skey[j];
-  const int b = key % B;
-  const int el = key / B;
+  const int sh = k.bin_shift;  // log2 B for a power of two: no integer division
+  const int b = sh >= 0 ? (key & (B - 1)) : key % B;
+  const int el = sh >= 0 ? (key >> sh) : key / B;
   const int lay = el % kLayers;
   const int e = el / kLayers;
   const double Xi = a.sX[j], Yi = a.sY[j], Zi = a.sZ[j], Ri = a.sR[j];
@@ -321,7 +340,10 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
     for (int r = 0; r < 2; ++r) {
       for (int o0 = ra[r]; o0 < rb[r]; o0 += kWave) {
         const int o = o0 + lane;
-        const bool pass = o < rb[r] && doublet_pass(k, tdphi, Xi, Yi, Zi, Ri, a.sX[o], a.sY[o], a.sZ[o], a.sR[o]);
+        const int oc = min(o, rb[r] - 1);  // lanes past the range test its last hit and are masked out
+        const bool pass = static_cast<int>(o < rb[r]) &
+                          static_cast<int>(doublet_pass<ALL>(k, tdphi, Xi, Yi, Zi, Ri, a.sX[oc], a.sY[oc], a.sZ[oc],
+                                                             a.sR[oc]));
         const uint64_t m = __ballot(pass);
         if (WRITE) {
           if (staged + kWave > kStage) flush();
@@ -393,22 +415,30 @@ size_t ws_doublets(int n_hits, int n_events, int n_bins) {
   return c.off + 256;
 }
 
-template <bool WRITE>
-static void launch_doublets(const DevCfg& k, const DoubletArgs& a, int n, int block, hipStream_t s) {
+template <bool WRITE, bool ALL>
+static void launch_doublets_as(const DevCfg& k, const DoubletArgs& a, int n, int block, hipStream_t s) {
   const int64_t hits = std::max(n, 1);
   switch (block) {
     case 64:
-      k_doublets<WRITE, 1><<<static_cast<unsigned>(hits), 64, 0, s>>>(k, a);
+      k_doublets<WRITE, 1, ALL><<<static_cast<unsigned>(hits), 64, 0, s>>>(k, a);
       break;
     case 128:
-      k_doublets<WRITE, 2><<<static_cast<unsigned>((hits + 1) / 2), 128, 0, s>>>(k, a);
+      k_doublets<WRITE, 2, ALL><<<static_cast<unsigned>((hits + 1) / 2), 128, 0, s>>>(k, a);
       break;
     case 512:
-      k_doublets<WRITE, 8><<<static_cast<unsigned>((hits + 7) / 8), 512, 0, s>>>(k, a);
+      k_doublets<WRITE, 8, ALL><<<static_cast<unsigned>((hits + 7) / 8), 512, 0, s>>>(k, a);
       break;
     default:
-      k_doublets<WRITE, 4><<<static_cast<unsigned>((hits + 3) / 4), 256, 0, s>>>(k, a);
+      k_doublets<WRITE, 4, ALL><<<static_cast<unsigned>((hits + 3) / 4), 256, 0, s>>>(k, a);
   }
+}
+
+template <bool WRITE>
+static void launch_doublets(const DevCfg& k, const DoubletArgs& a, int n, int block, hipStream_t s) {
+  if ((k.cut_mask & kCutsAll) == kCutsAll)
+    launch_doublets_as<WRITE, true>(k, a, n, block, s);
+  else
+    launch_doublets_as<WRITE, false>(k, a, n, block, s);
 }
 
 template <class T>

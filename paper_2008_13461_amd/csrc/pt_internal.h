@@ -29,6 +29,7 @@ struct DevCfg {
   uint32_t cut_mask;
   int32_t n_pairs;
   int32_t n_bins;                       // azimuth bins per layer
+  int32_t bin_shift;                    // log2(n_bins) when a power of two, else -1
   float bin_scale;                      // n_bins / (2 pi)
   int32_t pair_inner[kMaxPairs];
   int32_t pair_outer[kMaxPairs];
