@@ -40,7 +40,7 @@ KERNEL_SOURCE = {"doublets_count": "doublets.hip", "doublets_write": "doublets.h
                  "dfs_write": "ntuplets.hip", "fit_fwd": "fit.hip", "fit_bwd": "fit.hip"}
 KERNEL_SYMBOL = {"doublets_count": "k_doublets<false>", "doublets_write": "k_doublets<true>",
                  "cell_index": "k_cell_index", "link_segments": "k_seg_scatter", "links": "k_link_hits",
-                 "link_emit": "k_link_emit", "root_count": "k_root_count", "root_write": "k_mask_write",
+                 "link_emit": "k_link_place", "root_count": "k_root_count", "root_write": "k_mask_write",
                  "dfs_count": "k_dfs<true>", "dfs_write": "k_dfs<false>", "fit_fwd": "k_fit<4,6>",
                  "fit_bwd": "k_grad<4,6>"}
 # Algorithmic work per unit, for the roofline of whichever kernel dominates:

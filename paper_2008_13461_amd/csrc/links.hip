@@ -32,9 +32,10 @@
 //     gained an inner link are flagged (has_inner) in one coalesced run.
 //  5. the counts are recorded straight into out_count; their scan into
 //     out_start places every in-cell's links, in cell order (no shared
-//     counter: same-address atomics serialise), k_link_emit writes the links
-//     of the cells with at most kLocal, and k_links_overflow recomputes the
-//     few in-cells with more.
+//     counter: same-address atomics serialise): after a scan of the counts'
+//     tile sums, k_link_place scans each tile, writes out_start and the
+//     links of the cells with at most kLocal, and k_links_overflow
+//     recomputes the few in-cells with more.
 #include "pt_internal.h"
 
 #include <algorithm>
@@ -767,7 +768,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
           a.ovf[slot] = cell;
         }
       }
-      if (n > 0 && n <= kLocal) {  // the links are sorted by k_link_emit
+      if (n > 0 && n <= kLocal) {  // the links are sorted by k_link_place
         static_assert(kRow == 8 && kLocal == 8, "a record is two 16-byte vectors");
         // two halves of 16 bytes per cell, so that the records of the cells
         // with at most four links (nearly all) are dense
@@ -833,49 +834,107 @@ __device__ __forceinline__ void emit_cell(const EmitArgs& a, int c, int cnt, int
   }
 }
 
-// Cells with none or more than kLocal links are skipped (the latter are
-// written by k_links_overflow).  VEC: out_count and out_start 16-byte
-// aligned; each thread then takes four consecutive cells, their counts and
-// first links read as one vector each.
+// Places the links: each block takes one tile of kScanTile cells, scans
+// their link counts (the tile's offset comes from the scan of the tile sums)
+// into out_start, and writes the links of its cells with 1..kLocal of them
+// from their records.  Cells with more than kLocal links are written by
+// k_links_overflow.  The counts are read once, the positions never read
+// back: each thread scans kEmitItems consecutive counts (16-byte vectors),
+// the counts and positions go through LDS, and the records are then taken
+// one cell per thread and round, consecutive cells on consecutive lanes.
 constexpr int kEmitBlock = 256;
-template <bool VEC>
-__global__ void __launch_bounds__(kEmitBlock) k_link_emit(EmitArgs a) {
-  constexpr int kCells = VEC ? 4 : 1;  // per thread
+constexpr int kEmitItems = kScanTile / kEmitBlock;
+static_assert(kEmitItems % 4 == 0, "counts are read as 16-byte vectors");
+
+__global__ void __launch_bounds__(kEmitBlock) k_link_place(EmitArgs a, const int32_t* __restrict__ tile_off,
+                                                          int32_t* __restrict__ out_start, int32_t* __restrict__ total) {
+  __shared__ int32_t s_cnt[kScanTile];
+  __shared__ int32_t s_pos[kScanTile];
+  __shared__ int32_t s_wave[kEmitBlock / kWave + 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *total = tile_off[gridDim.x];
   const int n = min(*a.cell_count, a.cells_cap);
-  const int64_t c0 = (static_cast<int64_t>(blockIdx.x) * kEmitBlock + threadIdx.x) * kCells;
-  if (c0 >= n) return;
-  int cnt[kCells], pos[kCells];
-  if (VEC && c0 + kCells <= n) {
-    const int4 k4 = *reinterpret_cast<const int4*>(a.out_count + c0);
-    const int4 p4 = *reinterpret_cast<const int4*>(a.out_start + c0);
-    const int kk[4] = {k4.x, k4.y, k4.z, k4.w}, pp[4] = {p4.x, p4.y, p4.z, p4.w};
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * kScanTile;
+  if (first >= n) return;
+  const int m = static_cast<int>(min<int64_t>(kScanTile, n - first));  // cells of this tile
+  const int t = threadIdx.x;
+  const int lane = __lane_id(), wave = t / kWave;
+  // the counts of cells t * kEmitItems .. + kEmitItems of the tile
+  int v[kEmitItems];
+  const int at = t * kEmitItems;
+  const bool vec = m == kScanTile && reinterpret_cast<uintptr_t>(a.out_count) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(out_start) % 16 == 0;
+  if (vec) {
+    const int4* p = reinterpret_cast<const int4*>(a.out_count + first + at);
 #pragma unroll
-    for (int q = 0; q < kCells; ++q) {
-      cnt[q] = kk[q];
-      pos[q] = pp[q];
+    for (int i = 0; i < kEmitItems / 4; ++i) {
+      const int4 q = p[i];
+      v[4 * i] = q.x;
+      v[4 * i + 1] = q.y;
+      v[4 * i + 2] = q.z;
+      v[4 * i + 3] = q.w;
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < kCells; ++q) {
-      cnt[q] = c0 + q < n ? a.out_count[c0 + q] : 0;
-      pos[q] = 0;
+    for (int i = 0; i < kEmitItems; ++i) v[i] = at + i < m ? a.out_count[first + at + i] : 0;
+  }
+  // exclusive prefix of the thread sums over the block
+  int sum = 0;
+#pragma unroll
+  for (int i = 0; i < kEmitItems; ++i) sum += v[i];
+  const int incl = wave_incl_scan(sum);
+  if (lane == kWave - 1) s_wave[wave] = incl;
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int w = 0; w < kEmitBlock / kWave; ++w) {
+      const int c = s_wave[w];
+      s_wave[w] = run;
+      run += c;
     }
   }
-  // every record load before any store
-  int4 r0[kCells], r1[kCells];
+  __syncthreads();
+  int run = tile_off[blockIdx.x] + s_wave[wave] + incl - sum;
+  int pos[kEmitItems];
 #pragma unroll
-  for (int q = 0; q < kCells; ++q) {
-    r0[q] = r1[q] = make_int4(0, 0, 0, 0);
-    if (cnt[q] > 0 && cnt[q] <= kLocal) {
-      const int4* sp = reinterpret_cast<const int4*>(a.spill);
-      r0[q] = sp[c0 + q];
-      if (cnt[q] > 4) r1[q] = sp[a.cells_cap + c0 + q];
-      if (!VEC || c0 + kCells > n) pos[q] = a.out_start[c0 + q];
-    }
+  for (int i = 0; i < kEmitItems; ++i) {
+    pos[i] = run;
+    run += v[i];
+    s_cnt[at + i] = v[i];
+    s_pos[at + i] = pos[i];
   }
+  if (vec) {
+    int4* p = reinterpret_cast<int4*>(out_start + first + at);
 #pragma unroll
-  for (int q = 0; q < kCells; ++q)
-    if (cnt[q] > 0 && cnt[q] <= kLocal) emit_cell(a, static_cast<int>(c0 + q), cnt[q], pos[q], r0[q], r1[q]);
+    for (int i = 0; i < kEmitItems / 4; ++i) p[i] = make_int4(pos[4 * i], pos[4 * i + 1], pos[4 * i + 2], pos[4 * i + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kEmitItems; ++i)
+      if (at + i < m) out_start[first + at + i] = pos[i];
+  }
+  __syncthreads();
+  // the links of the cells with 1..kLocal, four rounds of cells at a time:
+  // every record load of the rounds before any store
+  const int4* sp = reinterpret_cast<const int4*>(a.spill);
+  constexpr int kBatch = 4;
+  for (int r0 = 0; r0 < kEmitItems; r0 += kBatch) {
+    int cnt[kBatch], ps[kBatch];
+    int4 q0[kBatch], q1[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int c = (r0 + u) * kEmitBlock + t;
+      cnt[u] = c < m ? s_cnt[c] : 0;
+      ps[u] = c < m ? s_pos[c] : 0;
+      q0[u] = q1[u] = make_int4(0, 0, 0, 0);
+      if (cnt[u] > 0 && cnt[u] <= kLocal) {
+        q0[u] = sp[first + c];
+        if (cnt[u] > 4) q1[u] = sp[a.cells_cap + first + c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (cnt[u] > 0 && cnt[u] <= kLocal)
+        emit_cell(a, static_cast<int>(first + (r0 + u) * kEmitBlock + t), cnt[u], ps[u], q0[u], q1[u]);
+  }
 }
 
 // In-cells with more than kLocal links: one wavefront each recomputes its
@@ -1069,16 +1128,16 @@ static pt_err run_links(const pt_hits& h, const DevCfg& k, const pt_cells& cells
     PT_LAUNCH_CHECK();
   }
   timing_end(tok, "links", s);
-  // first link of each cell, and the number of links
-  PT_HIP_CHECK(exclusive_scan_to(L.out_count, L.out_start, cells.cap, cells.count, L.count, tmp, s));
+  // first link of each cell and the links: the tile sums of the counts are
+  // scanned, then each tile scans itself and places its links
+  const int32_t* tile_off = nullptr;
+  PT_HIP_CHECK(scan_tile_offsets(L.out_count, cells.cap, cells.count, tmp, s, &tile_off));
   tok = timing_begin(s);
   EmitArgs e{cells.count, cells.cap, L.out_start, L.out_count, spill, L.cap, L.in_cell, L.out_cell};
-  if (reinterpret_cast<uintptr_t>(L.out_count) % 16 == 0 && reinterpret_cast<uintptr_t>(L.out_start) % 16 == 0)
-    k_link_emit<true><<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + 4 * kEmitBlock - 1) / (4 * kEmitBlock)),
-                        kEmitBlock, 0, s>>>(e);
-  else
-    k_link_emit<false><<<static_cast<unsigned>((static_cast<int64_t>(cells.cap) + kEmitBlock - 1) / kEmitBlock),
-                         kEmitBlock, 0, s>>>(e);
+  {
+    const int64_t tiles = std::max<int64_t>(1, (static_cast<int64_t>(cells.cap) + kScanTile - 1) / kScanTile);
+    k_link_place<<<static_cast<unsigned>(tiles), kEmitBlock, 0, s>>>(e, tile_off, L.out_start, L.count);
+  }
   timing_end(tok, "link_emit", s);
   PT_LAUNCH_CHECK();
   k_links_overflow<T><<<1024, kOvfWaves * kWave, 0, s>>>(k, a, cells.inner, h.layer, L.out_start, L.cap, L.in_cell,

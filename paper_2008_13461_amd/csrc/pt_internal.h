@@ -111,6 +111,13 @@ hipError_t exclusive_scan_dev(int32_t* data, int64_t n, const int32_t* n_dev, in
 // (dst[that count] when total is null).  src may equal dst.
 hipError_t exclusive_scan_to(const int32_t* src, int32_t* dst, int64_t n, const int32_t* n_dev, int32_t* total,
                              int32_t* tmp, hipStream_t s);
+// The first step of such a scan alone, for a kernel that scans its own tile
+// of kScanTile values: *offsets (in tmp) receives, for each of the
+// ceil(n / kScanTile) tiles, the sum of the values before it, and after them
+// the total (the values counted as above).
+constexpr int kScanTile = 4096;
+hipError_t scan_tile_offsets(const int32_t* src, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s,
+                             const int32_t** offsets);
 
 // Fill helpers (graph-safe: kernels, not hipMemsetAsync).
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

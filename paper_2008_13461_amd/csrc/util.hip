@@ -7,6 +7,7 @@ namespace {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kTile = kScanBlock * kScanItems;
+static_assert(kTile == kScanTile, "the tile of the declared scan steps");
 
 // Inclusive scan of one int32 per thread across the block; returns the
 // inclusive value and writes the block total to *total.
@@ -170,6 +171,17 @@ hipError_t exclusive_scan_to(const int32_t* src, int32_t* dst, int64_t n, const 
   else
     k_tile_scan<false><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(src, dst, n, n_dev, offsets, total);
   return hipGetLastError();
+}
+
+hipError_t scan_tile_offsets(const int32_t* src, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s,
+                             const int32_t** offsets) {
+  const int64_t nb = n > 0 ? (n + kTile - 1) / kTile : 1;
+  *offsets = tmp;
+  if (n <= 0) return fill_i32(tmp, 0, 2, s);
+  k_tile_sums<<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(src, n, n_dev, tmp);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return exclusive_scan_dev(tmp, nb, nullptr, tmp + nb + 1, s);
 }
 
 hipError_t exclusive_scan_dev(int32_t* data, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s) {
