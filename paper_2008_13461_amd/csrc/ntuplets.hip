@@ -220,45 +220,69 @@ __global__ void __launch_bounds__(kWave) k_mask_write(const int32_t* __restrict_
   }
 }
 
-// The roots that emit a row (paths scanned: root i emits rows
-// [paths[i], paths[i + 1]), kept when some of them lie below the capacity),
-// counted per chunk of kRootChunk roots and flagged in a bit mask as
-// k_root_count does for cells.
-__global__ void __launch_bounds__(kBlock) k_prod_count(TupIn a, const int32_t* __restrict__ paths,
+// The roots that emit a row, from the rows each root emits (paths[i], the
+// count pass's output): each block scans its chunk of kRootChunk counts
+// (16 consecutive ones per thread; the chunk's offset comes from the scan of
+// the chunk sums) into first rows, writes the first row of every root that
+// emits one below the capacity over its count (the only first rows the
+// write pass reads), flags those roots in a bit mask (word w: roots
+// base + 64 w .. + 63) and counts them per chunk.  Block 0 writes the total
+// number of rows after the last root.
+__global__ void __launch_bounds__(kBlock) k_prod_count(TupIn a, int32_t* __restrict__ paths,
+                                                       const int32_t* __restrict__ chunk_off,
                                                        int32_t* __restrict__ chunk_count, uint64_t* __restrict__ bits) {
-  constexpr int kWaves = kBlock / kWave;
-  __shared__ uint64_t s_bits[kRootWords];
-  __shared__ int32_t s_cnt[kWaves];
+  static_assert(kRootItems == 16 && kBlock / 4 == kRootWords, "four threads' 16-bit masks per mask word");
+  __shared__ int32_t s_scan[kBlock / kWave + 1];
+  __shared__ uint16_t s_m16[kBlock];
   const int nr = min(*a.n_roots, a.cells_cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) paths[nr] = chunk_off[gridDim.x];
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kRootChunk;
   if (base >= nr) {
     if (threadIdx.x == 0) chunk_count[blockIdx.x] = 0;
     return;
   }
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  int p0[kRootItems], p1[kRootItems];
+  const int64_t at = base + static_cast<int64_t>(threadIdx.x) * kRootItems;
+  int c[kRootItems];
+  if (base + kRootChunk <= nr && reinterpret_cast<uintptr_t>(paths) % 16 == 0) {
+    const int4* p = reinterpret_cast<const int4*>(paths + at);
 #pragma unroll
-  for (int i = 0; i < kRootItems; ++i) {
-    const int64_t r = base + i * kBlock + threadIdx.x;
-    p0[i] = r < nr ? paths[r] : 0;
-    p1[i] = r < nr ? paths[r + 1] : 0;
+    for (int i = 0; i < kRootItems / 4; ++i) {
+      const int4 q = p[i];
+      c[4 * i] = q.x;
+      c[4 * i + 1] = q.y;
+      c[4 * i + 2] = q.z;
+      c[4 * i + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kRootItems; ++i) c[i] = at + i < nr ? paths[at + i] : 0;
   }
+  int sum = 0;
+#pragma unroll
+  for (int i = 0; i < kRootItems; ++i) sum += c[i];
+  int tot;
+  int run = chunk_off[blockIdx.x] + block_exclusive(sum, s_scan, &tot);  // every count is read by now
+  uint32_t m16 = 0;
   int cnt = 0;
 #pragma unroll
   for (int i = 0; i < kRootItems; ++i) {
-    const uint64_t m = __ballot(p1[i] > p0[i] && p0[i] < a.cap);
-    cnt += __popcll(m);
-    if (lane == 0) s_bits[i * kWaves + wave] = m;
+    if (c[i] > 0 && run < a.cap) {
+      m16 |= 1u << i;
+      paths[at + i] = run;
+      ++cnt;
+    }
+    run += c[i];
   }
-  if (lane == 0) s_cnt[wave] = cnt;
-  __syncthreads();
-  if (threadIdx.x < kRootWords) bits[blockIdx.x * static_cast<int64_t>(kRootWords) + threadIdx.x] = s_bits[threadIdx.x];
-  if (threadIdx.x == 0) {
-    int total = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) total += s_cnt[w];
-    chunk_count[blockIdx.x] = total;
+  s_m16[threadIdx.x] = static_cast<uint16_t>(m16);
+  int n_prod;
+  block_exclusive(cnt, s_scan, &n_prod);  // its barriers also order the mask writes
+  if (threadIdx.x < kRootWords) {
+    const int q = 4 * threadIdx.x;
+    bits[blockIdx.x * static_cast<int64_t>(kRootWords) + threadIdx.x] =
+        static_cast<uint64_t>(s_m16[q]) | (static_cast<uint64_t>(s_m16[q + 1]) << 16) |
+        (static_cast<uint64_t>(s_m16[q + 2]) << 32) | (static_cast<uint64_t>(s_m16[q + 3]) << 48);
   }
+  if (threadIdx.x == 0) chunk_count[blockIdx.x] = n_prod;
 }
 
 // Depth-first search from each root.  COUNT: paths[i] = rows root i emits
@@ -498,9 +522,13 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   k_dfs<true><<<grid_for(cells.cap, 256, 65536), 256, 0, s>>>(k, a, paths, nullptr, nullptr);
   timing_end(tok, "dfs_count", s);
   PT_LAUNCH_CHECK();
-  PT_HIP_CHECK(exclusive_scan_dev(paths, cells.cap, n_roots, tmp, s));
+  // first rows: the chunk sums of the counts are scanned, then each chunk
+  // scans itself (and writes the total rows after the last root)
+  static_assert(kRootChunk == kScanTile, "the chunks are the scan's tiles");
+  const int32_t* row_off = nullptr;
+  PT_HIP_CHECK(scan_tile_offsets(paths, cells.cap, n_roots, tmp, s, &row_off));
   tok = timing_begin(s);
-  k_prod_count<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(a, paths, chunk_prod, root_bits);
+  k_prod_count<<<static_cast<unsigned>(chunks), kBlock, 0, s>>>(a, paths, row_off, chunk_prod, root_bits);
   PT_LAUNCH_CHECK();
   PT_HIP_CHECK(exclusive_scan(chunk_prod, chunks, tmp, s));
   k_mask_write<<<static_cast<unsigned>(chunks), kWave, 0, s>>>(n_roots, cells.cap, root_bits, chunk_prod, prod);
@@ -508,7 +536,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   k_dfs<false><<<grid_for(cells.cap, 128, 16384), 128, 0, s>>>(k, a, paths, prod, chunk_prod + chunks);
   timing_end(tok, "dfs_write", s);
   PT_LAUNCH_CHECK();
-  // rows found = paths[n_roots] (the scan's total)
+  // rows found = paths[n_roots] (written by k_prod_count)
   k_copy_total_rows<<<1, 1, 0, s>>>(paths, n_roots, T.count_raw);
   PT_LAUNCH_CHECK();
   k_row_hits<<<grid_for(T.cap, 256, 8192), 256, 0, s>>>(a);
