@@ -840,16 +840,16 @@ __device__ __forceinline__ void emit_cell(const EmitArgs& a, int c, int cnt, int
 // from their records.  Cells with more than kLocal links are written by
 // k_links_overflow.  The counts are read once, the positions never read
 // back: each thread scans kEmitItems consecutive counts (16-byte vectors),
-// the counts and positions go through LDS, and the records are then taken
-// one cell per thread and round, consecutive cells on consecutive lanes.
+// the positions go through LDS (a count is the difference of two), and the
+// records are then taken one cell per thread and round, consecutive cells
+// on consecutive lanes.
 constexpr int kEmitBlock = 256;
 constexpr int kEmitItems = kScanTile / kEmitBlock;
 static_assert(kEmitItems % 4 == 0, "counts are read as 16-byte vectors");
 
 __global__ void __launch_bounds__(kEmitBlock) k_link_place(EmitArgs a, const int32_t* __restrict__ tile_off,
                                                           int32_t* __restrict__ out_start, int32_t* __restrict__ total) {
-  __shared__ int32_t s_cnt[kScanTile];
-  __shared__ int32_t s_pos[kScanTile];
+  __shared__ int32_t s_pos[kScanTile + 1];  // positions; a cell's count is the difference to the next
   __shared__ int32_t s_wave[kEmitBlock / kWave + 1];
   if (blockIdx.x == 0 && threadIdx.x == 0) *total = tile_off[gridDim.x];
   const int n = min(*a.cell_count, a.cells_cap);
@@ -899,9 +899,9 @@ __global__ void __launch_bounds__(kEmitBlock) k_link_place(EmitArgs a, const int
   for (int i = 0; i < kEmitItems; ++i) {
     pos[i] = run;
     run += v[i];
-    s_cnt[at + i] = v[i];
     s_pos[at + i] = pos[i];
   }
+  if (t == kEmitBlock - 1) s_pos[kScanTile] = run;  // the tile's end (cells past m count nothing)
   if (vec) {
     int4* p = reinterpret_cast<int4*>(out_start + first + at);
 #pragma unroll
@@ -922,8 +922,8 @@ __global__ void __launch_bounds__(kEmitBlock) k_link_place(EmitArgs a, const int
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int c = (r0 + u) * kEmitBlock + t;
-      cnt[u] = c < m ? s_cnt[c] : 0;
       ps[u] = c < m ? s_pos[c] : 0;
+      cnt[u] = c < m ? s_pos[c + 1] - ps[u] : 0;
       q0[u] = q1[u] = make_int4(0, 0, 0, 0);
       if (cnt[u] > 0 && cnt[u] <= kLocal) {
         q0[u] = sp[first + c];
