@@ -339,7 +339,7 @@ template <class T>
 struct alignas(16) WaveLds {
   int32_t queue[2 * kWave];      // queued pairs: out-cell offset << 6 | in-cell lane
   int32_t cnt[kWave];            // links found per in-cell lane
-  int32_t found[kWave * kLocal]; // their out-cells
+  uint16_t found[kWave * kLocal];  // their out-cells' offsets in the hit's out-cells (windowed search)
   int32_t sfirst[kSegWin];       // a window of the hit's segments: first entry ...
   int32_t spre[kSegWin + 1];     // ... and the in-cells before each (exclusive prefix)
   int32_t segat[kWave];          // segment starting at each in-cell of a pass, or -1
@@ -348,7 +348,7 @@ struct alignas(16) WaveLds {
   // bit << 15), bucket B - 1 copied in front and bucket 0 behind, and where
   // each bucket starts
   double wdr[kWinCap];
-  double wdz[kWinCap];
+  T wz2[kWinCap];  // the outer hit's z (dz = z2 - Z1 as the doublet step computes it)
   uint16_t wj[kWinCap];
   uint16_t bst[kRzBuckets + 1];
   // and the outer hits' x and y, by out-cell offset (values of the input
@@ -357,7 +357,8 @@ struct alignas(16) WaveLds {
   T wy2[kWinCap];
 };
 static_assert(kRzBuckets <= 2 * kWave, "the bucket counts use the queue, two buckets per lane");
-static_assert(kWinCap <= kWave * kLocal && kWinCap <= 0x8000, "staging uses the found array; offsets fit 15 bits");
+static_assert(kWinCap * sizeof(int32_t) <= sizeof(WaveLds<float>::found) && kWinCap <= 0x8000,
+              "staging uses the found array; offsets fit 15 bits");
 
 template <class T>
 struct HitArgs {
@@ -383,17 +384,21 @@ struct HitArgs {
 // Beam-spot test of the first nq queued pairs, one per lane; cb is the first
 // out-cell of the segment the queued offsets refer to, hb its offset in the
 // hit's out-cells (for the has_inner bits).  The in-cells' inner hits (X0,
-// Y0, BPix1 flag) are read from the lanes that hold them; all lanes call it.
+// Y0, BPix1 flag, cell) are read from the lanes that hold them; all lanes
+// call it.  The windowed search (staged) keeps the links in LDS as offsets
+// in the hit's out-cells; the sweeps of larger hits write them straight to
+// the in-cell's record.
 template <class T>
 __device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L, int nq, int cb,
                                            int hb, double X1, double Y1, double X0l, double Y0l, int bpix1l,
-                                           bool staged) {
+                                           int celll, bool staged) {
   const int lane = __lane_id();
   const int e = lane < nq ? L.queue[lane] : 0;
   const int j = e >> 6;
   const int li = e & (kWave - 1);
   const double X0 = __shfl(X0l, li, kWave), Y0 = __shfl(Y0l, li, kWave);
   const int bpix1 = __shfl(bpix1l, li, kWave);
+  const int cl = __shfl(celll, li, kWave);
   if (lane < nq) {
     double X2, Y2;
     if (staged) {  // the windowed search staged the outer hits
@@ -407,7 +412,14 @@ __device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a,
     const double rmax = bpix1 ? k.rmax_bpix1 : k.rmax_other;
     if (beam_pass(X0, Y0, X1, Y1, X2, Y2, rmax)) {
       const int slot = atomicAdd(&L.cnt[li], 1);
-      if (slot < kLocal) L.found[li * kLocal + slot] = cb + j;
+      if (slot < kLocal) {
+        if (staged) {
+          L.found[li * kLocal + slot] = static_cast<uint16_t>(hb + j);
+        } else {
+          const int64_t row = slot < 4 ? cl : static_cast<int64_t>(a.cells_cap) + cl;
+          a.spill[row * 4 + (slot & 3)] = cb + j;
+        }
+      }
       const int bit = hb + j;
       if (bit < kHinBits)
         atomicOr(&L.hin[bit >> 5], 1u << (bit & 31));
@@ -418,7 +430,7 @@ __device__ __forceinline__ void beam_batch(const DevCfg& k, const HitArgs<T>& a,
 }
 
 // Stages the hit's nb out-cells (from cb on) for the windowed search, sorted
-// by bucket into wdr / wdz / wj, and the bucket starts into bst; (R1, Z1)
+// by bucket into wdr / wz2 / wj, and the bucket starts into bst; (R1, Z1)
 // is the middle hit.  Returns false (wave-uniform) when an out-cell has no
 // key or the list with its copies does not fit; the hit is then swept pair
 // by pair.
@@ -428,25 +440,27 @@ __device__ bool stage_window(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L
   const int lane = __lane_id();
   const int B = k.rz_buckets;
   int32_t* hist = L.queue;  // bucket counts (the queue is empty between passes)
-  int32_t* tmp = L.found;   // per out-cell: bucket | rank in the bucket << 8
+  int32_t* tmp = reinterpret_cast<int32_t*>(L.found);  // per out-cell: bucket | rank in the bucket << 8
   for (int b = lane; b < B; b += kWave) hist[b] = 0;
   wave_sync();
   bool bad = false;
   // out-cell j = r kWave + lane; its segment stays in registers
   constexpr int kRounds = (kWinCap + kWave - 1) / kWave;
-  double sdr[kRounds], sdz[kRounds];
+  double sdr[kRounds];
+  T sz2[kRounds];
   bool send[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const int j = r * kWave + lane;
-    sdr[r] = sdz[r] = 0.0;
+    sdr[r] = 0.0;
+    sz2[r] = T(0);
     send[r] = false;
     if (j < nb) {
       const double4 P2 = a.hx[a.outer[cb + j]];
       sdr[r] = P2.w - R1;  // as the doublet step computes dr and dz
-      sdz[r] = P2.z - Z1;
+      sz2[r] = static_cast<T>(P2.z);  // exact: the hit table holds values of the input type
       send[r] = endcap_outer(k, a.pair[cb + j]);
-      const float key = rz_key(sdr[r], sdz[r]);
+      const float key = rz_key(sdr[r], P2.z - Z1);
       bad |= !(key == key);
       const int b = key == key ? rz_bucket(key, B) : 0;
       tmp[j] = b | (atomicAdd(&hist[b], 1) << 8);
@@ -476,18 +490,19 @@ __device__ bool stage_window(const DevCfg& k, const HitArgs<T>& a, WaveLds<T>& L
   for (int q = 0; q < kRounds; ++q) {
     const int j = q * kWave + lane;
     if (j >= nb) continue;
-    const double dr = sdr[q], dz = sdz[q];
+    const double dr = sdr[q];
+    const T z2 = sz2[q];
     const int v = tmp[j];
     const int b = v & 0xFF, r = v >> 8;
     const uint16_t jv = static_cast<uint16_t>(j | (send[q] ? 0x8000 : 0));
     const int at = L.bst[b] + r;
     L.wdr[at] = dr;
-    L.wdz[at] = dz;
+    L.wz2[at] = z2;
     L.wj[at] = jv;
     if (b == B - 1 || b == 0) {  // its copy at the other end
       const int c = b == B - 1 ? r : front + nb + r;
       L.wdr[c] = dr;
-      L.wdz[c] = dz;
+      L.wz2[c] = z2;
       L.wj[c] = jv;
     }
   }
@@ -600,7 +615,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
           qn += __popcll(mk);
           if (qn >= kWave) {
             wave_sync();
-            beam_batch(k, a, L, kWave, cs, jb, X1, Y1, X0, Y0, bpix1, win);
+            beam_batch(k, a, L, kWave, cs, jb, X1, Y1, X0, Y0, bpix1, cell, win);
             qn -= kWave;
             const int t = (lane < qn) ? L.queue[kWave + lane] : 0;
             wave_sync();
@@ -665,7 +680,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
             bool pass = false;
             int j = 0;
             if (f < npairs) {
-              const double br = L.wdr[at], bz = L.wdz[at];
+              const double br = L.wdr[at], bz = static_cast<double>(L.wz2[at]) - Z1;
               const int jv = L.wj[at];
               pass = rz_pass(oar, oaz, oLa, br, bz, br * br + bz * bz, (jv & 0x8000) ? th2e : th2b);
               j = jv & 0x7FFF;
@@ -675,7 +690,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
           }
           if (qn > 0) {
             wave_sync();
-            beam_batch(k, a, L, qn, cs, jb, X1, Y1, X0, Y0, bpix1, win);
+            beam_batch(k, a, L, qn, cs, jb, X1, Y1, X0, Y0, bpix1, cell, win);
           }
           wave_sync();
           continue;
@@ -701,7 +716,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
           }
           if (qn > 0) {
             wave_sync();
-            beam_batch(k, a, L, qn, cs, jb, X1, Y1, X0, Y0, bpix1, win);
+            beam_batch(k, a, L, qn, cs, jb, X1, Y1, X0, Y0, bpix1, cell, win);
           }
           wave_sync();
           continue;
@@ -753,7 +768,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
         }
         if (qn > 0) {
           wave_sync();
-          beam_batch(k, a, L, qn, cs, jb, X1, Y1, X0, Y0, bpix1, win);
+          beam_batch(k, a, L, qn, cs, jb, X1, Y1, X0, Y0, bpix1, cell, win);
         }
         wave_sync();
       }
@@ -768,14 +783,15 @@ __global__ void __launch_bounds__(WAVES * kWave)
           a.ovf[slot] = cell;
         }
       }
-      if (n > 0 && n <= kLocal) {  // the links are sorted by k_link_place
+      if (win && n > 0 && n <= kLocal) {  // the links are sorted by k_link_place
         static_assert(kRow == 8 && kLocal == 8, "a record is two 16-byte vectors");
         // two halves of 16 bytes per cell, so that the records of the cells
-        // with at most four links (nearly all) are dense
+        // with at most four links (nearly all) are dense; places past n are
+        // never read.  (The sweeps wrote their records as they went.)
         int4* sp = reinterpret_cast<int4*>(a.spill);
-        const int4* fl = reinterpret_cast<const int4*>(L.found + lane * kLocal);
-        sp[cell] = fl[0];  // places past n are never read
-        if (n > 4) sp[static_cast<int64_t>(a.cells_cap) + cell] = fl[1];
+        const uint16_t* fl = L.found + lane * kLocal;
+        sp[cell] = make_int4(cb + fl[0], cb + fl[1], cb + fl[2], cb + fl[3]);
+        if (n > 4) sp[static_cast<int64_t>(a.cells_cap) + cell] = make_int4(cb + fl[4], cb + fl[5], cb + fl[6], cb + fl[7]);
       }
       wave_sync();
     }
