@@ -143,7 +143,7 @@ template <class T, int CAP, int WAVES, bool LISTED>
 __global__ void __launch_bounds__(WAVES * kWave) k_fb_kill(FbArgs<T> a) {
   __shared__ int32_t s_bin[WAVES][kNB + 1];   // cells per key bucket, then first position
   __shared__ int32_t s_bk[WAVES][CAP];        // per staged cell: bucket | rank in it << 16
-  __shared__ int32_t s_val[WAVES][CAP];       // staged cells in bucket order
+  __shared__ uint16_t s_val[WAVES][CAP];      // staged cells in bucket order (16 bits: five work-groups fit per CU)
   __shared__ int32_t s_cell[WAVES][CAP];
   __shared__ float s_phi[WAVES][CAP];
   __shared__ T s_x[WAVES][CAP];               // the inner hit's coordinates
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(WAVES * kWave) k_fb_kill(FbArgs<T> a) {
   wave_sync();
   for (int i = lane; i < m; i += kWave) {
     const int v = s_bk[w][i];
-    s_val[w][s_bin[w][v & 0xffff] + (v >> 16)] = i;
+    s_val[w][s_bin[w][v & 0xffff] + (v >> 16)] = static_cast<uint16_t>(i);
   }
   wave_sync();
   // each cell against the cells of its bucket and the two next to it, and of
