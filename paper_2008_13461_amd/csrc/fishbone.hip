@@ -21,6 +21,7 @@
 // contraction, from the hits' coordinates promoted to double.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "pt_internal.h"
 
@@ -95,12 +96,28 @@ __device__ inline float azimuth(double ux, double uy, double uz) {
   return t2 >= (kS0 * kS0) * l2 ? atan2f(float(uy), float(ux)) : kNoPhi;
 }
 
+// Azimuths are staged as 16-bit quanta of 2 pi / 65535 (kNoPhiQ: none).
+// The test on quanta accepts every pair whose float azimuths are within the
+// window (a quantum is the floor of the scaled azimuth, so two are at most
+// one quantum further apart than the azimuths, and the window is widened by
+// two quanta): it stays a filter in front of the exact test.
+constexpr float kPhiScale = 65535.f / 6.28318531f;
+constexpr int kNoPhiQ = 0xFFFF;
+__device__ inline uint16_t phi_quantum(float phi) {
+  if (phi == kNoPhi) return kNoPhiQ;
+  const int q = static_cast<int>((phi + 3.14159265f) * kPhiScale);
+  return static_cast<uint16_t>(min(max(q, 0), kNoPhiQ - 1));
+}
+// The window in quanta (the whole circle when the azimuth test is off).
+__device__ inline int phi_window_q(float win) {
+  return win >= 3.2f ? 65535 : static_cast<int>(ceilf(win * kPhiScale)) + 2;
+}
 // Whether two azimuths allow an angle within the cut (opp: nearly opposite).
-__device__ inline bool phi_ok(float pi, float pj, float win, bool opp) {
-  if (pi == kNoPhi || pj == kNoPhi) return true;
-  float d = fabsf(pi - pj);
-  if (d > 3.14159265f) d = 6.28318531f - d;
-  return (opp ? 3.14159265f - d : d) <= win;
+__device__ inline bool phi_ok(int qi, int qj, int wq, bool opp) {
+  if (qi == kNoPhiQ || qj == kNoPhiQ) return true;
+  int d = abs(qi - qj);
+  d = min(d, 65535 - d);
+  return opp ? 2 * d >= 65535 - 2 * wq : d <= wq;
 }
 
 // Bucket of a key in [-1, 1] among nb buckets of width 2 / nb.
@@ -142,10 +159,14 @@ __global__ void k_fb_flags(FbArgs<T> a) {
 template <class T, int CAP, int WAVES, bool LISTED>
 __global__ void __launch_bounds__(WAVES * kWave) k_fb_kill(FbArgs<T> a) {
   __shared__ int32_t s_bin[WAVES][kNB + 1];   // cells per key bucket, then first position
-  __shared__ int32_t s_bk[WAVES][CAP];        // per staged cell: bucket | rank in it << 16
+  // per staged cell: bucket | rank in it << kBkShift (16 bits when both fit 8)
+  constexpr int kBkShift = CAP <= 256 ? 8 : 16;
+  static_assert(kNB <= 256 && CAP <= 0x10000, "buckets fit 8 bits, ranks the rest");
+  using Bk = std::conditional_t<CAP <= 256, uint16_t, int32_t>;
+  __shared__ Bk s_bk[WAVES][CAP];
   __shared__ uint16_t s_val[WAVES][CAP];      // staged cells in bucket order (16 bits: five work-groups fit per CU)
   __shared__ int32_t s_cell[WAVES][CAP];
-  __shared__ float s_phi[WAVES][CAP];
+  __shared__ uint16_t s_phi[WAVES][CAP];      // azimuth quanta
   __shared__ T s_x[WAVES][CAP];               // the inner hit's coordinates
   __shared__ T s_y[WAVES][CAP];
   __shared__ T s_z[WAVES][CAP];
@@ -205,10 +226,10 @@ __global__ void __launch_bounds__(WAVES * kWave) k_fb_kill(FbArgs<T> a) {
       s_y[w][at + f] = hy;
       s_z[w][at + f] = hz;
       const double ux = Xh - double(hx), uy = Yh - double(hy), uz = Zh - double(hz);
-      s_phi[w][at + f] = azimuth(ux, uy, uz);
+      s_phi[w][at + f] = phi_quantum(azimuth(ux, uy, uz));
       const float kz = polar_key(ux, uy, uz);
       const int b = bucket(kz, a.nb);
-      s_bk[w][at + f] = b | (atomicAdd(&s_bin[w][b], 1) << 16);
+      s_bk[w][at + f] = static_cast<Bk>(b | (atomicAdd(&s_bin[w][b], 1) << kBkShift));
       // key of the vector about the outer hit's transverse direction
       const double ur = ux * nx + uy * ny;
       const double ox = ux - ur * nx, oy = uy - ur * ny;
@@ -240,26 +261,26 @@ __global__ void __launch_bounds__(WAVES * kWave) k_fb_kill(FbArgs<T> a) {
   wave_sync();
   for (int i = lane; i < m; i += kWave) {
     const int v = s_bk[w][i];
-    s_val[w][s_bin[w][v & 0xffff] + (v >> 16)] = static_cast<uint16_t>(i);
+    s_val[w][s_bin[w][v & ((1 << kBkShift) - 1)] + (v >> kBkShift)] = static_cast<uint16_t>(i);
   }
   wave_sync();
   // each cell against the cells of its bucket and the two next to it, and of
   // the buckets around its negated key (nearly opposite vectors); the
   // azimuth test first, the exact test from the staged coordinates last
-  const float phw = a.phwin;
+  const int wq = phi_window_q(a.phwin);
   for (int i = lane; i < m; i += kWave) {
     const double ux = Xh - double(s_x[w][i]), uy = Yh - double(s_y[w][i]), uz = Zh - double(s_z[w][i]);
     const double U2 = (ux * ux + uy * uy) + uz * uz;
     bool killed = false;
     const int nb = a.nb;
     const float ki = polar_key(ux, uy, uz);  // the staged key, recomputed
-    const float pi = s_phi[w][i];
+    const int pi = s_phi[w][i];
     for (int pass = 0; pass < (mirror ? 2 : 1) && !killed; ++pass) {
       const int c = bucket(pass == 0 ? ki : -ki, nb);
       const int q0 = s_bin[w][max(c - 1, 0)], q1 = s_bin[w][min(c + 2, nb)];
       for (int q = q0; q < q1 && !killed; ++q) {
         const int j = s_val[w][q];
-        if (j == i || !phi_ok(pi, s_phi[w][j], phw, pass == 1)) continue;
+        if (j == i || !phi_ok(pi, s_phi[w][j], wq, pass == 1)) continue;
         const double vx = Xh - double(s_x[w][j]), vy = Yh - double(s_y[w][j]), vz = Zh - double(s_z[w][j]);
         const double V2 = (vx * vx + vy * vy) + vz * vz;
         killed = kills(ux, uy, uz, U2, vx, vy, vz, V2, a.theta2);
