@@ -56,7 +56,7 @@ typedef enum {
   PT_OK = 0,
   PT_ERR_ARG = 1,         /* invalid argument; nothing was enqueued */
   PT_ERR_DEVICE = 2,      /* a HIP runtime call or kernel launch failed */
-  PT_ERR_UNSUPPORTED = 3, /* valid request that this build does not implement */
+  PT_ERR_UNSUPPORTED = 3, /* valid request that the library does not implement */
   PT_ERR_WORKSPACE = 4,   /* workspace smaller than pt_workspace_size() */
   PT_ERR_TOO_LARGE = 5    /* request beyond the fixed scratch of pt_fit_broken_line_noalloc */
 } pt_err;
