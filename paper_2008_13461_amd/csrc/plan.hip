@@ -169,6 +169,7 @@ pt_err pt_plan_create(const pt_config* cfg, int32_t n_hits_max, int32_t n_events
     delete p;
     return PT_ERR_ARG;
   }
+  if (p->dev.fishbone_theta2 > 0.0) fishbone_prepare();
   hipError_t he = hipMalloc(&p->ws, p->ws_bytes);
   if (he == hipSuccess) he = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
   if (he != hipSuccess) {

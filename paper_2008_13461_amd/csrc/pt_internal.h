@@ -85,6 +85,9 @@ size_t ws_ntuplets(int cells_cap, int tuplets_cap);
 size_t ws_fit(int n_max, int n_modules);
 size_t ws_ambiguity(int n_hits, int cells_cap, int n_max);
 size_t ws_fishbone(int n_hits, int cells_cap);
+// Host-side set-up of the Fishbone's launch shapes (device queries), done
+// before a plan captures its graph.
+void fishbone_prepare();
 
 // The index of the stored cells by outer hit (links.hip): hit h's cells are
 // the entries ent[f .. f + k) (cell, inner hit with bit 31 set when on
