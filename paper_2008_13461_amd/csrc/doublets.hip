@@ -1,8 +1,9 @@
 // Doublet building (paper section 3.2, Table 1).
 //
 // Hits are first binned per (event, layer, azimuth bin) by a counting sort
-// (the "tiled data structure along phi" of the paper), with the sorted
-// coordinates promoted to double.  Doublets are then built by one wavefront
+// (the "tiled data structure along phi" of the paper), with sorted copies
+// of the coordinates (in the input type, converted to double exactly where
+// they are used) and of R in double.  Doublets are then built by one wavefront
 // per inner hit that loops over the layer pairs starting on its layer and
 // scans the outer hits in the azimuth bins around it, one outer hit per lane.
 // Two passes -- count, scan, write -- give every inner hit a contiguous,
@@ -141,8 +142,8 @@ __global__ void k_scatter(HitsIn<T> in, const int32_t* __restrict__ key, const i
 template <class T>
 __global__ void k_bin_order(HitsIn<T> in, const int32_t* __restrict__ valid, const int32_t* __restrict__ bin_start,
                             const int32_t* __restrict__ arrived, const int32_t* __restrict__ skey,
-                            int32_t* __restrict__ sorted_hit, double* __restrict__ sX, double* __restrict__ sY,
-                            double* __restrict__ sZ, double* __restrict__ sR) {
+                            int32_t* __restrict__ sorted_hit, T* __restrict__ sX, T* __restrict__ sY,
+                            T* __restrict__ sZ, double* __restrict__ sR) {
   const int total = *valid;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
     const int k = skey[p];
@@ -154,21 +155,22 @@ __global__ void k_bin_order(HitsIn<T> in, const int32_t* __restrict__ valid, con
     const double X = static_cast<double>(in.x[h]);
     const double Y = static_cast<double>(in.y[h]);
     sorted_hit[pos] = h;
-    sX[pos] = X;
-    sY[pos] = Y;
-    sZ[pos] = static_cast<double>(in.z[h]);
+    sX[pos] = in.x[h];  // in the input type: converted where used, exactly
+    sY[pos] = in.y[h];
+    sZ[pos] = in.z[h];
     sR[pos] = sqrt(X * X + Y * Y);
   }
 }
 
+template <class T>
 struct DoubletArgs {
   int32_t n_hits;
   const int32_t* bin_start;
   const int32_t* skey;
   const int32_t* sorted_hit;
-  const double* sX;
-  const double* sY;
-  const double* sZ;
+  const T* sX;  // sorted coordinates in the input type (4 bytes each for float hits)
+  const T* sY;
+  const T* sZ;
   const double* sR;
   int32_t* cnt;            // pass 1: per sorted inner hit
   const int32_t* off;      // pass 2: scanned counts
@@ -232,8 +234,8 @@ static_assert(kMaskChunks == kWave, "one kept group per lane");
 // single-wavefront hits per block measured fastest for the stores.
 constexpr int kWriteBlock = 256;
 
-template <bool WRITE, int WAVES, bool ALL>
-__global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArgs a) {
+template <bool WRITE, int WAVES, bool ALL, class T>
+__global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArgs<T> a) {
   __shared__ int32_t s_out[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   __shared__ uint8_t s_pair[WRITE ? WAVES : 1][WRITE ? kStage : 1];
   __shared__ int4 s_chunk[WRITE ? WAVES : 1][WRITE ? kMaskChunks : 1];
@@ -258,7 +260,7 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   const int el = sh >= 0 ? (key >> sh) : key / B;
   const int lay = el % kLayers;
   const int e = el / kLayers;
-  const double Xi = a.sX[j], Yi = a.sY[j], Zi = a.sZ[j], Ri = a.sR[j];
+  const double Xi = double(a.sX[j]), Yi = double(a.sY[j]), Zi = double(a.sZ[j]), Ri = a.sR[j];
   const int first = WRITE ? a.off[j] : 0;
   const int last = WRITE ? a.off[j + 1] : 0;
   int pos = first;  // uniform: next cell position (write pass) or count
@@ -342,7 +344,7 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
         const int o = o0 + lane;
         const int oc = min(o, rb[r] - 1);  // lanes past the range test its last hit and are masked out
         const bool pass = static_cast<int>(o < rb[r]) &
-                          static_cast<int>(doublet_pass<ALL>(k, tdphi, Xi, Yi, Zi, Ri, a.sX[oc], a.sY[oc], a.sZ[oc],
+                          static_cast<int>(doublet_pass<ALL>(k, tdphi, Xi, Yi, Zi, Ri, double(a.sX[oc]), double(a.sY[oc]), double(a.sZ[oc]),
                                                              a.sR[oc]));
         const uint64_t m = __ballot(pass);
         if (WRITE) {
@@ -415,30 +417,30 @@ size_t ws_doublets(int n_hits, int n_events, int n_bins) {
   return c.off + 256;
 }
 
-template <bool WRITE, bool ALL>
-static void launch_doublets_as(const DevCfg& k, const DoubletArgs& a, int n, int block, hipStream_t s) {
+template <bool WRITE, bool ALL, class T>
+static void launch_doublets_as(const DevCfg& k, const DoubletArgs<T>& a, int n, int block, hipStream_t s) {
   const int64_t hits = std::max(n, 1);
   switch (block) {
     case 64:
-      k_doublets<WRITE, 1, ALL><<<static_cast<unsigned>(hits), 64, 0, s>>>(k, a);
+      k_doublets<WRITE, 1, ALL, T><<<static_cast<unsigned>(hits), 64, 0, s>>>(k, a);
       break;
     case 128:
-      k_doublets<WRITE, 2, ALL><<<static_cast<unsigned>((hits + 1) / 2), 128, 0, s>>>(k, a);
+      k_doublets<WRITE, 2, ALL, T><<<static_cast<unsigned>((hits + 1) / 2), 128, 0, s>>>(k, a);
       break;
     case 512:
-      k_doublets<WRITE, 8, ALL><<<static_cast<unsigned>((hits + 7) / 8), 512, 0, s>>>(k, a);
+      k_doublets<WRITE, 8, ALL, T><<<static_cast<unsigned>((hits + 7) / 8), 512, 0, s>>>(k, a);
       break;
     default:
-      k_doublets<WRITE, 4, ALL><<<static_cast<unsigned>((hits + 3) / 4), 256, 0, s>>>(k, a);
+      k_doublets<WRITE, 4, ALL, T><<<static_cast<unsigned>((hits + 3) / 4), 256, 0, s>>>(k, a);
   }
 }
 
-template <bool WRITE>
-static void launch_doublets(const DevCfg& k, const DoubletArgs& a, int n, int block, hipStream_t s) {
+template <bool WRITE, class T>
+static void launch_doublets(const DevCfg& k, const DoubletArgs<T>& a, int n, int block, hipStream_t s) {
   if ((k.cut_mask & kCutsAll) == kCutsAll)
-    launch_doublets_as<WRITE, true>(k, a, n, block, s);
+    launch_doublets_as<WRITE, true, T>(k, a, n, block, s);
   else
-    launch_doublets_as<WRITE, false>(k, a, n, block, s);
+    launch_doublets_as<WRITE, false, T>(k, a, n, block, s);
 }
 
 template <class T>
@@ -453,9 +455,9 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   int32_t* bins = c.take<int32_t>(nb + 2);   // bins[0] = valid hits; bins+1 = counts -> starts
   int32_t* sorted_hit = c.take<int32_t>(n);
   int32_t* skey = c.take<int32_t>(n);
-  double* sX = c.take<double>(n);
-  double* sY = c.take<double>(n);
-  double* sZ = c.take<double>(n);
+  T* sX = c.take<T>(n);
+  T* sY = c.take<T>(n);
+  T* sZ = c.take<T>(n);
   double* sR = c.take<double>(n);
   int32_t* cnt = c.take<int32_t>(n + 1);
   int4* chunks = c.take<int4>(static_cast<size_t>(n) * kMaskChunks);
@@ -479,18 +481,18 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   k_bin_order<T><<<grid_for(n, 256), 256, 0, s>>>(in, bins, bin_start, arrived, skey, sorted_hit, sX, sY, sZ, sR);
   PT_LAUNCH_CHECK();
 
-  DoubletArgs a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, chunks, n_chunks, cells.cap, cells.inner,
+  DoubletArgs<T> a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, chunks, n_chunks, cells.cap, cells.inner,
                 cells.outer, cells.pair, cells.inner_first, cells.inner_count};
   // bin_start[-1] holds the number of valid hits (sorted positions).
   const int block = (k.block_doublets == 64 || k.block_doublets == 128 || k.block_doublets == 512)
                         ? k.block_doublets : 256;
   void* tok = timing_begin(s);
-  launch_doublets<false>(k, a, n, block, s);
+  launch_doublets<false, T>(k, a, n, block, s);
   timing_end(tok, "doublets_count", s);
   PT_LAUNCH_CHECK();
   PT_HIP_CHECK(exclusive_scan(cnt, n, tmp, s));
   tok = timing_begin(s);
-  launch_doublets<true>(k, a, n, kWriteBlock, s);
+  launch_doublets<true, T>(k, a, n, kWriteBlock, s);
   timing_end(tok, "doublets_write", s);
   PT_LAUNCH_CHECK();
   k_finish_cells<<<1, 1, 0, s>>>(cnt + n, cells.cap, cells.count, status);
