@@ -67,6 +67,16 @@ __device__ __forceinline__ bool doublet_pass(const DevCfg& k, double tdphi, doub
 
 namespace {
 
+// Four values of the input type in one vector (one load).
+template <class T>
+struct Vec4Of;
+template <>
+struct Vec4Of<float> { using type = float4; };
+template <>
+struct Vec4Of<double> { using type = double4; };
+template <class T>
+using Vec4 = typename Vec4Of<T>::type;
+
 template <class T>
 struct HitsIn {
   int32_t n_hits, n_events;
@@ -142,8 +152,7 @@ __global__ void k_scatter(HitsIn<T> in, const int32_t* __restrict__ key, const i
 template <class T>
 __global__ void k_bin_order(HitsIn<T> in, const int32_t* __restrict__ valid, const int32_t* __restrict__ bin_start,
                             const int32_t* __restrict__ arrived, const int32_t* __restrict__ skey,
-                            int32_t* __restrict__ sorted_hit, T* __restrict__ sX, T* __restrict__ sY,
-                            T* __restrict__ sZ, double* __restrict__ sR) {
+                            int32_t* __restrict__ sorted_hit, Vec4<T>* __restrict__ sP, double* __restrict__ sR) {
   const int total = *valid;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < total; p += gridDim.x * blockDim.x) {
     const int k = skey[p];
@@ -155,9 +164,12 @@ __global__ void k_bin_order(HitsIn<T> in, const int32_t* __restrict__ valid, con
     const double X = static_cast<double>(in.x[h]);
     const double Y = static_cast<double>(in.y[h]);
     sorted_hit[pos] = h;
-    sX[pos] = in.x[h];  // in the input type: converted where used, exactly
-    sY[pos] = in.y[h];
-    sZ[pos] = in.z[h];
+    Vec4<T> q;  // in the input type: converted where used, exactly
+    q.x = in.x[h];
+    q.y = in.y[h];
+    q.z = in.z[h];
+    q.w = T(0);
+    sP[pos] = q;
     sR[pos] = sqrt(X * X + Y * Y);
   }
 }
@@ -168,9 +180,7 @@ struct DoubletArgs {
   const int32_t* bin_start;
   const int32_t* skey;
   const int32_t* sorted_hit;
-  const T* sX;  // sorted coordinates in the input type (4 bytes each for float hits)
-  const T* sY;
-  const T* sZ;
+  const Vec4<T>* sP;  // sorted (x, y, z, 0) in the input type: one 16-byte load for float hits
   const double* sR;
   int32_t* cnt;            // pass 1: per sorted inner hit
   const int32_t* off;      // pass 2: scanned counts
@@ -260,7 +270,8 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   const int el = sh >= 0 ? (key >> sh) : key / B;
   const int lay = el % kLayers;
   const int e = el / kLayers;
-  const double Xi = double(a.sX[j]), Yi = double(a.sY[j]), Zi = double(a.sZ[j]), Ri = a.sR[j];
+  const Vec4<T> Pi = a.sP[j];
+  const double Xi = double(Pi.x), Yi = double(Pi.y), Zi = double(Pi.z), Ri = a.sR[j];
   const int first = WRITE ? a.off[j] : 0;
   const int last = WRITE ? a.off[j + 1] : 0;
   int pos = first;  // uniform: next cell position (write pass) or count
@@ -343,9 +354,10 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
       for (int o0 = ra[r]; o0 < rb[r]; o0 += kWave) {
         const int o = o0 + lane;
         const int oc = min(o, rb[r] - 1);  // lanes past the range test its last hit and are masked out
+        const Vec4<T> Po = a.sP[oc];
         const bool pass = static_cast<int>(o < rb[r]) &
-                          static_cast<int>(doublet_pass<ALL>(k, tdphi, Xi, Yi, Zi, Ri, double(a.sX[oc]), double(a.sY[oc]), double(a.sZ[oc]),
-                                                             a.sR[oc]));
+                          static_cast<int>(doublet_pass<ALL>(k, tdphi, Xi, Yi, Zi, Ri, double(Po.x), double(Po.y),
+                                                             double(Po.z), a.sR[oc]));
         const uint64_t m = __ballot(pass);
         if (WRITE) {
           if (staged + kWave > kStage) flush();
@@ -405,9 +417,7 @@ size_t ws_doublets(int n_hits, int n_events, int n_bins) {
   c.take<int32_t>(nb + 2);        // [total] + bin counts/starts (+ end)
   c.take<int32_t>(n_hits);        // sorted_hit
   c.take<int32_t>(n_hits);        // skey
-  c.take<double>(n_hits);         // sX
-  c.take<double>(n_hits);         // sY
-  c.take<double>(n_hits);         // sZ
+  c.take<double4>(n_hits);        // sP (x, y, z) in the input type: at most 32 bytes
   c.take<double>(n_hits);         // sR
   c.take<int32_t>(n_hits + 1);    // cnt / off
   c.take<int4>(static_cast<size_t>(n_hits) * kMaskChunks);  // kept groups of candidates
@@ -455,9 +465,7 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   int32_t* bins = c.take<int32_t>(nb + 2);   // bins[0] = valid hits; bins+1 = counts -> starts
   int32_t* sorted_hit = c.take<int32_t>(n);
   int32_t* skey = c.take<int32_t>(n);
-  T* sX = c.take<T>(n);
-  T* sY = c.take<T>(n);
-  T* sZ = c.take<T>(n);
+  Vec4<T>* sP = c.take<Vec4<T>>(n);
   double* sR = c.take<double>(n);
   int32_t* cnt = c.take<int32_t>(n + 1);
   int4* chunks = c.take<int4>(static_cast<size_t>(n) * kMaskChunks);
@@ -478,10 +486,10 @@ static pt_err run_doublets(const pt_hits& h, const DevCfg& k, pt_cells& cells, u
   int32_t* arrived = cnt;  // the per-hit counts are free until the count pass
   k_scatter<T><<<grid_for(n, 256), 256, 0, s>>>(in, key, rank, bin_start, arrived, skey, cells.inner_count);
   PT_LAUNCH_CHECK();
-  k_bin_order<T><<<grid_for(n, 256), 256, 0, s>>>(in, bins, bin_start, arrived, skey, sorted_hit, sX, sY, sZ, sR);
+  k_bin_order<T><<<grid_for(n, 256), 256, 0, s>>>(in, bins, bin_start, arrived, skey, sorted_hit, sP, sR);
   PT_LAUNCH_CHECK();
 
-  DoubletArgs<T> a{n, bin_start, skey, sorted_hit, sX, sY, sZ, sR, cnt, cnt, chunks, n_chunks, cells.cap, cells.inner,
+  DoubletArgs<T> a{n, bin_start, skey, sorted_hit, sP, sR, cnt, cnt, chunks, n_chunks, cells.cap, cells.inner,
                 cells.outer, cells.pair, cells.inner_first, cells.inner_count};
   // bin_start[-1] holds the number of valid hits (sorted positions).
   const int block = (k.block_doublets == 64 || k.block_doublets == 128 || k.block_doublets == 512)
