@@ -205,7 +205,10 @@ typedef struct {
 /* Cell links c_in -> c_out: c_out starts on the outer hit of c_in.  The links
  * are ordered by inner cell, and those of one inner cell by outer cell: cell
  * c's outer links are out_cell[j] for j in [out_start[c], out_start[c] +
- * out_count[c]) (clipped to cap).  has_inner[c] = 1 when some link ends on c.
+ * out_count[c]) (clipped to cap).  out_start is the exclusive prefix sum of
+ * out_count, so a cell's run ends where the next cell's starts, and the last
+ * cell's at count[0]; the n-tuplet search relies on this.  has_inner[c] = 1
+ * when some link ends on c.
  * The per-cell arrays hold the cells' capacity; entries below count[0] of
  * the cells are written. */
 typedef struct {
@@ -302,7 +305,9 @@ pt_err pt_link_cells(const pt_hits* hits, const pt_config* cfg, const pt_cells* 
  * search follows outer links; a path is emitted when its last cell has no
  * outer link or it has max_hits hits (then PT_ST_TRUNCATED counts it), and
  * it has at least min_hits hits.  A row is kept unless one of its cells
- * belongs to a row with more hits. */
+ * belongs to a row with more hits.  The links must be laid out as
+ * pt_link_cells writes them (runs in cell order, links->count[0] after the
+ * last); links->count may not be NULL. */
 pt_err pt_find_ntuplets(const pt_hits* hits, const pt_config* cfg, const pt_cells* cells,
                         const pt_links* links, pt_ntuplets* tuplets, uint32_t* status,
                         pt_workspace ws, pt_stream stream);

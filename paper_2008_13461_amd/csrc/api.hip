@@ -225,7 +225,7 @@ pt_err pt_find_ntuplets(const pt_hits* hits, const pt_config* cfg, const pt_cell
   if (!hits_ok(hits) || !cfg || !cells || !links || !tuplets || !derive_config(*cfg, &d)) return PT_ERR_ARG;
   if (tuplets->cap < 0 || !tuplets->count || !tuplets->count_raw) return PT_ERR_ARG;
   if (tuplets->cap > 0 && (!tuplets->hits || !tuplets->cells || !tuplets->n || !tuplets->kept)) return PT_ERR_ARG;
-  if (cells->cap < 0 || !cells->count || links->cap < 0) return PT_ERR_ARG;
+  if (cells->cap < 0 || !cells->count || links->cap < 0 || !links->count) return PT_ERR_ARG;
   if (cells->cap > 0 && (!cells->inner || !cells->outer || !cells->pair || !links->out_start ||
                          !links->out_count || !links->has_inner))
     return PT_ERR_ARG;

@@ -34,6 +34,7 @@ struct TupIn {
   const int32_t* out_cell;
   const uint8_t* has_inner;
   int32_t links_cap;
+  const int32_t* link_total;  // links found (the end of the last cell's run)
   int32_t* roots;
   int32_t* n_roots;
   int32_t cap;
@@ -285,6 +286,17 @@ __global__ void __launch_bounds__(kBlock) k_prod_count(TupIn a, int32_t* __restr
   if (threadIdx.x == 0) chunk_count[blockIdx.x] = n_prod;
 }
 
+// The run of cell c's outer links, [*first, *end): the links are placed in
+// cell order, so the run ends where the next cell's starts (at the total
+// after the last cell).  Both loads are issued together, so that a child's
+// run comes one dependent load after its index instead of two.
+__device__ inline void link_run(const TupIn& a, int c, int n_cells, int total, int* first, int* end) {
+  const int f = a.out_start[c];
+  const int e = a.out_start[min(c + 1, n_cells - 1)];
+  *first = f;
+  *end = c + 1 < n_cells ? e : total;
+}
+
 // Depth-first search from each root.  COUNT: paths[i] = rows root i emits
 // (and the truncation count); otherwise the rows are written from row
 // first_row[i] on.
@@ -294,6 +306,8 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths, const int3
   // the write pass takes only the roots that emit a row below the capacity
   // (most roots emit none: their paths are too short)
   const int nr = COUNT ? *a.n_roots : *n_prod;
+  const int n_cells = min(*a.cell_count, a.cells_cap);
+  const int total = *a.link_total;
   uint32_t truncated = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nr; t += gridDim.x * blockDim.x) {
     int stack[kMaxHits];   // cells of the current path
@@ -302,8 +316,7 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths, const int3
     const int i = COUNT ? t : prod[t];
     const int root = a.roots[i];
     stack[0] = root;
-    next[0] = a.out_start[root];
-    end[0] = next[0] + a.out_count[root];
+    link_run(a, root, n_cells, total, &next[0], &end[0]);
     int depth = 0;
     int row = COUNT ? 0 : paths[i];
     while (depth >= 0) {
@@ -315,7 +328,9 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths, const int3
       if (li >= a.links_cap) continue;
       const int child = a.out_cell[li];
       const int nh = depth + 3;  // hits of the path root..child
-      const int coc = a.out_count[child];
+      int cf, ce;
+      link_run(a, child, n_cells, total, &cf, &ce);
+      const int coc = ce - cf;
       if (coc == 0 || nh == k.max_hits) {
         if (COUNT && coc > 0) ++truncated;
         if (nh >= k.min_hits) {
@@ -331,8 +346,8 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths, const int3
       } else {
         ++depth;
         stack[depth] = child;
-        next[depth] = a.out_start[child];
-        end[depth] = next[depth] + coc;
+        next[depth] = cf;
+        end[depth] = ce;
       }
     }
     if (COUNT) paths[i] = row;
@@ -502,7 +517,7 @@ pt_err launch_ntuplets(const pt_hits& h, const DevCfg& k, const pt_cells& cells,
   int32_t* tmp = c.take<int32_t>(scan_tmp_elems(scan_n));
   int32_t* n_roots = chunk_roots + chunks;  // the scan's total
   TupIn a{cells.inner, cells.outer, cells.pair, cells.count, cells.cap, L.out_start, L.out_count, L.out_cell,
-          L.has_inner, L.cap, roots, n_roots, T.cap, T.hits, T.cells, T.n, T.count_raw, T.kept, T.count,
+          L.has_inner, L.cap, L.count, roots, n_roots, T.cap, T.hits, T.cells, T.n, T.count_raw, T.kept, T.count,
           max_n, status};
   void* tok = timing_begin(s);
   const bool vec = reinterpret_cast<uintptr_t>(L.out_count) % 16 == 0 &&
