@@ -21,6 +21,8 @@
 #include "fit_core.h"
 #include "pt_internal.h"
 
+#include <type_traits>
+
 namespace pt {
 namespace {
 
@@ -365,12 +367,52 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit(DevCfg k, FitArgs a) {
 // ---------------------------------------------------------------------------
 // adjoint
 
+// The hit gradients of the last track a thread took, added with device-scope
+// atomics only once the next track's inputs have been loaded: one counter
+// tracks loads and atomics alike, so a load issued after the atomics would
+// wait for them to complete.
+template <class GT>
+struct PendingGrad {
+  int n = 0;
+  int hit[kMaxHits];
+  GT g[kMaxHits][3];
+};
+
+template <class GT>
+__device__ inline void flush_pending(PendingGrad<GT>& p, void* grad_hits) {
+#pragma unroll
+  for (int kk = 0; kk < kMaxHits; ++kk) {
+    if (kk < p.n) {
+      GT* gh = static_cast<GT*>(grad_hits) + static_cast<int64_t>(p.hit[kk]) * 3;
+      unsafeAtomicAdd(gh + 0, p.g[kk][0]);
+      unsafeAtomicAdd(gh + 1, p.g[kk][1]);
+      unsafeAtomicAdd(gh + 2, p.g[kk][2]);
+    }
+  }
+  p.n = 0;
+}
+
+template <class GT>
+__device__ inline void load_cotangents(const FitArgs& a, int i, GT (&g)[6]) {
+  const GT* gp = static_cast<const GT*>(a.g_params) + static_cast<int64_t>(i) * 5;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) g[q] = gp[q];
+  g[5] = a.g_chi2 ? static_cast<const GT*>(a.g_chi2)[i] : GT(0);
+}
+
 template <int N, class S, class HT, class GT>
 __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const FitArgs& a, int i, bool fallback,
-                                double* lds_mod, uint32_t& n_redo) {
+                                double* lds_mod, uint32_t& n_redo, PendingGrad<GT>& pend) {
+  // deferred in the float adjoint of four or more hits only (the double
+  // state leaves no registers for it; three hits keep two wavefronts per SIMD)
+  constexpr bool kDefer = std::is_same<S, float>::value && std::is_same<GT, float>::value && N > 3;
   fit::State<N, S> f;
   int hit[N], mod[N];
-  if (!load_track<N, S, HT>(a, k.layer_barrel, track_row(a, i), f, hit, mod)) return;
+  const bool ok = load_track<N, S, HT>(a, k.layer_barrel, track_row(a, i), f, hit, mod);
+  GT gin[6];
+  if (kDefer) load_cotangents(a, i, gin);
+  if (kDefer && pend.n) flush_pending(pend, a.grad_hits);  // the previous track's, after this one's loads
+  if (!ok) return;
   fit::forward<N, S>(C, f);
   if (fallback && (f.status == fit::ST_FAILED || (f.status == fit::ST_OK && double(f.cond) > C.thr))) {
     const int slot = atomicAdd(a.redo_count, 1);
@@ -379,22 +421,27 @@ __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const Fit
     return;
   }
   if (f.status != fit::ST_OK) return;
+  if (!kDefer) load_cotangents(a, i, gin);
   double g[6];
-  const GT* gp = static_cast<const GT*>(a.g_params) + static_cast<int64_t>(i) * 5;
 #pragma unroll
-  for (int q = 0; q < 5; ++q) g[q] = double(gp[q]);
-  g[5] = a.g_chi2 ? double(static_cast<const GT*>(a.g_chi2)[i]) : 0.0;
+  for (int q = 0; q < 6; ++q) g[q] = double(gin[q]);
   S gP[N][3];
   fit::backward<N, S>(C, f, g, gP);
 #pragma unroll
   for (int kk = 0; kk < N; ++kk) {
     if (a.grad_hits) {
-      GT* gh = static_cast<GT*>(a.grad_hits) + static_cast<int64_t>(hit[kk]) * 3;
       if (k.exclusive_hits) {  // the row is this track's alone
+        GT* gh = static_cast<GT*>(a.grad_hits) + static_cast<int64_t>(hit[kk]) * 3;
         gh[0] += GT(gP[kk][0]);
         gh[1] += GT(gP[kk][1]);
         gh[2] += GT(gP[kk][2]);
+      } else if (kDefer) {
+        pend.hit[kk] = hit[kk];
+        pend.g[kk][0] = GT(gP[kk][0]);
+        pend.g[kk][1] = GT(gP[kk][1]);
+        pend.g[kk][2] = GT(gP[kk][2]);
       } else {
+        GT* gh = static_cast<GT*>(a.grad_hits) + static_cast<int64_t>(hit[kk]) * 3;
         unsafeAtomicAdd(gh + 0, GT(gP[kk][0]));
         unsafeAtomicAdd(gh + 1, GT(gP[kk][1]));
         unsafeAtomicAdd(gh + 2, GT(gP[kk][2]));
@@ -407,6 +454,7 @@ __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const Fit
       atomicAdd(lm + 2, double(gP[kk][2]));
     }
   }
+  if (kDefer && a.grad_hits && !k.exclusive_hits) pend.n = N;
 }
 
 __device__ inline void lds_clear(double* lds, int n) {
@@ -438,17 +486,19 @@ __global__ void __launch_bounds__(kBlock) k_grad(DevCfg k, FitArgs a, bool fallb
   const int m = bin_total<NLO, NHI>(a);
   uint32_t n_redo = 0;
   bool any = false;
+  PendingGrad<GT> pend;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
     int nh;
     const int i = bin_item<NLO, NHI>(a, j, nh);
     any = true;
-    if (NLO <= 3 && 3 <= NHI && nh == 3) grad_one<3, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
-    if (NLO <= 4 && 4 <= NHI && nh == 4) grad_one<4, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
-    if (NLO <= 5 && 5 <= NHI && nh == 5) grad_one<5, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
-    if (NLO <= 6 && 6 <= NHI && nh == 6) grad_one<6, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
-    if (NLO <= 7 && 7 <= NHI && nh == 7) grad_one<7, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
-    if (NLO <= 8 && 8 <= NHI && nh == 8) grad_one<8, S, HT, GT>(k, C, a, i, fallback, lm, n_redo);
+    if (NLO <= 3 && 3 <= NHI && nh == 3) grad_one<3, S, HT, GT>(k, C, a, i, fallback, lm, n_redo, pend);
+    if (NLO <= 4 && 4 <= NHI && nh == 4) grad_one<4, S, HT, GT>(k, C, a, i, fallback, lm, n_redo, pend);
+    if (NLO <= 5 && 5 <= NHI && nh == 5) grad_one<5, S, HT, GT>(k, C, a, i, fallback, lm, n_redo, pend);
+    if (NLO <= 6 && 6 <= NHI && nh == 6) grad_one<6, S, HT, GT>(k, C, a, i, fallback, lm, n_redo, pend);
+    if (NLO <= 7 && 7 <= NHI && nh == 7) grad_one<7, S, HT, GT>(k, C, a, i, fallback, lm, n_redo, pend);
+    if (NLO <= 8 && 8 <= NHI && nh == 8) grad_one<8, S, HT, GT>(k, C, a, i, fallback, lm, n_redo, pend);
   }
+  if (pend.n) flush_pending(pend, a.grad_hits);
   if (nm3) lds_flush<FIRST>(lds_mod, nm3, any, a.partials + static_cast<int64_t>(blockIdx.x) * nm3);
 }
 
@@ -462,19 +512,21 @@ __global__ void __launch_bounds__(kBlock) k_regrad(DevCfg k, FitArgs a) {
   uint32_t n_redo = 0;
   double* lm = nm3 ? lds_mod : nullptr;
   bool any = false;
+  PendingGrad<float> pend;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
     const int i = a.redo[j];
     any = true;
     switch (a.tup_n[track_row(a, i)]) {
-      case 3: grad_one<3, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
-      case 4: grad_one<4, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
-      case 5: grad_one<5, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
-      case 6: grad_one<6, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
-      case 7: grad_one<7, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
-      case 8: grad_one<8, double, HT, float>(k, C, a, i, false, lm, n_redo); break;
+      case 3: grad_one<3, double, HT, float>(k, C, a, i, false, lm, n_redo, pend); break;
+      case 4: grad_one<4, double, HT, float>(k, C, a, i, false, lm, n_redo, pend); break;
+      case 5: grad_one<5, double, HT, float>(k, C, a, i, false, lm, n_redo, pend); break;
+      case 6: grad_one<6, double, HT, float>(k, C, a, i, false, lm, n_redo, pend); break;
+      case 7: grad_one<7, double, HT, float>(k, C, a, i, false, lm, n_redo, pend); break;
+      case 8: grad_one<8, double, HT, float>(k, C, a, i, false, lm, n_redo, pend); break;
       default: break;
     }
   }
+  if (pend.n) flush_pending(pend, a.grad_hits);
   if (nm3) lds_flush<false>(lds_mod, nm3, any, a.partials + static_cast<int64_t>(blockIdx.x) * nm3);
 }
 
