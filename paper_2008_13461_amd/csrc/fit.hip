@@ -368,9 +368,10 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit(DevCfg k, FitArgs a) {
 // adjoint
 
 // The hit gradients of the last track a thread took, added with device-scope
-// atomics only once the next track's inputs have been loaded: one counter
-// tracks loads and atomics alike, so a load issued after the atomics would
-// wait for them to complete.
+// atomics (or, when no hit is shared, stored as final sums) only once the
+// next track's inputs have been loaded: one counter tracks loads, stores and
+// atomics alike, so a load issued after them would wait for them to
+// complete.
 template <class GT>
 struct PendingGrad {
   int n = 0;
@@ -379,14 +380,20 @@ struct PendingGrad {
 };
 
 template <class GT>
-__device__ inline void flush_pending(PendingGrad<GT>& p, void* grad_hits) {
+__device__ inline void flush_pending(PendingGrad<GT>& p, void* grad_hits, bool exclusive) {
 #pragma unroll
   for (int kk = 0; kk < kMaxHits; ++kk) {
     if (kk < p.n) {
       GT* gh = static_cast<GT*>(grad_hits) + static_cast<int64_t>(p.hit[kk]) * 3;
-      unsafeAtomicAdd(gh + 0, p.g[kk][0]);
-      unsafeAtomicAdd(gh + 1, p.g[kk][1]);
-      unsafeAtomicAdd(gh + 2, p.g[kk][2]);
+      if (exclusive) {
+        gh[0] = p.g[kk][0];
+        gh[1] = p.g[kk][1];
+        gh[2] = p.g[kk][2];
+      } else {
+        unsafeAtomicAdd(gh + 0, p.g[kk][0]);
+        unsafeAtomicAdd(gh + 1, p.g[kk][1]);
+        unsafeAtomicAdd(gh + 2, p.g[kk][2]);
+      }
     }
   }
   p.n = 0;
@@ -411,7 +418,7 @@ __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const Fit
   const bool ok = load_track<N, S, HT>(a, k.layer_barrel, track_row(a, i), f, hit, mod);
   GT gin[6];
   if (kDefer) load_cotangents(a, i, gin);
-  if (kDefer && pend.n) flush_pending(pend, a.grad_hits);  // the previous track's, after this one's loads
+  if (kDefer && pend.n) flush_pending(pend, a.grad_hits, k.exclusive_hits);  // the previous track's, after this one's loads
   if (!ok) return;
   fit::forward<N, S>(C, f);
   if (fallback && (f.status == fit::ST_FAILED || (f.status == fit::ST_OK && double(f.cond) > C.thr))) {
@@ -427,15 +434,36 @@ __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const Fit
   for (int q = 0; q < 6; ++q) g[q] = double(gin[q]);
   S gP[N][3];
   fit::backward<N, S>(C, f, g, gP);
+  if (a.grad_hits && k.exclusive_hits) {
+    // the row is this track's alone, its hits distinct: every load before
+    // the first store, so that no load waits for a store
+    GT cur[N][3];
+#pragma unroll
+    for (int kk = 0; kk < N; ++kk) {
+      const GT* gh = static_cast<const GT*>(a.grad_hits) + static_cast<int64_t>(hit[kk]) * 3;
+      cur[kk][0] = gh[0];
+      cur[kk][1] = gh[1];
+      cur[kk][2] = gh[2];
+    }
+#pragma unroll
+    for (int kk = 0; kk < N; ++kk) {
+      if (kDefer) {
+        pend.hit[kk] = hit[kk];
+        pend.g[kk][0] = cur[kk][0] + GT(gP[kk][0]);
+        pend.g[kk][1] = cur[kk][1] + GT(gP[kk][1]);
+        pend.g[kk][2] = cur[kk][2] + GT(gP[kk][2]);
+      } else {
+        GT* gh = static_cast<GT*>(a.grad_hits) + static_cast<int64_t>(hit[kk]) * 3;
+        gh[0] = cur[kk][0] + GT(gP[kk][0]);
+        gh[1] = cur[kk][1] + GT(gP[kk][1]);
+        gh[2] = cur[kk][2] + GT(gP[kk][2]);
+      }
+    }
+  }
 #pragma unroll
   for (int kk = 0; kk < N; ++kk) {
-    if (a.grad_hits) {
-      if (k.exclusive_hits) {  // the row is this track's alone
-        GT* gh = static_cast<GT*>(a.grad_hits) + static_cast<int64_t>(hit[kk]) * 3;
-        gh[0] += GT(gP[kk][0]);
-        gh[1] += GT(gP[kk][1]);
-        gh[2] += GT(gP[kk][2]);
-      } else if (kDefer) {
+    if (a.grad_hits && !k.exclusive_hits) {
+      if (kDefer) {
         pend.hit[kk] = hit[kk];
         pend.g[kk][0] = GT(gP[kk][0]);
         pend.g[kk][1] = GT(gP[kk][1]);
@@ -454,7 +482,7 @@ __device__ inline void grad_one(const DevCfg& k, const fit::Consts& C, const Fit
       atomicAdd(lm + 2, double(gP[kk][2]));
     }
   }
-  if (kDefer && a.grad_hits && !k.exclusive_hits) pend.n = N;
+  if (kDefer && a.grad_hits) pend.n = N;
 }
 
 __device__ inline void lds_clear(double* lds, int n) {
@@ -498,7 +526,7 @@ __global__ void __launch_bounds__(kBlock) k_grad(DevCfg k, FitArgs a, bool fallb
     if (NLO <= 7 && 7 <= NHI && nh == 7) grad_one<7, S, HT, GT>(k, C, a, i, fallback, lm, n_redo, pend);
     if (NLO <= 8 && 8 <= NHI && nh == 8) grad_one<8, S, HT, GT>(k, C, a, i, fallback, lm, n_redo, pend);
   }
-  if (pend.n) flush_pending(pend, a.grad_hits);
+  if (pend.n) flush_pending(pend, a.grad_hits, k.exclusive_hits);
   if (nm3) lds_flush<FIRST>(lds_mod, nm3, any, a.partials + static_cast<int64_t>(blockIdx.x) * nm3);
 }
 
@@ -526,7 +554,7 @@ __global__ void __launch_bounds__(kBlock) k_regrad(DevCfg k, FitArgs a) {
       default: break;
     }
   }
-  if (pend.n) flush_pending(pend, a.grad_hits);
+  if (pend.n) flush_pending(pend, a.grad_hits, k.exclusive_hits);
   if (nm3) lds_flush<false>(lds_mod, nm3, any, a.partials + static_cast<int64_t>(blockIdx.x) * nm3);
 }
 
