@@ -307,7 +307,7 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths, const int3
   // (most roots emit none: their paths are too short)
   const int nr = COUNT ? *a.n_roots : *n_prod;
   const int n_cells = min(*a.cell_count, a.cells_cap);
-  const int total = *a.link_total;
+  const int links_found = *a.link_total;
   uint32_t truncated = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nr; t += gridDim.x * blockDim.x) {
     int stack[kMaxHits];   // cells of the current path
@@ -316,7 +316,7 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths, const int3
     const int i = COUNT ? t : prod[t];
     const int root = a.roots[i];
     stack[0] = root;
-    link_run(a, root, n_cells, total, &next[0], &end[0]);
+    link_run(a, root, n_cells, links_found, &next[0], &end[0]);
     int depth = 0;
     int row = COUNT ? 0 : paths[i];
     while (depth >= 0) {
@@ -329,7 +329,7 @@ __global__ void k_dfs(DevCfg k, TupIn a, int32_t* __restrict__ paths, const int3
       const int child = a.out_cell[li];
       const int nh = depth + 3;  // hits of the path root..child
       int cf, ce;
-      link_run(a, child, n_cells, total, &cf, &ce);
+      link_run(a, child, n_cells, links_found, &cf, &ce);
       const int coc = ce - cf;
       if (coc == 0 || nh == k.max_hits) {
         if (COUNT && coc > 0) ++truncated;
