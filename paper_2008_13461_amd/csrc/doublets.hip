@@ -255,6 +255,12 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   if (j >= a.n_hits) return;
   // count pass: the kept groups of the hit, record t on lane t
   int4 rec = make_int4(0, 0, 0, 0);
+  // the write pass's own loads go out with the bound's (j < n_hits: every
+  // one is in range), so that its chain of dependent loads is one shorter
+  const int first = WRITE ? a.off[j] : 0;
+  const int last = WRITE ? a.off[j + 1] : 0;
+  const int hit_i = WRITE ? a.sorted_hit[j] : 0;
+  const int nst = WRITE ? a.n_chunks[j] : 0;
   const int total = a.bin_start[-1];  // valid (sorted) hits
   if (j >= total) {
     if (!WRITE && lane == 0) {
@@ -263,20 +269,8 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
     }
     return;
   }
-  const int B = k.n_bins;
-  const int key = a.skey[j];
-  const int sh = k.bin_shift;  // log2 B for a power of two: no integer division
-  const int b = sh >= 0 ? (key & (B - 1)) : key % B;
-  const int el = sh >= 0 ? (key >> sh) : key / B;
-  const int lay = el % kLayers;
-  const int e = el / kLayers;
-  const Vec4<T> Pi = a.sP[j];
-  const double Xi = double(Pi.x), Yi = double(Pi.y), Zi = double(Pi.z), Ri = a.sR[j];
-  const int first = WRITE ? a.off[j] : 0;
-  const int last = WRITE ? a.off[j + 1] : 0;
   int pos = first;  // uniform: next cell position (write pass) or count
-  const int hit_i = WRITE ? a.sorted_hit[j] : 0;
-  int staged = 0;                   // uniform: staged cells, to be written from pos on
+  int staged = 0;   // uniform: staged cells, to be written from pos on
   // stores the staged cells (outer hit, pair), consecutive positions on
   // consecutive lanes
   auto flush = [&]() {
@@ -295,49 +289,55 @@ __global__ void __launch_bounds__(WAVES * kWave) k_doublets(DevCfg k, DoubletArg
   };
   // the write pass takes the groups the count pass kept instead of testing
   // the candidates again
-  if (WRITE) {
-    const int nst = a.n_chunks[j];
-    if (nst >= 0) {
-      if (lane < nst) s_chunk[wave][lane] = a.chunks[static_cast<int64_t>(j) * kMaskChunks + lane];
-      wave_sync();
-      // kGroupBatch groups at a time: the gathers of all of them are issued
-      // before any is staged
-      constexpr int kGroupBatch = 4;
-      for (int t0 = 0; t0 < nst; t0 += kGroupBatch) {
-        uint64_t m[kGroupBatch];
-        int pr[kGroupBatch], hit[kGroupBatch];
+  if (WRITE && nst >= 0) {
+    if (lane < nst) s_chunk[wave][lane] = a.chunks[static_cast<int64_t>(j) * kMaskChunks + lane];
+    wave_sync();
+    // kGroupBatch groups at a time: the gathers of all of them are issued
+    // before any is staged
+    constexpr int kGroupBatch = 4;
+    for (int t0 = 0; t0 < nst; t0 += kGroupBatch) {
+      uint64_t m[kGroupBatch];
+      int pr[kGroupBatch], hit[kGroupBatch];
 #pragma unroll
-        for (int u = 0; u < kGroupBatch; ++u) {
-          m[u] = 0;
-          pr[u] = 0;
-          if (t0 + u < nst) {  // uniform
-            const int4 d = s_chunk[wave][t0 + u];
-            m[u] = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.y))) << 32) |
-                   static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.x));
-            pr[u] = __builtin_amdgcn_readfirstlane(d.w);
-            const int o = __builtin_amdgcn_readfirstlane(d.z) + lane;
-            if ((m[u] >> lane) & 1u) hit[u] = a.sorted_hit[o];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kGroupBatch; ++u) {
-          if (staged + kWave > kStage) flush();
-          if ((m[u] >> lane) & 1u) {
-            const int at = staged + lane_prefix(m[u]);
-            s_out[wave][at] = hit[u];
-            s_pair[wave][at] = static_cast<uint8_t>(pr[u]);
-          }
-          staged += __popcll(m[u]);
+      for (int u = 0; u < kGroupBatch; ++u) {
+        m[u] = 0;
+        pr[u] = 0;
+        if (t0 + u < nst) {  // uniform
+          const int4 d = s_chunk[wave][t0 + u];
+          m[u] = (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.y))) << 32) |
+                 static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(d.x));
+          pr[u] = __builtin_amdgcn_readfirstlane(d.w);
+          const int o = __builtin_amdgcn_readfirstlane(d.z) + lane;
+          if ((m[u] >> lane) & 1u) hit[u] = a.sorted_hit[o];
         }
       }
-      flush();
-      if (lane == 0) {
-        a.inner_first[hit_i] = first;
-        a.inner_count[hit_i] = last - first;
+#pragma unroll
+      for (int u = 0; u < kGroupBatch; ++u) {
+        if (staged + kWave > kStage) flush();
+        if ((m[u] >> lane) & 1u) {
+          const int at = staged + lane_prefix(m[u]);
+          s_out[wave][at] = hit[u];
+          s_pair[wave][at] = static_cast<uint8_t>(pr[u]);
+        }
+        staged += __popcll(m[u]);
       }
-      return;
     }
+    flush();
+    if (lane == 0) {
+      a.inner_first[hit_i] = first;
+      a.inner_count[hit_i] = last - first;
+    }
+    return;
   }
+  const int B = k.n_bins;
+  const int key = a.skey[j];
+  const int sh = k.bin_shift;  // log2 B for a power of two: no integer division
+  const int b = sh >= 0 ? (key & (B - 1)) : key % B;
+  const int el = sh >= 0 ? (key >> sh) : key / B;
+  const int lay = el % kLayers;
+  const int e = el / kLayers;
+  const Vec4<T> Pi = a.sP[j];
+  const double Xi = double(Pi.x), Yi = double(Pi.y), Zi = double(Pi.z), Ri = a.sR[j];
   // the count pass, or the write pass of a hit with more groups than kept:
   // every group of candidates, in pair order, then window order
   int kept = 0;  // uniform: groups with a passing candidate (count pass)
