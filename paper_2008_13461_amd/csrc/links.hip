@@ -520,14 +520,17 @@ __global__ void __launch_bounds__(WAVES * kWave)
   WaveLds<T>& L = lds[wave];
   const int h1 = blockIdx.x * WAVES + wave;
   if (h1 >= a.n_hits) return;
+  // every load of the hit's own entries at once (all in range for h1 < n_hits)
   const int sb = a.seg_first[h1];
   const int se = a.seg_first[h1 + 1];
-  if (se <= sb) return;
-  const int n_cells = min(*a.cell_count, a.cells_cap);
+  const int cell_count = *a.cell_count;
   const int cb = a.inner_first[h1];
-  const int nb = min(cb + a.inner_count[h1], n_cells) - cb;
-  if (a.inner_count[h1] <= 0 || nb <= 0) return;  // no out-cells: no links (counts are zero)
+  const int icount = a.inner_count[h1];
   const double4 P1 = a.hx[h1];
+  if (se <= sb) return;
+  const int n_cells = min(cell_count, a.cells_cap);
+  const int nb = min(cb + icount, n_cells) - cb;
+  if (icount <= 0 || nb <= 0) return;  // no out-cells: no links (counts are zero)
   const double X1 = P1.x, Y1 = P1.y, Z1 = P1.z, R1 = P1.w;
   const double th2b = k.theta2_barrel, th2e = k.theta2_endcap;
   const int nh = min(nb, kHinBits);  // out-cells whose has_inner bit is kept in LDS
